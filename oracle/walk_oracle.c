@@ -1,0 +1,510 @@
+/*
+ * CPU oracle for the dynamic random-walk transition sampler.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may load this file: only the
+ * test-suite, the package smoke check and the benchmark's CPU-baseline leg do.  It
+ * shares no code with the GPU implementation.
+ *
+ * It is written to be read against FlexiWalker (arXiv 2512.00705):
+ *   - transition weight and probability: w~ = w * h, p(u) = w~(v,u) / sum_t w~(v,t)
+ *     (Section 2.1, Eq. prob);
+ *   - Node2Vec workload weight 1/a, 1, 1/b by dist(v', u) = 0, 1, 2 (Eq. node2vec);
+ *     a and b are called p and q here;
+ *   - MetaPath: weight 1 when the edge label matches the schema position, else 0
+ *     (Section 2.1);
+ *   - eRVS: exponential keys k_i = u_i^(1/w~_i), argmax wins, ">=" so later items win
+ *     ties (Section 3.2, Algorithm 1), plus the jump of Eq. (jump) run per lane with a
+ *     shared initial maximum (Section 3.2, parallel description);
+ *   - eRJS: uniform proposal, accept when U * c' < w~ for any bound c' >= max w~
+ *     (Section 3.3 and its proof);
+ *   - bound max(w) * max(h) and sum estimate mean(w) * sum(h) (Section 3.3, Section 4.2
+ *     helper generation, Eq. sum_estimation);
+ *   - cost model: choose eRJS iff (EdgeCost_RJS / EdgeCost_RVS) * max w~ < sum w~
+ *     (Section 4.1, Eq. runtime).
+ *
+ * Canonical stream.  To compare samples one by one with a GPU run the random numbers
+ * are a fixed function of (seed, walker, step, draw): Philox4x32-10 (Salmon, Moraes,
+ * Dror, Shaw, "Parallel Random Numbers: As Easy as 1, 2, 3", SC'11) with key = seed and
+ * counter = (walker, step, draw, tag); tag 0 = eRJS trial, 1 = eRVS item, 3 = ITS.
+ * All sampling arithmetic is IEEE float32 with round-to-nearest and no contraction;
+ * logarithms are evaluated in double and rounded once to float32.
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC walk_oracle.c -lm
+ *
+ * OG_MUTANT (tests only) plants one known mistake so that the test-suite can show its
+ * pins catch it: 1 swaps the Node2Vec return weight 1/p for 1/q, 2 drops the
+ * conditioning of the jump key, 3 keeps the skip sum after a jump, 4 never proposes
+ * the last neighbour in eRJS, 5 drops h_MAX from the eRJS bound.
+ */
+#ifndef OG_MUTANT
+#define OG_MUTANT 0
+#endif
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ Philox4x32-10 */
+/* Round function and constants as published by Salmon et al. (SC'11). */
+void og_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Uniform on the open interval (0,1): (2m+1) * 2^-24 with m the top 23 bits.
+ * Every value is exact in float32 and the set is symmetric about 1/2. */
+float og_uniform(uint32_t x)
+{
+    return (float)(2u * (x >> 9) + 1u) * 0x1p-24f;
+}
+
+static void draw(uint64_t seed, uint32_t walker, uint32_t step, uint32_t idx, uint32_t tag, uint32_t out[4])
+{
+    uint32_t ctr[4] = {walker, step, idx, tag};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    og_philox(ctr, key, out);
+}
+
+/* Transcendentals: exact value (double libm) rounded once to float32. */
+static float ln_f(float x) { return (float)log((double)x); }
+static float expm1_f(float x) { return (float)expm1((double)x); }
+static float log1p_f(float x) { return (float)log1p((double)x); }
+
+/* ------------------------------------------------------------------ inputs */
+typedef struct {
+    int64_t nv, ne;
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const float *h;       /* NULL: unweighted (h = 1) */
+    const uint8_t *label; /* NULL unless MetaPath */
+} og_graph;
+
+enum { OG_NODE2VEC = 1, OG_METAPATH = 2 };
+typedef struct {
+    int32_t kind;
+    int32_t weighted;
+    float p, q;          /* Node2Vec a, b */
+    int32_t schema_len;  /* MetaPath */
+    uint8_t schema[64];
+} og_logic;
+
+typedef struct {
+    float rho;           /* EdgeCost_RJS / EdgeCost_RVS */
+    int32_t d_lo;        /* degree below which eRVS is always used */
+    int32_t rjs_cap;     /* eRJS trials before falling back to eRVS */
+    int32_t lanes;       /* eRVS lanes P */
+    int32_t jump;        /* 1: Eq. (jump); 0: a key for every item */
+    float bound_scale;   /* multiplies the eRJS bound (>= 1 keeps it a bound) */
+} og_plan;
+
+enum { OG_AUTO = 0, OG_RVS_ONLY = 1, OG_RJS_ONLY = 2, OG_ITS = 3 };
+
+/* Per-node preprocessing: h_MAX is the row maximum of h; h_SUM is the row sum of h,
+ * accumulated in double and rounded once to float32 (Section 4.2, preprocess()). */
+void og_preprocess(const og_graph *g, float *hmax, float *hsum)
+{
+    #pragma omp parallel for schedule(dynamic, 1024)
+    for (int64_t v = 0; v < g->nv; ++v) {
+        float mx = 0.0f;
+        double sm = 0.0;
+        for (int64_t k = g->row_ptr[v]; k < g->row_ptr[v + 1]; ++k) {
+            float hv = g->h ? g->h[k] : 1.0f;
+            if (hv > mx) mx = hv;
+            sm += (double)hv;
+        }
+        hmax[v] = mx;
+        hsum[v] = (float)sm;
+    }
+}
+
+/* ------------------------------------------------------------------ one step */
+typedef struct {
+    const og_graph *g;
+    const float *hmax, *hsum;
+    const og_logic *lg;
+    const og_plan *pl;
+    int strategy;
+    uint64_t seed;
+} og_ctx;
+
+typedef struct {
+    float margin;   /* smallest relative gap of a float comparison in this step */
+    int kind;       /* 0 eRVS, 1 eRJS accepted, 2 eRJS capped then eRVS, 3 ITS, -1 terminated */
+    int trials;
+    int triggers;
+    double bytes;   /* algorithmic bytes of this step */
+} og_info;
+
+static void note_margin(og_info *info, float a, float b)
+{
+    float d = fabsf(a - b), m = fmaxf(fabsf(a), fabsf(b));
+    float r = m > 0.0f ? d / m : 0.0f;
+    if (r < info->margin) info->margin = r;
+}
+
+static int cmp_i32(const void *x, const void *y)
+{
+    int32_t a = *(const int32_t *)x, b = *(const int32_t *)y;
+    return (a > b) - (a < b);
+}
+
+static int is_neighbour(const og_graph *g, int32_t prev, int32_t u)
+{
+    int64_t b = g->row_ptr[prev], n = g->row_ptr[prev + 1] - b;
+    return n > 0 && bsearch(&u, g->col + b, (size_t)n, sizeof(int32_t), cmp_i32) != NULL;
+}
+
+static int ceil_log2_plus1(int64_t m) /* ceil(log2(m + 1)): probes of a binary search */
+{
+    int c = 0;
+    while (((int64_t)1 << c) < m + 1) ++c;
+    return c;
+}
+
+/* Workload weight w(v, u) for the edge at CSR position k (u = col[k]) at step j. */
+static float workload_weight(const og_ctx *cx, int64_t k, int j, int32_t prev)
+{
+    const og_logic *lg = cx->lg;
+    if (lg->kind == OG_NODE2VEC) {
+        if (j == 0) return 1.0f;                     /* no previous vertex yet */
+        int32_t u = cx->g->col[k];
+        if (u == prev) return 1.0f / (OG_MUTANT == 1 ? lg->q : lg->p); /* dist(v', u) = 0 */
+        if (is_neighbour(cx->g, prev, u)) return 1.0f; /* dist(v', u) = 1 */
+        return 1.0f / lg->q;                         /* dist(v', u) = 2 */
+    }
+    /* MetaPath: schema repeated along the walk */
+    return cx->g->label[k] == lg->schema[j % lg->schema_len] ? 1.0f : 0.0f;
+}
+
+static float transition_weight(const og_ctx *cx, int64_t k, int j, int32_t prev)
+{
+    float w = workload_weight(cx, k, j, prev);
+    if (cx->lg->weighted && cx->g->h) return w * cx->g->h[k];
+    return w;
+}
+
+/* max over the workload's return values, and their mean (Section 4.2 helpers) */
+static float w_max(const og_logic *lg, int j)
+{
+    if (lg->kind == OG_NODE2VEC && j > 0) return fmaxf(fmaxf(1.0f / lg->p, 1.0f), 1.0f / lg->q);
+    return 1.0f;
+}
+
+static float w_avg(const og_logic *lg, int j)
+{
+    if (lg->kind == OG_NODE2VEC) {
+        if (j == 0) return 1.0f;
+        return ((1.0f / lg->p + 1.0f) + 1.0f / lg->q) / 3.0f;
+    }
+    return (1.0f + 0.0f) / 2.0f;
+}
+
+static double bytes_per_item(const og_ctx *cx)
+{
+    double b = 4.0;                                   /* col */
+    if (cx->lg->weighted && cx->g->h) b += 4.0;       /* h */
+    if (cx->lg->kind == OG_METAPATH) b += 1.0;        /* label */
+    return b;
+}
+
+/* eRVS over the row of `cur`, Section 3.2.  Returns the CSR offset within the row or -1. */
+static int64_t rvs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int64_t base, int64_t deg,
+                          og_info *info)
+{
+    const int64_t P = cx->pl->lanes;
+    uint32_t x[4];
+
+    if (!cx->pl->jump) {
+        /* Algorithm 1 as written: one key per item, keep the last maximum */
+        float best = -INFINITY;
+        int64_t best_i = -1;
+        for (int64_t i = 0; i < deg; ++i) {
+            float wt = transition_weight(cx, base + i, j, prev);
+            if (!(wt > 0.0f)) continue;
+            draw(cx->seed, w, (uint32_t)j, (uint32_t)i, 1, x);
+            float k = ln_f(og_uniform(x[0])) / wt;
+            if (best_i >= 0) note_margin(info, k, best);
+            if (k >= best) { best = k; best_i = i; }
+        }
+        return best_i;
+    }
+
+    /* Round 0: lane l keys its first item l; the maximum is shared by all lanes. */
+    const int64_t n0 = deg < P ? deg : P;
+    float *key0 = (float *)malloc(sizeof(float) * (size_t)n0);
+    float *thr_u = (float *)malloc(sizeof(float) * (size_t)n0);
+    float lkg = -INFINITY;
+    for (int64_t l = 0; l < n0; ++l) {
+        float wt = transition_weight(cx, base + l, j, prev);
+        draw(cx->seed, w, (uint32_t)j, (uint32_t)l, 1, x);
+        key0[l] = wt > 0.0f ? ln_f(og_uniform(x[0])) / wt : -INFINITY;
+        thr_u[l] = og_uniform(x[1]);
+        if (key0[l] > lkg) lkg = key0[l];
+    }
+
+    /* Each lane scans items l+P, l+2P, ... with the jump of Eq. (jump). */
+    float best = -INFINITY, second = -INFINITY;
+    int64_t best_i = -1;
+    for (int64_t l = 0; l < n0; ++l) {
+        float lk = key0[l];
+        int64_t li = l;
+        float thr = lkg;
+        float T = thr == -INFINITY ? 0.0f : (thr >= 0.0f ? INFINITY : ln_f(thr_u[l]) / thr);
+        float S = 0.0f;
+        for (int64_t i = l + P; i < deg; i += P) {
+            float wt = transition_weight(cx, base + i, j, prev);
+            S = S + wt;
+            if (T > 0.0f && T < INFINITY) note_margin(info, S, T);
+            if (S > T) {
+                /* the item that ends the skip gets a key conditioned to beat thr:
+                   u' ~ U(thr_lin^wt, 1), i.e. log u' = log1p(expm1(wt*thr) * V) */
+                draw(cx->seed, w, (uint32_t)j, (uint32_t)i, 1, x);
+                float a = wt * thr;
+                float m1 = expm1_f(a);
+                float z = m1 * og_uniform(x[0]);
+                float L = log1p_f(z);
+                if (OG_MUTANT == 2) L = ln_f(og_uniform(x[0]));
+                lk = L / wt;
+                li = i;
+                thr = lk;
+                if (OG_MUTANT != 3) S = 0.0f;
+                T = thr >= 0.0f ? INFINITY : ln_f(og_uniform(x[1])) / thr;
+                info->triggers++;
+            }
+        }
+        /* lexicographic maximum over (key, index): larger index wins ties */
+        if (lk > best || (lk == best && li > best_i)) {
+            second = best;
+            best = lk;
+            best_i = li;
+        } else if (lk > second) {
+            second = lk;
+        }
+    }
+    if (best > -INFINITY && second > -INFINITY) note_margin(info, best, second);
+    free(key0);
+    free(thr_u);
+    return best > -INFINITY ? best_i : -1;
+}
+
+/* eRJS, Section 3.3.  Returns the row offset, or -2 when the cap is reached. */
+static int64_t rjs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int64_t base, int64_t deg,
+                          float B, og_info *info)
+{
+    uint32_t x[4];
+    const og_logic *lg = cx->lg;
+    for (int t = 0; t < cx->pl->rjs_cap; ++t) {
+        draw(cx->seed, w, (uint32_t)j, (uint32_t)t, 0, x);
+        uint64_t R = ((uint64_t)x[1] << 32) | x[0];
+        int64_t idx = (int64_t)(((unsigned __int128)R * (unsigned __int128)(uint64_t)deg) >> 64);
+        if (OG_MUTANT == 4 && deg > 1) idx = (int64_t)(((unsigned __int128)R * (unsigned __int128)(uint64_t)(deg - 1)) >> 64);
+        float wt = transition_weight(cx, base + idx, j, prev);
+        float y = og_uniform(x[2]) * B;
+        info->trials++;
+        info->bytes += bytes_per_item(cx);
+        /* a membership search is needed only when the accept test is not already
+           decided by the smallest and largest weight u could have */
+        if (lg->kind == OG_NODE2VEC && j > 0 && cx->g->col[base + idx] != prev) {
+            float hv = (lg->weighted && cx->g->h) ? cx->g->h[base + idx] : 1.0f;
+            float lo = fminf(1.0f, 1.0f / lg->q) * hv, hi = fmaxf(1.0f, 1.0f / lg->q) * hv;
+            if (!(y < lo) && y < hi) {
+                int64_t pdeg = cx->g->row_ptr[prev + 1] - cx->g->row_ptr[prev];
+                info->bytes += 4.0 * ceil_log2_plus1(pdeg);
+            }
+        }
+        if (y < wt) return idx;
+    }
+    return -2;
+}
+
+/* Inverse transform sampling over the exact weights (plain CPU sampler). */
+static int64_t its_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int64_t base, int64_t deg,
+                          og_info *info)
+{
+    double *cum = (double *)malloc(sizeof(double) * (size_t)deg);
+    double run = 0.0;
+    for (int64_t i = 0; i < deg; ++i) {
+        run += (double)transition_weight(cx, base + i, j, prev);
+        cum[i] = run;
+    }
+    int64_t res = -1;
+    if (run > 0.0) {
+        uint32_t x[4];
+        draw(cx->seed, w, (uint32_t)j, 0, 3, x);
+        double u = ((double)(x[0] >> 5) * 67108864.0 + (double)(x[1] >> 6)) * 0x1p-53;
+        double target = u * run;
+        /* first item whose cumulative weight exceeds the target; it always has
+           a positive weight because the cumulative sum is flat over zero weights */
+        int64_t lo = 0, hi = deg - 1;
+        while (lo < hi) {
+            int64_t mid = (lo + hi) / 2;
+            if (cum[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        res = lo;
+    }
+    info->bytes += (double)deg * bytes_per_item(cx);
+    free(cum);
+    return res;
+}
+
+/* One transition from state (prev, cur, j) of walker w.  Returns the next vertex or -1. */
+int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, og_info *info)
+{
+    const og_graph *g = cx->g;
+    const og_logic *lg = cx->lg;
+    info->margin = FLT_MAX;
+    info->kind = -1;
+    info->trials = 0;
+    info->triggers = 0;
+    info->bytes = 16.0; /* row_ptr[cur], row_ptr[cur + 1] */
+    const int64_t base = g->row_ptr[cur], deg = g->row_ptr[cur + 1] - base;
+    if (deg == 0) return -1;
+
+    const int weighted = lg->weighted && g->h;
+    const float hm = (weighted && OG_MUTANT != 5) ? cx->hmax[cur] : 1.0f;
+    const float hs = weighted ? cx->hsum[cur] : (float)deg;
+    const float B = (w_max(lg, j) * hm) * cx->pl->bound_scale; /* upper bound of max w~ */
+    const float Shat = w_avg(lg, j) * hs;                      /* estimate of sum w~ */
+
+    int use_rjs = 0;
+    if (cx->strategy == OG_RJS_ONLY) {
+        use_rjs = 1;
+        if (weighted) info->bytes += 4.0;
+    } else if (cx->strategy == OG_AUTO) {
+        if (weighted) info->bytes += 8.0;
+        if (deg >= cx->pl->d_lo) {
+            float lhs = cx->pl->rho * B;
+            note_margin(info, lhs, Shat);
+            use_rjs = lhs < Shat;
+        }
+    }
+
+    int64_t off;
+    if (cx->strategy == OG_ITS) {
+        info->kind = 3;
+        off = its_sample(cx, w, j, prev, base, deg, info);
+    } else {
+        off = -2;
+        if (use_rjs) {
+            off = rjs_sample(cx, w, j, prev, base, deg, B, info);
+            info->kind = 1;
+        }
+        if (off == -2) {
+            info->kind = use_rjs ? 2 : 0;
+            info->bytes += (double)deg * bytes_per_item(cx);
+            if (lg->kind == OG_NODE2VEC && j > 0) {
+                int64_t pdeg = g->row_ptr[prev + 1] - g->row_ptr[prev];
+                double stage = 4.0 * (double)pdeg;
+                double search = 4.0 * (double)deg * ceil_log2_plus1(pdeg);
+                info->bytes += stage < search ? stage : search;
+            }
+            off = rvs_sample(cx, w, j, prev, base, deg, info);
+        }
+    }
+    if (off < 0) {
+        info->kind = -1;
+        return -1;
+    }
+    return g->col[base + off];
+}
+
+/* ------------------------------------------------------------------ walks */
+/* counters: 0 steps, 1 eRJS accepted, 2 eRVS, 3 eRJS capped -> eRVS, 4 eRJS trials,
+ *           5 eRVS jump triggers, 6 walks ended early, 7 algorithmic bytes,
+ *           8 steps with margin < 1e-6 */
+enum { OG_NCOUNTERS = 9 };
+
+/*
+ * Free-running walks.  Walker i starts at starts[i], uses RNG walker index
+ * walker_ids[i] (or i) and writes paths[i*(L+1) .. i*(L+1)+L] (start, then the vertex
+ * after each step, -1 after termination) and lengths[i] (steps taken).  margins and
+ * kinds, when non-NULL, receive per-step diagnostics ([i*L + j]).  Returns 0, or -1
+ * if a start vertex is out of range.
+ */
+int og_walk(const og_graph *g, const float *hmax, const float *hsum, const og_logic *lg, const og_plan *pl,
+            int strategy, const int32_t *starts, const int64_t *walker_ids, int64_t n, int32_t L, uint64_t seed,
+            int32_t *paths, int32_t *lengths, float *margins, int8_t *kinds, double *counters, int nthreads)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (starts[i] < 0 || starts[i] >= g->nv) return -1;
+    og_ctx cx = {g, hmax, hsum, lg, pl, strategy, seed};
+    double c[OG_NCOUNTERS];
+    memset(c, 0, sizeof(c));
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    double c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0, c6 = 0, c7 = 0, c8 = 0;
+    #pragma omp parallel for schedule(dynamic, 16) reduction(+:c0,c1,c2,c3,c4,c5,c6,c7,c8)
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t w = (uint32_t)(walker_ids ? walker_ids[i] : i);
+        int32_t *path = paths + i * (int64_t)(L + 1);
+        int32_t cur = starts[i], prev = -1;
+        int32_t len = 0;
+        path[0] = cur;
+        c7 += 4.0 + 4.0 * (L + 1) + 4.0; /* start read, path row, length */
+        for (int j = 0; j < L; ++j) {
+            og_info info;
+            int32_t nxt = og_step(&cx, w, j, prev, cur, &info);
+            if (margins) margins[i * (int64_t)L + j] = info.margin;
+            if (kinds) kinds[i * (int64_t)L + j] = (int8_t)info.kind;
+            c7 += info.bytes;
+            c4 += info.trials;
+            c5 += info.triggers;
+            if (info.margin < 1e-6f) c8 += 1;
+            if (nxt < 0) {
+                c6 += 1;
+                for (int r = j + 1; r < L; ++r) {
+                    if (margins) margins[i * (int64_t)L + r] = FLT_MAX;
+                    if (kinds) kinds[i * (int64_t)L + r] = -1;
+                }
+                break;
+            }
+            c0 += 1;
+            if (info.kind == 1) c1 += 1;
+            else if (info.kind == 0) c2 += 1;
+            else if (info.kind == 2) c3 += 1;
+            path[j + 1] = nxt;
+            prev = cur;
+            cur = nxt;
+            len++;
+        }
+        for (int r = len + 1; r <= L; ++r) path[r] = -1;
+        lengths[i] = len;
+    }
+    c[0] = c0; c[1] = c1; c[2] = c2; c[3] = c3; c[4] = c4; c[5] = c5; c[6] = c6; c[7] = c7; c[8] = c8;
+    if (counters) memcpy(counters, c, sizeof(c));
+    return 0;
+}
+
+/* Single transition for a given state (diagnostics and small tests). */
+int32_t og_step_once(const og_graph *g, const float *hmax, const float *hsum, const og_logic *lg,
+                     const og_plan *pl, int strategy, uint64_t seed, uint32_t walker, int32_t j, int32_t prev,
+                     int32_t cur, float *margin, int32_t *kind, int32_t *trials)
+{
+    og_ctx cx = {g, hmax, hsum, lg, pl, strategy, seed};
+    og_info info;
+    int32_t r = og_step(&cx, walker, j, prev, cur, &info);
+    if (margin) *margin = info.margin;
+    if (kind) *kind = info.kind;
+    if (trials) *trials = info.trials;
+    return r;
+}

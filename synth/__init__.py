@@ -1,0 +1,177 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the GPU path.
+
+This module only *produces inputs* (graphs, edge properties, start vertices).  It
+contains none of the random-walk arithmetic, so sharing it does not couple the
+oracle to the GPU implementation.
+
+Graphs are R-MAT (Chakrabarti, Zhan, Faloutsos, SDM 2004), the standard stand-in
+for the social/web graphs a random-walk paper evaluates on: undirected, self-loops
+dropped, duplicates merged, vertex ids shuffled by a seeded permutation, rows
+sorted ascending, ``int64`` row pointers, ``int32`` column indices, ``float32``
+property weights and ``uint8`` labels.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rmat.c")
+_LIB = os.path.join(_HERE, "librmat.so")
+_lib = None
+
+
+class _CSR(ctypes.Structure):
+    _fields_ = [
+        ("nv", ctypes.c_int64),
+        ("ne", ctypes.c_int64),
+        ("row_ptr", ctypes.POINTER(ctypes.c_int64)),
+        ("col", ctypes.POINTER(ctypes.c_int32)),
+        ("h", ctypes.POINTER(ctypes.c_float)),
+        ("label", ctypes.POINTER(ctypes.c_uint8)),
+    ]
+
+
+def build(force: bool = True) -> str:
+    """Compile the generator with gcc (OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O3", "-fopenmp", "-shared", "-fPIC", "-std=c11", _SRC, "-o", tmp, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        lib.synth_rmat.argtypes = [
+            ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+            ctypes.c_uint64, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_int,
+            ctypes.c_int, ctypes.c_int, ctypes.POINTER(_CSR),
+        ]
+        lib.synth_rmat.restype = ctypes.c_int
+        lib.synth_free.argtypes = [ctypes.POINTER(_CSR)]
+        lib.synth_free.restype = None
+        lib.synth_edge_props.argtypes = [
+            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
+            ctypes.c_float, ctypes.c_float, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+        ]
+        lib.synth_edge_props.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def rmat(scale: int, ndraws: int, a: float = 0.57, b: float = 0.19, c: float = 0.19,
+         seed: int = 1, permute: bool = True, weighted: bool = True, wlo: float = 1.0,
+         whi: float = 10.0, nlabels: int = 0) -> dict:
+    """Undirected R-MAT graph with ``2**scale`` vertices from ``ndraws`` edge draws.
+
+    Returns a dict with ``nv, ne, row_ptr (i64), col (i32), h (f32 or None),
+    label (u8 or None)``.
+    """
+    lib = _load()
+    out = _CSR()
+    rc = lib.synth_rmat(scale, ndraws, a, b, c, seed, int(permute), wlo, whi, max(nlabels, 1),
+                        int(weighted), int(nlabels > 0), ctypes.byref(out))
+    if rc != 0:
+        raise MemoryError("synth_rmat: allocation failed")
+    try:
+        nv, ne = out.nv, out.ne
+        g = {
+            "nv": nv,
+            "ne": ne,
+            "row_ptr": np.ctypeslib.as_array(out.row_ptr, shape=(nv + 1,)).copy(),
+            "col": np.ctypeslib.as_array(out.col, shape=(max(ne, 1),))[:ne].copy(),
+            "h": np.ctypeslib.as_array(out.h, shape=(max(ne, 1),))[:ne].copy() if weighted else None,
+            "label": np.ctypeslib.as_array(out.label, shape=(max(ne, 1),))[:ne].copy() if nlabels > 0 else None,
+        }
+    finally:
+        lib.synth_free(ctypes.byref(out))
+    return g
+
+
+def edge_props(row_ptr: np.ndarray, col: np.ndarray, seed: int, wlo: float = 1.0, whi: float = 10.0,
+               nlabels: int = 0, want_h: bool = True):
+    """Hashed per-edge weights U[wlo, whi) and labels U{0..nlabels-1} for an existing CSR."""
+    lib = _load()
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col = np.ascontiguousarray(col, dtype=np.int32)
+    h = np.empty(col.shape[0], np.float32) if want_h else None
+    lab = np.empty(col.shape[0], np.uint8) if nlabels > 0 else None
+    lib.synth_edge_props(row_ptr.shape[0] - 1, row_ptr.ctypes.data, col.ctypes.data, seed, wlo, whi,
+                         max(nlabels, 1), h.ctypes.data if h is not None else None,
+                         lab.ctypes.data if lab is not None else None)
+    return h, lab
+
+
+def csr_from_edges(nv: int, edges, h=None, label=None, symmetric: bool = True) -> dict:
+    """Small hand-built graphs: CSR from an edge list with optional per-edge values.
+
+    With ``symmetric`` each (u, v) is stored in both directions with the same value.
+    Rows come out sorted; duplicate edges are rejected.
+    """
+    rows = [[] for _ in range(nv)]
+    for k, (u, v) in enumerate(edges):
+        hv = None if h is None else float(h[k])
+        lv = None if label is None else int(label[k])
+        rows[u].append((v, hv, lv))
+        if symmetric and u != v:
+            rows[v].append((u, hv, lv))
+    row_ptr = np.zeros(nv + 1, np.int64)
+    cols, hs, ls = [], [], []
+    for v in range(nv):
+        r = sorted(rows[v], key=lambda t: t[0])
+        if len({t[0] for t in r}) != len(r):
+            raise ValueError(f"duplicate edge in row {v}")
+        row_ptr[v + 1] = row_ptr[v] + len(r)
+        cols += [t[0] for t in r]
+        hs += [t[1] for t in r]
+        ls += [t[2] for t in r]
+    return {
+        "nv": nv,
+        "ne": int(row_ptr[-1]),
+        "row_ptr": row_ptr,
+        "col": np.array(cols, np.int32),
+        "h": None if h is None else np.array(hs, np.float32),
+        "label": None if label is None else np.array(ls, np.uint8),
+    }
+
+
+def uniform_starts(nv: int, n: int, seed: int) -> np.ndarray:
+    """``n`` start vertices drawn uniformly with replacement (numpy PCG64)."""
+    return np.random.Generator(np.random.PCG64(seed)).integers(0, nv, size=n, dtype=np.int64).astype(np.int32)
+
+
+def all_vertices(nv: int) -> np.ndarray:
+    """One walker per vertex, in vertex order."""
+    return np.arange(nv, dtype=np.int32)
+
+
+# --- named workloads -------------------------------------------------------------
+# R-MAT (a, b, c) = (0.57, 0.19, 0.19), d = 0.05; graph seed 1; weights U(1, 10).
+
+def workload_graph(name: str) -> dict:
+    """Graphs of the named workloads.
+
+    * ``rmat12``: scale 12, average degree 16 (8 * 2^12 undirected draws).
+    * ``rmat22``: scale 22, edge factor 16 (16 * 2^22 draws, <= 134M entries).
+    * ``rmat22_labels``: the scale-22 graph plus uint8 labels uniform in 0..4.
+    """
+    if name == "rmat12":
+        return rmat(12, 8 << 12, seed=1)
+    if name == "rmat22":
+        return rmat(22, 16 << 22, seed=1)
+    if name == "rmat22_labels":
+        return rmat(22, 16 << 22, seed=1, nlabels=5)
+    if name.startswith("rmat") and name[4:].isdigit():
+        s = int(name[4:])
+        return rmat(s, 16 << s, seed=1)
+    raise KeyError(name)

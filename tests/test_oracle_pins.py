@@ -1,0 +1,313 @@
+"""Pins of the CPU oracle to the paper and to mathematics (no GPU).
+
+Each test checks the oracle against something other than itself: values printed in
+the paper (the worked example), published Philox answers, closed forms of Markov
+chains, brute-force path enumeration, and the theorems the paper proves (eRJS bound
+invariance, exponential-key and jump equivalence).  The last group plants known
+mistakes in the oracle and shows that these pins catch them.
+"""
+from __future__ import annotations
+
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import exact
+from tests._helpers import (chisq_pvalue, hub_ring_graph, path_counts, triangle_graph,
+                            worked_example_graph)
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+P_OK = 1e-3   # a correct sampler passes at this level (fixed seeds: deterministic)
+P_BAD = 1e-8  # a planted mistake must fail far below it
+
+N2V = dict(kind=oracle.NODE2VEC, weighted=True, p=2.0, q=0.5)
+
+
+def _walk_counts(g, logic, plan, strategy, start, L, n, seed=42):
+    og = oracle.Graph(g)
+    r = oracle.walk(og, logic, plan, strategy, np.full(n, start, np.int32), L, seed, diagnostics=False)
+    return path_counts(r.paths), r
+
+
+# ------------------------------------------------------------------ Philox, uniforms
+def test_philox_published_answers():
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(x, 16) for x in r]
+        out = oracle.philox(v[0:4], v[4:6])
+        assert out.tolist() == v[6:10]
+
+
+def test_uniform_exact_open_symmetric():
+    lo, hi = oracle.uniform(0), oracle.uniform(0xFFFFFFFF)
+    assert lo == 2.0 ** -24 and hi == 1.0 - 2.0 ** -24
+    rng = np.random.default_rng(0)
+    for x in rng.integers(0, 2 ** 32, 2000, dtype=np.uint64):
+        u = oracle.uniform(int(x))
+        m = int(x) >> 9
+        assert Fraction(u) == Fraction(2 * m + 1, 2 ** 24)  # exact in float32
+        assert 0.0 < u < 1.0
+        # symmetric: complementing the top 23 bits mirrors u about 1/2
+        assert oracle.uniform(int(x) ^ 0xFFFFFE00) == 1.0 - u
+
+
+# ------------------------------------------------------------------ plain definition
+def test_worked_example_exact():
+    """Section 2.2 worked example: weights {3,2,4,1} -> {0.3,0.2,0.4,0.1}."""
+    with open(os.path.join(GOLDEN, "worked_example.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    g = worked_example_graph()
+    t = exact.transition(g, oracle.Logic(**N2V), 0, -1, 0)  # first step: static walk
+    for nb, w, p in rows:
+        assert t[int(nb)] == Fraction(p)
+
+
+def test_node2vec_case_table():
+    """Eq. node2vec: weights 1/a, 1, 1/b for dist 0, 1, 2 (hand-computed state)."""
+    g = triangle_graph()
+    # state prev=0, cur=1; N(1) = {0, 2, 3}; 0 is prev, 2 in N(0), 3 not in N(0)
+    # h(1,0)=1, h(1,2)=3, h(1,3)=4 ; a=2, b=0.5 -> 1/2*1, 1*3, 2*4 = 0.5, 3, 8
+    t = exact.transition(g, oracle.Logic(**N2V), 1, 0, 1)
+    tot = Fraction(1, 2) + 3 + 8
+    assert t == {0: Fraction(1, 2) / tot, 2: Fraction(3) / tot, 3: Fraction(8) / tot}
+    # unweighted: 1/2, 1, 2
+    t = exact.transition(g, oracle.Logic(kind=oracle.NODE2VEC, weighted=False, p=2.0, q=0.5), 1, 0, 1)
+    assert t == {0: Fraction(1, 7), 2: Fraction(2, 7), 3: Fraction(4, 7)}
+
+
+def test_metapath_schema_rule():
+    g = triangle_graph(labels=True)
+    lg = oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(0, 1, 2))
+    # N(2) = {0 (lab 1, h 2), 1 (lab 2, h 3), 3 (lab 1, h 1), 4 (lab 0, h 3)}
+    assert exact.transition(g, lg, 0, -1, 2) == {4: Fraction(1)}
+    assert exact.transition(g, lg, 1, -1, 2) == {0: Fraction(2, 3), 3: Fraction(1, 3)}
+    assert exact.transition(g, lg, 5, -1, 2) == {1: Fraction(1)}      # schema repeats: 5 % 3 = 2
+    assert exact.transition(g, lg, 0, -1, 6) == {}                    # isolated vertex: walk ends
+
+
+def test_enumeration_matches_matrix_power():
+    """p = q = 1 makes Node2Vec first order: k-step marginals equal e_s P^k."""
+    g = triangle_graph()
+    lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=1.0, q=1.0)
+    P = exact.first_order_matrix(g)
+    for start in (0, 3, 5):
+        dist = exact.path_distribution(g, lg, start, 4)
+        assert sum(dist.values()) == 1
+        for k in range(1, 5):
+            marg = np.zeros(g["nv"])
+            for path, pr in dist.items():
+                marg[path[k]] += float(pr)
+            want = np.linalg.matrix_power(P, k)[start]
+            np.testing.assert_allclose(marg, want, rtol=0, atol=1e-12)
+
+
+def test_hmax_hsum_preprocess():
+    g = synth.rmat(10, 8 << 10, seed=5)
+    hmax, hsum = oracle.Graph(g).aux()
+    rp, h = g["row_ptr"], g["h"].astype(np.float64)
+    for v in range(g["nv"]):
+        seg = h[rp[v]:rp[v + 1]]
+        assert hmax[v] == (np.float32(seg.max()) if seg.size else 0.0)
+        assert hsum[v] == np.float32(math.fsum(seg))  # double sum of these values is exact
+
+
+# ------------------------------------------------------------------ samplers vs definition
+STRATS = [
+    ("auto", oracle.AUTO, oracle.Plan(rho=2.0, lanes=2)),
+    ("rvs_P1", oracle.RVS_ONLY, oracle.Plan(lanes=1)),
+    ("rvs_P2", oracle.RVS_ONLY, oracle.Plan(lanes=2)),
+    ("rvs_P64", oracle.RVS_ONLY, oracle.Plan(lanes=64)),
+    ("rvs_nojump", oracle.RVS_ONLY, oracle.Plan(jump=False)),
+    ("rjs", oracle.RJS_ONLY, oracle.Plan()),
+    ("rjs_x4", oracle.RJS_ONLY, oracle.Plan(bound_scale=4.0)),
+    ("rjs_x64", oracle.RJS_ONLY, oracle.Plan(bound_scale=64.0)),
+    ("rjs_cap1", oracle.RJS_ONLY, oracle.Plan(rjs_cap=1, lanes=2)),
+    ("its", oracle.ITS, oracle.Plan()),
+]
+
+
+@pytest.mark.parametrize("name,strategy,plan", STRATS, ids=[s[0] for s in STRATS])
+def test_worked_example_sampled(name, strategy, plan):
+    g = worked_example_graph()
+    n = 40000
+    counts, _ = _walk_counts(g, oracle.Logic(**N2V), plan, strategy, 0, 1, n)
+    probs = {(0, v): Fraction(p) for v, p in ((1, "0.3"), (2, "0.2"), (3, "0.4"), (4, "0.1"))}
+    assert chisq_pvalue(counts, probs, n) > P_OK
+
+
+@pytest.mark.parametrize("name,strategy,plan", STRATS, ids=[s[0] for s in STRATS])
+def test_node2vec_paths_chisquare(name, strategy, plan):
+    g = triangle_graph()
+    lg = oracle.Logic(**N2V)
+    n = 60000
+    for start in (0, 4):
+        counts, _ = _walk_counts(g, lg, plan, strategy, start, 3, n, seed=7 + start)
+        probs = exact.path_distribution(g, lg, start, 3)
+        assert chisq_pvalue(counts, probs, n) > P_OK, (name, start)
+
+
+@pytest.mark.parametrize("strategy", [oracle.AUTO, oracle.RVS_ONLY, oracle.RJS_ONLY])
+def test_metapath_paths_chisquare(strategy):
+    g = triangle_graph(labels=True)
+    lg = oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(0, 1, 2))
+    n = 40000
+    plan = oracle.Plan(rho=1.0, lanes=2, rjs_cap=8)
+    for start in (0, 2, 6):
+        counts, r = _walk_counts(g, lg, plan, strategy, start, 4, n, seed=11)
+        probs = exact.path_distribution(g, lg, start, 4)
+        assert chisq_pvalue(counts, probs, n) > P_OK, start
+
+
+def _hub_case(plan, strategy, n=40000, seed=5):
+    """Second step at the hub: prev = leaf 1, so N(hub) holds all three Node2Vec cases."""
+    g = hub_ring_graph()
+    lg = oracle.Logic(**N2V)
+    og = oracle.Graph(g)
+    r = oracle.walk(og, lg, plan, strategy, np.full(n, 1, np.int32), 2, seed, diagnostics=False)
+    went_hub = r.paths[:, 1] == 0
+    nxt = r.paths[went_hub, 2]
+    counts = {}
+    for v, c in zip(*np.unique(nxt, return_counts=True)):
+        counts[int(v)] = int(c)
+    probs = exact.transition(g, lg, 1, 1, 0)
+    return chisq_pvalue(counts, probs, int(went_hub.sum())), r
+
+
+@pytest.mark.parametrize("name,strategy,plan", [
+    ("rvs_jump_P64", oracle.RVS_ONLY, oracle.Plan(lanes=64)),
+    ("rvs_jump_P7", oracle.RVS_ONLY, oracle.Plan(lanes=7)),
+    ("rvs_nojump", oracle.RVS_ONLY, oracle.Plan(jump=False)),
+    ("rjs", oracle.RJS_ONLY, oracle.Plan()),
+])
+def test_hub_distribution(name, strategy, plan):
+    p, r = _hub_case(plan, strategy)
+    assert p > P_OK
+    if strategy == oracle.RVS_ONLY and plan.jump:
+        # the jump skips most keys: far fewer key draws than items scanned
+        assert r.counters["rvs_triggers"] < 0.2 * 600 * r.counters["steps"] / 2
+
+
+def test_rjs_mean_trials_and_known_bound():
+    """Pr[accept] = 1/c (Section 3.3): mean trials = deg * B / sum w~.
+
+    Unweighted Node2Vec with a = 1, b = 0.5 has max weight exactly 2 (Section 3.3),
+    so B = 2 and the mean trial count pins the bound.
+    """
+    g = triangle_graph()
+    for lg, B in ((oracle.Logic(kind=oracle.NODE2VEC, weighted=False, p=1.0, q=0.5), 2.0),
+                  (oracle.Logic(**N2V), None)):
+        og = oracle.Graph(g)
+        hmax, _ = og.aux()
+        n = 40000
+        # state: prev = 0, cur = 1 (teacher-forced single step), walker ids distinct
+        trials = np.empty(n)
+        for i in range(n):
+            nxt, m, kind, t = oracle.step_once(og, lg, oracle.Plan(rjs_cap=100000), oracle.RJS_ONLY, 3, i, 1, 0, 1)
+            trials[i] = t
+        t = exact.transition(g, lg, 1, 0, 1)
+        ws = [exact.transition_weight(g, lg, 1, 0, k) for k in range(int(g["row_ptr"][1]), int(g["row_ptr"][2]))]
+        bound = B if B is not None else 2.0 * float(hmax[1])
+        want = len(ws) * bound / float(sum(ws))
+        se = math.sqrt(want * (want - 1) / n)  # geometric distribution
+        assert abs(trials.mean() - want) < 5 * se, (trials.mean(), want)
+
+
+# ------------------------------------------------------------------ closed form / invariants
+def test_stationary_visits_proportional_to_degree():
+    """p = q = 1, h = 1 on a connected non-bipartite graph: visits -> deg / 2|E|."""
+    g = triangle_graph()
+    g = synth.csr_from_edges(6, [(0, 1), (0, 2), (1, 2), (1, 3), (2, 3), (3, 4), (2, 4), (4, 5), (0, 5)])
+    lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=False, p=1.0, q=1.0)
+    og = oracle.Graph(g)
+    r = oracle.walk(og, lg, oracle.Plan(rho=1.0, lanes=2), oracle.AUTO, np.zeros(400, np.int32), 2000, 9,
+                    diagnostics=False)
+    visits = np.bincount(r.paths[:, 200:].ravel(), minlength=6) / r.paths[:, 200:].size
+    deg = np.diff(g["row_ptr"]) / g["row_ptr"][-1]
+    np.testing.assert_allclose(visits, deg, atol=0.01)
+
+
+def _check_invariants(g, lg, paths, lengths, L):
+    rp, col = g["row_ptr"], g["col"]
+    for i in range(paths.shape[0]):
+        n = int(lengths[i])
+        prev = -1
+        for j in range(n):
+            cur, nxt = int(paths[i, j]), int(paths[i, j + 1])
+            row = col[rp[cur]:rp[cur + 1]]
+            k = int(np.searchsorted(row, nxt))
+            assert k < row.size and row[k] == nxt, "step must land on a neighbour"
+            assert exact.transition_weight(g, lg, j, prev, int(rp[cur]) + k) > 0, "weight must be positive"
+            prev = cur
+        assert (paths[i, n + 1:] == -1).all()
+        if n < L:  # ended early only when no neighbour has positive weight
+            assert exact.transition(g, lg, n, prev, int(paths[i, n])) == {}
+
+
+@pytest.mark.parametrize("strategy", [oracle.AUTO, oracle.RVS_ONLY, oracle.RJS_ONLY])
+def test_invariants_rmat(strategy):
+    g = synth.rmat(9, 8 << 9, seed=2, nlabels=5)
+    og = oracle.Graph(g)
+    starts = synth.uniform_starts(g["nv"], 300, 4)
+    for lg in (oracle.Logic(**N2V), oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(0, 1, 2, 3, 4))):
+        r = oracle.walk(og, lg, oracle.Plan(rho=4.0, rjs_cap=64), strategy, starts, 12, 42)
+        _check_invariants(g, lg, r.paths, r.lengths, 12)
+        if lg.kind == oracle.METAPATH:
+            rp, col, lab = g["row_ptr"], g["col"], g["label"]
+            for i in range(len(starts)):
+                for j in range(int(r.lengths[i])):
+                    a, b = int(r.paths[i, j]), int(r.paths[i, j + 1])
+                    k = rp[a] + np.searchsorted(col[rp[a]:rp[a + 1]], b)
+                    assert lab[k] == lg.schema[j % 5]
+
+
+def test_determinism_and_walker_ids():
+    """The stream depends on (seed, walker id, step, draw) only, not on the batch."""
+    g = synth.rmat(10, 8 << 10, seed=2)
+    og = oracle.Graph(g)
+    lg = oracle.Logic(**N2V)
+    starts = synth.uniform_starts(g["nv"], 500, 1)
+    full = oracle.walk(og, lg, oracle.Plan(), oracle.AUTO, starts, 10, 42, diagnostics=False)
+    sub = np.arange(100, 500, 7)
+    part = oracle.walk(og, lg, oracle.Plan(), oracle.AUTO, starts[sub], 10, 42, walker_ids=sub, diagnostics=False)
+    np.testing.assert_array_equal(full.paths[sub], part.paths)
+    again = oracle.walk(og, lg, oracle.Plan(), oracle.AUTO, starts, 10, 42, diagnostics=False, nthreads=1)
+    np.testing.assert_array_equal(full.paths, again.paths)
+
+
+# ------------------------------------------------------------------ planted mistakes
+MUTANTS = {
+    1: "Node2Vec return weight uses 1/q",
+    2: "jump key not conditioned on beating the threshold",
+    3: "skip sum not reset after a jump",
+    4: "eRJS never proposes the last neighbour",
+    5: "eRJS bound without h_MAX",
+}
+
+
+@pytest.fixture(scope="module")
+def mutant_libs(tmp_path_factory):
+    d = tmp_path_factory.mktemp("mutants")
+    return {k: oracle.build_variant(str(d / f"liboracle_m{k}.so"), {"OG_MUTANT": k}) for k in MUTANTS}
+
+
+@pytest.mark.parametrize("mut", sorted(MUTANTS), ids=[MUTANTS[k] for k in sorted(MUTANTS)])
+def test_planted_mistake_is_caught(mut, mutant_libs):
+    lg = oracle.Logic(**N2V)
+    g = triangle_graph()
+    caught = []
+    with oracle.use_library(mutant_libs[mut]):
+        for name, strategy, plan in (("rvs_P2", oracle.RVS_ONLY, oracle.Plan(lanes=2)),
+                                     ("rvs_P1", oracle.RVS_ONLY, oracle.Plan(lanes=1)),
+                                     ("rjs", oracle.RJS_ONLY, oracle.Plan())):
+            n = 60000
+            counts, _ = _walk_counts(g, lg, plan, strategy, 0, 3, n, seed=7)
+            probs = exact.path_distribution(g, lg, 0, 3)
+            caught.append(chisq_pvalue(counts, probs, n) < P_BAD)
+    assert any(caught), MUTANTS[mut]
