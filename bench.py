@@ -1,0 +1,183 @@
+"""Benchmark: walker-steps/s of Node2Vec walks on R-MAT scale 22 on one MI355X.
+
+A "step" of this benchmark is one whole walk job: one walker per vertex of the
+scale-22 R-MAT graph (4.19M walkers), Node2Vec p=0.5 q=2.0 weighted, 80 steps each,
+strategies chosen per step by the cost model.  The graph and the start vertices are
+resident in HBM before the timed region.  Prints one JSON line on stdout; details go
+to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+CACHE = os.environ.get("FLEXIWALK_CACHE", "/tmp/flexiwalk_cache")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cached_graph(name: str) -> dict:
+    import synth
+    path = os.path.join(CACHE, f"{name}.npz")
+    if os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        g = {k: z[k] for k in z.files}
+        g["nv"], g["ne"] = int(g["nv"]), int(g["ne"])
+        g.setdefault("h", None)
+        g.setdefault("label", None)
+        return g
+    g = synth.workload_graph(name)
+    os.makedirs(CACHE, exist_ok=True)
+    np.savez(path + ".tmp.npz", **{k: v for k, v in g.items() if v is not None})
+    os.replace(path + ".tmp.npz", path)
+    return g
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--graph", default="rmat22")
+    ap.add_argument("--L", type=int, default=80)
+    ap.add_argument("--p", type=float, default=0.5)
+    ap.add_argument("--q", type=float, default=2.0)
+    ap.add_argument("--strategy", default="auto", choices=["auto", "rvs", "rjs"])
+    ap.add_argument("--modes", type=int, default=1, help="also time the single-kernel modes")
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-sample", type=int, default=4096)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "walkers shard across GPUs with no exchange, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2512_00705_amd as fw
+
+    t0 = time.time()
+    g = cached_graph(args.graph)
+    log(f"graph {args.graph}: nv={g['nv']} ne={g['ne']} ({time.time() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(g[k]).to(dev) for k in ("row_ptr", "col", "h") if g.get(k) is not None}
+    gh = fw.fw_graph_create(g["nv"], g["ne"], t["row_ptr"], t["col"], t.get("h"), None, on_device=True)
+    del t
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    fw.fw_graph_preprocess(gh)
+    e1.record()
+    torch.cuda.synchronize()
+    prep_ms = e0.elapsed_time(e1)
+    logic = fw.fw_logic_node2vec(args.p, args.q, True)
+    t1 = time.time()
+    plan = fw.fw_plan_autotune(gh, logic)
+    tune_ms = (time.time() - t1) * 1e3
+    log(f"preprocess {prep_ms:.2f} ms, autotune {tune_ms:.1f} ms, rho={plan.rho:.3f}")
+
+    nv, L, seed = g["nv"], args.L, 42
+    starts = torch.arange(nv, dtype=torch.int32, device=dev)
+    paths = torch.empty((nv, L + 1), dtype=torch.int32, device=dev)
+    lengths = torch.empty(nv, dtype=torch.int32, device=dev)
+    stats = torch.zeros(fw.FW_NSTATS, dtype=torch.int64, device=dev)
+    strat = {"auto": fw.FW_AUTO, "rvs": fw.FW_RVS_ONLY, "rjs": fw.FW_RJS_ONLY}
+
+    def run(mode: str, steps: int, warmup: int):
+        for _ in range(warmup):
+            fw.fw_walk(gh, logic, plan, strat[mode], starts, nv, L, seed, paths, lengths, None)
+        torch.cuda.synchronize()
+        stats.zero_()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for a, b in evs:
+            a.record()
+            fw.fw_walk(gh, logic, plan, strat[mode], starts, nv, L, seed, paths, lengths, stats)
+            b.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        fw.fw_graph_check(gh)
+        ms = [a.elapsed_time(b) for a, b in evs]
+        st = dict(zip(fw.STAT_NAMES, (stats.cpu().numpy() // max(steps, 1)).tolist()))
+        return ms, wall, st
+
+    ms, wall, st = run(args.strategy, args.steps, args.warmup)
+    avg_ms = float(np.mean(ms))
+    steps_per_walk = st["steps"]
+    value = steps_per_walk / (avg_ms / 1e3)
+    achieved = st["alg_bytes"] / (avg_ms / 1e3) / 1e9
+    log(f"{args.strategy}: per-walk ms {['%.2f' % x for x in ms]}, wall {wall:.3f}s, stats {st}")
+
+    modes = {}
+    if args.modes:
+        for m in ("rvs", "rjs"):
+            if m == args.strategy:
+                continue
+            mms, _, mst = run(m, 2, 1)
+            a = float(np.mean(mms))
+            modes[m + "_only"] = {"ms": round(a, 3), "walker_steps_per_s": mst["steps"] / (a / 1e3),
+                                  "alg_GBps": mst["alg_bytes"] / (a / 1e3) / 1e9,
+                                  "rjs_steps": mst["rjs_steps"], "rvs_steps": mst["rvs_steps"]}
+            log(f"{m}: ms {mms}, stats {mst}")
+
+    cpu = None
+    if args.cpu_baseline:
+        import oracle
+        og = oracle.Graph(g)
+        og.aux()
+        rng = np.random.default_rng(7)
+        sample = np.sort(rng.choice(nv, size=min(args.cpu_sample, nv), replace=False)).astype(np.int64)
+        lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=args.p, q=args.q)
+        pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap)
+        cores = os.cpu_count() or 1
+        c0 = time.perf_counter()
+        r = oracle.walk(og, lg, pl, {"auto": 0, "rvs": 1, "rjs": 2}[args.strategy], sample.astype(np.int32), L,
+                        seed, walker_ids=sample, diagnostics=False, nthreads=cores)
+        cs = time.perf_counter() - c0
+        # the GPU run covered these walkers too: compare the sample
+        gp = paths[torch.from_numpy(sample).to(dev)].cpu().numpy()
+        same = float((gp == r.paths).all(axis=1).mean())
+        cpu = {"value": r.counters["steps"] / cs, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
+               "sample": f"{len(sample)} of {nv} walkers (seeded), full {L}-step walks, {cs:.1f}s; "
+                         f"{same * 100:.3f}% identical to the GPU walks"}
+        log(f"cpu oracle: {cpu}")
+
+    fw.fw_graph_destroy(gh)
+    out = {
+        "metric": "walker-steps/sec + achieved HBM GB/s, node2vec R-MAT s22; p99 latency served",
+        "value": value,
+        "unit": "walker-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": avg_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"node2vec p={args.p} q={args.q} weighted h~U(1,10), R-MAT scale 22 "
+                               f"(a=0.57,b=0.19,c=0.19, edge factor 16, {g['ne']} CSR entries), one walker "
+                               f"per vertex ({nv}), L={L}, strategy={args.strategy}",
+                   "walker_steps_per_walk_job": steps_per_walk, "preprocess_ms": prep_ms,
+                   "autotune_ms": tune_ms, "rho": plan.rho, "stats": st, "modes": modes},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,171 @@
+/*
+ * flexiwalk.h -- C ABI of the MI355X (gfx950) dynamic random-walk sampler.
+ *
+ * The library runs the per-step transition sampling of FlexiWalker (arXiv 2512.00705):
+ * at every step each walker evaluates runtime-dependent weights w~ = w * h over the
+ * neighbours of its current vertex (Section 2.1, Eq. prob) and draws the next vertex
+ * with exponential-key reservoir sampling plus jumps (eRVS, Section 3.2, Algorithm 1,
+ * Eq. jump) or bounded rejection sampling (eRJS, Section 3.3), picked per step by the
+ * first-order cost model (Section 4.1, Eq. runtime).  All work runs in HIP kernels.
+ *
+ * Conventions for every call:
+ *   - return value: FW_OK (0) or an fw_status code; fw_last_error() gives a message
+ *     (thread-local, valid until the next call on the same thread);
+ *   - "device pointer": memory on the current HIP device (e.g. a torch tensor's
+ *     data_ptr()); "host pointer": ordinary process memory;
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Kernel
+ *     launches are asynchronous on that stream; argument errors are returned before
+ *     anything is enqueued.
+ *   - A graph may be used by many fw_walk calls, but calls that share one graph must
+ *     be ordered on one stream (they share the graph's work counter).
+ */
+#ifndef FLEXIWALK_H
+#define FLEXIWALK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fw_status {
+    FW_OK = 0,
+    FW_E_INVALID = 1, /* bad argument or malformed input; nothing was changed */
+    FW_E_NOMEM = 2,   /* device allocation failed; nothing was allocated */
+    FW_E_DEVICE = 3,  /* a HIP runtime call failed */
+    FW_E_STATE = 4    /* object not ready (e.g. graph not preprocessed) */
+} fw_status;
+
+/* Sampling strategy per step (Section 4.1; single-kernel modes of the ablation). */
+enum { FW_AUTO = 0, FW_RVS_ONLY = 1, FW_RJS_ONLY = 2 };
+
+/* Walk logics (Section 2.1). */
+enum { FW_NODE2VEC = 1, FW_METAPATH = 2 };
+
+#define FW_MAX_SCHEMA 64
+#define FW_NSTATS 8
+
+/* CSR graph handed to fw_graph_create.  Row v holds the neighbours N(v) in
+ * col[row_ptr[v] .. row_ptr[v+1]), strictly ascending (Node2Vec tests membership in
+ * N(prev) by binary search).  h: per-edge property weights h(v,u) >= 0, finite (NULL:
+ * unweighted, h = 1).  label: per-edge labels for MetaPath (NULL if unused).  All
+ * arrays are host pointers when on_device == 0, device pointers when 1. */
+typedef struct fw_csr {
+    int64_t nv, ne;
+    const int64_t *row_ptr; /* nv + 1 entries, row_ptr[0] = 0, row_ptr[nv] = ne */
+    const int32_t *col;     /* ne entries in [0, nv) */
+    const float *h;         /* ne entries or NULL */
+    const uint8_t *label;   /* ne entries or NULL */
+    int32_t on_device;
+} fw_csr;
+
+typedef struct fw_graph fw_graph; /* opaque, library-owned device copy of a graph */
+
+/* Walk logic (value type).
+ * FW_NODE2VEC (Eq. node2vec): w = 1/p if u is the previous vertex, 1 if u is a
+ *   neighbour of the previous vertex, 1/q otherwise; p, q are the paper's a, b.  The
+ *   first step of a walk has no previous vertex and uses w = 1.
+ * FW_METAPATH (Section 2.1): w = 1 if the label of edge (v,u) equals
+ *   schema[j mod schema_len] at step j, else 0; a walk ends when no neighbour has
+ *   positive weight.
+ * weighted: 1 uses w~ = w * h, 0 uses w~ = w. */
+typedef struct fw_logic {
+    int32_t kind;
+    int32_t weighted;
+    float p, q;
+    int32_t schema_len;
+    uint8_t schema[FW_MAX_SCHEMA];
+} fw_logic;
+
+/* Plan.  rho, d_lo and rjs_cap change which kernel samples a step and therefore the
+ * random stream (never the distribution); the remaining fields change speed only.
+ *   rho      EdgeCost_RJS / EdgeCost_RVS of Eq. (runtime), > 0
+ *   d_lo     steps at vertices of degree < d_lo always use eRVS (0 disables)
+ *   rjs_cap  eRJS trials before an exact fall-back to eRVS, >= 1
+ *   lanes    eRVS lanes per step; must be 64 (one wavefront)
+ *   lds_cap  int32 entries of N(prev) staged in LDS per wavefront (0 = default)
+ *   grid     persistent blocks (0 = fill the device) */
+typedef struct fw_plan {
+    float rho;
+    int32_t d_lo;
+    int32_t rjs_cap;
+    int32_t lanes;
+    int32_t lds_cap;
+    int32_t grid;
+    int32_t reserved[2];
+} fw_plan;
+
+/* Counters accumulated by fw_walk into a device array of FW_NSTATS uint64 values:
+ *   0 steps taken, 1 steps sampled by eRJS, 2 steps sampled by eRVS, 3 eRJS steps that
+ *   reached rjs_cap and fell back to eRVS, 4 eRJS trials, 5 eRVS jump events (keys drawn
+ *   after round 0), 6 walks that ended before L steps, 7 algorithmic bytes (the bytes
+ *   the method itself must move: row pointers, bounds, scanned or proposed edges,
+ *   membership probes, start/path/length I/O). */
+
+/* Copy a CSR graph into library-owned device memory (Section 2.1 graph G with N(v),
+ * d(v), h, labels).  Validates row_ptr (monotone, row_ptr[0] = 0, row_ptr[nv] = ne), col
+ * (in range, strictly ascending per row) and h (finite, >= 0); on failure returns
+ * FW_E_INVALID and allocates nothing.  Device-side inputs are validated on the device
+ * before the call returns (synchronous).  *out is set only on FW_OK. */
+int fw_graph_create(const fw_csr *g, fw_graph **out);
+
+/* Free a graph and its device memory.  NULL is accepted.  The caller must ensure no
+ * work that uses the graph is still running. */
+int fw_graph_destroy(fw_graph *g);
+
+/* Per-node preprocessing (Section 4.2, preprocess()): h_MAX[v] = max h over N(v) and
+ * h_SUM[v] = sum of h over N(v) accumulated in double precision and rounded once to
+ * float32 (0 for an empty row).  Asynchronous on `stream`; idempotent.  Must run before
+ * fw_walk with a weighted logic. */
+int fw_graph_preprocess(fw_graph *g, void *stream);
+
+/* Copy h_MAX and h_SUM (nv floats each, host pointers) back to the host; synchronous. */
+int fw_graph_export_aux(const fw_graph *g, float *hmax, float *hsum);
+
+/* Sizes of a graph: vertices, edges, maximum degree (any pointer may be NULL). */
+int fw_graph_info(const fw_graph *g, int64_t *nv, int64_t *ne, int64_t *max_deg);
+
+/* Build a Node2Vec logic; p, q finite and > 0. */
+int fw_logic_node2vec(float p, float q, int32_t weighted, fw_logic *out);
+
+/* Build a MetaPath logic from `m` labels (1 <= m <= FW_MAX_SCHEMA, host pointer). */
+int fw_logic_metapath(const uint8_t *schema, int32_t m, int32_t weighted, fw_logic *out);
+
+/* Default plan: rho = 8, d_lo = 0, rjs_cap = 1024, lanes = 64, lds_cap and grid chosen
+ * by the library. */
+int fw_plan_default(fw_plan *out);
+
+/* Profiling kernels of Section 5: time weight evaluation of sampled nodes with eRJS-style
+ * random proposals and with eRVS-style coalesced scans on this graph and logic, and set
+ * out->rho to the per-edge cost ratio; other fields start from fw_plan_default.
+ * Synchronous on `stream`. */
+int fw_plan_autotune(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stream);
+
+/* Run n walks of at most L steps (Section 5 runtime kernel with dynamic query
+ * scheduling).
+ *   starts  device pointer, n int32 start vertices
+ *   paths   device pointer, n * (L + 1) int32: paths[i*(L+1)] = starts[i], slot k holds
+ *           the vertex after k steps, -1 after the walk ended
+ *   lengths device pointer, n int32: steps taken (0..L)
+ *   stats   device pointer to FW_NSTATS uint64 counters that are ADDED to, or NULL
+ * Walker i draws its random numbers from Philox4x32-10 keyed by `seed` with counter
+ * (i, step, draw, tag), so results do not depend on the launch shape.  0 <= L < 2^20,
+ * 0 <= n < 2^31.  A start vertex outside [0, nv) gives that walker length 0 and marks the
+ * graph's error flag, reported by fw_graph_check.  Asynchronous on `stream`. */
+int fw_walk(fw_graph *g, const fw_logic *logic, const fw_plan *plan, int32_t strategy,
+            const int32_t *starts, int64_t n, int32_t L, uint64_t seed, int32_t *paths,
+            int32_t *lengths, uint64_t *stats, void *stream);
+
+/* Wait for `stream`, then report and clear the graph's device error flag: FW_OK, or
+ * FW_E_INVALID if a walk since the last check met an out-of-range start vertex. */
+int fw_graph_check(fw_graph *g, void *stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *fw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLEXIWALK_H */

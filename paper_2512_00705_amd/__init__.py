@@ -1,0 +1,179 @@
+"""Python binding of libflexiwalk.so, the MI355X dynamic random-walk sampler.
+
+Argument marshalling only: every step of the walk runs in the HIP kernels behind the
+C ABI declared in ``include/flexiwalk.h``.  The functions keep the C names.  Pointer
+arguments accept a torch tensor (its ``data_ptr()``), a numpy array (host memory), a
+plain integer address or ``None``.  ``stream`` defaults to torch's current stream.
+
+There is no fallback: importing the package without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libflexiwalk.so")
+
+FW_OK, FW_E_INVALID, FW_E_NOMEM, FW_E_DEVICE, FW_E_STATE = 0, 1, 2, 3, 4
+FW_AUTO, FW_RVS_ONLY, FW_RJS_ONLY = 0, 1, 2
+FW_NODE2VEC, FW_METAPATH = 1, 2
+FW_MAX_SCHEMA = 64
+FW_NSTATS = 8
+STAT_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", "rvs_triggers",
+              "ended_early", "alg_bytes")
+EXPORTED = ("fw_graph_create", "fw_graph_destroy", "fw_graph_preprocess", "fw_graph_export_aux",
+            "fw_graph_info", "fw_logic_node2vec", "fw_logic_metapath", "fw_plan_default",
+            "fw_plan_autotune", "fw_walk", "fw_graph_check", "fw_last_error")
+
+
+class FlexiWalkError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[fw status {code}] {msg}")
+        self.code = code
+
+
+class fw_csr(ctypes.Structure):
+    _fields_ = [("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("h", ctypes.c_void_p), ("label", ctypes.c_void_p),
+                ("on_device", ctypes.c_int32)]
+
+
+class fw_logic(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("weighted", ctypes.c_int32), ("p", ctypes.c_float),
+                ("q", ctypes.c_float), ("schema_len", ctypes.c_int32),
+                ("schema", ctypes.c_uint8 * FW_MAX_SCHEMA)]
+
+
+class fw_plan(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_float), ("d_lo", ctypes.c_int32), ("rjs_cap", ctypes.c_int32),
+                ("lanes", ctypes.c_int32), ("lds_cap", ctypes.c_int32), ("grid", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2512_00705_amd._build` "
+                           "(or __graft_entry__.build()) first. There is no CPU fallback.")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "fw_graph_create": ([ctypes.POINTER(fw_csr), ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+        "fw_graph_destroy": ([P], ctypes.c_int),
+        "fw_graph_preprocess": ([P, P], ctypes.c_int),
+        "fw_graph_export_aux": ([P, P, P], ctypes.c_int),
+        "fw_graph_info": ([P, P, P, P], ctypes.c_int),
+        "fw_logic_node2vec": ([ctypes.c_float, ctypes.c_float, I32, ctypes.POINTER(fw_logic)], ctypes.c_int),
+        "fw_logic_metapath": ([P, I32, I32, ctypes.POINTER(fw_logic)], ctypes.c_int),
+        "fw_plan_default": ([ctypes.POINTER(fw_plan)], ctypes.c_int),
+        "fw_plan_autotune": ([P, ctypes.POINTER(fw_logic), ctypes.POINTER(fw_plan), P], ctypes.c_int),
+        "fw_walk": ([P, ctypes.POINTER(fw_logic), ctypes.POINTER(fw_plan), I32, P, I64, I32, ctypes.c_uint64,
+                     P, P, P, P], ctypes.c_int),
+        "fw_graph_check": ([P, P], ctypes.c_int),
+        "fw_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc: int):
+    if rc != FW_OK:
+        raise FlexiWalkError(rc, _lib.fw_last_error().decode())
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    raise TypeError(f"cannot pass {type(x)} as a pointer")
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream if isinstance(stream, int) else getattr(stream, "cuda_stream", stream)
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def fw_last_error() -> str:
+    return _lib.fw_last_error().decode()
+
+
+def fw_graph_create(nv: int, ne: int, row_ptr, col, h=None, label=None, on_device: bool = False) -> int:
+    """Returns an opaque graph handle (int).  Arrays: numpy (host) or torch (device)."""
+    c = fw_csr(nv, ne, _ptr(row_ptr), _ptr(col), _ptr(h), _ptr(label), int(on_device))
+    out = ctypes.c_void_p()
+    _check(_lib.fw_graph_create(ctypes.byref(c), ctypes.byref(out)))
+    return out.value
+
+
+def fw_graph_destroy(g: int):
+    _check(_lib.fw_graph_destroy(g))
+
+
+def fw_graph_preprocess(g: int, stream=None):
+    _check(_lib.fw_graph_preprocess(g, _stream(stream)))
+
+
+def fw_graph_export_aux(g: int, nv: int):
+    hmax = np.empty(nv, np.float32)
+    hsum = np.empty(nv, np.float32)
+    _check(_lib.fw_graph_export_aux(g, hmax.ctypes.data, hsum.ctypes.data))
+    return hmax, hsum
+
+
+def fw_graph_info(g: int):
+    nv, ne, md = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.fw_graph_info(g, ctypes.byref(nv), ctypes.byref(ne), ctypes.byref(md)))
+    return nv.value, ne.value, md.value
+
+
+def fw_logic_node2vec(p: float, q: float, weighted: bool = True) -> fw_logic:
+    out = fw_logic()
+    _check(_lib.fw_logic_node2vec(p, q, int(weighted), ctypes.byref(out)))
+    return out
+
+
+def fw_logic_metapath(schema, weighted: bool = True) -> fw_logic:
+    arr = np.ascontiguousarray(np.asarray(schema, dtype=np.uint8))
+    out = fw_logic()
+    _check(_lib.fw_logic_metapath(arr.ctypes.data, len(arr), int(weighted), ctypes.byref(out)))
+    return out
+
+
+def fw_plan_default(**overrides) -> fw_plan:
+    out = fw_plan()
+    _check(_lib.fw_plan_default(ctypes.byref(out)))
+    for k, v in overrides.items():
+        setattr(out, k, v)
+    return out
+
+
+def fw_plan_autotune(g: int, logic: fw_logic, stream=None) -> fw_plan:
+    out = fw_plan()
+    _check(_lib.fw_plan_autotune(g, ctypes.byref(logic), ctypes.byref(out), _stream(stream)))
+    return out
+
+
+def fw_walk(g: int, logic: fw_logic, plan: fw_plan, strategy: int, starts, n: int, L: int, seed: int, paths,
+            lengths, stats=None, stream=None):
+    """Asynchronous on ``stream``; pointers are device pointers (torch tensors)."""
+    _check(_lib.fw_walk(g, ctypes.byref(logic), ctypes.byref(plan), strategy, _ptr(starts), n, L,
+                        seed & 0xFFFFFFFFFFFFFFFF, _ptr(paths), _ptr(lengths), _ptr(stats), _stream(stream)))
+
+
+def fw_graph_check(g: int, stream=None):
+    _check(_lib.fw_graph_check(g, _stream(stream)))

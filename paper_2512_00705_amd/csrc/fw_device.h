@@ -1,0 +1,140 @@
+// Device primitives of the gfx950 walk kernels: counter-based RNG, exact unit
+// uniforms, correctly rounded float32 logarithms, and wave64 reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fw {
+
+constexpr int kWave = 64;
+
+struct U4 {
+    uint32_t x0, x1, x2, x3;
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
+// multiplies with the published multipliers and Weyl key increments.
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                     uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t m0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t m1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(m1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(m0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)m1;
+        c3 = (uint32_t)m0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// (2m + 1) * 2^-24 from the top 23 bits: exact in float32, strictly inside (0, 1).
+__device__ __forceinline__ float unit_uniform(uint32_t x)
+{
+    return (float)(2u * (x >> 9) + 1u) * 0x1p-24f;
+}
+
+// floor(R * n / 2^64) for a 64-bit random R: an index in [0, n).
+__device__ __forceinline__ int64_t scaled_index(uint32_t lo, uint32_t hi, int64_t n)
+{
+    const uint64_t r = ((uint64_t)hi << 32) | lo;
+    return (int64_t)__umul64hi(r, (uint64_t)n);
+}
+
+// Logarithms rounded once to float32 from a double-precision evaluation, so the value
+// is the correctly rounded one except within ~1e-16 of a rounding tie.
+__device__ __forceinline__ float ln_f(float x) { return (float)log((double)x); }
+__device__ __forceinline__ float expm1_f(float x) { return (float)expm1((double)x); }
+__device__ __forceinline__ float log1p_f(float x) { return (float)log1p((double)x); }
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+__device__ __forceinline__ uint64_t lanes_below(int lane) { return (lane == 0) ? 0ull : (~0ull >> (64 - lane)); }
+
+__device__ __forceinline__ int32_t bcast_i32(int32_t v, int src) { return __builtin_amdgcn_readlane(v, src); }
+
+__device__ __forceinline__ uint32_t bcast_u32(uint32_t v, int src)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, src);
+}
+
+__device__ __forceinline__ int64_t bcast_i64(int64_t v, int src)
+{
+    const uint32_t lo = bcast_u32((uint32_t)(uint64_t)v, src);
+    const uint32_t hi = bcast_u32((uint32_t)((uint64_t)v >> 32), src);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += (uint64_t)__shfl_xor((long long)v, o, kWave);
+    return v;
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+// Lexicographic maximum over (key, index); the larger index wins equal keys.
+__device__ __forceinline__ void wave_argmax(float &key, int32_t &idx)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const float k2 = __shfl_xor(key, o, kWave);
+        const int32_t i2 = __shfl_xor(idx, o, kWave);
+        if (k2 > key || (k2 == key && i2 > idx)) {
+            key = k2;
+            idx = i2;
+        }
+    }
+}
+
+// Orders this wave's LDS writes before its later LDS reads (and vice versa).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Binary search for u in the ascending array a[0, n).
+template <typename IdxT>
+__device__ __forceinline__ bool sorted_contains(const int32_t *a, IdxT n, int32_t u)
+{
+    const IdxT total = n;
+    IdxT lo = 0;
+    while (n > 0) {
+        const IdxT half = n >> 1;
+        if (a[lo + half] < u) {
+            lo += half + 1;
+            n -= half + 1;
+        } else {
+            n = half;
+        }
+    }
+    return lo < total && a[lo] == u;
+}
+
+// ceil(log2(m + 1)): probes of a binary search over m entries.
+__device__ __host__ __forceinline__ int probes(int64_t m)
+{
+    return m <= 0 ? 0 : 64 - __builtin_clzll((unsigned long long)m);
+}
+
+}  // namespace fw

@@ -1,0 +1,521 @@
+// gfx950 kernels of the dynamic random-walk sampler.
+//
+// walk_kernel is the runtime kernel of FlexiWalker (arXiv 2512.00705, Section 5,
+// "Concurrent Rejection and Reservoir Sampling" and "Dynamic Query Scheduling")
+// re-designed for wave64:
+//   * every lane owns one walker and runs the cost model of Section 4.1 (Eq. runtime)
+//     at each step; eRJS (Section 3.3) runs inside the lane;
+//   * a 64-bit ballot collects the lanes whose step needs eRVS (Section 3.2); the whole
+//     wave serves them one at a time, the lane's state broadcast with readlane;
+//   * eRVS keys the first 64 neighbours (Algorithm 1 in the log domain), takes a wave
+//     maximum, then each lane scans its strided neighbours with the jump of Eq. (jump)
+//     and a final wave argmax picks the next vertex;
+//   * walkers are handed out from a global counter, one atomic per wave refill.
+// The membership test u in N(prev) of Node2Vec is a binary search over the sorted row
+// of prev, staged in LDS when that row is short enough, else read through L2.
+#include "fw_device.h"
+#include "fw_internal.h"
+
+namespace fw {
+
+enum Mode : int { kIdle = 0, kSetup = 1, kRjs = 2, kRvs = 3, kAdv = 4 };
+
+// Transition weight w~ = w * h of the edge at CSR position k with neighbour u at step j
+// (Section 2.1, Eq. prob; Eq. node2vec; MetaPath rule).  `mem` holds N(prev) sorted.
+template <int KIND, bool W>
+__device__ __forceinline__ float edge_weight(const WalkArgs &a, int64_t k, int32_t u, int j, int32_t prev,
+                                             const int32_t *mem, int64_t mlen, uint8_t want)
+{
+    const float hv = W ? a.h[k] : 1.0f;
+    if (KIND == kNode2Vec) {
+        if (j == 0) return hv;
+        if (u == prev) return a.inv_p * hv;
+        return sorted_contains(mem, mlen, u) ? hv : a.inv_q * hv;
+    } else {
+        return a.label[k] == want ? hv : 0.0f;
+    }
+}
+
+// eRVS for one step, all 64 lanes cooperating.  Returns the next vertex or -1 when no
+// neighbour has positive weight.  `trig` receives the number of jump events.
+template <int KIND, bool W>
+__device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const int32_t *mem, int64_t mlen, uint32_t wid,
+                                            int j, int32_t prev, int64_t base, int64_t deg, uint8_t want,
+                                            uint32_t &trig)
+{
+    const int lane = lane_id();
+    float key = -INFINITY;
+    int32_t bi = -1;
+    float ru = 0.5f;
+    // round 0: lane l keys neighbour l, k = u^(1/w~) kept as log(u) / w~
+    if (lane < deg) {
+        const int64_t k = base + lane;
+        const int32_t u = a.col[k];
+        const float wt = edge_weight<KIND, W>(a, k, u, j, prev, mem, mlen, want);
+        const U4 x = philox(wid, (uint32_t)j, (uint32_t)lane, 1u, a.key0, a.key1);
+        key = wt > 0.0f ? ln_f(unit_uniform(x.x0)) / wt : -INFINITY;
+        ru = unit_uniform(x.x1);
+        bi = lane;
+    }
+    const float lkg = wave_max(key);
+    float thr = lkg;
+    float T = (thr == -INFINITY) ? 0.0f : (thr >= 0.0f ? INFINITY : ln_f(ru) / thr);
+    float S = 0.0f;
+    uint32_t nt = 0;
+    // scan: lane l owns neighbours l + 64, l + 128, ...; a key is drawn only where the
+    // running weight passes the skip threshold T = log(r) / log(k_thr)
+    for (int64_t i0 = kWave; i0 < deg; i0 += kWave) {
+        const int64_t i = i0 + lane;
+        if (i < deg) {
+            const int64_t k = base + i;
+            const int32_t u = a.col[k];
+            const float wt = edge_weight<KIND, W>(a, k, u, j, prev, mem, mlen, want);
+            S = S + wt;
+            if (S > T) {
+                // key conditioned to beat thr: log u' = log1p(expm1(w~ * thr) * V)
+                const U4 x = philox(wid, (uint32_t)j, (uint32_t)i, 1u, a.key0, a.key1);
+                const float av = wt * thr;
+                const float m1 = expm1_f(av);
+                const float z = m1 * unit_uniform(x.x0);
+                const float lg = log1p_f(z);
+                key = lg / wt;
+                bi = (int32_t)i;
+                thr = key;
+                S = 0.0f;
+                T = thr >= 0.0f ? INFINITY : ln_f(unit_uniform(x.x1)) / thr;
+                ++nt;
+            }
+        }
+    }
+    wave_argmax(key, bi);
+    trig = (uint32_t)wave_sum_u64(nt);
+    return key > -INFINITY ? a.col[base + bi] : -1;
+}
+
+template <int KIND, bool W>
+__global__ void __launch_bounds__(kBlock) walk_kernel(WalkArgs a)
+{
+    extern __shared__ int32_t lds_all[];
+    int32_t *lds = lds_all + (threadIdx.x / kWave) * a.lds_cap;
+    const int lane = lane_id();
+    const uint64_t below = lanes_below(lane);
+    const int64_t row_len = (int64_t)a.L + 1;
+
+    int mode = kIdle;
+    int64_t wid = -1;
+    int32_t cur = 0, prev = -1, j = 0, nxt = -1;
+    int64_t base = 0, deg = 0, pbase = 0, pdeg = 0;
+    int32_t trials = 0;
+    bool fell_back = false;
+    float B = 0.0f;
+    uint64_t st[kNumStats];
+#pragma unroll
+    for (int c = 0; c < kNumStats; ++c) st[c] = 0;
+    bool exhausted = false;
+
+    for (;;) {
+        // 1. hand walkers to idle lanes: one atomic per wave
+        const uint64_t idle = __ballot(mode == kIdle);
+        if (idle != 0 && !exhausted) {
+            const int leader = __ffsll((unsigned long long)idle) - 1;
+            const int cnt = __popcll(idle);
+            unsigned long long first = 0;
+            if (lane == leader) first = atomicAdd(a.queue, (unsigned long long)cnt);
+            first = (unsigned long long)bcast_i64((int64_t)first, leader);
+            if ((int64_t)first + cnt >= a.n) exhausted = true;
+            if (mode == kIdle) {
+                const int64_t w = (int64_t)first + __popcll(idle & below);
+                if (w < a.n) {
+                    const int32_t s = a.starts[w];
+                    int32_t *row = a.paths + w * row_len;
+                    row[0] = s;
+                    st[kStBytes] += 12 + 4 * (uint64_t)a.L;
+                    if (s < 0 || (int64_t)s >= a.nv) {
+                        atomicOr(a.err, 1);
+                        for (int r = 1; r <= a.L; ++r) row[r] = -1;
+                        a.lengths[w] = 0;
+                    } else {
+                        wid = w;
+                        cur = s;
+                        prev = -1;
+                        j = 0;
+                        mode = kSetup;
+                    }
+                }
+            }
+        }
+        if (__ballot(mode != kIdle) == 0) {
+            if (exhausted) break;
+            continue;
+        }
+
+        // 2. step set-up: row of cur, bound B, strategy (Section 4.1)
+        if (mode == kSetup) {
+            if (j == a.L) {
+                a.lengths[wid] = j;
+                mode = kIdle;
+                wid = -1;
+            } else {
+                base = a.row_ptr[cur];
+                deg = a.row_ptr[cur + 1] - base;
+                st[kStBytes] += 16;
+                if (deg == 0) {
+                    nxt = -1;
+                    mode = kAdv;
+                } else {
+                    bool rjs = false;
+                    if (a.strategy != kRvsOnly) {
+                        const float wmax = (j == 0) ? a.wmax0 : a.wmax1;
+                        const float hm = W ? a.hmax[cur] : 1.0f;
+                        B = wmax * hm;  // get_weight_max: max(w) * h_MAX
+                        if (a.strategy == kRjsOnly) {
+                            rjs = true;
+                            st[kStBytes] += W ? 4 : 0;
+                        } else {
+                            const float wavg = (j == 0) ? a.wavg0 : a.wavg1;
+                            const float hs = W ? a.hsum[cur] : (float)deg;
+                            st[kStBytes] += W ? 8 : 0;
+                            // Eq. (runtime) with get_weight_sum = mean(w) * h_SUM
+                            rjs = deg >= a.d_lo && (a.rho * B) < (wavg * hs);
+                        }
+                    }
+                    mode = rjs ? kRjs : kRvs;
+                    trials = 0;
+                    fell_back = false;
+                }
+            }
+        }
+
+        // 3. eRJS trials inside the lane (Section 3.3): propose uniformly, accept if
+        //    U * B < w~; the membership search runs only when the bounds of w~ leave
+        //    the test open
+        if (mode == kRjs) {
+            const uint8_t want = (KIND == kMetaPath) ? a.schema[j % a.schema_len] : (uint8_t)0;
+            for (int r = 0; r < kRjsPerRound; ++r) {
+                const U4 x = philox((uint32_t)wid, (uint32_t)j, (uint32_t)trials, 0u, a.key0, a.key1);
+                const int64_t k = base + scaled_index(x.x0, x.x1, deg);
+                const int32_t u = a.col[k];
+                const float hv = W ? a.h[k] : 1.0f;
+                const float y = unit_uniform(x.x2) * B;
+                bool acc;
+                if (KIND == kNode2Vec) {
+                    if (j == 0) {
+                        acc = y < hv;
+                    } else if (u == prev) {
+                        acc = y < a.inv_p * hv;
+                    } else {
+                        const float lo = a.lo_w * hv, hi = a.hi_w * hv;
+                        if (y < lo) {
+                            acc = true;
+                        } else if (!(y < hi)) {
+                            acc = false;
+                        } else {
+                            st[kStBytes] += 4 * (uint64_t)probes(pdeg);
+                            const float wt = sorted_contains(a.col + pbase, pdeg, u) ? hv : a.inv_q * hv;
+                            acc = y < wt;
+                        }
+                    }
+                } else {
+                    acc = y < (a.label[k] == want ? hv : 0.0f);
+                }
+                ++trials;
+                st[kStTrials] += 1;
+                st[kStBytes] += (uint64_t)a.item_bytes;
+                if (acc) {
+                    nxt = u;
+                    mode = kAdv;
+                    st[kStRjs] += 1;
+                    break;
+                }
+                if (trials >= a.rjs_cap) {
+                    mode = kRvs;  // exact fall-back: eRVS draws are independent of eRJS draws
+                    fell_back = true;
+                    break;
+                }
+            }
+        }
+
+        // 4. eRVS for every lane that needs it, the wave cooperating (Section 5)
+        uint64_t need = __ballot(mode == kRvs);
+        while (need != 0) {
+            const int src = __ffsll((unsigned long long)need) - 1;
+            need &= need - 1;
+            const uint32_t s_wid = bcast_u32((uint32_t)wid, src);
+            const int32_t s_j = bcast_i32(j, src);
+            const int32_t s_prev = bcast_i32(prev, src);
+            const int64_t s_base = bcast_i64(base, src);
+            const int64_t s_deg = bcast_i64(deg, src);
+            const int64_t s_pbase = bcast_i64(pbase, src);
+            const int64_t s_pdeg = bcast_i64(pdeg, src);
+            const uint8_t want = (KIND == kMetaPath) ? a.schema[s_j % a.schema_len] : (uint8_t)0;
+            const bool member_test = (KIND == kNode2Vec) && s_j > 0;
+            uint32_t trig = 0;
+            int32_t res;
+            if (member_test && s_pdeg <= a.lds_cap && s_pdeg <= s_deg * probes(s_pdeg)) {
+                wave_lds_sync();
+                for (int64_t i = lane; i < s_pdeg; i += kWave) lds[i] = a.col[s_pbase + i];
+                wave_lds_sync();
+                res = rvs_step<KIND, W>(a, lds, s_pdeg, s_wid, s_j, s_prev, s_base, s_deg, want, trig);
+            } else {
+                res = rvs_step<KIND, W>(a, a.col + s_pbase, s_pdeg, s_wid, s_j, s_prev, s_base, s_deg, want,
+                                        trig);
+            }
+            if (lane == src) {
+                nxt = res;
+                mode = kAdv;
+                st[kStTriggers] += trig;
+                uint64_t by = (uint64_t)s_deg * (uint64_t)a.item_bytes;
+                if (member_test) {
+                    const uint64_t stage = 4 * (uint64_t)s_pdeg;
+                    const uint64_t search = 4 * (uint64_t)s_deg * (uint64_t)probes(s_pdeg);
+                    by += stage < search ? stage : search;
+                }
+                st[kStBytes] += by;
+                if (res >= 0) st[fell_back ? kStFallback : kStRvs] += 1;
+            }
+        }
+
+        // 5. apply the step (update) and write the path
+        if (mode == kAdv) {
+            int32_t *row = a.paths + wid * row_len;
+            if (nxt < 0) {
+                for (int r = j + 1; r <= a.L; ++r) row[r] = -1;
+                a.lengths[wid] = j;
+                st[kStEarly] += 1;
+                mode = kIdle;
+                wid = -1;
+            } else {
+                row[j + 1] = nxt;
+                st[kStSteps] += 1;
+                prev = cur;
+                cur = nxt;
+                pbase = base;
+                pdeg = deg;
+                ++j;
+                mode = kSetup;
+            }
+        }
+    }
+
+    if (a.stats != nullptr) {
+#pragma unroll
+        for (int c = 0; c < kNumStats; ++c) {
+            const uint64_t v = wave_sum_u64(st[c]);
+            if (lane == 0 && v != 0) atomicAdd(&a.stats[c], (unsigned long long)v);
+        }
+    }
+}
+
+__global__ void zero_kernel(unsigned long long *p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+// h_MAX and h_SUM per row (Section 4.2 preprocess()), one wave per row.  The sum is
+// accumulated in double, so for float32 inputs of moderate range it is exact and the
+// rounding to float32 does not depend on the summation order.
+__global__ void __launch_bounds__(kBlock) preprocess_kernel(const int64_t *row_ptr, const float *h, int64_t nv,
+                                                            float *hmax, float *hsum)
+{
+    const int lane = lane_id();
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; v < nv; v += nw) {
+        const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+        float mx = 0.0f;
+        double sm = 0.0;
+        for (int64_t k = b + lane; k < e; k += kWave) {
+            const float x = h ? h[k] : 1.0f;
+            mx = x > mx ? x : mx;
+            sm += (double)x;
+        }
+        mx = wave_max(mx);
+        sm = wave_sum_f64(sm);
+        if (lane == 0) {
+            hmax[v] = mx;
+            hsum[v] = (float)sm;
+        }
+    }
+}
+
+__global__ void validate_rows_kernel(const int64_t *row_ptr, int64_t nv, int64_t ne, int *err)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= nv; v += stride) {
+        bool bad = false;
+        if (v == 0 && row_ptr[0] != 0) bad = true;
+        if (v == nv && row_ptr[nv] != ne) bad = true;
+        if (v < nv && row_ptr[v] > row_ptr[v + 1]) bad = true;
+        if (bad) atomicOr(err, 1);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) validate_edges_kernel(const int64_t *row_ptr, const int32_t *col,
+                                                                const float *h, int64_t nv, int *err,
+                                                                unsigned long long *max_deg)
+{
+    const int lane = lane_id();
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; v < nv; v += nw) {
+        const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+        if (lane == 0) atomicMax(max_deg, (unsigned long long)(e - b));
+        bool bad = false;
+        for (int64_t k = b + lane; k < e; k += kWave) {
+            const int32_t c = col[k];
+            if (c < 0 || (int64_t)c >= nv) bad = true;
+            if (k > b && col[k - 1] >= c) bad = true;
+            if (h) {
+                const float x = h[k];
+                if (!(x >= 0.0f) || isinf(x)) bad = true;
+            }
+        }
+        if (bad) atomicOr(err, 2);
+    }
+}
+
+// Profiling kernels (Section 5, "Flexi-Runtime Profiling Kernels"): evaluate workload
+// weights of sampled nodes either as eRVS does (a wave scanning a row, coalesced) or
+// as eRJS does (a lane proposing random neighbours).  Their time ratio per edge is the
+// EdgeCost_RJS / EdgeCost_RVS constant of Eq. (runtime).
+template <int KIND, bool W>
+__global__ void __launch_bounds__(kBlock) profile_rvs_kernel(WalkArgs a, const int32_t *nodes, int nsample,
+                                                             int per_node, float *sink)
+{
+    const int lane = lane_id();
+    const int nw = gridDim.x * (kBlock / kWave);
+    float acc = 0.0f;
+    for (int s = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; s < nsample; s += nw) {
+        const int32_t v = nodes[s];
+        const int64_t b = a.row_ptr[v], d = a.row_ptr[v + 1] - b;
+        const int64_t m = d < per_node ? d : per_node;
+        const int32_t prev = a.col[b];
+        const int64_t pb = a.row_ptr[prev], pd = a.row_ptr[prev + 1] - pb;
+        for (int64_t i = lane; i < m; i += kWave)
+            acc += edge_weight<KIND, W>(a, b + i, a.col[b + i], 1, prev, a.col + pb, pd, a.schema[0]);
+    }
+    acc = wave_max(acc);
+    if (lane == 0 && acc < 0.0f) sink[0] = acc;  // never true; keeps the loads alive
+}
+
+template <int KIND, bool W>
+__global__ void __launch_bounds__(kBlock) profile_rjs_kernel(WalkArgs a, const int32_t *nodes, int nsample,
+                                                             int per_node, float *sink)
+{
+    const int s = blockIdx.x * kBlock + threadIdx.x;
+    float acc = 0.0f;
+    if (s < nsample) {
+        const int32_t v = nodes[s];
+        const int64_t b = a.row_ptr[v], d = a.row_ptr[v + 1] - b;
+        const int32_t prev = a.col[b];
+        const int64_t pb = a.row_ptr[prev], pd = a.row_ptr[prev + 1] - pb;
+        for (int t = 0; t < per_node; ++t) {
+            const U4 x = philox((uint32_t)s, 0u, (uint32_t)t, 2u, a.key0, a.key1);
+            const int64_t k = b + scaled_index(x.x0, x.x1, d);
+            acc += edge_weight<KIND, W>(a, k, a.col[k], 1, prev, a.col + pb, pd, a.schema[0]);
+        }
+    }
+    if (acc < 0.0f) sink[0] = acc;
+}
+
+// ---------------------------------------------------------------- launchers
+template <int KIND, bool W>
+static hipError_t launch_walk_t(const WalkArgs &a, int grid, hipStream_t s)
+{
+    const size_t lds = (size_t)kWavesPerBlock * (size_t)a.lds_cap * sizeof(int32_t);
+    hipLaunchKernelGGL((walk_kernel<KIND, W>), dim3(grid), dim3(kBlock), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk(const WalkArgs &a, int kind, bool weighted, int grid, hipStream_t s)
+{
+    if (kind == kNode2Vec) return weighted ? launch_walk_t<kNode2Vec, true>(a, grid, s)
+                                           : launch_walk_t<kNode2Vec, false>(a, grid, s);
+    return weighted ? launch_walk_t<kMetaPath, true>(a, grid, s) : launch_walk_t<kMetaPath, false>(a, grid, s);
+}
+
+template <int KIND, bool W>
+static int occupancy_blocks(int lds_cap)
+{
+    int nb = 0;
+    const size_t lds = (size_t)kWavesPerBlock * (size_t)lds_cap * sizeof(int32_t);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<KIND, W>, kBlock, lds) != hipSuccess) nb = 1;
+    return nb > 0 ? nb : 1;
+}
+
+int walk_grid(int kind, bool weighted, int lds_cap, int64_t n)
+{
+    int dev = 0, cus = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (cus <= 0) cus = 1;
+    int nb;
+    if (kind == kNode2Vec) nb = weighted ? occupancy_blocks<kNode2Vec, true>(lds_cap)
+                                         : occupancy_blocks<kNode2Vec, false>(lds_cap);
+    else nb = weighted ? occupancy_blocks<kMetaPath, true>(lds_cap) : occupancy_blocks<kMetaPath, false>(lds_cap);
+    int64_t grid = (int64_t)nb * cus;
+    const int64_t need = (n + kBlock - 1) / kBlock;
+    if (grid > need) grid = need;
+    return (int)(grid > 0 ? grid : 1);
+}
+
+hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv, float *hmax, float *hsum,
+                             hipStream_t s)
+{
+    int64_t blocks = (nv + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(preprocess_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, h, nv, hmax, hsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_rows(const int64_t *row_ptr, int64_t nv, int64_t ne, int *err, hipStream_t s)
+{
+    int64_t blocks = (nv + 1 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(validate_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, s, row_ptr, nv, ne, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_edges(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv,
+                                 int *err, unsigned long long *max_deg, hipStream_t s)
+{
+    int64_t blocks = (nv + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(validate_edges_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, nv, err,
+                       max_deg);
+    return hipGetLastError();
+}
+
+template <int KIND, bool W>
+static hipError_t launch_profile_t(const WalkArgs &a, bool rjs_style, const int32_t *nodes, int nsample,
+                                   int per_node, float *sink, hipStream_t s)
+{
+    if (rjs_style) {
+        hipLaunchKernelGGL((profile_rjs_kernel<KIND, W>), dim3((nsample + kBlock - 1) / kBlock), dim3(kBlock), 0,
+                           s, a, nodes, nsample, per_node, sink);
+    } else {
+        int blocks = (nsample + kWavesPerBlock - 1) / kWavesPerBlock;
+        hipLaunchKernelGGL((profile_rvs_kernel<KIND, W>), dim3(blocks), dim3(kBlock), 0, s, a, nodes, nsample,
+                           per_node, sink);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_profile(const WalkArgs &a, int kind, bool weighted, bool rjs_style, const int32_t *nodes,
+                          int nsample, int per_node, float *sink, hipStream_t s)
+{
+    if (kind == kNode2Vec)
+        return weighted ? launch_profile_t<kNode2Vec, true>(a, rjs_style, nodes, nsample, per_node, sink, s)
+                        : launch_profile_t<kNode2Vec, false>(a, rjs_style, nodes, nsample, per_node, sink, s);
+    return weighted ? launch_profile_t<kMetaPath, true>(a, rjs_style, nodes, nsample, per_node, sink, s)
+                    : launch_profile_t<kMetaPath, false>(a, rjs_style, nodes, nsample, per_node, sink, s);
+}
+
+}  // namespace fw

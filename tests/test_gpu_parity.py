@@ -1,0 +1,225 @@
+"""Parity of the HIP walk kernels with the CPU oracle (needs an MI355X).
+
+Walks run through the C ABI; the oracle replays the same inputs free-running.  The
+bar: every walker identical to the oracle except at a step whose oracle float
+decision lies within 1e-6 relative of its boundary (counted, at most 1e-5 of steps),
+and when nothing differs the device counters equal the oracle's (steps per kernel,
+eRJS trials, jump events, algorithmic bytes).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import exact
+from tests._gpu import GpuGraph, assert_parity, gpu_walk, parity
+from tests._helpers import chisq_pvalue, hub_ring_graph, worked_example_graph
+
+import paper_2512_00705_amd as fw
+
+pytestmark = pytest.mark.gpu
+
+N2V = oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=2.0, q=0.5)
+MP = oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(0, 1, 2, 3, 4))
+STRATS = {"auto": oracle.AUTO, "rvs": oracle.RVS_ONLY, "rjs": oracle.RJS_ONLY}
+COUNTERS = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", "rvs_triggers", "ended_early",
+            "alg_bytes")
+
+
+@pytest.fixture(scope="module")
+def g12():
+    return synth.rmat(12, 8 << 12, seed=1, nlabels=5)
+
+
+@pytest.fixture(scope="module")
+def gg12(g12):
+    gg = GpuGraph(g12)
+    yield gg
+    gg.close()
+
+
+def _run_both(gg, g, lg, pl, strategy, starts, L, seed, walker_ids=None, **speed):
+    p, ln, st = gpu_walk(gg, lg, pl, strategy, starts, L, seed, **speed)
+    ora = oracle.walk(oracle.Graph(g), lg, pl, strategy, starts, L, seed)
+    return p, ln, st, ora
+
+
+def _assert_counters(st, ora):
+    for k in COUNTERS:
+        assert st[k] == int(ora.counters[k]), (k, st[k], ora.counters[k])
+
+
+def test_preprocess_bit_exact(g12, gg12):
+    hmax, hsum = fw.fw_graph_export_aux(gg12.handle, gg12.nv)
+    ohmax, ohsum = oracle.Graph(g12).aux()
+    np.testing.assert_array_equal(hmax, ohmax)
+    np.testing.assert_array_equal(hsum, ohsum)
+    assert fw.fw_graph_info(gg12.handle)[2] == int(np.diff(g12["row_ptr"]).max())
+
+
+@pytest.mark.parametrize("strategy", list(STRATS), ids=list(STRATS))
+@pytest.mark.parametrize("rho", [8.0, 0.5])
+def test_node2vec_scale12(g12, gg12, strategy, rho):
+    """Node2Vec p=2, q=0.5, weighted, one walker per vertex, L=20, seed 42."""
+    pl = oracle.Plan(rho=rho)
+    starts = synth.all_vertices(g12["nv"])
+    p, ln, st, ora = _run_both(gg12, g12, N2V, pl, STRATS[strategy], starts, 20, 42)
+    rep = parity(p, ln, ora)
+    assert_parity(rep)
+    if rep["mismatch_walkers"] == 0:
+        _assert_counters(st, ora)
+    if strategy == "auto" and rho == 8.0:
+        assert st["rjs_steps"] > 0 and st["rvs_steps"] > 0  # both kernels exercised
+
+
+@pytest.mark.parametrize("strategy", list(STRATS), ids=list(STRATS))
+def test_metapath_scale12(g12, gg12, strategy):
+    pl = oracle.Plan(rho=2.0, rjs_cap=64)
+    starts = synth.uniform_starts(g12["nv"], 5000, 42)
+    p, ln, st, ora = _run_both(gg12, g12, MP, pl, STRATS[strategy], starts, 20, 42)
+    rep = parity(p, ln, ora)
+    assert_parity(rep)
+    if rep["mismatch_walkers"] == 0:
+        _assert_counters(st, ora)
+    assert st["ended_early"] > 0  # schema dead ends occur
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_unweighted_and_d_lo(g12, gg12, weighted):
+    lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=weighted, p=1.0, q=0.5)
+    pl = oracle.Plan(rho=3.0, d_lo=24, rjs_cap=16)
+    starts = synth.uniform_starts(g12["nv"], 3000, 7)
+    p, ln, st, ora = _run_both(gg12, g12, lg, pl, oracle.AUTO, starts, 15, 1234567891234)
+    rep = parity(p, ln, ora)
+    assert_parity(rep)
+    if rep["mismatch_walkers"] == 0:
+        _assert_counters(st, ora)
+
+
+def test_host_upload_and_launch_shape(g12, gg12):
+    """Host-copied graph, one-block grid and no LDS staging give the same walks."""
+    starts = synth.uniform_starts(g12["nv"], 3001, 3)
+    pl = oracle.Plan(rho=4.0)
+    ref = gpu_walk(gg12, N2V, pl, oracle.AUTO, starts, 12, 5)
+    gh = GpuGraph(g12, on_device=False)
+    try:
+        alt = gpu_walk(gh, N2V, pl, oracle.AUTO, starts, 12, 5, grid=1, lds_cap=0)
+    finally:
+        gh.close()
+    np.testing.assert_array_equal(ref[0], alt[0])
+    np.testing.assert_array_equal(ref[1], alt[1])
+    assert ref[2] == alt[2]
+
+
+@pytest.mark.parametrize("lds_cap", [2048, 16])
+@pytest.mark.parametrize("strategy", ["rvs", "auto"])
+def test_hub_rows(lds_cap, strategy):
+    """Rows longer than a wavefront (jump scan) and N(prev) in LDS or in global memory."""
+    g = hub_ring_graph(3000)
+    gg = GpuGraph(g)
+    try:
+        starts = np.arange(1, 3001, dtype=np.int32)
+        pl = oracle.Plan(rho=1.0)
+        p, ln, st, ora = _run_both(gg, g, N2V, pl, STRATS[strategy], starts, 6, 11, lds_cap=lds_cap)
+        rep = parity(p, ln, ora)
+        assert_parity(rep)
+        if rep["mismatch_walkers"] == 0:
+            _assert_counters(st, ora)
+        assert st["rvs_triggers"] > 0
+    finally:
+        gg.close()
+
+
+def test_edge_cases(g12, gg12):
+    deg = np.diff(g12["row_ptr"])
+    iso = int(np.flatnonzero(deg == 0)[0])
+    pl = oracle.Plan()
+    # L = 0: paths hold the starts only
+    s = np.array([0, 1, iso], np.int32)
+    p, ln, st = gpu_walk(gg12, N2V, pl, oracle.AUTO, s, 0, 1)
+    assert p[:, 0].tolist() == s.tolist() and ln.tolist() == [0, 0, 0]
+    # isolated start: length 0, padded with -1; ragged sizes
+    for n in (1, 63, 65, 4097):
+        s = synth.uniform_starts(g12["nv"], n, n)
+        s[0] = iso
+        p, ln, st, ora = _run_both(gg12, g12, N2V, pl, oracle.AUTO, s, 9, 99)
+        assert ln[0] == 0 and (p[0, 1:] == -1).all()
+        assert_parity(parity(p, ln, ora))
+    # n = 0 is a no-op
+    gpu_walk(gg12, N2V, pl, oracle.AUTO, np.zeros(0, np.int32), 5, 1)
+    # out-of-range start: walker gets length 0, others unaffected, check reports it
+    s = np.array([5, g12["nv"] + 3, 7], np.int32)
+    p, ln, st = gpu_walk(gg12, N2V, pl, oracle.AUTO, s, 4, 2)
+    assert ln[1] == 0 and (p[1, 1:] == -1).all()
+    with pytest.raises(fw.FlexiWalkError):
+        fw.fw_graph_check(gg12.handle)
+    fw.fw_graph_check(gg12.handle)  # flag cleared
+    ok = s[[0, 2]]
+    ora = oracle.walk(oracle.Graph(g12), N2V, pl, oracle.AUTO, ok, 4, 2, walker_ids=np.array([0, 2]))
+    np.testing.assert_array_equal(p[[0, 2]], ora.paths)
+
+
+def test_argument_errors(g12, gg12):
+    pl = fw.fw_plan_default()
+    lg = fw.fw_logic_node2vec(2.0, 0.5, True)
+    dev = torch.device("cuda:0")
+    s = torch.zeros(4, dtype=torch.int32, device=dev)
+    out = torch.zeros(4 * 6, dtype=torch.int32, device=dev)
+    ln = torch.zeros(4, dtype=torch.int32, device=dev)
+    with pytest.raises(fw.FlexiWalkError):
+        fw.fw_walk(gg12.handle, lg, pl, 7, s, 4, 5, 1, out, ln)
+    bad = fw.fw_plan_default(lanes=32)
+    with pytest.raises(fw.FlexiWalkError):
+        fw.fw_walk(gg12.handle, lg, bad, 0, s, 4, 5, 1, out, ln)
+    # malformed CSR: unsorted row
+    with pytest.raises(fw.FlexiWalkError):
+        fw.fw_graph_create(2, 2, np.array([0, 2, 2], np.int64), np.array([1, 0], np.int32))
+    with pytest.raises(fw.FlexiWalkError):
+        fw.fw_graph_create(2, 2, np.array([0, 2, 1], np.int64), np.array([0, 1], np.int32))
+    with pytest.raises(fw.FlexiWalkError):
+        fw.fw_graph_create(2, 1, np.array([0, 1, 1], np.int64), np.array([5], np.int32))
+    with pytest.raises(fw.FlexiWalkError):
+        fw.fw_graph_create(2, 1, np.array([0, 1, 1], np.int64), np.array([1], np.int32),
+                           np.array([np.nan], np.float32))
+    # metapath without labels
+    g = synth.rmat(6, 64, seed=1)
+    gg = GpuGraph(g)
+    try:
+        with pytest.raises(fw.FlexiWalkError):
+            fw.fw_walk(gg.handle, fw.fw_logic_metapath([0, 1]), pl, 0, s, 4, 5, 1, out, ln)
+    finally:
+        gg.close()
+
+
+@pytest.mark.parametrize("strategy", list(STRATS), ids=list(STRATS))
+def test_chisquare_worked_example(strategy):
+    g = worked_example_graph()
+    gg = GpuGraph(g)
+    try:
+        n = 200000
+        p, ln, st = gpu_walk(gg, N2V, oracle.Plan(), STRATS[strategy], np.zeros(n, np.int32), 1, 17)
+    finally:
+        gg.close()
+    counts = {int(v): int(c) for v, c in zip(*np.unique(p[:, 1], return_counts=True))}
+    probs = exact.transition(g, N2V, 0, -1, 0)
+    assert chisq_pvalue(counts, probs, n) > 1e-3
+
+
+@pytest.mark.parametrize("strategy", list(STRATS), ids=list(STRATS))
+def test_chisquare_hub_second_step(strategy):
+    """Second step at a 600-neighbour hub, prev = leaf 1: all three Node2Vec cases."""
+    g = hub_ring_graph(600)
+    gg = GpuGraph(g)
+    try:
+        n = 300000
+        p, ln, st = gpu_walk(gg, N2V, oracle.Plan(rho=1.0), STRATS[strategy], np.ones(n, np.int32), 2, 23)
+    finally:
+        gg.close()
+    at_hub = p[:, 1] == 0
+    nxt = p[at_hub, 2]
+    counts = {int(v): int(c) for v, c in zip(*np.unique(nxt, return_counts=True))}
+    probs = exact.transition(g, N2V, 1, 1, 0)
+    assert chisq_pvalue(counts, probs, int(at_hub.sum())) > 1e-3
