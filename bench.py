@@ -20,28 +20,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-CACHE = os.environ.get("FLEXIWALK_CACHE", "/tmp/flexiwalk_cache")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
-
-
-def cached_graph(name: str) -> dict:
-    import synth
-    path = os.path.join(CACHE, f"{name}.npz")
-    if os.path.exists(path):
-        z = np.load(path, allow_pickle=False)
-        g = {k: z[k] for k in z.files}
-        g["nv"], g["ne"] = int(g["nv"]), int(g["ne"])
-        g.setdefault("h", None)
-        g.setdefault("label", None)
-        return g
-    g = synth.workload_graph(name)
-    os.makedirs(CACHE, exist_ok=True)
-    np.savez(path + ".tmp.npz", **{k: v for k, v in g.items() if v is not None})
-    os.replace(path + ".tmp.npz", path)
-    return g
 
 
 def main():
@@ -49,7 +31,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--graph", default="rmat22")
+    ap.add_argument("--graph", default="rmat22_labels")
     ap.add_argument("--L", type=int, default=80)
     ap.add_argument("--p", type=float, default=0.5)
     ap.add_argument("--q", type=float, default=2.0)
@@ -65,9 +47,10 @@ def main():
 
     import torch
     import paper_2512_00705_amd as fw
+    import synth
 
     t0 = time.time()
-    g = cached_graph(args.graph)
+    g = synth.cached(args.graph)
     log(f"graph {args.graph}: nv={g['nv']} ne={g['ne']} ({time.time() - t0:.1f}s)")
     dev = torch.device("cuda:0")
     t = {k: torch.from_numpy(g[k]).to(dev) for k in ("row_ptr", "col", "h") if g.get(k) is not None}

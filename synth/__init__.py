@@ -158,6 +158,26 @@ def all_vertices(nv: int) -> np.ndarray:
 # --- named workloads -------------------------------------------------------------
 # R-MAT (a, b, c) = (0.57, 0.19, 0.19), d = 0.05; graph seed 1; weights U(1, 10).
 
+def cached(name: str, cache_dir: str | None = None) -> dict:
+    """``workload_graph(name)`` memoised as an uncompressed .npz under ``cache_dir``
+    (default ``$FLEXIWALK_CACHE`` or /tmp/flexiwalk_cache)."""
+    d = cache_dir or os.environ.get("FLEXIWALK_CACHE", "/tmp/flexiwalk_cache")
+    path = os.path.join(d, f"{name}.npz")
+    if os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        g = {k: z[k] for k in z.files}
+        g["nv"], g["ne"] = int(g["nv"]), int(g["ne"])
+        g.setdefault("h", None)
+        g.setdefault("label", None)
+        return g
+    g = workload_graph(name)
+    os.makedirs(d, exist_ok=True)
+    tmp = path + f".{os.getpid()}.tmp.npz"
+    np.savez(tmp, **{k: v for k, v in g.items() if v is not None})
+    os.replace(tmp, path)
+    return g
+
+
 def workload_graph(name: str) -> dict:
     """Graphs of the named workloads.
 
