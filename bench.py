@@ -38,8 +38,20 @@ def main():
     ap.add_argument("--strategy", default="auto", choices=["auto", "rvs", "rjs"])
     ap.add_argument("--modes", type=int, default=1, help="also time the single-kernel modes")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-sample", type=int, default=4096)
+    ap.add_argument("--cpu-sample", type=int, default=0, help="walkers for the CPU baseline (0: sized to ~15 s)")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB: only run a plain device-to-device copy of this size 3 times (counter calibration)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        n = args.calibrate_copy << 20
+        a = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "walkers shard across GPUs with no exchange, see DESIGN.md", file=sys.stderr)
@@ -96,6 +108,9 @@ def main():
         return ms, wall, st
 
     ms, wall, st = run(args.strategy, args.steps, args.warmup)
+    rng = np.random.default_rng(7)
+    probe = np.sort(rng.choice(nv, size=min(4096, nv), replace=False)).astype(np.int64)
+    probe_paths = paths[torch.from_numpy(probe).to(dev)].cpu().numpy()  # before other modes overwrite paths
     avg_ms = float(np.mean(ms))
     steps_per_walk = st["steps"]
     value = steps_per_walk / (avg_ms / 1e3)
@@ -119,15 +134,20 @@ def main():
         import oracle
         og = oracle.Graph(g)
         og.aux()
-        rng = np.random.default_rng(7)
-        sample = np.sort(rng.choice(nv, size=min(args.cpu_sample, nv), replace=False)).astype(np.int64)
         lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=args.p, q=args.q)
         pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap)
-        cores = os.cpu_count() or 1
-        c0 = time.perf_counter()
-        r = oracle.walk(og, lg, pl, {"auto": 0, "rvs": 1, "rjs": 2}[args.strategy], sample.astype(np.int32), L,
-                        seed, walker_ids=sample, diagnostics=False, nthreads=cores)
-        cs = time.perf_counter() - c0
+        cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        smode = {"auto": 0, "rvs": 1, "rjs": 2}[args.strategy]
+        k = args.cpu_sample or 2048
+        while True:  # grow a seeded walker sample until the oracle works for ~10-30 s
+            sample = np.sort(rng.choice(nv, size=min(k, nv), replace=False)).astype(np.int64)
+            c0 = time.perf_counter()
+            r = oracle.walk(og, lg, pl, smode, sample.astype(np.int32), L, seed, walker_ids=sample,
+                            diagnostics=False, nthreads=cores)
+            cs = time.perf_counter() - c0
+            if args.cpu_sample or cs >= 10.0 or k >= nv:
+                break
+            k = int(min(nv, k * max(2.0, 15.0 / max(cs, 1e-3))))
         # the GPU run covered these walkers too: compare the sample
         gp = paths[torch.from_numpy(sample).to(dev)].cpu().numpy()
         same = float((gp == r.paths).all(axis=1).mean())

@@ -50,8 +50,9 @@ struct fw_graph {
     int32_t *col = nullptr;
     float *h = nullptr;
     uint8_t *label = nullptr;
-    float *hmax = nullptr;
-    float *hsum = nullptr;
+    uint2 *edges = nullptr;                 // {col, bits(h)} per entry
+    uint4 *vrec = nullptr;                  // {start_lo, degree, bits(h_MAX), bits(h_SUM)} per vertex
+    uint32_t *start_hi = nullptr;           // high row-start bits, only when ne >= 2^32
     unsigned long long *scratch = nullptr;  // [0] walker queue, [1] error flag (int)
     bool prepped = false;
 };
@@ -63,8 +64,9 @@ static void graph_free(fw_graph *g)
     (void)hipFree(g->col);
     (void)hipFree(g->h);
     (void)hipFree(g->label);
-    (void)hipFree(g->hmax);
-    (void)hipFree(g->hsum);
+    (void)hipFree(g->edges);
+    (void)hipFree(g->vrec);
+    (void)hipFree(g->start_hi);
     (void)hipFree(g->scratch);
     delete g;
 }
@@ -106,8 +108,10 @@ int fw_graph_create(const fw_csr *in, fw_graph **out)
         graph_free(g);
         return rc;
     }
-    if (hipMalloc((void **)&g->hmax, sizeof(float) * (size_t)(g->nv > 0 ? g->nv : 1)) != hipSuccess ||
-        hipMalloc((void **)&g->hsum, sizeof(float) * (size_t)(g->nv > 0 ? g->nv : 1)) != hipSuccess ||
+    const bool wide = g->ne >= ((int64_t)1 << 32);
+    if (hipMalloc((void **)&g->edges, sizeof(uint2) * (size_t)(g->ne > 0 ? g->ne : 1)) != hipSuccess ||
+        hipMalloc((void **)&g->vrec, sizeof(uint4) * (size_t)(g->nv > 0 ? g->nv : 1)) != hipSuccess ||
+        (wide && hipMalloc((void **)&g->start_hi, sizeof(uint32_t) * (size_t)g->nv) != hipSuccess) ||
         hipMalloc((void **)&g->scratch, 4 * sizeof(unsigned long long)) != hipSuccess) {
         graph_free(g);
         return fail(FW_E_NOMEM, "fw_graph_create: hipMalloc failed");
@@ -142,9 +146,12 @@ int fw_graph_create(const fw_csr *in, fw_graph **out)
                     "fw_graph_create: col must be in [0, nv) and strictly ascending per row; h finite and >= 0");
     }
     g->max_deg = (int64_t)host_chk[1];
-    if (hipMemset(g->scratch, 0, 4 * sizeof(unsigned long long)) != hipSuccess) {
+    e = fw::launch_layout(g->row_ptr, g->col, g->h, g->nv, g->ne, g->edges, g->vrec, g->start_hi, nullptr);
+    if (e == hipSuccess) e = hipMemset(g->scratch, 0, 4 * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
         graph_free(g);
-        return fail(FW_E_DEVICE, "fw_graph_create: hipMemset failed");
+        return fail(FW_E_DEVICE, "fw_graph_create: %s", hipGetErrorString(e));
     }
     *out = g;
     return ok();
@@ -160,7 +167,7 @@ int fw_graph_preprocess(fw_graph *g, void *stream)
 {
     if (!g) return fail(FW_E_INVALID, "fw_graph_preprocess: null graph");
     HIP_TRY(hipSetDevice(g->device));
-    HIP_TRY(fw::launch_preprocess(g->row_ptr, g->h, g->nv, g->hmax, g->hsum, (hipStream_t)stream));
+    HIP_TRY(fw::launch_preprocess(g->row_ptr, g->h, g->nv, g->vrec, (hipStream_t)stream));
     g->prepped = true;
     return ok();
 }
@@ -171,8 +178,13 @@ int fw_graph_export_aux(const fw_graph *g, float *hmax, float *hsum)
     if (!g->prepped) return fail(FW_E_STATE, "fw_graph_export_aux: graph not preprocessed");
     HIP_TRY(hipSetDevice(g->device));
     HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemcpy(hmax, g->hmax, sizeof(float) * (size_t)g->nv, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(hsum, g->hsum, sizeof(float) * (size_t)g->nv, hipMemcpyDeviceToHost));
+    std::vector<uint4> rec((size_t)g->nv);
+    if (g->nv > 0) HIP_TRY(hipMemcpy(rec.data(), g->vrec, sizeof(uint4) * rec.size(), hipMemcpyDeviceToHost));
+    for (int64_t v = 0; v < g->nv; ++v) {
+        uint32_t zb = rec[(size_t)v].z, wb = rec[(size_t)v].w;
+        memcpy(&hmax[v], &zb, sizeof(float));
+        memcpy(&hsum[v], &wb, sizeof(float));
+    }
     return ok();
 }
 
@@ -242,12 +254,11 @@ static int check_logic(const fw_graph *g, const fw_logic *lg)
 static void fill_args(const fw_graph *g, const fw_logic *lg, fw::WalkArgs &a)
 {
     memset(&a, 0, sizeof(a));
-    a.row_ptr = g->row_ptr;
+    a.edges = g->edges;
+    a.vrec = g->vrec;
+    a.start_hi = g->start_hi;
     a.col = g->col;
-    a.h = g->h;
     a.label = g->label;
-    a.hmax = g->hmax;
-    a.hsum = g->hsum;
     a.nv = g->nv;
     if (lg->kind == FW_NODE2VEC) {
         a.inv_p = 1.0f / lg->p;

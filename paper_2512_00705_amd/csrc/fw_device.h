@@ -131,6 +131,40 @@ __device__ __forceinline__ bool sorted_contains(const int32_t *a, IdxT n, int32_
     return lo < total && a[lo] == u;
 }
 
+// Membership of u in the strictly ascending array a[0, n) whose values lie in [0, vend).
+// Interpolation search: the bracket (lo, hi) starts at the virtual ends a[-1] = -1 and
+// a[n] = vend; each probe guesses u's position from the bracket values.  Vertex ids of
+// a row are spread almost uniformly, so a few probes suffice; after three guesses the
+// search bisects, which bounds it by 3 + log2(n) probes for any input.
+template <typename IdxT>
+__device__ __forceinline__ bool sorted_contains_interp(const int32_t *a, IdxT n, int32_t u, int64_t vend)
+{
+    IdxT lo = -1, hi = n;
+    int64_t vlo = -1, vhi = vend;
+    int it = 0;
+    while (hi - lo > 1) {
+        IdxT pos;
+        if (it < 3) {
+            const float f = (float)(u - vlo) / (float)(vhi - vlo);
+            pos = lo + (IdxT)(f * (float)(hi - lo));
+        } else {
+            pos = lo + ((hi - lo) >> 1);
+        }
+        pos = pos <= lo ? lo + 1 : (pos >= hi ? hi - 1 : pos);
+        const int32_t v = a[pos];
+        ++it;
+        if (v == u) return true;
+        if (v < u) {
+            lo = pos;
+            vlo = v;
+        } else {
+            hi = pos;
+            vhi = v;
+        }
+    }
+    return false;
+}
+
 // ceil(log2(m + 1)): probes of a binary search over m entries.
 __device__ __host__ __forceinline__ int probes(int64_t m)
 {

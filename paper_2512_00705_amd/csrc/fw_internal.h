@@ -24,17 +24,25 @@ enum Stat : int {
 constexpr int kBlock = 256;          // 4 wavefronts per block, each independent
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kDefaultLdsCap = 2048; // int32 entries of N(prev) per wavefront
-constexpr int kRjsPerRound = 4;      // eRJS trials a lane runs between eRVS services
+#ifndef FW_RJS_BATCH
+#define FW_RJS_BATCH 4
+#endif
+constexpr int kRjsBatch = FW_RJS_BATCH; // eRJS proposals whose loads a lane issues together
 
 // Everything a walk launch reads.  Float constants are prepared on the host in float32
 // so that the device and every other float32 evaluation agree bit for bit.
+// Device layout of a graph.  Besides the caller's CSR the library keeps
+//   edges[k] = {col[k], bits(h[k])}: one 8-byte load per proposed or scanned edge;
+//   vrec[v]  = {low 32 bits of row start, degree, bits(h_MAX[v]), bits(h_SUM[v])}:
+//              one 16-byte load per step set-up;
+//   start_hi[v] = high 32 bits of the row start (only when ne >= 2^32, else null);
+//   col (alone) for the membership search and LDS staging of N(prev).
 struct WalkArgs {
-    const int64_t *row_ptr;
+    const uint2 *edges;
+    const uint4 *vrec;
+    const uint32_t *start_hi;
     const int32_t *col;
-    const float *h;
     const uint8_t *label;
-    const float *hmax;
-    const float *hsum;
     int64_t nv;
 
     const int32_t *starts;
@@ -63,8 +71,9 @@ struct WalkArgs {
 
 hipError_t launch_walk(const WalkArgs &a, int kind, bool weighted, int grid, hipStream_t s);
 hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s);
-hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv, float *hmax, float *hsum,
-                             hipStream_t s);
+hipError_t launch_layout(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int64_t ne,
+                         uint2 *edges, uint4 *vrec, uint32_t *start_hi, hipStream_t s);
+hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv, uint4 *vrec, hipStream_t s);
 hipError_t launch_validate_rows(const int64_t *row_ptr, int64_t nv, int64_t ne, int *err, hipStream_t s);
 hipError_t launch_validate_edges(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv,
                                  int *err, unsigned long long *max_deg, hipStream_t s);

@@ -11,8 +11,10 @@
 //     maximum, then each lane scans its strided neighbours with the jump of Eq. (jump)
 //     and a final wave argmax picks the next vertex;
 //   * walkers are handed out from a global counter, one atomic per wave refill.
-// The membership test u in N(prev) of Node2Vec is a binary search over the sorted row
-// of prev, staged in LDS when that row is short enough, else read through L2.
+// The membership test u in N(prev) of Node2Vec is an interpolation search over the
+// sorted row of prev, staged in LDS when that row is short enough, else read through L2.
+// Random reads are what this kernel pays for (each costs a DRAM line), so an edge is one
+// 8-byte record {col, h} and a vertex one 16-byte record {start, degree, h_MAX, h_SUM}.
 #include "fw_device.h"
 #include "fw_internal.h"
 
@@ -22,24 +24,30 @@ enum Mode : int { kIdle = 0, kSetup = 1, kRjs = 2, kRvs = 3, kAdv = 4 };
 
 // Transition weight w~ = w * h of the edge at CSR position k with neighbour u at step j
 // (Section 2.1, Eq. prob; Eq. node2vec; MetaPath rule).  `mem` holds N(prev) sorted.
-template <int KIND, bool W>
-__device__ __forceinline__ float edge_weight(const WalkArgs &a, int64_t k, int32_t u, int j, int32_t prev,
-                                             const int32_t *mem, int64_t mlen, uint8_t want)
+template <int KIND, bool W, typename IdxT>
+__device__ __forceinline__ float edge_weight(const WalkArgs &a, int64_t k, uint2 e, int j, int32_t prev,
+                                             const int32_t *mem, IdxT mlen, uint8_t want)
 {
-    const float hv = W ? a.h[k] : 1.0f;
+    const float hv = W ? __uint_as_float(e.y) : 1.0f;
     if (KIND == kNode2Vec) {
         if (j == 0) return hv;
+        const int32_t u = (int32_t)e.x;
         if (u == prev) return a.inv_p * hv;
-        return sorted_contains(mem, mlen, u) ? hv : a.inv_q * hv;
+        return sorted_contains_interp(mem, mlen, u, a.nv) ? hv : a.inv_q * hv;
     } else {
         return a.label[k] == want ? hv : 0.0f;
     }
 }
 
+__device__ __forceinline__ int64_t row_start(const WalkArgs &a, uint4 r, int32_t v)
+{
+    return a.start_hi ? (int64_t)(((uint64_t)a.start_hi[v] << 32) | r.x) : (int64_t)r.x;
+}
+
 // eRVS for one step, all 64 lanes cooperating.  Returns the next vertex or -1 when no
 // neighbour has positive weight.  `trig` receives the number of jump events.
-template <int KIND, bool W>
-__device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const int32_t *mem, int64_t mlen, uint32_t wid,
+template <int KIND, bool W, typename IdxT>
+__device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const int32_t *mem, IdxT mlen, uint32_t wid,
                                             int j, int32_t prev, int64_t base, int64_t deg, uint8_t want,
                                             uint32_t &trig)
 {
@@ -50,8 +58,7 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const int32_t *me
     // round 0: lane l keys neighbour l, k = u^(1/w~) kept as log(u) / w~
     if (lane < deg) {
         const int64_t k = base + lane;
-        const int32_t u = a.col[k];
-        const float wt = edge_weight<KIND, W>(a, k, u, j, prev, mem, mlen, want);
+        const float wt = edge_weight<KIND, W>(a, k, a.edges[k], j, prev, mem, mlen, want);
         const U4 x = philox(wid, (uint32_t)j, (uint32_t)lane, 1u, a.key0, a.key1);
         key = wt > 0.0f ? ln_f(unit_uniform(x.x0)) / wt : -INFINITY;
         ru = unit_uniform(x.x1);
@@ -68,8 +75,7 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const int32_t *me
         const int64_t i = i0 + lane;
         if (i < deg) {
             const int64_t k = base + i;
-            const int32_t u = a.col[k];
-            const float wt = edge_weight<KIND, W>(a, k, u, j, prev, mem, mlen, want);
+            const float wt = edge_weight<KIND, W>(a, k, a.edges[k], j, prev, mem, mlen, want);
             S = S + wt;
             if (S > T) {
                 // key conditioned to beat thr: log u' = log1p(expm1(w~ * thr) * V)
@@ -92,8 +98,23 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const int32_t *me
     return key > -INFINITY ? a.col[base + bi] : -1;
 }
 
+// Adds a wave's counters to the device totals and clears them.
+__device__ __forceinline__ void flush_stats(const WalkArgs &a, uint32_t (&cnt)[kStBytes], uint64_t &bytes)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int c = 0; c < kStBytes; ++c) {
+        const uint64_t v = wave_sum_u64(cnt[c]);
+        if (lane == 0 && v != 0) atomicAdd(&a.stats[c], (unsigned long long)v);
+        cnt[c] = 0;
+    }
+    const uint64_t b = wave_sum_u64(bytes);
+    if (lane == 0 && b != 0) atomicAdd(&a.stats[kStBytes], (unsigned long long)b);
+    bytes = 0;
+}
+
 template <int KIND, bool W>
-__global__ void __launch_bounds__(kBlock) walk_kernel(WalkArgs a)
+__global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
 {
     extern __shared__ int32_t lds_all[];
     int32_t *lds = lds_all + (threadIdx.x / kWave) * a.lds_cap;
@@ -108,12 +129,17 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(WalkArgs a)
     int32_t trials = 0;
     bool fell_back = false;
     float B = 0.0f;
-    uint64_t st[kNumStats];
+    // per-lane counters (32-bit counts, 64-bit bytes), flushed before a count could wrap
+    uint32_t st[kStBytes];
 #pragma unroll
-    for (int c = 0; c < kNumStats; ++c) st[c] = 0;
+    for (int c = 0; c < kStBytes; ++c) st[c] = 0;
+    uint64_t st_bytes = 0;
     bool exhausted = false;
 
     for (;;) {
+        if (a.stats != nullptr && __ballot((st[kStTrials] | st[kStTriggers] | st[kStSteps]) > 0x40000000u) != 0)
+            flush_stats(a, st, st_bytes);
+
         // 1. hand walkers to idle lanes: one atomic per wave
         const uint64_t idle = __ballot(mode == kIdle);
         if (idle != 0 && !exhausted) {
@@ -129,7 +155,7 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(WalkArgs a)
                     const int32_t s = a.starts[w];
                     int32_t *row = a.paths + w * row_len;
                     row[0] = s;
-                    st[kStBytes] += 12 + 4 * (uint64_t)a.L;
+                    st_bytes += 12 + 4 * (uint64_t)a.L;
                     if (s < 0 || (int64_t)s >= a.nv) {
                         atomicOr(a.err, 1);
                         for (int r = 1; r <= a.L; ++r) row[r] = -1;
@@ -156,9 +182,10 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(WalkArgs a)
                 mode = kIdle;
                 wid = -1;
             } else {
-                base = a.row_ptr[cur];
-                deg = a.row_ptr[cur + 1] - base;
-                st[kStBytes] += 16;
+                const uint4 r = a.vrec[cur];
+                base = row_start(a, r, cur);
+                deg = (int64_t)r.y;
+                st_bytes += 16;
                 if (deg == 0) {
                     nxt = -1;
                     mode = kAdv;
@@ -166,15 +193,15 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(WalkArgs a)
                     bool rjs = false;
                     if (a.strategy != kRvsOnly) {
                         const float wmax = (j == 0) ? a.wmax0 : a.wmax1;
-                        const float hm = W ? a.hmax[cur] : 1.0f;
+                        const float hm = W ? __uint_as_float(r.z) : 1.0f;
                         B = wmax * hm;  // get_weight_max: max(w) * h_MAX
                         if (a.strategy == kRjsOnly) {
                             rjs = true;
-                            st[kStBytes] += W ? 4 : 0;
+                            st_bytes += W ? 4 : 0;
                         } else {
                             const float wavg = (j == 0) ? a.wavg0 : a.wavg1;
-                            const float hs = W ? a.hsum[cur] : (float)deg;
-                            st[kStBytes] += W ? 8 : 0;
+                            const float hs = W ? __uint_as_float(r.w) : (float)deg;
+                            st_bytes += W ? 8 : 0;
                             // Eq. (runtime) with get_weight_sum = mean(w) * h_SUM
                             rjs = deg >= a.d_lo && (a.rho * B) < (wavg * hs);
                         }
@@ -191,46 +218,63 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(WalkArgs a)
         //    the test open
         if (mode == kRjs) {
             const uint8_t want = (KIND == kMetaPath) ? a.schema[j % a.schema_len] : (uint8_t)0;
-            for (int r = 0; r < kRjsPerRound; ++r) {
-                const U4 x = philox((uint32_t)wid, (uint32_t)j, (uint32_t)trials, 0u, a.key0, a.key1);
-                const int64_t k = base + scaled_index(x.x0, x.x1, deg);
-                const int32_t u = a.col[k];
-                const float hv = W ? a.h[k] : 1.0f;
-                const float y = unit_uniform(x.x2) * B;
-                bool acc;
-                if (KIND == kNode2Vec) {
-                    if (j == 0) {
-                        acc = y < hv;
-                    } else if (u == prev) {
-                        acc = y < a.inv_p * hv;
-                    } else {
-                        const float lo = a.lo_w * hv, hi = a.hi_w * hv;
-                        if (y < lo) {
-                            acc = true;
-                        } else if (!(y < hi)) {
-                            acc = false;
+            // issue the loads of the next kRjsBatch proposals together, then decide them
+            // in trial order; the first accepted trial is the sample, exactly as if the
+            // trials ran one by one
+            uint32_t ux[kRjsBatch];
+            int64_t kk[kRjsBatch];
+            uint2 ee[kRjsBatch];
+            uint8_t ll[kRjsBatch];
+#pragma unroll
+            for (int r = 0; r < kRjsBatch; ++r) {
+                const U4 x = philox((uint32_t)wid, (uint32_t)j, (uint32_t)(trials + r), 0u, a.key0, a.key1);
+                kk[r] = base + scaled_index(x.x0, x.x1, deg);
+                ux[r] = x.x2;
+                ee[r] = a.edges[kk[r]];
+                ll[r] = (KIND == kMetaPath) ? a.label[kk[r]] : (uint8_t)0;
+            }
+            bool open = true;
+#pragma unroll
+            for (int r = 0; r < kRjsBatch; ++r) {
+                if (open) {
+                    const int32_t u = (int32_t)ee[r].x;
+                    const float hv = W ? __uint_as_float(ee[r].y) : 1.0f;
+                    const float y = unit_uniform(ux[r]) * B;
+                    bool acc;
+                    if (KIND == kNode2Vec) {
+                        if (j == 0) {
+                            acc = y < hv;
+                        } else if (u == prev) {
+                            acc = y < a.inv_p * hv;
                         } else {
-                            st[kStBytes] += 4 * (uint64_t)probes(pdeg);
-                            const float wt = sorted_contains(a.col + pbase, pdeg, u) ? hv : a.inv_q * hv;
-                            acc = y < wt;
+                            const float lo = a.lo_w * hv, hi = a.hi_w * hv;
+                            if (y < lo) {
+                                acc = true;
+                            } else if (!(y < hi)) {
+                                acc = false;
+                            } else {
+                                st_bytes += 4 * (uint64_t)probes(pdeg);
+                                const float wt =
+                                    sorted_contains_interp(a.col + pbase, pdeg, u, a.nv) ? hv : a.inv_q * hv;
+                                acc = y < wt;
+                            }
                         }
+                    } else {
+                        acc = y < (ll[r] == want ? hv : 0.0f);
                     }
-                } else {
-                    acc = y < (a.label[k] == want ? hv : 0.0f);
-                }
-                ++trials;
-                st[kStTrials] += 1;
-                st[kStBytes] += (uint64_t)a.item_bytes;
-                if (acc) {
-                    nxt = u;
-                    mode = kAdv;
-                    st[kStRjs] += 1;
-                    break;
-                }
-                if (trials >= a.rjs_cap) {
-                    mode = kRvs;  // exact fall-back: eRVS draws are independent of eRJS draws
-                    fell_back = true;
-                    break;
+                    ++trials;
+                    st[kStTrials] += 1;
+                    st_bytes += (uint64_t)a.item_bytes;
+                    if (acc) {
+                        nxt = u;
+                        mode = kAdv;
+                        st[kStRjs] += 1;
+                        open = false;
+                    } else if (trials >= a.rjs_cap) {
+                        mode = kRvs;  // exact fall-back: eRVS draws are independent of eRJS draws
+                        fell_back = true;
+                        open = false;
+                    }
                 }
             }
         }
@@ -255,7 +299,7 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(WalkArgs a)
                 wave_lds_sync();
                 for (int64_t i = lane; i < s_pdeg; i += kWave) lds[i] = a.col[s_pbase + i];
                 wave_lds_sync();
-                res = rvs_step<KIND, W>(a, lds, s_pdeg, s_wid, s_j, s_prev, s_base, s_deg, want, trig);
+                res = rvs_step<KIND, W>(a, lds, (int32_t)s_pdeg, s_wid, s_j, s_prev, s_base, s_deg, want, trig);
             } else {
                 res = rvs_step<KIND, W>(a, a.col + s_pbase, s_pdeg, s_wid, s_j, s_prev, s_base, s_deg, want,
                                         trig);
@@ -270,7 +314,7 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(WalkArgs a)
                     const uint64_t search = 4 * (uint64_t)s_deg * (uint64_t)probes(s_pdeg);
                     by += stage < search ? stage : search;
                 }
-                st[kStBytes] += by;
+                st_bytes += by;
                 if (res >= 0) st[fell_back ? kStFallback : kStRvs] += 1;
             }
         }
@@ -297,13 +341,7 @@ __global__ void __launch_bounds__(kBlock) walk_kernel(WalkArgs a)
         }
     }
 
-    if (a.stats != nullptr) {
-#pragma unroll
-        for (int c = 0; c < kNumStats; ++c) {
-            const uint64_t v = wave_sum_u64(st[c]);
-            if (lane == 0 && v != 0) atomicAdd(&a.stats[c], (unsigned long long)v);
-        }
-    }
+    if (a.stats != nullptr) flush_stats(a, st, st_bytes);
 }
 
 __global__ void zero_kernel(unsigned long long *p, int n)
@@ -316,7 +354,7 @@ __global__ void zero_kernel(unsigned long long *p, int n)
 // accumulated in double, so for float32 inputs of moderate range it is exact and the
 // rounding to float32 does not depend on the summation order.
 __global__ void __launch_bounds__(kBlock) preprocess_kernel(const int64_t *row_ptr, const float *h, int64_t nv,
-                                                            float *hmax, float *hsum)
+                                                            uint4 *vrec)
 {
     const int lane = lane_id();
     const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
@@ -331,10 +369,22 @@ __global__ void __launch_bounds__(kBlock) preprocess_kernel(const int64_t *row_p
         }
         mx = wave_max(mx);
         sm = wave_sum_f64(sm);
-        if (lane == 0) {
-            hmax[v] = mx;
-            hsum[v] = (float)sm;
-        }
+        if (lane == 0) vrec[v] = make_uint4((uint32_t)b, (uint32_t)(e - b), __float_as_uint(mx), __float_as_uint((float)sm));
+    }
+}
+
+// Device layout: {col, h} edge records and {start, degree, -, -} vertex records.
+__global__ void layout_kernel(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int64_t ne,
+                              uint2 *edges, uint4 *vrec, uint32_t *start_hi)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t k = t0; k < ne; k += stride)
+        edges[k] = make_uint2((uint32_t)col[k], __float_as_uint(h ? h[k] : 1.0f));
+    for (int64_t v = t0; v < nv; v += stride) {
+        const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+        vrec[v] = make_uint4((uint32_t)b, (uint32_t)(e - b), 0u, 0u);
+        if (start_hi) start_hi[v] = (uint32_t)((uint64_t)b >> 32);
     }
 }
 
@@ -356,9 +406,10 @@ __global__ void __launch_bounds__(kBlock) validate_edges_kernel(const int64_t *r
 {
     const int lane = lane_id();
     const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    unsigned long long dmax = 0;
     for (int64_t v = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; v < nv; v += nw) {
         const int64_t b = row_ptr[v], e = row_ptr[v + 1];
-        if (lane == 0) atomicMax(max_deg, (unsigned long long)(e - b));
+        dmax = (unsigned long long)(e - b) > dmax ? (unsigned long long)(e - b) : dmax;
         bool bad = false;
         for (int64_t k = b + lane; k < e; k += kWave) {
             const int32_t c = col[k];
@@ -371,6 +422,7 @@ __global__ void __launch_bounds__(kBlock) validate_edges_kernel(const int64_t *r
         }
         if (bad) atomicOr(err, 2);
     }
+    if (lane == 0 && dmax > 0) atomicMax(max_deg, dmax);
 }
 
 // Profiling kernels (Section 5, "Flexi-Runtime Profiling Kernels"): evaluate workload
@@ -386,12 +438,14 @@ __global__ void __launch_bounds__(kBlock) profile_rvs_kernel(WalkArgs a, const i
     float acc = 0.0f;
     for (int s = blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; s < nsample; s += nw) {
         const int32_t v = nodes[s];
-        const int64_t b = a.row_ptr[v], d = a.row_ptr[v + 1] - b;
+        const uint4 rv = a.vrec[v];
+        const int64_t b = row_start(a, rv, v), d = (int64_t)rv.y;
         const int64_t m = d < per_node ? d : per_node;
         const int32_t prev = a.col[b];
-        const int64_t pb = a.row_ptr[prev], pd = a.row_ptr[prev + 1] - pb;
+        const uint4 rp = a.vrec[prev];
+        const int64_t pb = row_start(a, rp, prev), pd = (int64_t)rp.y;
         for (int64_t i = lane; i < m; i += kWave)
-            acc += edge_weight<KIND, W>(a, b + i, a.col[b + i], 1, prev, a.col + pb, pd, a.schema[0]);
+            acc += edge_weight<KIND, W>(a, b + i, a.edges[b + i], 1, prev, a.col + pb, pd, a.schema[0]);
     }
     acc = wave_max(acc);
     if (lane == 0 && acc < 0.0f) sink[0] = acc;  // never true; keeps the loads alive
@@ -405,13 +459,15 @@ __global__ void __launch_bounds__(kBlock) profile_rjs_kernel(WalkArgs a, const i
     float acc = 0.0f;
     if (s < nsample) {
         const int32_t v = nodes[s];
-        const int64_t b = a.row_ptr[v], d = a.row_ptr[v + 1] - b;
+        const uint4 rv = a.vrec[v];
+        const int64_t b = row_start(a, rv, v), d = (int64_t)rv.y;
         const int32_t prev = a.col[b];
-        const int64_t pb = a.row_ptr[prev], pd = a.row_ptr[prev + 1] - pb;
+        const uint4 rp = a.vrec[prev];
+        const int64_t pb = row_start(a, rp, prev), pd = (int64_t)rp.y;
         for (int t = 0; t < per_node; ++t) {
             const U4 x = philox((uint32_t)s, 0u, (uint32_t)t, 2u, a.key0, a.key1);
             const int64_t k = b + scaled_index(x.x0, x.x1, d);
-            acc += edge_weight<KIND, W>(a, k, a.col[k], 1, prev, a.col + pb, pd, a.schema[0]);
+            acc += edge_weight<KIND, W>(a, k, a.edges[k], 1, prev, a.col + pb, pd, a.schema[0]);
         }
     }
     if (acc < 0.0f) sink[0] = acc;
@@ -464,13 +520,24 @@ hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv, float *hmax, float *hsum,
-                             hipStream_t s)
+hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv, uint4 *vrec, hipStream_t s)
 {
     int64_t blocks = (nv + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(preprocess_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, h, nv, hmax, hsum);
+    hipLaunchKernelGGL(preprocess_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, h, nv, vrec);
+    return hipGetLastError();
+}
+
+hipError_t launch_layout(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int64_t ne,
+                         uint2 *edges, uint4 *vrec, uint32_t *start_hi, hipStream_t s)
+{
+    int64_t work = ne > nv ? ne : nv;
+    int64_t blocks = (work + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(layout_kernel, dim3((unsigned)blocks), dim3(256), 0, s, row_ptr, col, h, nv, ne, edges, vrec,
+                       start_hi);
     return hipGetLastError();
 }
 
