@@ -24,16 +24,23 @@ enum Mode : int { kIdle = 0, kSetup = 1, kRjs = 2, kRvs = 3, kAdv = 4 };
 
 // Transition weight w~ = w * h of the edge at CSR position k with neighbour u at step j
 // (Section 2.1, Eq. prob; Eq. node2vec; MetaPath rule).  `mem` holds N(prev) sorted.
-template <int KIND, bool W, typename IdxT>
+// N(prev) for the membership test: a copy in this wave's LDS or the row of prev in col,
+// read through one flat pointer either way.
+struct Mem {
+    const int32_t *p;
+    int64_t len;
+};
+
+template <int KIND, bool W>
 __device__ __forceinline__ float edge_weight(const WalkArgs &a, int64_t k, uint2 e, int j, int32_t prev,
-                                             const int32_t *mem, IdxT mlen, uint8_t want)
+                                             const Mem &m, uint8_t want)
 {
     const float hv = W ? __uint_as_float(e.y) : 1.0f;
     if (KIND == kNode2Vec) {
         if (j == 0) return hv;
         const int32_t u = (int32_t)e.x;
         if (u == prev) return a.inv_p * hv;
-        return sorted_contains_interp(mem, mlen, u, a.nv) ? hv : a.inv_q * hv;
+        return sorted_contains_interp(m.p, m.len, u, a.nv) ? hv : a.inv_q * hv;
     } else {
         return a.label[k] == want ? hv : 0.0f;
     }
@@ -46,10 +53,9 @@ __device__ __forceinline__ int64_t row_start(const WalkArgs &a, uint4 r, int32_t
 
 // eRVS for one step, all 64 lanes cooperating.  Returns the next vertex or -1 when no
 // neighbour has positive weight.  `trig` receives the number of jump events.
-template <int KIND, bool W, typename IdxT>
-__device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const int32_t *mem, IdxT mlen, uint32_t wid,
-                                            int j, int32_t prev, int64_t base, int64_t deg, uint8_t want,
-                                            uint32_t &trig)
+template <int KIND, bool W>
+__device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const Mem &mem, uint32_t wid, int j, int32_t prev,
+                                            int64_t base, int64_t deg, uint8_t want, uint32_t &trig)
 {
     const int lane = lane_id();
     float key = -INFINITY;
@@ -58,7 +64,7 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const int32_t *me
     // round 0: lane l keys neighbour l, k = u^(1/w~) kept as log(u) / w~
     if (lane < deg) {
         const int64_t k = base + lane;
-        const float wt = edge_weight<KIND, W>(a, k, a.edges[k], j, prev, mem, mlen, want);
+        const float wt = edge_weight<KIND, W>(a, k, a.edges[k], j, prev, mem, want);
         const U4 x = philox(wid, (uint32_t)j, (uint32_t)lane, 1u, a.key0, a.key1);
         key = wt > 0.0f ? ln_f(unit_uniform(x.x0)) / wt : -INFINITY;
         ru = unit_uniform(x.x1);
@@ -75,7 +81,7 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const int32_t *me
         const int64_t i = i0 + lane;
         if (i < deg) {
             const int64_t k = base + i;
-            const float wt = edge_weight<KIND, W>(a, k, a.edges[k], j, prev, mem, mlen, want);
+            const float wt = edge_weight<KIND, W>(a, k, a.edges[k], j, prev, mem, want);
             S = S + wt;
             if (S > T) {
                 // key conditioned to beat thr: log u' = log1p(expm1(w~ * thr) * V)
@@ -96,6 +102,64 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const int32_t *me
     wave_argmax(key, bi);
     trig = (uint32_t)wave_sum_u64(nt);
     return key > -INFINITY ? a.col[base + bi] : -1;
+}
+
+// eRVS for up to 64/G steps at once, one G-lane group per step, for rows of at most G
+// neighbours.  Such a step is decided by round 0 alone (every neighbour gets its key,
+// there is nothing to scan), so the result equals the one-wave eRVS bit for bit.
+// Takes its steps from `pool` (lanes in trial order of the ballot) and returns true
+// for the lanes that were served, with the next vertex (or -1) in `res`.
+template <int KIND, bool W>
+__device__ __forceinline__ bool rvs_group_pass(const WalkArgs &a, int G, uint64_t &pool, int32_t wid, int32_t j,
+                                               int32_t prev, int64_t base, int32_t deg, int64_t pbase, int32_t pdeg,
+                                               int32_t &res)
+{
+    const int lane = lane_id();
+    const int g = lane / G, r = lane % G;
+    int src_of_group = -1, my_slot = -1;
+    for (int s = 0; s < kWave / G; ++s) {
+        int src = -1;
+        if (pool != 0) {
+            src = __ffsll((unsigned long long)pool) - 1;
+            pool &= pool - 1;
+        }
+        if (g == s) src_of_group = src;
+        if (lane == src) my_slot = s;
+    }
+    // every lane takes part in every shuffle: a step's owner may sit in a group that
+    // serves nothing this pass, and a lane reading from an inactive lane gets garbage
+    const int sl = src_of_group < 0 ? lane : src_of_group;
+    const uint32_t s_wid = (uint32_t)__shfl(wid, sl, kWave);
+    const int32_t s_j = __shfl(j, sl, kWave);
+    const int32_t s_prev = __shfl(prev, sl, kWave);
+    const int64_t s_base = __shfl((long long)base, sl, kWave);
+    const int32_t deg_of_src = __shfl(deg, sl, kWave);
+    const int64_t s_pbase = __shfl((long long)pbase, sl, kWave);
+    const int32_t s_pdeg = __shfl(pdeg, sl, kWave);
+    const int32_t s_deg = src_of_group < 0 ? 0 : deg_of_src;
+    float key = -INFINITY;
+    int32_t bi = -1;
+    if (r < s_deg) {
+        const int64_t k = s_base + r;
+        const uint8_t want = (KIND == kMetaPath) ? a.schema[s_j % a.schema_len] : (uint8_t)0;
+        const Mem m = {a.col + s_pbase, s_pdeg};
+        const float wt = edge_weight<KIND, W>(a, k, a.edges[k], s_j, s_prev, m, want);
+        const U4 x = philox(s_wid, (uint32_t)s_j, (uint32_t)r, 1u, a.key0, a.key1);
+        key = wt > 0.0f ? ln_f(unit_uniform(x.x0)) / wt : -INFINITY;
+        bi = r;
+    }
+    for (int o = G / 2; o > 0; o >>= 1) {
+        const float k2 = __shfl_xor(key, o, kWave);
+        const int32_t i2 = __shfl_xor(bi, o, kWave);
+        if (k2 > key || (k2 == key && i2 > bi)) {
+            key = k2;
+            bi = i2;
+        }
+    }
+    const int32_t nx = key > -INFINITY ? a.col[s_base + bi] : -1;
+    const int32_t got = __shfl(nx, my_slot >= 0 ? my_slot * G : lane, kWave);
+    if (my_slot >= 0) res = got;
+    return my_slot >= 0;
 }
 
 // Adds a wave's counters to the device totals and clears them.
@@ -123,9 +187,10 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
     const int64_t row_len = (int64_t)a.L + 1;
 
     int mode = kIdle;
-    int64_t wid = -1;
+    int32_t wid = -1;  // walker index (n < 2^31)
     int32_t cur = 0, prev = -1, j = 0, nxt = -1;
-    int64_t base = 0, deg = 0, pbase = 0, pdeg = 0;
+    int64_t base = 0, pbase = 0;
+    int32_t deg = 0, pdeg = 0;  // degrees (nv < 2^31)
     int32_t trials = 0;
     bool fell_back = false;
     float B = 0.0f;
@@ -161,7 +226,7 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
                         for (int r = 1; r <= a.L; ++r) row[r] = -1;
                         a.lengths[w] = 0;
                     } else {
-                        wid = w;
+                        wid = (int32_t)w;
                         cur = s;
                         prev = -1;
                         j = 0;
@@ -184,7 +249,7 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
             } else {
                 const uint4 r = a.vrec[cur];
                 base = row_start(a, r, cur);
-                deg = (int64_t)r.y;
+                deg = (int32_t)r.y;
                 st_bytes += 16;
                 if (deg == 0) {
                     nxt = -1;
@@ -222,100 +287,127 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
             // in trial order; the first accepted trial is the sample, exactly as if the
             // trials ran one by one
             uint32_t ux[kRjsBatch];
-            int64_t kk[kRjsBatch];
             uint2 ee[kRjsBatch];
             uint8_t ll[kRjsBatch];
 #pragma unroll
             for (int r = 0; r < kRjsBatch; ++r) {
                 const U4 x = philox((uint32_t)wid, (uint32_t)j, (uint32_t)(trials + r), 0u, a.key0, a.key1);
-                kk[r] = base + scaled_index(x.x0, x.x1, deg);
+                const int64_t k = base + scaled_index(x.x0, x.x1, deg);
                 ux[r] = x.x2;
-                ee[r] = a.edges[kk[r]];
-                ll[r] = (KIND == kMetaPath) ? a.label[kk[r]] : (uint8_t)0;
+                ee[r] = a.edges[k];
+                ll[r] = (KIND == kMetaPath) ? a.label[k] : (uint8_t)0;
             }
-            bool open = true;
-#pragma unroll
+            // decide proposals in order; the batch shifts down one slot per trial so the
+            // decision code appears once
+#pragma unroll 1
             for (int r = 0; r < kRjsBatch; ++r) {
-                if (open) {
-                    const int32_t u = (int32_t)ee[r].x;
-                    const float hv = W ? __uint_as_float(ee[r].y) : 1.0f;
-                    const float y = unit_uniform(ux[r]) * B;
-                    bool acc;
-                    if (KIND == kNode2Vec) {
-                        if (j == 0) {
-                            acc = y < hv;
-                        } else if (u == prev) {
-                            acc = y < a.inv_p * hv;
-                        } else {
-                            const float lo = a.lo_w * hv, hi = a.hi_w * hv;
-                            if (y < lo) {
-                                acc = true;
-                            } else if (!(y < hi)) {
-                                acc = false;
-                            } else {
-                                st_bytes += 4 * (uint64_t)probes(pdeg);
-                                const float wt =
-                                    sorted_contains_interp(a.col + pbase, pdeg, u, a.nv) ? hv : a.inv_q * hv;
-                                acc = y < wt;
-                            }
-                        }
+                const int32_t u = (int32_t)ee[0].x;
+                const float hv = W ? __uint_as_float(ee[0].y) : 1.0f;
+                const float y = unit_uniform(ux[0]) * B;
+                bool acc;
+                if (KIND == kNode2Vec) {
+                    if (j == 0) {
+                        acc = y < hv;
+                    } else if (u == prev) {
+                        acc = y < a.inv_p * hv;
                     } else {
-                        acc = y < (ll[r] == want ? hv : 0.0f);
+                        const float lo = a.lo_w * hv, hi = a.hi_w * hv;
+                        if (y < lo) {
+                            acc = true;
+                        } else if (!(y < hi)) {
+                            acc = false;
+                        } else {
+                            st_bytes += 4 * (uint64_t)probes(pdeg);
+                            const float wt =
+                                sorted_contains_interp(a.col + pbase, (int64_t)pdeg, u, a.nv) ? hv : a.inv_q * hv;
+                            acc = y < wt;
+                        }
                     }
-                    ++trials;
-                    st[kStTrials] += 1;
-                    st_bytes += (uint64_t)a.item_bytes;
-                    if (acc) {
-                        nxt = u;
-                        mode = kAdv;
-                        st[kStRjs] += 1;
-                        open = false;
-                    } else if (trials >= a.rjs_cap) {
-                        mode = kRvs;  // exact fall-back: eRVS draws are independent of eRJS draws
-                        fell_back = true;
-                        open = false;
-                    }
+                } else {
+                    acc = y < (ll[0] == want ? hv : 0.0f);
+                }
+                ++trials;
+                st[kStTrials] += 1;
+                st_bytes += (uint64_t)a.item_bytes;
+                if (acc) {
+                    nxt = u;
+                    mode = kAdv;
+                    st[kStRjs] += 1;
+                    break;
+                }
+                if (trials >= a.rjs_cap) {
+                    mode = kRvs;  // exact fall-back: eRVS draws are independent of eRJS draws
+                    fell_back = true;
+                    break;
+                }
+#pragma unroll
+                for (int q = 0; q + 1 < kRjsBatch; ++q) {
+                    ee[q] = ee[q + 1];
+                    ux[q] = ux[q + 1];
+                    ll[q] = ll[q + 1];
                 }
             }
         }
 
-        // 4. eRVS for every lane that needs it, the wave cooperating (Section 5)
-        uint64_t need = __ballot(mode == kRvs);
-        while (need != 0) {
-            const int src = __ffsll((unsigned long long)need) - 1;
-            need &= need - 1;
-            const uint32_t s_wid = bcast_u32((uint32_t)wid, src);
-            const int32_t s_j = bcast_i32(j, src);
-            const int32_t s_prev = bcast_i32(prev, src);
-            const int64_t s_base = bcast_i64(base, src);
-            const int64_t s_deg = bcast_i64(deg, src);
-            const int64_t s_pbase = bcast_i64(pbase, src);
-            const int64_t s_pdeg = bcast_i64(pdeg, src);
-            const uint8_t want = (KIND == kMetaPath) ? a.schema[s_j % a.schema_len] : (uint8_t)0;
-            const bool member_test = (KIND == kNode2Vec) && s_j > 0;
-            uint32_t trig = 0;
-            int32_t res;
-            if (member_test && s_pdeg <= a.lds_cap && s_pdeg <= s_deg * probes(s_pdeg)) {
-                wave_lds_sync();
-                for (int64_t i = lane; i < s_pdeg; i += kWave) lds[i] = a.col[s_pbase + i];
-                wave_lds_sync();
-                res = rvs_step<KIND, W>(a, lds, (int32_t)s_pdeg, s_wid, s_j, s_prev, s_base, s_deg, want, trig);
-            } else {
-                res = rvs_step<KIND, W>(a, a.col + s_pbase, s_pdeg, s_wid, s_j, s_prev, s_base, s_deg, want,
-                                        trig);
+        // 4. eRVS for every lane that needs it (Section 5): short rows in groups of
+        //    8/16/32 lanes, several steps per pass; longer rows one at a time with the
+        //    whole wave
+        {
+            const bool want_rvs = mode == kRvs;
+            uint64_t s8 = __ballot(want_rvs && deg <= 8);
+            uint64_t s16 = __ballot(want_rvs && deg > 8 && deg <= 16);
+            uint64_t s32 = __ballot(want_rvs && deg > 16 && deg <= 32);
+            uint64_t big = __ballot(want_rvs && deg > 32);
+            if (__popcll(s8) <= 4) {
+                s16 |= s8;
+                s8 = 0;
             }
-            if (lane == src) {
+            if (__popcll(s16) <= 2) {
+                s32 |= s16;
+                s16 = 0;
+            }
+            // the per-step accounting is the same whichever lanes served the step
+            auto served = [&](int32_t res, uint32_t trig) {
                 nxt = res;
                 mode = kAdv;
                 st[kStTriggers] += trig;
-                uint64_t by = (uint64_t)s_deg * (uint64_t)a.item_bytes;
-                if (member_test) {
-                    const uint64_t stage = 4 * (uint64_t)s_pdeg;
-                    const uint64_t search = 4 * (uint64_t)s_deg * (uint64_t)probes(s_pdeg);
+                uint64_t by = (uint64_t)deg * (uint64_t)a.item_bytes;
+                if (KIND == kNode2Vec && j > 0) {
+                    const uint64_t stage = 4 * (uint64_t)pdeg;
+                    const uint64_t search = 4 * (uint64_t)deg * (uint64_t)probes(pdeg);
                     by += stage < search ? stage : search;
                 }
                 st_bytes += by;
                 if (res >= 0) st[fell_back ? kStFallback : kStRvs] += 1;
+            };
+            int32_t res = -1;
+            for (int G = 8; G <= 32; G <<= 1) {
+                uint64_t &pool = G == 8 ? s8 : (G == 16 ? s16 : s32);
+                while (pool != 0)
+                    if (rvs_group_pass<KIND, W>(a, G, pool, wid, j, prev, base, deg, pbase, pdeg, res)) served(res, 0);
+            }
+            while (big != 0) {
+                const int src = __ffsll((unsigned long long)big) - 1;
+                big &= big - 1;
+                const uint32_t s_wid = bcast_u32((uint32_t)wid, src);
+                const int32_t s_j = bcast_i32(j, src);
+                const int32_t s_prev = bcast_i32(prev, src);
+                const int64_t s_base = bcast_i64(base, src);
+                const int32_t s_deg = bcast_i32(deg, src);
+                const int64_t s_pbase = bcast_i64(pbase, src);
+                const int32_t s_pdeg = bcast_i32(pdeg, src);
+                const uint8_t want = (KIND == kMetaPath) ? a.schema[s_j % a.schema_len] : (uint8_t)0;
+                const bool member_test = (KIND == kNode2Vec) && s_j > 0;
+                Mem m = {a.col + s_pbase, s_pdeg};
+                if (member_test && s_pdeg <= a.lds_cap && (int64_t)s_pdeg <= (int64_t)s_deg * probes(s_pdeg)) {
+                    wave_lds_sync();
+                    for (int32_t i = lane; i < s_pdeg; i += kWave) lds[i] = a.col[s_pbase + i];
+                    wave_lds_sync();
+                    m.p = lds;
+                }
+                uint32_t trig = 0;
+                res = rvs_step<KIND, W>(a, m, s_wid, s_j, s_prev, s_base, s_deg, want, trig);
+                if (lane == src) served(res, trig);
             }
         }
 
@@ -445,7 +537,8 @@ __global__ void __launch_bounds__(kBlock) profile_rvs_kernel(WalkArgs a, const i
         const uint4 rp = a.vrec[prev];
         const int64_t pb = row_start(a, rp, prev), pd = (int64_t)rp.y;
         for (int64_t i = lane; i < m; i += kWave)
-            acc += edge_weight<KIND, W>(a, b + i, a.edges[b + i], 1, prev, a.col + pb, pd, a.schema[0]);
+            acc += edge_weight<KIND, W>(a, b + i, a.edges[b + i], 1, prev, Mem{a.col + pb, pd},
+                                        a.schema[0]);
     }
     acc = wave_max(acc);
     if (lane == 0 && acc < 0.0f) sink[0] = acc;  // never true; keeps the loads alive
@@ -467,7 +560,7 @@ __global__ void __launch_bounds__(kBlock) profile_rjs_kernel(WalkArgs a, const i
         for (int t = 0; t < per_node; ++t) {
             const U4 x = philox((uint32_t)s, 0u, (uint32_t)t, 2u, a.key0, a.key1);
             const int64_t k = b + scaled_index(x.x0, x.x1, d);
-            acc += edge_weight<KIND, W>(a, k, a.edges[k], 1, prev, a.col + pb, pd, a.schema[0]);
+            acc += edge_weight<KIND, W>(a, k, a.edges[k], 1, prev, Mem{a.col + pb, pd}, a.schema[0]);
         }
     }
     if (acc < 0.0f) sink[0] = acc;
