@@ -39,6 +39,9 @@ def main():
     ap.add_argument("--modes", type=int, default=1, help="also time the single-kernel modes")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=0, help="walkers for the CPU baseline (0: sized to ~15 s)")
+    ap.add_argument("--workload", default="node2vec", choices=["node2vec", "batched"],
+                    help="node2vec: the headline scale-22 job; batched: 4096 queries on skewed scale 24")
+    ap.add_argument("--per-query", type=int, default=1, help="batched: also time one launch per query")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB: only run a plain device-to-device copy of this size 3 times (counter calibration)")
     args = ap.parse_args()
@@ -61,6 +64,8 @@ def main():
     import paper_2512_00705_amd as fw
     import synth
 
+    if args.workload == "batched":
+        return bench_batched(args)
     t0 = time.time()
     g = synth.cached(args.graph)
     log(f"graph {args.graph}: nv={g['nv']} ne={g['ne']} ({time.time() - t0:.1f}s)")
@@ -178,6 +183,89 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_batched(args):
+    """4096 Node2Vec queries (per-query p, q, start set, L, seed) on the skewed scale-24
+    R-MAT: one captured HIP-graph launch for all of them against one launch per query."""
+    import torch
+    import paper_2512_00705_amd as fw
+    import synth
+
+    t0 = time.time()
+    g = synth.cached("rmat24_skew")
+    log(f"graph rmat24_skew: nv={g['nv']} ne={g['ne']} max_deg={int(np.diff(g['row_ptr']).max())} "
+        f"({time.time() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(g[k]).to(dev) for k in ("row_ptr", "col", "h")}
+    gh = fw.fw_graph_create(g["nv"], g["ne"], t["row_ptr"], t["col"], t["h"], None, on_device=True)
+    del t
+    fw.fw_graph_preprocess(gh)
+    plan = fw.fw_plan_autotune(gh, fw.fw_logic_node2vec(1.0, 1.0, True))
+    qd = synth.batch_queries(g["nv"], 4096, 7)
+    starts = torch.from_numpy(qd["starts"]).to(dev)
+    paths = torch.empty((qd["total_paths"],), dtype=torch.int32, device=dev)
+    lengths = torch.empty((int(qd["n"].sum()),), dtype=torch.int32, device=dev)
+    stats = torch.zeros(fw.FW_NSTATS, dtype=torch.int64, device=dev)
+    qs, lgs = [], []
+    for i in range(4096):
+        q = fw.fw_query()
+        q.logic = fw.fw_logic_node2vec(float(qd["p"][i]), float(qd["q"][i]), True)
+        q.n, q.L, q.seed = int(qd["n"][i]), int(qd["L"][i]), int(qd["seed"][i])
+        q.start_off, q.out_off, q.len_off = int(qd["start_off"][i]), int(qd["out_off"][i]), int(qd["len_off"][i])
+        qs.append(q)
+        lgs.append(q.logic)
+    b = fw.fw_batch_create(gh, qs, plan, fw.FW_AUTO, starts, paths, lengths)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        for _ in range(args.warmup):
+            fw.fw_batch_launch(b, None, stream)
+        fw.fw_batch_capture(b, stats, stream)
+        stream.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+        for e_a, e_b in evs:
+            e_a.record(stream)
+            fw.fw_batch_replay(b, stream)
+            e_b.record(stream)
+        stream.synchronize()
+    fw.fw_graph_check(gh)
+    ms = [e_a.elapsed_time(e_b) for e_a, e_b in evs]
+    st = dict(zip(fw.STAT_NAMES, (stats.cpu().numpy() // max(args.steps, 1)).tolist()))
+    avg = float(np.mean(ms))
+    log(f"batched graph replay ms {['%.2f' % x for x in ms]}, stats {st}")
+    per_q = None
+    if args.per_query:
+        e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e_a.record()
+        for i in range(4096):
+            n, L = int(qd["n"][i]), int(qd["L"][i])
+            fw.fw_walk(gh, lgs[i], plan, fw.FW_AUTO, starts.data_ptr() + 4 * int(qd["start_off"][i]), n, L,
+                       int(qd["seed"][i]), paths.data_ptr() + 4 * int(qd["out_off"][i]),
+                       lengths.data_ptr() + 4 * int(qd["len_off"][i]), None)
+        e_b.record()
+        torch.cuda.synchronize()
+        per_q = e_a.elapsed_time(e_b)
+        log(f"one launch per query: {per_q:.2f} ms")
+    fw.fw_batch_destroy(b)
+    fw.fw_graph_destroy(gh)
+    out = {
+        "metric": "walker-steps/sec, batched node2vec queries on R-MAT scale 24 (a=0.6)",
+        "value": st["steps"] / (avg / 1e3),
+        "unit": "walker-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": avg,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"4096 node2vec queries, p,q in {{0.25,0.5,1,2,4}}, start sets log-uniform 1..65536 "
+                               f"({int(qd['n'].sum())} walkers), L in 5..200, one captured HIP-graph launch, "
+                               f"R-MAT scale 24 (0.6,0.175,0.175), {g['ne']} CSR entries",
+                   "stats": st, "rho": plan.rho, "d_lo": plan.d_lo,
+                   "per_query_launches_ms": per_q,
+                   "per_query_walker_steps_per_s": (st["steps"] / (per_q / 1e3)) if per_q else None},
+        "roofline": {"bound": "hbm", "achieved": st["alg_bytes"] / (avg / 1e3) / 1e9, "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": st["alg_bytes"] / (avg / 1e3) / 1e9 / PEAK_HBM_GBS, "traffic": None},
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

@@ -136,10 +136,19 @@ int fw_logic_metapath(const uint8_t *schema, int32_t m, int32_t weighted, fw_log
  * by the library. */
 int fw_plan_default(fw_plan *out);
 
-/* Profiling kernels of Section 5: time weight evaluation of sampled nodes with eRJS-style
- * random proposals and with eRVS-style coalesced scans on this graph and logic, and set
- * out->rho to the per-edge cost ratio; other fields start from fw_plan_default.
- * Synchronous on `stream`. */
+/* Profiling kernels of Section 5: time weight evaluation of a fixed fraction of the nodes
+ * with eRJS-style random proposals and with eRVS-style coalesced scans on this graph and
+ * logic, and set out->rho to the per-edge cost ratio EdgeCost_RJS / EdgeCost_RVS of
+ * Eq. (runtime); the other fields come from fw_plan_default.  Synchronous on `stream`;
+ * the graph must be preprocessed for a weighted logic. */
+int fw_plan_profile(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stream);
+
+/* fw_plan_profile, then a measured search: short seeded sample walks (up to 2^18 walkers,
+ * 16 steps, AUTO) are timed for rho scaled by 1/16 .. 4 around the profiled value, then for
+ * the degree gate d_lo in {0, 8, 32, 128} and the LDS budget for N(prev); the fastest plan
+ * is returned.  Every candidate samples the same distribution; only the choice of kernel
+ * per step, and so the random stream, differs.  Allocates temporary device memory;
+ * synchronous on `stream`. */
 int fw_plan_autotune(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stream);
 
 /* Run n walks of at most L steps (Section 5 runtime kernel with dynamic query
@@ -156,6 +165,48 @@ int fw_plan_autotune(fw_graph *g, const fw_logic *logic, fw_plan *out, void *str
 int fw_walk(fw_graph *g, const fw_logic *logic, const fw_plan *plan, int32_t strategy,
             const int32_t *starts, int64_t n, int32_t L, uint64_t seed, int32_t *paths,
             int32_t *lengths, uint64_t *stats, void *stream);
+
+/* One query of a batch: `n` walkers of at most L steps with the given logic and seed.
+ * Its start vertices are starts[start_off .. start_off + n), its paths occupy
+ * paths[out_off .. out_off + n*(L+1)) in the fw_walk layout and its lengths
+ * lengths[len_off .. len_off + n).  Walker i of the query uses Philox counter (i, step,
+ * draw, tag) under key `seed`, so its walk is the same as in fw_walk of that query alone. */
+typedef struct fw_query {
+    fw_logic logic;
+    int64_t n;
+    int32_t L;
+    uint64_t seed;
+    int64_t start_off;
+    int64_t out_off;
+    int64_t len_off;
+} fw_query;
+
+typedef struct fw_batch fw_batch; /* opaque: a query table resident on the device */
+
+/* Prepare a batch of nq queries (host array) over graph g for one persistent launch
+ * (Section 5 runtime kernel; dynamic scheduling over the walkers of all queries).  All
+ * queries share the logic kind and weighting (mixed kinds go in separate batches).
+ * starts, paths and lengths are device pointers owned by the caller and bound to the
+ * batch: they must stay valid, and query blocks must not overlap.  Copies the query table
+ * to the device (synchronous); does not launch.  The plan and strategy apply to all. */
+int fw_batch_create(fw_graph *g, const fw_query *queries, int64_t nq, const fw_plan *plan, int32_t strategy,
+                    const int32_t *starts, int32_t *paths, int32_t *lengths, fw_batch **out);
+
+/* Run every query of the batch in one launch on `stream` (asynchronous).  Allocates
+ * nothing and issues no memset or host synchronisation, so it can be captured into a HIP
+ * graph.  stats: device pointer to FW_NSTATS uint64 counters added to, or NULL.
+ * Launches of one batch must be ordered on one stream (they share its walker counter). */
+int fw_batch_launch(fw_batch *b, uint64_t *stats, void *stream);
+
+/* Capture fw_batch_launch(b, stats, stream) into a HIP graph held by the batch (replacing
+ * an earlier capture); `stream` must be a created, non-null stream.  Nothing runs. */
+int fw_batch_capture(fw_batch *b, uint64_t *stats, void *stream);
+
+/* Launch the captured graph on `stream` (asynchronous).  FW_E_STATE without a capture. */
+int fw_batch_replay(fw_batch *b, void *stream);
+
+/* Free the batch and its graph.  NULL is accepted; its launches must have finished. */
+int fw_batch_destroy(fw_batch *b);
 
 /* Wait for `stream`, then report and clear the graph's device error flag: FW_OK, or
  * FW_E_INVALID if a walk since the last check met an out-of-range start vertex. */

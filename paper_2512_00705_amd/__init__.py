@@ -26,7 +26,8 @@ STAT_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", 
               "ended_early", "alg_bytes")
 EXPORTED = ("fw_graph_create", "fw_graph_destroy", "fw_graph_preprocess", "fw_graph_export_aux",
             "fw_graph_info", "fw_logic_node2vec", "fw_logic_metapath", "fw_plan_default",
-            "fw_plan_autotune", "fw_walk", "fw_graph_check", "fw_last_error")
+            "fw_plan_profile", "fw_plan_autotune", "fw_walk", "fw_graph_check", "fw_last_error",
+            "fw_batch_create", "fw_batch_launch", "fw_batch_capture", "fw_batch_replay", "fw_batch_destroy")
 
 
 class FlexiWalkError(RuntimeError):
@@ -53,6 +54,11 @@ class fw_plan(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 2)]
 
 
+class fw_query(ctypes.Structure):
+    _fields_ = [("logic", fw_logic), ("n", ctypes.c_int64), ("L", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("start_off", ctypes.c_int64), ("out_off", ctypes.c_int64), ("len_off", ctypes.c_int64)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2512_00705_amd._build` "
@@ -68,10 +74,17 @@ def _load():
         "fw_logic_node2vec": ([ctypes.c_float, ctypes.c_float, I32, ctypes.POINTER(fw_logic)], ctypes.c_int),
         "fw_logic_metapath": ([P, I32, I32, ctypes.POINTER(fw_logic)], ctypes.c_int),
         "fw_plan_default": ([ctypes.POINTER(fw_plan)], ctypes.c_int),
+        "fw_plan_profile": ([P, ctypes.POINTER(fw_logic), ctypes.POINTER(fw_plan), P], ctypes.c_int),
         "fw_plan_autotune": ([P, ctypes.POINTER(fw_logic), ctypes.POINTER(fw_plan), P], ctypes.c_int),
         "fw_walk": ([P, ctypes.POINTER(fw_logic), ctypes.POINTER(fw_plan), I32, P, I64, I32, ctypes.c_uint64,
                      P, P, P, P], ctypes.c_int),
         "fw_graph_check": ([P, P], ctypes.c_int),
+        "fw_batch_create": ([P, ctypes.POINTER(fw_query), I64, ctypes.POINTER(fw_plan), I32, P, P, P,
+                             ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+        "fw_batch_launch": ([P, P, P], ctypes.c_int),
+        "fw_batch_capture": ([P, P, P], ctypes.c_int),
+        "fw_batch_replay": ([P, P], ctypes.c_int),
+        "fw_batch_destroy": ([P], ctypes.c_int),
         "fw_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -162,6 +175,12 @@ def fw_plan_default(**overrides) -> fw_plan:
     return out
 
 
+def fw_plan_profile(g: int, logic: fw_logic, stream=None) -> fw_plan:
+    out = fw_plan()
+    _check(_lib.fw_plan_profile(g, ctypes.byref(logic), ctypes.byref(out), _stream(stream)))
+    return out
+
+
 def fw_plan_autotune(g: int, logic: fw_logic, stream=None) -> fw_plan:
     out = fw_plan()
     _check(_lib.fw_plan_autotune(g, ctypes.byref(logic), ctypes.byref(out), _stream(stream)))
@@ -177,3 +196,28 @@ def fw_walk(g: int, logic: fw_logic, plan: fw_plan, strategy: int, starts, n: in
 
 def fw_graph_check(g: int, stream=None):
     _check(_lib.fw_graph_check(g, _stream(stream)))
+
+
+def fw_batch_create(g: int, queries, plan: fw_plan, strategy: int, starts, paths, lengths) -> int:
+    """queries: a sequence of fw_query.  Returns an opaque batch handle (int)."""
+    arr = (fw_query * max(len(queries), 1))(*queries)
+    out = ctypes.c_void_p()
+    _check(_lib.fw_batch_create(g, arr, len(queries), ctypes.byref(plan), strategy, _ptr(starts), _ptr(paths),
+                                _ptr(lengths), ctypes.byref(out)))
+    return out.value
+
+
+def fw_batch_launch(b: int, stats=None, stream=None):
+    _check(_lib.fw_batch_launch(b, _ptr(stats), _stream(stream)))
+
+
+def fw_batch_capture(b: int, stats=None, stream=None):
+    _check(_lib.fw_batch_capture(b, _ptr(stats), _stream(stream)))
+
+
+def fw_batch_replay(b: int, stream=None):
+    _check(_lib.fw_batch_replay(b, _stream(stream)))
+
+
+def fw_batch_destroy(b: int):
+    _check(_lib.fw_batch_destroy(b))

@@ -250,7 +250,27 @@ static int check_logic(const fw_graph *g, const fw_logic *lg)
     return FW_OK;
 }
 
-// Float constants of a launch, computed in float32 exactly as the definition states.
+// Per-query float constants, computed in float32 exactly as the definition states.
+static void fill_query(const fw_logic *lg, fw::QueryDev &q)
+{
+    memset(&q, 0, sizeof(q));
+    if (lg->kind == FW_NODE2VEC) {
+        q.inv_p = 1.0f / lg->p;
+        q.inv_q = 1.0f / lg->q;
+        q.lo_w = fminf(1.0f, q.inv_q);
+        q.hi_w = fmaxf(1.0f, q.inv_q);
+        q.wmax0 = 1.0f;
+        q.wavg0 = 1.0f;
+        q.wmax1 = fmaxf(fmaxf(q.inv_p, 1.0f), q.inv_q);      // max over the three return values
+        q.wavg1 = ((q.inv_p + 1.0f) + q.inv_q) / 3.0f;       // their mean (Section 4.2)
+    } else {
+        q.wmax0 = q.wmax1 = 1.0f;
+        q.wavg0 = q.wavg1 = (1.0f + 0.0f) / 2.0f;
+        q.schema_len = lg->schema_len;
+        memcpy(q.schema, lg->schema, (size_t)lg->schema_len);
+    }
+}
+
 static void fill_args(const fw_graph *g, const fw_logic *lg, fw::WalkArgs &a)
 {
     memset(&a, 0, sizeof(a));
@@ -260,23 +280,29 @@ static void fill_args(const fw_graph *g, const fw_logic *lg, fw::WalkArgs &a)
     a.col = g->col;
     a.label = g->label;
     a.nv = g->nv;
-    if (lg->kind == FW_NODE2VEC) {
-        a.inv_p = 1.0f / lg->p;
-        a.inv_q = 1.0f / lg->q;
-        a.lo_w = fminf(1.0f, a.inv_q);
-        a.hi_w = fmaxf(1.0f, a.inv_q);
-        a.wmax0 = 1.0f;
-        a.wavg0 = 1.0f;
-        a.wmax1 = fmaxf(fmaxf(a.inv_p, 1.0f), a.inv_q);      // max over the three return values
-        a.wavg1 = ((a.inv_p + 1.0f) + a.inv_q) / 3.0f;       // their mean (Section 4.2)
-    } else {
-        a.wmax0 = a.wmax1 = 1.0f;
-        a.wavg0 = a.wavg1 = (1.0f + 0.0f) / 2.0f;
-        a.schema_len = lg->schema_len;
-        memcpy(a.schema, lg->schema, (size_t)lg->schema_len);
-    }
+    fill_query(lg, a.q0);
     const bool weighted = lg->weighted && g->h;
     a.item_bytes = 4 + (weighted ? 4 : 0) + (lg->kind == FW_METAPATH ? 1 : 0);
+}
+
+static int check_plan(const fw_plan *pl)
+{
+    if (pl->lanes != 64) return fail(FW_E_INVALID, "plan.lanes must be 64");
+    if (pl->rjs_cap < 1) return fail(FW_E_INVALID, "plan.rjs_cap must be >= 1");
+    if (!(pl->rho > 0.0f) || isinf(pl->rho)) return fail(FW_E_INVALID, "plan.rho must be finite and > 0");
+    if (pl->d_lo < 0) return fail(FW_E_INVALID, "plan.d_lo must be >= 0");
+    if (pl->lds_cap < 0 || pl->lds_cap > 16384) return fail(FW_E_INVALID, "plan.lds_cap in [0, 16384]");
+    if (pl->grid < 0) return fail(FW_E_INVALID, "plan.grid must be >= 0");
+    return FW_OK;
+}
+
+static void plan_args(const fw_plan *pl, int32_t strategy, fw::WalkArgs &a)
+{
+    a.rho = pl->rho;
+    a.d_lo = pl->d_lo;
+    a.rjs_cap = pl->rjs_cap;
+    a.strategy = strategy;
+    a.lds_cap = pl->lds_cap;
 }
 
 int fw_walk(fw_graph *g, const fw_logic *lg, const fw_plan *pl, int32_t strategy, const int32_t *starts, int64_t n,
@@ -289,12 +315,7 @@ int fw_walk(fw_graph *g, const fw_logic *lg, const fw_plan *pl, int32_t strategy
     if (n > 0 && (!starts || !paths || !lengths)) return fail(FW_E_INVALID, "fw_walk: null starts/paths/lengths");
     int rc = check_logic(g, lg);
     if (rc != FW_OK) return rc;
-    if (pl->lanes != 64) return fail(FW_E_INVALID, "fw_walk: plan.lanes must be 64");
-    if (pl->rjs_cap < 1) return fail(FW_E_INVALID, "fw_walk: plan.rjs_cap must be >= 1");
-    if (!(pl->rho > 0.0f) || isinf(pl->rho)) return fail(FW_E_INVALID, "fw_walk: plan.rho must be finite and > 0");
-    if (pl->d_lo < 0) return fail(FW_E_INVALID, "fw_walk: plan.d_lo must be >= 0");
-    if (pl->lds_cap < 0 || pl->lds_cap > 16384) return fail(FW_E_INVALID, "fw_walk: plan.lds_cap in [0, 16384]");
-    if (pl->grid < 0) return fail(FW_E_INVALID, "fw_walk: plan.grid must be >= 0");
+    if ((rc = check_plan(pl)) != FW_OK) return rc;
     const bool weighted = lg->weighted && g->h;
     if (weighted && strategy != FW_RVS_ONLY && !g->prepped)
         return fail(FW_E_STATE, "fw_walk: call fw_graph_preprocess before a weighted eRJS/AUTO walk");
@@ -303,25 +324,24 @@ int fw_walk(fw_graph *g, const fw_logic *lg, const fw_plan *pl, int32_t strategy
     HIP_TRY(hipSetDevice(g->device));
     fw::WalkArgs a;
     fill_args(g, lg, a);
-    a.starts = starts;
+    plan_args(pl, strategy, a);
     a.n = n;
-    a.L = L;
-    a.paths = paths;
-    a.lengths = lengths;
     a.stats = (unsigned long long *)stats;
     a.queue = g->scratch;
     a.err = (int *)(g->scratch + 1);
-    a.key0 = (uint32_t)seed;
-    a.key1 = (uint32_t)(seed >> 32);
-    a.rho = pl->rho;
-    a.d_lo = pl->d_lo;
-    a.rjs_cap = pl->rjs_cap;
-    a.strategy = strategy;
-    a.lds_cap = pl->lds_cap;
-    const int grid = pl->grid > 0 ? pl->grid : fw::walk_grid(lg->kind, weighted, a.lds_cap, n);
+    a.q0.first = 0;
+    a.q0.n = n;
+    a.q0.starts = starts;
+    a.q0.paths = paths;
+    a.q0.lengths = lengths;
+    a.q0.L = L;
+    a.q0.key0 = (uint32_t)seed;
+    a.q0.key1 = (uint32_t)(seed >> 32);
+    a.nq = 1;
+    const int grid = pl->grid > 0 ? pl->grid : fw::walk_grid(lg->kind, weighted, false, a.lds_cap, n);
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(fw::launch_zero(g->scratch, 1, s));
-    HIP_TRY(fw::launch_walk(a, lg->kind, weighted, grid, s));
+    HIP_TRY(fw::launch_walk(a, lg->kind, weighted, false, grid, s));
     return ok();
 }
 
@@ -339,14 +359,29 @@ int fw_graph_check(fw_graph *g, void *stream)
     return ok();
 }
 
-int fw_plan_autotune(fw_graph *g, const fw_logic *lg, fw_plan *out, void *stream)
+// Device buffer released on scope exit.
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() { (void)hipFree(p); }
+};
+
+struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~Events()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+int fw_plan_profile(fw_graph *g, const fw_logic *lg, fw_plan *out, void *stream)
 {
-    if (!g || !lg || !out) return fail(FW_E_INVALID, "fw_plan_autotune: null argument");
+    if (!g || !lg || !out) return fail(FW_E_INVALID, "fw_plan_profile: null argument");
     int rc = check_logic(g, lg);
     if (rc != FW_OK) return rc;
     fw_plan_default(out);
     const bool weighted = lg->weighted && g->h;
-    if (weighted && !g->prepped) return fail(FW_E_STATE, "fw_plan_autotune: graph not preprocessed");
+    if (weighted && !g->prepped) return fail(FW_E_STATE, "fw_plan_profile: graph not preprocessed");
     HIP_TRY(hipSetDevice(g->device));
     hipStream_t s = (hipStream_t)stream;
 
@@ -371,36 +406,243 @@ int fw_plan_autotune(fw_graph *g, const fw_logic *lg, fw_plan *out, void *stream
 
     fw::WalkArgs a;
     fill_args(g, lg, a);
-    a.key0 = 0x5eed;
-    int32_t *d_nodes = nullptr;
-    float *d_sink = nullptr;
-    HIP_TRY(hipMalloc((void **)&d_nodes, sizeof(int32_t) * nodes.size()));
-    HIP_TRY(hipMalloc((void **)&d_sink, sizeof(float)));
-    HIP_TRY(hipMemcpy(d_nodes, nodes.data(), sizeof(int32_t) * nodes.size(), hipMemcpyHostToDevice));
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
+    a.q0.key0 = 0x5eed;
+    DevBuf d_nodes, d_sink;
+    HIP_TRY(hipMalloc(&d_nodes.p, sizeof(int32_t) * nodes.size()));
+    HIP_TRY(hipMalloc(&d_sink.p, sizeof(float)));
+    HIP_TRY(hipMemcpy(d_nodes.p, nodes.data(), sizeof(int32_t) * nodes.size(), hipMemcpyHostToDevice));
+    Events ev;
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
     float best[2] = {1e30f, 1e30f};
     for (int style = 0; style < 2; ++style) {
         for (int rep = 0; rep < 4; ++rep) {
-            HIP_TRY(hipEventRecord(e0, s));
-            HIP_TRY(fw::launch_profile(a, lg->kind, weighted, style == 1, d_nodes, (int)nodes.size(),
-                                       style == 1 ? per_rjs : per_rvs, d_sink, s));
-            HIP_TRY(hipEventRecord(e1, s));
-            HIP_TRY(hipEventSynchronize(e1));
+            HIP_TRY(hipEventRecord(ev.a, s));
+            HIP_TRY(fw::launch_profile(a, lg->kind, weighted, style == 1, (const int32_t *)d_nodes.p,
+                                       (int)nodes.size(), style == 1 ? per_rjs : per_rvs, (float *)d_sink.p, s));
+            HIP_TRY(hipEventRecord(ev.b, s));
+            HIP_TRY(hipEventSynchronize(ev.b));
             float ms = 0;
-            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
             if (rep > 0) best[style] = std::min(best[style], ms);
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipFree(d_nodes);
-    (void)hipFree(d_sink);
     const double per_rvs_edge = best[0] / e_rvs, per_rjs_edge = best[1] / e_rjs;
     double rho = per_rjs_edge / per_rvs_edge;
     if (!(rho > 0.0)) rho = 8.0;
     out->rho = (float)std::min(1000.0, std::max(0.25, rho));
+    return ok();
+}
+
+int fw_plan_autotune(fw_graph *g, const fw_logic *lg, fw_plan *out, void *stream)
+{
+    int rc = fw_plan_profile(g, lg, out, stream);
+    if (rc != FW_OK) return rc;
+    if (g->nv == 0 || g->ne == 0) return ok();
+    hipStream_t s = (hipStream_t)stream;
+
+    // sample walks: seeded walkers spread over all vertices, as many as fill the device a
+    // few times, long enough for the walk's degree bias to set in
+    const int64_t n = std::min<int64_t>(g->nv, 1 << 18);
+    const int32_t L = 16;
+    std::vector<int32_t> starts((size_t)n);
+    uint64_t x = 0x9E3779B97F4A7C15ull;
+    for (int64_t i = 0; i < n; ++i) {
+        x ^= x << 13;
+        x ^= x >> 7;
+        x ^= x << 17;
+        starts[(size_t)i] = (int32_t)(x % (uint64_t)g->nv);
+    }
+    DevBuf d_starts, d_paths, d_len;
+    HIP_TRY(hipMalloc(&d_starts.p, sizeof(int32_t) * (size_t)n));
+    HIP_TRY(hipMalloc(&d_paths.p, sizeof(int32_t) * (size_t)n * (L + 1)));
+    HIP_TRY(hipMalloc(&d_len.p, sizeof(int32_t) * (size_t)n));
+    HIP_TRY(hipMemcpy(d_starts.p, starts.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
+    Events ev;
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    auto time_plan = [&](const fw_plan &p, float *ms) -> int {
+        float best = 1e30f;
+        for (int rep = 0; rep < 2; ++rep) {
+            HIP_TRY(hipEventRecord(ev.a, s));
+            int r = fw_walk(g, lg, &p, FW_AUTO, (const int32_t *)d_starts.p, n, L, 7, (int32_t *)d_paths.p,
+                            (int32_t *)d_len.p, nullptr, stream);
+            if (r != FW_OK) return r;
+            HIP_TRY(hipEventRecord(ev.b, s));
+            HIP_TRY(hipEventSynchronize(ev.b));
+            float t = 0;
+            HIP_TRY(hipEventElapsedTime(&t, ev.a, ev.b));
+            best = std::min(best, t);
+        }
+        *ms = best;
+        return FW_OK;
+    };
+    // cost-model constant around the profiled value, then the degree gate, then the LDS
+    // budget for N(prev)
+    fw_plan bestp = *out;
+    float bestt = 1e30f;
+    const float rho0 = out->rho;
+    const float scales[] = {0.0625f, 0.25f, 0.5f, 1.0f, 2.0f, 4.0f};
+    for (float sc : scales) {
+        fw_plan p = *out;
+        p.rho = std::max(1e-3f, rho0 * sc);
+        float t;
+        if ((rc = time_plan(p, &t)) != FW_OK) return rc;
+        if (t < bestt) bestt = t, bestp = p;
+    }
+    for (int32_t d : {8, 32, 128}) {
+        fw_plan p = bestp;
+        p.d_lo = d;
+        float t;
+        if ((rc = time_plan(p, &t)) != FW_OK) return rc;
+        if (t < bestt) bestt = t, bestp = p;
+    }
+    for (int32_t cap : {1024, 4096}) {
+        fw_plan p = bestp;
+        p.lds_cap = cap;
+        float t;
+        if ((rc = time_plan(p, &t)) != FW_OK) return rc;
+        if (t < bestt) bestt = t, bestp = p;
+    }
+    *out = bestp;
+    return ok();
+}
+
+struct fw_batch {
+    fw_graph *g = nullptr;
+    fw::WalkArgs a;
+    int kind = 0;
+    bool weighted = false;
+    int grid = 1;
+    fw::QueryDev *d_queries = nullptr;
+    unsigned long long *d_queue = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static void batch_free(fw_batch *b)
+{
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    (void)hipFree(b->d_queries);
+    (void)hipFree(b->d_queue);
+    delete b;
+}
+
+int fw_batch_create(fw_graph *g, const fw_query *qs, int64_t nq, const fw_plan *pl, int32_t strategy,
+                    const int32_t *starts, int32_t *paths, int32_t *lengths, fw_batch **out)
+{
+    if (!g || !pl || !out || (nq > 0 && !qs)) return fail(FW_E_INVALID, "fw_batch_create: null argument");
+    if (nq < 0 || nq >= ((int64_t)1 << 31)) return fail(FW_E_INVALID, "fw_batch_create: nq must be in [0, 2^31)");
+    if (strategy < FW_AUTO || strategy > FW_RJS_ONLY)
+        return fail(FW_E_INVALID, "fw_batch_create: bad strategy %d", strategy);
+    int rc = check_plan(pl);
+    if (rc != FW_OK) return rc;
+    std::vector<fw::QueryDev> tab((size_t)(nq > 0 ? nq : 1));
+    int64_t total = 0;
+    for (int64_t i = 0; i < nq; ++i) {
+        const fw_query &q = qs[i];
+        if ((rc = check_logic(g, &q.logic)) != FW_OK) return rc;
+        if (q.logic.kind != qs[0].logic.kind || (q.logic.weighted != 0) != (qs[0].logic.weighted != 0))
+            return fail(FW_E_INVALID, "fw_batch_create: all queries of a batch share kind and weighting");
+        if (q.n < 0 || q.n >= ((int64_t)1 << 31)) return fail(FW_E_INVALID, "query %lld: n out of range", (long long)i);
+        if (q.L < 0 || q.L >= (1 << 20)) return fail(FW_E_INVALID, "query %lld: L out of range", (long long)i);
+        if (q.start_off < 0 || q.out_off < 0 || q.len_off < 0)
+            return fail(FW_E_INVALID, "query %lld: negative offset", (long long)i);
+        if (q.n > 0 && (!starts || !paths || !lengths))
+            return fail(FW_E_INVALID, "fw_batch_create: null starts/paths/lengths");
+        fw::QueryDev &d = tab[(size_t)i];
+        fill_query(&q.logic, d);
+        d.first = total;
+        d.n = q.n;
+        d.starts = starts ? starts + q.start_off : nullptr;
+        d.paths = paths ? paths + q.out_off : nullptr;
+        d.lengths = lengths ? lengths + q.len_off : nullptr;
+        d.L = q.L;
+        d.key0 = (uint32_t)q.seed;
+        d.key1 = (uint32_t)(q.seed >> 32);
+        total += q.n;
+    }
+    const bool weighted = nq > 0 && qs[0].logic.weighted && g->h;
+    if (weighted && strategy != FW_RVS_ONLY && !g->prepped)
+        return fail(FW_E_STATE, "fw_batch_create: call fw_graph_preprocess before a weighted eRJS/AUTO batch");
+    HIP_TRY(hipSetDevice(g->device));
+    fw_batch *b = new fw_batch();
+    b->g = g;
+    if (hipMalloc((void **)&b->d_queries, sizeof(fw::QueryDev) * tab.size()) != hipSuccess ||
+        hipMalloc((void **)&b->d_queue, sizeof(unsigned long long)) != hipSuccess) {
+        batch_free(b);
+        return fail(FW_E_NOMEM, "fw_batch_create: hipMalloc failed");
+    }
+    if (hipMemcpy(b->d_queries, tab.data(), sizeof(fw::QueryDev) * tab.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        batch_free(b);
+        return fail(FW_E_DEVICE, "fw_batch_create: hipMemcpy failed");
+    }
+    if (nq > 0) fill_args(g, &qs[0].logic, b->a);
+    else memset(&b->a, 0, sizeof(b->a));
+    plan_args(pl, strategy, b->a);
+    b->a.n = total;
+    b->a.queue = b->d_queue;
+    b->a.err = (int *)(g->scratch + 1);
+    b->a.queries = b->d_queries;
+    b->a.nq = (int32_t)nq;
+    b->kind = nq > 0 ? qs[0].logic.kind : FW_NODE2VEC;
+    b->weighted = weighted;
+    b->grid = pl->grid > 0 ? pl->grid : fw::walk_grid(b->kind, weighted, true, pl->lds_cap, total);
+    *out = b;
+    return ok();
+}
+
+int fw_batch_launch(fw_batch *b, uint64_t *stats, void *stream)
+{
+    if (!b) return fail(FW_E_INVALID, "fw_batch_launch: null batch");
+    if (b->a.n == 0) return ok();
+    fw::WalkArgs a = b->a;
+    a.stats = (unsigned long long *)stats;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(fw::launch_zero(b->d_queue, 1, s));
+    HIP_TRY(fw::launch_walk(a, b->kind, b->weighted, true, b->grid, s));
+    return ok();
+}
+
+int fw_batch_capture(fw_batch *b, uint64_t *stats, void *stream)
+{
+    if (!b) return fail(FW_E_INVALID, "fw_batch_capture: null batch");
+    if (!stream) return fail(FW_E_INVALID, "fw_batch_capture: needs a non-null stream");
+    hipStream_t s = (hipStream_t)stream;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const int rc = fw_batch_launch(b, stats, stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc != FW_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(FW_E_DEVICE, "fw_batch_capture: %s", hipGetErrorString(e));
+    b->graph = graph;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return ok();
+}
+
+int fw_batch_replay(fw_batch *b, void *stream)
+{
+    if (!b || !b->exec) return fail(FW_E_STATE, "fw_batch_replay: no captured graph");
+    HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+    return ok();
+}
+
+int fw_batch_destroy(fw_batch *b)
+{
+    batch_free(b);
     return ok();
 }
 

@@ -29,8 +29,26 @@ constexpr int kDefaultLdsCap = 2048; // int32 entries of N(prev) per wavefront
 #endif
 constexpr int kRjsBatch = FW_RJS_BATCH; // eRJS proposals whose loads a lane issues together
 
-// Everything a walk launch reads.  Float constants are prepared on the host in float32
-// so that the device and every other float32 evaluation agree bit for bit.
+// Per-query constants of a walk job.  Float constants are prepared on the host in float32
+// exactly as the definition states, so every float32 evaluation agrees bit for bit.
+// A single-query launch carries one of these in its kernel arguments; a batched launch
+// reads them from a device table indexed by query.
+struct QueryDev {
+    int64_t first;              // first flattened walker index of the query
+    int64_t n;                  // walkers
+    const int32_t *starts;      // n start vertices
+    int32_t *paths;             // n * (L + 1) path slots
+    int32_t *lengths;           // n lengths
+    uint32_t key0, key1;        // Philox key = the query's seed
+    float inv_p, inv_q;         // 1/p, 1/q
+    float lo_w, hi_w;           // min(1, 1/q), max(1, 1/q)
+    float wmax0, wavg0;         // max and mean workload weight at step 0
+    float wmax1, wavg1;         // ... at steps >= 1
+    int32_t L;
+    int32_t schema_len;
+    uint8_t schema[64];
+};
+
 // Device layout of a graph.  Besides the caller's CSR the library keeps
 //   edges[k] = {col[k], bits(h[k])}: one 8-byte load per proposed or scanned edge;
 //   vrec[v]  = {low 32 bits of row start, degree, bits(h_MAX[v]), bits(h_SUM[v])}:
@@ -45,31 +63,23 @@ struct WalkArgs {
     const uint8_t *label;
     int64_t nv;
 
-    const int32_t *starts;
-    int64_t n;
-    int32_t L;
-    int32_t *paths;
-    int32_t *lengths;
+    int64_t n;                  // walkers in the launch (all queries)
     unsigned long long *stats;  // may be null
     unsigned long long *queue;  // next walker to hand out
     int *err;                   // set to 1 on an out-of-range start
-
-    uint32_t key0, key1;        // Philox key = seed
-    float inv_p, inv_q;         // 1/p, 1/q
-    float lo_w, hi_w;           // min(1, 1/q), max(1, 1/q)
-    float wmax0, wavg0;         // max and mean workload weight at step 0
-    float wmax1, wavg1;         // ... at steps >= 1
     float rho;
     int32_t d_lo;
     int32_t rjs_cap;
     int32_t strategy;
     int32_t lds_cap;
-    int32_t schema_len;
-    uint8_t schema[64];
     int32_t item_bytes;         // col (+ h) (+ label) per scanned or proposed edge
+
+    QueryDev q0;                // the query of a single-query launch
+    const QueryDev *queries;    // batched launch: nq entries, ascending `first`
+    int32_t nq;
 };
 
-hipError_t launch_walk(const WalkArgs &a, int kind, bool weighted, int grid, hipStream_t s);
+hipError_t launch_walk(const WalkArgs &a, int kind, bool weighted, bool batch, int grid, hipStream_t s);
 hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_layout(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int64_t ne,
                          uint2 *edges, uint4 *vrec, uint32_t *start_hi, hipStream_t s);
@@ -79,6 +89,6 @@ hipError_t launch_validate_edges(const int64_t *row_ptr, const int32_t *col, con
                                  int *err, unsigned long long *max_deg, hipStream_t s);
 hipError_t launch_profile(const WalkArgs &a, int kind, bool weighted, bool rjs_style, const int32_t *nodes,
                           int nsample, int per_node, float *sink, hipStream_t s);
-int walk_grid(int kind, bool weighted, int lds_cap, int64_t n);
+int walk_grid(int kind, bool weighted, bool batch, int lds_cap, int64_t n);
 
 }  // namespace fw

@@ -22,8 +22,6 @@ namespace fw {
 
 enum Mode : int { kIdle = 0, kSetup = 1, kRjs = 2, kRvs = 3, kAdv = 4 };
 
-// Transition weight w~ = w * h of the edge at CSR position k with neighbour u at step j
-// (Section 2.1, Eq. prob; Eq. node2vec; MetaPath rule).  `mem` holds N(prev) sorted.
 // N(prev) for the membership test: a copy in this wave's LDS or the row of prev in col,
 // read through one flat pointer either way.
 struct Mem {
@@ -31,16 +29,38 @@ struct Mem {
     int64_t len;
 };
 
+// The constants of query q: a device table for batched launches, the kernel argument
+// block otherwise.
+template <bool BATCH>
+__device__ __forceinline__ const QueryDev &query(const WalkArgs &a, int32_t q)
+{
+    return BATCH ? a.queries[q] : a.q0;
+}
+
+// Query holding flattened walker w: the last one whose first walker is <= w.
+__device__ __forceinline__ int32_t query_of(const WalkArgs &a, int64_t w)
+{
+    int32_t lo = 0, hi = a.nq - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (a.queries[mid].first <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Transition weight w~ = w * h of the edge at CSR position k (record e) at step j
+// (Section 2.1, Eq. prob; Eq. node2vec; MetaPath rule).  `m` holds N(prev) sorted.
 template <int KIND, bool W>
-__device__ __forceinline__ float edge_weight(const WalkArgs &a, int64_t k, uint2 e, int j, int32_t prev,
-                                             const Mem &m, uint8_t want)
+__device__ __forceinline__ float edge_weight(const WalkArgs &a, const QueryDev &Q, int64_t k, uint2 e, int j,
+                                             int32_t prev, const Mem &m, uint8_t want)
 {
     const float hv = W ? __uint_as_float(e.y) : 1.0f;
     if (KIND == kNode2Vec) {
         if (j == 0) return hv;
         const int32_t u = (int32_t)e.x;
-        if (u == prev) return a.inv_p * hv;
-        return sorted_contains_interp(m.p, m.len, u, a.nv) ? hv : a.inv_q * hv;
+        if (u == prev) return Q.inv_p * hv;
+        return sorted_contains_interp(m.p, m.len, u, a.nv) ? hv : Q.inv_q * hv;
     } else {
         return a.label[k] == want ? hv : 0.0f;
     }
@@ -54,18 +74,20 @@ __device__ __forceinline__ int64_t row_start(const WalkArgs &a, uint4 r, int32_t
 // eRVS for one step, all 64 lanes cooperating.  Returns the next vertex or -1 when no
 // neighbour has positive weight.  `trig` receives the number of jump events.
 template <int KIND, bool W>
-__device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const Mem &mem, uint32_t wid, int j, int32_t prev,
-                                            int64_t base, int64_t deg, uint8_t want, uint32_t &trig)
+__device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q, const Mem &mem, uint32_t wid,
+                                            int j, int32_t prev, int64_t base, int64_t deg, uint8_t want,
+                                            uint32_t &trig)
 {
     const int lane = lane_id();
+    const uint32_t k0 = Q.key0, k1 = Q.key1;
     float key = -INFINITY;
     int32_t bi = -1;
     float ru = 0.5f;
     // round 0: lane l keys neighbour l, k = u^(1/w~) kept as log(u) / w~
     if (lane < deg) {
         const int64_t k = base + lane;
-        const float wt = edge_weight<KIND, W>(a, k, a.edges[k], j, prev, mem, want);
-        const U4 x = philox(wid, (uint32_t)j, (uint32_t)lane, 1u, a.key0, a.key1);
+        const float wt = edge_weight<KIND, W>(a, Q, k, a.edges[k], j, prev, mem, want);
+        const U4 x = philox(wid, (uint32_t)j, (uint32_t)lane, 1u, k0, k1);
         key = wt > 0.0f ? ln_f(unit_uniform(x.x0)) / wt : -INFINITY;
         ru = unit_uniform(x.x1);
         bi = lane;
@@ -81,11 +103,11 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const Mem &mem, u
         const int64_t i = i0 + lane;
         if (i < deg) {
             const int64_t k = base + i;
-            const float wt = edge_weight<KIND, W>(a, k, a.edges[k], j, prev, mem, want);
+            const float wt = edge_weight<KIND, W>(a, Q, k, a.edges[k], j, prev, mem, want);
             S = S + wt;
             if (S > T) {
                 // key conditioned to beat thr: log u' = log1p(expm1(w~ * thr) * V)
-                const U4 x = philox(wid, (uint32_t)j, (uint32_t)i, 1u, a.key0, a.key1);
+                const U4 x = philox(wid, (uint32_t)j, (uint32_t)i, 1u, k0, k1);
                 const float av = wt * thr;
                 const float m1 = expm1_f(av);
                 const float z = m1 * unit_uniform(x.x0);
@@ -109,10 +131,10 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const Mem &mem, u
 // there is nothing to scan), so the result equals the one-wave eRVS bit for bit.
 // Takes its steps from `pool` (lanes in trial order of the ballot) and returns true
 // for the lanes that were served, with the next vertex (or -1) in `res`.
-template <int KIND, bool W>
-__device__ __forceinline__ bool rvs_group_pass(const WalkArgs &a, int G, uint64_t &pool, int32_t wid, int32_t j,
-                                               int32_t prev, int64_t base, int32_t deg, int64_t pbase, int32_t pdeg,
-                                               int32_t &res)
+template <int KIND, bool W, bool BATCH>
+__device__ __forceinline__ bool rvs_group_pass(const WalkArgs &a, int G, uint64_t &pool, int32_t q, int32_t wid,
+                                               int32_t j, int32_t prev, int64_t base, int32_t deg, int64_t pbase,
+                                               int32_t pdeg, int32_t &res)
 {
     const int lane = lane_id();
     const int g = lane / G, r = lane % G;
@@ -129,6 +151,7 @@ __device__ __forceinline__ bool rvs_group_pass(const WalkArgs &a, int G, uint64_
     // every lane takes part in every shuffle: a step's owner may sit in a group that
     // serves nothing this pass, and a lane reading from an inactive lane gets garbage
     const int sl = src_of_group < 0 ? lane : src_of_group;
+    const int32_t s_q = BATCH ? __shfl(q, sl, kWave) : 0;
     const uint32_t s_wid = (uint32_t)__shfl(wid, sl, kWave);
     const int32_t s_j = __shfl(j, sl, kWave);
     const int32_t s_prev = __shfl(prev, sl, kWave);
@@ -140,11 +163,12 @@ __device__ __forceinline__ bool rvs_group_pass(const WalkArgs &a, int G, uint64_
     float key = -INFINITY;
     int32_t bi = -1;
     if (r < s_deg) {
+        const QueryDev &Q = query<BATCH>(a, s_q);
         const int64_t k = s_base + r;
-        const uint8_t want = (KIND == kMetaPath) ? a.schema[s_j % a.schema_len] : (uint8_t)0;
+        const uint8_t want = (KIND == kMetaPath) ? Q.schema[s_j % Q.schema_len] : (uint8_t)0;
         const Mem m = {a.col + s_pbase, s_pdeg};
-        const float wt = edge_weight<KIND, W>(a, k, a.edges[k], s_j, s_prev, m, want);
-        const U4 x = philox(s_wid, (uint32_t)s_j, (uint32_t)r, 1u, a.key0, a.key1);
+        const float wt = edge_weight<KIND, W>(a, Q, k, a.edges[k], s_j, s_prev, m, want);
+        const U4 x = philox(s_wid, (uint32_t)s_j, (uint32_t)r, 1u, Q.key0, Q.key1);
         key = wt > 0.0f ? ln_f(unit_uniform(x.x0)) / wt : -INFINITY;
         bi = r;
     }
@@ -177,17 +201,20 @@ __device__ __forceinline__ void flush_stats(const WalkArgs &a, uint32_t (&cnt)[k
     bytes = 0;
 }
 
-template <int KIND, bool W>
+// BATCH: walkers of many queries (each with its own logic constants, length, seed,
+// starts and outputs) share one launch; walker i of a query draws from that query's
+// seed with counter (i, step, draw, tag), exactly as in a launch of its own.
+template <int KIND, bool W, bool BATCH>
 __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
 {
     extern __shared__ int32_t lds_all[];
     int32_t *lds = lds_all + (threadIdx.x / kWave) * a.lds_cap;
     const int lane = lane_id();
     const uint64_t below = lanes_below(lane);
-    const int64_t row_len = (int64_t)a.L + 1;
 
     int mode = kIdle;
-    int32_t wid = -1;  // walker index (n < 2^31)
+    int32_t q = 0;     // query of the lane's walker
+    int32_t wid = -1;  // walker index within its query (n < 2^31)
     int32_t cur = 0, prev = -1, j = 0, nxt = -1;
     int64_t base = 0, pbase = 0;
     int32_t deg = 0, pdeg = 0;  // degrees (nv < 2^31)
@@ -217,16 +244,20 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
             if (mode == kIdle) {
                 const int64_t w = (int64_t)first + __popcll(idle & below);
                 if (w < a.n) {
-                    const int32_t s = a.starts[w];
-                    int32_t *row = a.paths + w * row_len;
+                    const int32_t wq = BATCH ? query_of(a, w) : 0;
+                    const QueryDev &Q = query<BATCH>(a, wq);
+                    const int64_t local = w - Q.first;
+                    const int32_t s = Q.starts[local];
+                    int32_t *row = Q.paths + local * ((int64_t)Q.L + 1);
                     row[0] = s;
-                    st_bytes += 12 + 4 * (uint64_t)a.L;
+                    st_bytes += 12 + 4 * (uint64_t)Q.L;
                     if (s < 0 || (int64_t)s >= a.nv) {
                         atomicOr(a.err, 1);
-                        for (int r = 1; r <= a.L; ++r) row[r] = -1;
-                        a.lengths[w] = 0;
+                        for (int r = 1; r <= Q.L; ++r) row[r] = -1;
+                        Q.lengths[local] = 0;
                     } else {
-                        wid = (int32_t)w;
+                        q = wq;
+                        wid = (int32_t)local;
                         cur = s;
                         prev = -1;
                         j = 0;
@@ -242,8 +273,9 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
 
         // 2. step set-up: row of cur, bound B, strategy (Section 4.1)
         if (mode == kSetup) {
-            if (j == a.L) {
-                a.lengths[wid] = j;
+            const QueryDev &Q = query<BATCH>(a, q);
+            if (j == Q.L) {
+                Q.lengths[wid] = j;
                 mode = kIdle;
                 wid = -1;
             } else {
@@ -257,14 +289,14 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
                 } else {
                     bool rjs = false;
                     if (a.strategy != kRvsOnly) {
-                        const float wmax = (j == 0) ? a.wmax0 : a.wmax1;
+                        const float wmax = (j == 0) ? Q.wmax0 : Q.wmax1;
                         const float hm = W ? __uint_as_float(r.z) : 1.0f;
                         B = wmax * hm;  // get_weight_max: max(w) * h_MAX
                         if (a.strategy == kRjsOnly) {
                             rjs = true;
                             st_bytes += W ? 4 : 0;
                         } else {
-                            const float wavg = (j == 0) ? a.wavg0 : a.wavg1;
+                            const float wavg = (j == 0) ? Q.wavg0 : Q.wavg1;
                             const float hs = W ? __uint_as_float(r.w) : (float)deg;
                             st_bytes += W ? 8 : 0;
                             // Eq. (runtime) with get_weight_sum = mean(w) * h_SUM
@@ -282,21 +314,24 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
         //    U * B < w~; the membership search runs only when the bounds of w~ leave
         //    the test open
         if (mode == kRjs) {
-            const uint8_t want = (KIND == kMetaPath) ? a.schema[j % a.schema_len] : (uint8_t)0;
+            const QueryDev &Q = query<BATCH>(a, q);
+            const uint8_t want = (KIND == kMetaPath) ? Q.schema[j % Q.schema_len] : (uint8_t)0;
             // issue the loads of the next kRjsBatch proposals together, then decide them
             // in trial order; the first accepted trial is the sample, exactly as if the
             // trials ran one by one
             uint32_t ux[kRjsBatch];
             uint2 ee[kRjsBatch];
             uint8_t ll[kRjsBatch];
+            const uint32_t k0 = Q.key0, k1 = Q.key1;
 #pragma unroll
             for (int r = 0; r < kRjsBatch; ++r) {
-                const U4 x = philox((uint32_t)wid, (uint32_t)j, (uint32_t)(trials + r), 0u, a.key0, a.key1);
+                const U4 x = philox((uint32_t)wid, (uint32_t)j, (uint32_t)(trials + r), 0u, k0, k1);
                 const int64_t k = base + scaled_index(x.x0, x.x1, deg);
                 ux[r] = x.x2;
                 ee[r] = a.edges[k];
                 ll[r] = (KIND == kMetaPath) ? a.label[k] : (uint8_t)0;
             }
+            const float inv_p = Q.inv_p, inv_q = Q.inv_q, lo_w = Q.lo_w, hi_w = Q.hi_w;
             // decide proposals in order; the batch shifts down one slot per trial so the
             // decision code appears once
 #pragma unroll 1
@@ -309,9 +344,9 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
                     if (j == 0) {
                         acc = y < hv;
                     } else if (u == prev) {
-                        acc = y < a.inv_p * hv;
+                        acc = y < inv_p * hv;
                     } else {
-                        const float lo = a.lo_w * hv, hi = a.hi_w * hv;
+                        const float lo = lo_w * hv, hi = hi_w * hv;
                         if (y < lo) {
                             acc = true;
                         } else if (!(y < hi)) {
@@ -319,7 +354,7 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
                         } else {
                             st_bytes += 4 * (uint64_t)probes(pdeg);
                             const float wt =
-                                sorted_contains_interp(a.col + pbase, (int64_t)pdeg, u, a.nv) ? hv : a.inv_q * hv;
+                                sorted_contains_interp(a.col + pbase, (int64_t)pdeg, u, a.nv) ? hv : inv_q * hv;
                             acc = y < wt;
                         }
                     }
@@ -341,10 +376,10 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
                     break;
                 }
 #pragma unroll
-                for (int q = 0; q + 1 < kRjsBatch; ++q) {
-                    ee[q] = ee[q + 1];
-                    ux[q] = ux[q + 1];
-                    ll[q] = ll[q + 1];
+                for (int t = 0; t + 1 < kRjsBatch; ++t) {
+                    ee[t] = ee[t + 1];
+                    ux[t] = ux[t + 1];
+                    ll[t] = ll[t + 1];
                 }
             }
         }
@@ -384,11 +419,13 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
             for (int G = 8; G <= 32; G <<= 1) {
                 uint64_t &pool = G == 8 ? s8 : (G == 16 ? s16 : s32);
                 while (pool != 0)
-                    if (rvs_group_pass<KIND, W>(a, G, pool, wid, j, prev, base, deg, pbase, pdeg, res)) served(res, 0);
+                    if (rvs_group_pass<KIND, W, BATCH>(a, G, pool, q, wid, j, prev, base, deg, pbase, pdeg, res))
+                        served(res, 0);
             }
             while (big != 0) {
                 const int src = __ffsll((unsigned long long)big) - 1;
                 big &= big - 1;
+                const int32_t s_q = BATCH ? bcast_i32(q, src) : 0;
                 const uint32_t s_wid = bcast_u32((uint32_t)wid, src);
                 const int32_t s_j = bcast_i32(j, src);
                 const int32_t s_prev = bcast_i32(prev, src);
@@ -396,7 +433,8 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
                 const int32_t s_deg = bcast_i32(deg, src);
                 const int64_t s_pbase = bcast_i64(pbase, src);
                 const int32_t s_pdeg = bcast_i32(pdeg, src);
-                const uint8_t want = (KIND == kMetaPath) ? a.schema[s_j % a.schema_len] : (uint8_t)0;
+                const QueryDev &Q = query<BATCH>(a, s_q);
+                const uint8_t want = (KIND == kMetaPath) ? Q.schema[s_j % Q.schema_len] : (uint8_t)0;
                 const bool member_test = (KIND == kNode2Vec) && s_j > 0;
                 Mem m = {a.col + s_pbase, s_pdeg};
                 if (member_test && s_pdeg <= a.lds_cap && (int64_t)s_pdeg <= (int64_t)s_deg * probes(s_pdeg)) {
@@ -406,17 +444,18 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
                     m.p = lds;
                 }
                 uint32_t trig = 0;
-                res = rvs_step<KIND, W>(a, m, s_wid, s_j, s_prev, s_base, s_deg, want, trig);
+                res = rvs_step<KIND, W>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, trig);
                 if (lane == src) served(res, trig);
             }
         }
 
         // 5. apply the step (update) and write the path
         if (mode == kAdv) {
-            int32_t *row = a.paths + wid * row_len;
+            const QueryDev &Q = query<BATCH>(a, q);
+            int32_t *row = Q.paths + (int64_t)wid * ((int64_t)Q.L + 1);
             if (nxt < 0) {
-                for (int r = j + 1; r <= a.L; ++r) row[r] = -1;
-                a.lengths[wid] = j;
+                for (int r = j + 1; r <= Q.L; ++r) row[r] = -1;
+                Q.lengths[wid] = j;
                 st[kStEarly] += 1;
                 mode = kIdle;
                 wid = -1;
@@ -537,8 +576,8 @@ __global__ void __launch_bounds__(kBlock) profile_rvs_kernel(WalkArgs a, const i
         const uint4 rp = a.vrec[prev];
         const int64_t pb = row_start(a, rp, prev), pd = (int64_t)rp.y;
         for (int64_t i = lane; i < m; i += kWave)
-            acc += edge_weight<KIND, W>(a, b + i, a.edges[b + i], 1, prev, Mem{a.col + pb, pd},
-                                        a.schema[0]);
+            acc += edge_weight<KIND, W>(a, a.q0, b + i, a.edges[b + i], 1, prev, Mem{a.col + pb, pd},
+                                        a.q0.schema[0]);
     }
     acc = wave_max(acc);
     if (lane == 0 && acc < 0.0f) sink[0] = acc;  // never true; keeps the loads alive
@@ -558,49 +597,63 @@ __global__ void __launch_bounds__(kBlock) profile_rjs_kernel(WalkArgs a, const i
         const uint4 rp = a.vrec[prev];
         const int64_t pb = row_start(a, rp, prev), pd = (int64_t)rp.y;
         for (int t = 0; t < per_node; ++t) {
-            const U4 x = philox((uint32_t)s, 0u, (uint32_t)t, 2u, a.key0, a.key1);
+            const U4 x = philox((uint32_t)s, 0u, (uint32_t)t, 2u, a.q0.key0, a.q0.key1);
             const int64_t k = b + scaled_index(x.x0, x.x1, d);
-            acc += edge_weight<KIND, W>(a, k, a.edges[k], 1, prev, Mem{a.col + pb, pd}, a.schema[0]);
+            acc += edge_weight<KIND, W>(a, a.q0, k, a.edges[k], 1, prev, Mem{a.col + pb, pd}, a.q0.schema[0]);
         }
     }
     if (acc < 0.0f) sink[0] = acc;
 }
 
 // ---------------------------------------------------------------- launchers
-template <int KIND, bool W>
+template <int KIND, bool W, bool BATCH>
 static hipError_t launch_walk_t(const WalkArgs &a, int grid, hipStream_t s)
 {
     const size_t lds = (size_t)kWavesPerBlock * (size_t)a.lds_cap * sizeof(int32_t);
-    hipLaunchKernelGGL((walk_kernel<KIND, W>), dim3(grid), dim3(kBlock), lds, s, a);
+    hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH>), dim3(grid), dim3(kBlock), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_walk(const WalkArgs &a, int kind, bool weighted, int grid, hipStream_t s)
+template <bool BATCH>
+static hipError_t launch_walk_b(const WalkArgs &a, int kind, bool weighted, int grid, hipStream_t s)
 {
-    if (kind == kNode2Vec) return weighted ? launch_walk_t<kNode2Vec, true>(a, grid, s)
-                                           : launch_walk_t<kNode2Vec, false>(a, grid, s);
-    return weighted ? launch_walk_t<kMetaPath, true>(a, grid, s) : launch_walk_t<kMetaPath, false>(a, grid, s);
+    if (kind == kNode2Vec) return weighted ? launch_walk_t<kNode2Vec, true, BATCH>(a, grid, s)
+                                           : launch_walk_t<kNode2Vec, false, BATCH>(a, grid, s);
+    return weighted ? launch_walk_t<kMetaPath, true, BATCH>(a, grid, s)
+                    : launch_walk_t<kMetaPath, false, BATCH>(a, grid, s);
 }
 
-template <int KIND, bool W>
+hipError_t launch_walk(const WalkArgs &a, int kind, bool weighted, bool batch, int grid, hipStream_t s)
+{
+    return batch ? launch_walk_b<true>(a, kind, weighted, grid, s) : launch_walk_b<false>(a, kind, weighted, grid, s);
+}
+
+template <int KIND, bool W, bool BATCH>
 static int occupancy_blocks(int lds_cap)
 {
     int nb = 0;
     const size_t lds = (size_t)kWavesPerBlock * (size_t)lds_cap * sizeof(int32_t);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<KIND, W>, kBlock, lds) != hipSuccess) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<KIND, W, BATCH>, kBlock, lds) != hipSuccess)
+        nb = 1;
     return nb > 0 ? nb : 1;
 }
 
-int walk_grid(int kind, bool weighted, int lds_cap, int64_t n)
+template <bool BATCH>
+static int occupancy_b(int kind, bool weighted, int lds_cap)
+{
+    if (kind == kNode2Vec) return weighted ? occupancy_blocks<kNode2Vec, true, BATCH>(lds_cap)
+                                           : occupancy_blocks<kNode2Vec, false, BATCH>(lds_cap);
+    return weighted ? occupancy_blocks<kMetaPath, true, BATCH>(lds_cap)
+                    : occupancy_blocks<kMetaPath, false, BATCH>(lds_cap);
+}
+
+int walk_grid(int kind, bool weighted, bool batch, int lds_cap, int64_t n)
 {
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (cus <= 0) cus = 1;
-    int nb;
-    if (kind == kNode2Vec) nb = weighted ? occupancy_blocks<kNode2Vec, true>(lds_cap)
-                                         : occupancy_blocks<kNode2Vec, false>(lds_cap);
-    else nb = weighted ? occupancy_blocks<kMetaPath, true>(lds_cap) : occupancy_blocks<kMetaPath, false>(lds_cap);
+    const int nb = batch ? occupancy_b<true>(kind, weighted, lds_cap) : occupancy_b<false>(kind, weighted, lds_cap);
     int64_t grid = (int64_t)nb * cus;
     const int64_t need = (n + kBlock - 1) / kBlock;
     if (grid > need) grid = need;

@@ -178,12 +178,38 @@ def cached(name: str, cache_dir: str | None = None) -> dict:
     return g
 
 
+def batch_queries(nv: int, nq: int, seed: int, n_max: int = 65536, L_lo: int = 5, L_hi: int = 200,
+                  pq=(0.25, 0.5, 1.0, 2.0, 4.0), first_seed: int = 42) -> dict:
+    """A batch of Node2Vec walk queries.
+
+    Per query: p and q drawn independently from ``pq``; start-set size
+    ``floor(exp(U(0, ln n_max)))`` (log-uniform in 1..n_max); length uniform in
+    L_lo..L_hi; seed ``first_seed + query index``; start vertices uniform over all
+    vertices.  Returns arrays ``p, q, n, L, seed`` per query, the concatenated
+    ``starts`` and the offsets ``start_off, out_off, len_off`` of each query's blocks.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p = rng.choice(np.asarray(pq, np.float32), nq)
+    q = rng.choice(np.asarray(pq, np.float32), nq)
+    n = np.floor(np.exp(rng.uniform(0.0, np.log(n_max), nq))).astype(np.int64)
+    n = np.clip(n, 1, n_max)
+    L = rng.integers(L_lo, L_hi + 1, nq).astype(np.int32)
+    starts = rng.integers(0, nv, int(n.sum()), dtype=np.int64).astype(np.int32)
+    start_off = np.concatenate([[0], np.cumsum(n)[:-1]]).astype(np.int64)
+    out_off = np.concatenate([[0], np.cumsum(n * (L.astype(np.int64) + 1))[:-1]]).astype(np.int64)
+    return {"p": p, "q": q, "n": n, "L": L, "seed": first_seed + np.arange(nq, dtype=np.int64),
+            "starts": starts, "start_off": start_off, "out_off": out_off, "len_off": start_off.copy(),
+            "total_paths": int((n * (L.astype(np.int64) + 1)).sum())}
+
+
 def workload_graph(name: str) -> dict:
     """Graphs of the named workloads.
 
     * ``rmat12``: scale 12, average degree 16 (8 * 2^12 undirected draws).
     * ``rmat22``: scale 22, edge factor 16 (16 * 2^22 draws, <= 134M entries).
     * ``rmat22_labels``: the scale-22 graph plus uint8 labels uniform in 0..4.
+    * ``rmat24_skew``: scale 24, edge factor 16, heavier skew (a, b, c) = (0.6, 0.175,
+      0.175).
     """
     if name == "rmat12":
         return rmat(12, 8 << 12, seed=1)
@@ -191,6 +217,8 @@ def workload_graph(name: str) -> dict:
         return rmat(22, 16 << 22, seed=1)
     if name == "rmat22_labels":
         return rmat(22, 16 << 22, seed=1, nlabels=5)
+    if name == "rmat24_skew":
+        return rmat(24, 16 << 24, a=0.6, b=0.175, c=0.175, seed=1)
     if name.startswith("rmat") and name[4:].isdigit():
         s = int(name[4:])
         return rmat(s, 16 << s, seed=1)

@@ -95,14 +95,28 @@ def assert_parity(rep: dict):
     assert len(rep["flagged"]) <= 1e-5 * max(rep["steps"], 1), f"flagged mismatches: {rep['flagged'][:10]}"
 
 
+_EDGE_KEYS: dict = {}
+
+
+def _edge_keys(g: dict):
+    """Sorted 64-bit keys src * nv + dst of every CSR entry, cached per graph."""
+    k = id(g["col"])
+    if k not in _EDGE_KEYS:
+        _EDGE_KEYS.clear()
+        dev = torch.device("cuda:0")
+        nv = int(g["nv"])
+        rp = torch.from_numpy(g["row_ptr"]).to(dev)
+        col = torch.from_numpy(g["col"]).to(dev).long()
+        src = torch.repeat_interleave(torch.arange(nv, device=dev), rp[1:] - rp[:-1])
+        _EDGE_KEYS[k] = src * nv + col  # ascending: rows in order, columns sorted
+    return _EDGE_KEYS[k]
+
+
 def edge_check_torch(g: dict, paths: np.ndarray, lengths: np.ndarray):
     """Every step lands on a neighbour (vectorised on the GPU with torch)."""
     dev = torch.device("cuda:0")
     nv = int(g["nv"])
-    rp = torch.from_numpy(g["row_ptr"]).to(dev)
-    col = torch.from_numpy(g["col"]).to(dev).long()
-    src = torch.repeat_interleave(torch.arange(nv, device=dev), rp[1:] - rp[:-1])
-    keys = src * nv + col  # ascending: rows in order, columns sorted
+    keys = _edge_keys(g)
     P = torch.from_numpy(paths).to(dev).long()
     ln = torch.from_numpy(lengths).to(dev).long()
     j = torch.arange(P.shape[1] - 1, device=dev)

@@ -75,7 +75,7 @@ def test_struct_layouts_match_header():
     """ctypes mirrors of the C structs have the sizes the C compiler gives them."""
     import paper_2512_00705_amd as fw
     src = ("#include <stdio.h>\n#include \"flexiwalk.h\"\nint main(void){printf(\"%zu %zu %zu\\n\","
-           "sizeof(fw_csr), sizeof(fw_logic), sizeof(fw_plan));return 0;}\n")
+           "sizeof(fw_csr), sizeof(fw_logic), sizeof(fw_plan));printf(\"%zu\\n\", sizeof(fw_query));return 0;}\n")
     d = os.path.join(ROOT, "_build")
     os.makedirs(d, exist_ok=True)
     c = os.path.join(d, "sizes.c")
@@ -83,4 +83,5 @@ def test_struct_layouts_match_header():
     open(c, "w").write(src)
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
     sizes = [int(x) for x in subprocess.check_output([exe]).split()]
-    assert sizes == [ctypes.sizeof(fw.fw_csr), ctypes.sizeof(fw.fw_logic), ctypes.sizeof(fw.fw_plan)]
+    assert sizes == [ctypes.sizeof(fw.fw_csr), ctypes.sizeof(fw.fw_logic), ctypes.sizeof(fw.fw_plan),
+                     ctypes.sizeof(fw.fw_query)]

@@ -85,3 +85,62 @@ def test_metapath_scale22(g22, gg22, og22):
     rep = parity(p[sub], ln[sub], ora)
     print("metapath22", {k2: (v if not isinstance(v, list) else len(v)) for k2, v in rep.items()}, st)
     assert_parity(rep)
+
+
+def test_batched_scale24():
+    """4096 Node2Vec queries (p, q from {0.25..4}, start sets log-uniform 1..65536, L in
+    5..200) on the skewed scale-24 R-MAT in one launch; 32 queries replayed by the oracle
+    on up to 256 walkers each, and every walk of 256 queries checked to follow edges."""
+    g = synth.cached("rmat24_skew")
+    gg = GpuGraph(g)
+    try:
+        qd = synth.batch_queries(g["nv"], 4096, 7)
+        dev = torch.device("cuda:0")
+        starts = torch.from_numpy(qd["starts"]).to(dev)
+        paths = torch.full((qd["total_paths"],), -7, dtype=torch.int32, device=dev)
+        lengths = torch.full((int(qd["n"].sum()),), -7, dtype=torch.int32, device=dev)
+        stats = torch.zeros(fw.FW_NSTATS, dtype=torch.int64, device=dev)
+        tuned = fw.fw_plan_autotune(gg.handle, fw.fw_logic_node2vec(1.0, 1.0, True))
+        pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap)
+        qs = []
+        for i in range(4096):
+            q = fw.fw_query()
+            q.logic = fw.fw_logic_node2vec(float(qd["p"][i]), float(qd["q"][i]), True)
+            q.n, q.L, q.seed = int(qd["n"][i]), int(qd["L"][i]), int(qd["seed"][i])
+            q.start_off, q.out_off, q.len_off = int(qd["start_off"][i]), int(qd["out_off"][i]), int(qd["len_off"][i])
+            qs.append(q)
+        b = fw.fw_batch_create(gg.handle, qs, tuned, fw.FW_AUTO, starts, paths, lengths)
+        fw.fw_batch_launch(b, stats)
+        fw.fw_graph_check(gg.handle)
+        torch.cuda.synchronize()
+        fw.fw_batch_destroy(b)
+        st = stats.cpu().numpy()
+        print("batched24", dict(zip(fw.STAT_NAMES, st.tolist())))
+        og = oracle.Graph(g)
+        og.aux()
+        rng = np.random.default_rng(5)
+        order = np.argsort(qd["n"])
+        picks = np.concatenate([order[:8], order[2040:2048], order[-16:]])
+        steps = 0
+        for i in picks:
+            n, L = int(qd["n"][i]), int(qd["L"][i])
+            o = int(qd["out_off"][i])
+            sub = np.sort(rng.choice(n, size=min(n, 256), replace=False)).astype(np.int64)
+            p = paths[o:o + n * (L + 1)].view(n, L + 1)[torch.from_numpy(sub).to(dev)].cpu().numpy()
+            ln = lengths[int(qd["len_off"][i]):int(qd["len_off"][i]) + n][torch.from_numpy(sub).to(dev)].cpu().numpy()
+            st_q = qd["starts"][qd["start_off"][i]:qd["start_off"][i] + n][sub]
+            lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=float(qd["p"][i]), q=float(qd["q"][i]))
+            ora = oracle.walk(og, lg, pl, oracle.AUTO, st_q, L, int(qd["seed"][i]), walker_ids=sub)
+            rep = parity(p, ln, ora)
+            assert_parity(rep)
+            steps += rep["steps"]
+        assert steps > 10000
+        for i in rng.choice(4096, 256, replace=False):
+            n, L = int(qd["n"][i]), int(qd["L"][i])
+            o = int(qd["out_off"][i])
+            p = paths[o:o + n * (L + 1)].view(n, L + 1).cpu().numpy()
+            ln = lengths[int(qd["len_off"][i]):int(qd["len_off"][i]) + n].cpu().numpy()
+            ok, pad_ok, _ = edge_check_torch(g, p, ln)
+            assert ok and pad_ok, i
+    finally:
+        gg.close()
