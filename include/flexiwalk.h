@@ -187,10 +187,13 @@ typedef struct fw_batch fw_batch; /* opaque: a query table resident on the devic
  * (Section 5 runtime kernel; dynamic scheduling over the walkers of all queries).  All
  * queries share the logic kind and weighting (mixed kinds go in separate batches).
  * starts, paths and lengths are device pointers owned by the caller and bound to the
- * batch: they must stay valid, and query blocks must not overlap.  Copies the query table
- * to the device (synchronous); does not launch.  The plan and strategy apply to all. */
+ * batch, holding starts_len, paths_len and lengths_len int32 elements: every query's
+ * blocks must lie inside them (FW_E_INVALID otherwise), must not overlap, and the arrays
+ * must stay valid while the batch is used.  Copies the query table to the device
+ * (synchronous); does not launch.  The plan and strategy apply to all queries. */
 int fw_batch_create(fw_graph *g, const fw_query *queries, int64_t nq, const fw_plan *plan, int32_t strategy,
-                    const int32_t *starts, int32_t *paths, int32_t *lengths, fw_batch **out);
+                    const int32_t *starts, int64_t starts_len, int32_t *paths, int64_t paths_len,
+                    int32_t *lengths, int64_t lengths_len, fw_batch **out);
 
 /* Run every query of the batch in one launch on `stream` (asynchronous).  Allocates
  * nothing and issues no memset or host synchronisation, so it can be captured into a HIP

@@ -79,8 +79,8 @@ def _load():
         "fw_walk": ([P, ctypes.POINTER(fw_logic), ctypes.POINTER(fw_plan), I32, P, I64, I32, ctypes.c_uint64,
                      P, P, P, P], ctypes.c_int),
         "fw_graph_check": ([P, P], ctypes.c_int),
-        "fw_batch_create": ([P, ctypes.POINTER(fw_query), I64, ctypes.POINTER(fw_plan), I32, P, P, P,
-                             ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+        "fw_batch_create": ([P, ctypes.POINTER(fw_query), I64, ctypes.POINTER(fw_plan), I32, P, I64, P, I64, P,
+                             I64, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
         "fw_batch_launch": ([P, P, P], ctypes.c_int),
         "fw_batch_capture": ([P, P, P], ctypes.c_int),
         "fw_batch_replay": ([P, P], ctypes.c_int),
@@ -198,12 +198,23 @@ def fw_graph_check(g: int, stream=None):
     _check(_lib.fw_graph_check(g, _stream(stream)))
 
 
-def fw_batch_create(g: int, queries, plan: fw_plan, strategy: int, starts, paths, lengths) -> int:
-    """queries: a sequence of fw_query.  Returns an opaque batch handle (int)."""
+def _numel(x, given):
+    if given is not None:
+        return int(given)
+    if x is None:
+        return 0
+    return int(x.numel()) if hasattr(x, "numel") else int(np.asarray(x).size)
+
+
+def fw_batch_create(g: int, queries, plan: fw_plan, strategy: int, starts, paths, lengths, starts_len=None,
+                    paths_len=None, lengths_len=None) -> int:
+    """queries: a sequence of fw_query.  Array lengths default to the tensors' sizes.
+    Returns an opaque batch handle (int)."""
     arr = (fw_query * max(len(queries), 1))(*queries)
     out = ctypes.c_void_p()
-    _check(_lib.fw_batch_create(g, arr, len(queries), ctypes.byref(plan), strategy, _ptr(starts), _ptr(paths),
-                                _ptr(lengths), ctypes.byref(out)))
+    _check(_lib.fw_batch_create(g, arr, len(queries), ctypes.byref(plan), strategy, _ptr(starts),
+                                _numel(starts, starts_len), _ptr(paths), _numel(paths, paths_len), _ptr(lengths),
+                                _numel(lengths, lengths_len), ctypes.byref(out)))
     return out.value
 
 

@@ -531,7 +531,8 @@ static void batch_free(fw_batch *b)
 }
 
 int fw_batch_create(fw_graph *g, const fw_query *qs, int64_t nq, const fw_plan *pl, int32_t strategy,
-                    const int32_t *starts, int32_t *paths, int32_t *lengths, fw_batch **out)
+                    const int32_t *starts, int64_t starts_len, int32_t *paths, int64_t paths_len, int32_t *lengths,
+                    int64_t lengths_len, fw_batch **out)
 {
     if (!g || !pl || !out || (nq > 0 && !qs)) return fail(FW_E_INVALID, "fw_batch_create: null argument");
     if (nq < 0 || nq >= ((int64_t)1 << 31)) return fail(FW_E_INVALID, "fw_batch_create: nq must be in [0, 2^31)");
@@ -552,6 +553,11 @@ int fw_batch_create(fw_graph *g, const fw_query *qs, int64_t nq, const fw_plan *
             return fail(FW_E_INVALID, "query %lld: negative offset", (long long)i);
         if (q.n > 0 && (!starts || !paths || !lengths))
             return fail(FW_E_INVALID, "fw_batch_create: null starts/paths/lengths");
+        // every block the query addresses must lie inside the caller's arrays
+        if (q.start_off + q.n > starts_len || q.len_off + q.n > lengths_len ||
+            q.out_off + q.n * ((int64_t)q.L + 1) > paths_len)
+            return fail(FW_E_INVALID, "query %lld: its starts/paths/lengths block exceeds the given array",
+                        (long long)i);
         fw::QueryDev &d = tab[(size_t)i];
         fill_query(&q.logic, d);
         d.first = total;

@@ -47,9 +47,15 @@ def _queries(qd, logics):
 class Batch:
     def __init__(self, gg, qd, logics, plan, strategy):
         self.qd = qd
+        n = qd["n"].astype(np.int64)
+        # buffers sized from the offsets the queries address, never from a recount
+        need_starts = int((qd["start_off"] + n).max(initial=0))
+        need_paths = int((qd["out_off"] + n * (qd["L"].astype(np.int64) + 1)).max(initial=0))
+        need_len = int((qd["len_off"] + n).max(initial=0))
+        assert qd["starts"].shape[0] >= need_starts
         self.starts = torch.from_numpy(qd["starts"]).to(DEV)
-        self.paths = torch.full((max(qd["total_paths"], 1),), -7, dtype=torch.int32, device=DEV)
-        self.lengths = torch.full((max(int(np.sum(qd["n"])), 1),), -7, dtype=torch.int32, device=DEV)
+        self.paths = torch.full((max(need_paths, 1),), -7, dtype=torch.int32, device=DEV)
+        self.lengths = torch.full((max(need_len, 1),), -7, dtype=torch.int32, device=DEV)
         self.stats = torch.zeros(fw.FW_NSTATS, dtype=torch.int64, device=DEV)
         self.h = fw.fw_batch_create(gg.handle, _queries(qd, logics), plan, strategy, self.starts, self.paths,
                                     self.lengths)
@@ -156,6 +162,11 @@ def test_batch_argument_errors(g12, gg12):
         fw.fw_batch_create(gg12.handle, _queries(qd, lgs), fw.fw_plan_default(), 0, dev, dev, dev)
     q = _queries(qd, [lgs[0]])
     q[0].L = -1
+    with pytest.raises(fw.FlexiWalkError):
+        fw.fw_batch_create(gg12.handle, q, fw.fw_plan_default(), 0, dev, dev, dev)
+    q = _queries(qd, [lgs[0]])
+    q[0].n = 17  # block larger than the 16-element arrays
+    q[0].start_off = q[0].out_off = q[0].len_off = 0
     with pytest.raises(fw.FlexiWalkError):
         fw.fw_batch_create(gg12.handle, q, fw.fw_plan_default(), 0, dev, dev, dev)
     empty = fw.fw_batch_create(gg12.handle, [], fw.fw_plan_default(), 0, None, None, None)
