@@ -39,8 +39,13 @@ def main():
     ap.add_argument("--modes", type=int, default=1, help="also time the single-kernel modes")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=0, help="walkers for the CPU baseline (0: sized to ~15 s)")
-    ap.add_argument("--workload", default="node2vec", choices=["node2vec", "batched"],
-                    help="node2vec: the headline scale-22 job; batched: 4096 queries on skewed scale 24")
+    ap.add_argument("--workload", default="node2vec", choices=["node2vec", "batched", "served"],
+                    help="node2vec: the headline scale-22 job; batched: 4096 queries on skewed scale 24; "
+                         "served: Poisson request stream against a resident scale-25 graph")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-scale", type=int, default=25)
+    ap.add_argument("--tick-steps", type=int, default=16)
     ap.add_argument("--per-query", type=int, default=1, help="batched: also time one launch per query")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB: only run a plain device-to-device copy of this size 3 times (counter calibration)")
@@ -66,6 +71,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "served":
+        return bench_served(args)
     t0 = time.time()
     g = synth.cached(args.graph)
     log(f"graph {args.graph}: nv={g['nv']} ne={g['ne']} ({time.time() - t0:.1f}s)")
@@ -266,6 +273,110 @@ def bench_batched(args):
         "roofline": {"bound": "hbm", "achieved": st["alg_bytes"] / (avg / 1e3) / 1e9, "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": st["alg_bytes"] / (avg / 1e3) / 1e9 / PEAK_HBM_GBS, "traffic": None},
         "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_served(args):
+    """Poisson arrivals of mixed Node2Vec / MetaPath requests against a resident R-MAT
+    graph with labels, served by continuous batching; p50/p99 latency and walker-steps/s."""
+    import threading
+
+    import torch
+    import paper_2512_00705_amd as fw
+    import synth
+
+    t0 = time.time()
+    s = args.serve_scale
+    g = synth.rmat(s, 16 << s, seed=1, nlabels=5)
+    log(f"graph rmat{s}_labels: nv={g['nv']} ne={g['ne']} ({time.time() - t0:.1f}s)")
+    dev = torch.device("cuda:0")
+    t = {k: torch.from_numpy(g[k]).to(dev) for k in ("row_ptr", "col", "h", "label")}
+    gh = fw.fw_graph_create(g["nv"], g["ne"], t["row_ptr"], t["col"], t["h"], t["label"], on_device=True)
+    del t
+    nv = g["nv"]
+    del g
+    fw.fw_graph_preprocess(gh)
+    plan = fw.fw_plan_autotune(gh, fw.fw_logic_node2vec(1.0, 1.0, True))
+    budget = 32 << 30
+    srv = fw.fw_server_create(gh, plan, fw.FW_AUTO, budget, tick_steps=args.tick_steps, max_active=8192,
+                              max_pending=1 << 16)
+    rng = np.random.default_rng(11)
+    T, lam = args.serve_seconds, args.serve_rate
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, int(lam * T * 1.2) + 16))
+    arrivals = arrivals[arrivals < T]
+    pq = np.array([0.25, 0.5, 1.0, 2.0, 4.0], np.float32)
+    reqs = []
+    for i in range(len(arrivals)):
+        n = int(np.clip(np.floor(np.exp(rng.uniform(0, np.log(65536)))), 1, 65536))
+        L = int(rng.integers(10, 101))
+        if i % 2 == 0:
+            lg = fw.fw_logic_node2vec(float(rng.choice(pq)), float(rng.choice(pq)), True)
+        else:
+            lg = fw.fw_logic_metapath([0, 1, 2, 3, 4], True)
+        reqs.append((lg, n, L, 1000 + i))
+    offered_steps = sum(n * L for _, n, L, _ in reqs)
+    log(f"{len(reqs)} requests over {T}s, offered {offered_steps / T / 1e6:.1f} M walker-steps/s")
+    busy = [0]
+    meta = {}
+    start = time.perf_counter()
+
+    def submit():
+        for i, (lg, n, L, seed) in enumerate(reqs):
+            wait = start + arrivals[i] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            starts = rng_s.integers(0, nv, n, dtype=np.int64).astype(np.int32)
+            while True:
+                try:
+                    rid = fw.fw_server_submit(srv, lg, starts, L, seed)
+                    break
+                except fw.FlexiWalkError as e:
+                    if e.code != fw.FW_E_BUSY:
+                        raise
+                    busy[0] += 1
+                    time.sleep(0.001)
+            meta[rid] = (n, L)
+
+    rng_s = np.random.default_rng(12)
+    th = threading.Thread(target=submit)
+    th.start()
+    lat, done_steps, t_last = [], 0, start
+    deadline = start + T + 120
+    while len(lat) < len(reqs) and time.perf_counter() < deadline:
+        rid = fw.fw_server_next_done(srv, 200)
+        if not rid:
+            continue
+        while rid not in meta:
+            time.sleep(0.0005)
+        n, L = meta[rid]
+        p, ln, l_s = fw.fw_server_result(srv, rid, n, L)
+        lat.append(l_s)
+        done_steps += int(ln.sum())
+        t_last = time.perf_counter()
+    th.join()
+    st = fw.fw_server_stats(srv)
+    fw.fw_server_destroy(srv)
+    fw.fw_graph_destroy(gh)
+    wall = t_last - start
+    lat_ms = np.array(lat) * 1e3
+    p50, p99 = float(np.percentile(lat_ms, 50)), float(np.percentile(lat_ms, 99))
+    sustained = len(lat) == len(reqs) and wall < T * 1.1 + 1.0
+    log(f"served {len(lat)}/{len(reqs)} in {wall:.2f}s, p50 {p50:.2f} ms, p99 {p99:.2f} ms, stats {st}, "
+        f"busy retries {busy[0]}")
+    out = {
+        "metric": "walker-steps/sec + p50/p99 latency served, mixed node2vec/metapath requests",
+        "value": done_steps / wall, "unit": "walker-steps/s", "n_gpus": 1, "steps": len(lat), "warmup": 0,
+        "ms_per_step": p50, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"Poisson arrivals {lam:.0f} req/s for {T:.0f}s, half node2vec (p,q in "
+                               f"{{0.25..4}}), half metapath schema (0,1,2,3,4) repeated, start sets log-uniform "
+                               f"1..65536, L in 10..100, resident R-MAT scale {s} with labels, continuous "
+                               f"batching (tick {args.tick_steps} steps), budget {budget >> 30} GiB",
+                   "p50_ms": p50, "p99_ms": p99, "requests": len(reqs), "completed": len(lat),
+                   "sustained": sustained, "offered_walker_steps_per_s": offered_steps / T, "server": st,
+                   "busy_retries": busy[0], "rho": plan.rho},
+        "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

@@ -34,7 +34,8 @@ typedef enum fw_status {
     FW_E_INVALID = 1, /* bad argument or malformed input; nothing was changed */
     FW_E_NOMEM = 2,   /* device allocation failed; nothing was allocated */
     FW_E_DEVICE = 3,  /* a HIP runtime call failed */
-    FW_E_STATE = 4    /* object not ready (e.g. graph not preprocessed) */
+    FW_E_STATE = 4,   /* object not ready (e.g. graph not preprocessed) */
+    FW_E_BUSY = 5     /* the server's waiting queue is full; retry later */
 } fw_status;
 
 /* Sampling strategy per step (Section 4.1; single-kernel modes of the ablation). */
@@ -210,6 +211,46 @@ int fw_batch_replay(fw_batch *b, void *stream);
 
 /* Free the batch and its graph.  NULL is accepted; its launches must have finished. */
 int fw_batch_destroy(fw_batch *b);
+
+/* Walk server: continuous batching of walk requests against a resident graph.
+ *
+ * A server thread runs ticks: one batched launch per (logic kind, weighting) over the
+ * walkers of every admitted request, each walker advancing at most `tick_steps` steps
+ * before it is suspended.  Between ticks finished requests are copied to host memory
+ * and released, and waiting requests are admitted in arrival order while their device
+ * block (n * (4L + 16) bytes, rounded) fits in `hbm_budget` bytes and fewer than
+ * `max_active` requests are admitted.  Requests that arrive while others run thus join
+ * at the next tick and share the device with them.  Walker i of a request uses Philox
+ * counter (i, step, draw, tag) under the request's seed: results are identical to
+ * fw_walk of the same (logic, starts, L, seed), whatever the mix and the tick length.
+ * The plan and strategy are fixed for the server's lifetime.  Allocates `hbm_budget`
+ * bytes of device memory up front; uses its own stream. */
+typedef struct fw_server fw_server;
+
+int fw_server_create(fw_graph *g, const fw_plan *plan, int32_t strategy, uint64_t hbm_budget,
+                     int32_t tick_steps, int32_t max_active, int32_t max_pending, fw_server **out);
+
+/* Queue a request: n walkers from starts (host pointer, copied), at most L steps.  Returns
+ * FW_E_BUSY when max_pending requests are already waiting, FW_E_INVALID when the request
+ * can never fit the budget.  *req_id identifies it (ids start at 1). */
+int fw_server_submit(fw_server *s, const fw_logic *logic, const int32_t *starts, int64_t n, int32_t L,
+                     uint64_t seed, uint64_t *req_id);
+
+/* Wait up to timeout_ms for a finished request; *req_id = its id, or 0 on timeout.
+ * Finished requests are reported once each, in completion order. */
+int fw_server_next_done(fw_server *s, int32_t timeout_ms, uint64_t *req_id);
+
+/* Copy a finished request's results (host pointers: n*(L+1) path slots in the fw_walk
+ * layout, n lengths; either may be NULL), report its submit-to-finish latency in
+ * seconds, and forget it.  FW_E_STATE if it has not finished. */
+int fw_server_result(fw_server *s, uint64_t req_id, int32_t *paths, int32_t *lengths, double *latency_s);
+
+/* Counters (8 uint64): 0 waiting, 1 admitted and unfinished, 2 finished, 3 ticks, 4 walker
+ * steps, 5 budget bytes in use, 6 peak bytes in use, 7 algorithmic bytes. */
+int fw_server_stats(fw_server *s, uint64_t *out);
+
+/* Stop after the current tick and free everything; unfinished requests are dropped. */
+int fw_server_destroy(fw_server *s);
 
 /* Wait for `stream`, then report and clear the graph's device error flag: FW_OK, or
  * FW_E_INVALID if a walk since the last check met an out-of-range start vertex. */

@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libflexiwalk.so")
 
-FW_OK, FW_E_INVALID, FW_E_NOMEM, FW_E_DEVICE, FW_E_STATE = 0, 1, 2, 3, 4
+FW_OK, FW_E_INVALID, FW_E_NOMEM, FW_E_DEVICE, FW_E_STATE, FW_E_BUSY = 0, 1, 2, 3, 4, 5
 FW_AUTO, FW_RVS_ONLY, FW_RJS_ONLY = 0, 1, 2
 FW_NODE2VEC, FW_METAPATH = 1, 2
 FW_MAX_SCHEMA = 64
@@ -27,7 +27,11 @@ STAT_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", 
 EXPORTED = ("fw_graph_create", "fw_graph_destroy", "fw_graph_preprocess", "fw_graph_export_aux",
             "fw_graph_info", "fw_logic_node2vec", "fw_logic_metapath", "fw_plan_default",
             "fw_plan_profile", "fw_plan_autotune", "fw_walk", "fw_graph_check", "fw_last_error",
-            "fw_batch_create", "fw_batch_launch", "fw_batch_capture", "fw_batch_replay", "fw_batch_destroy")
+            "fw_batch_create", "fw_batch_launch", "fw_batch_capture", "fw_batch_replay", "fw_batch_destroy",
+            "fw_server_create", "fw_server_submit", "fw_server_next_done", "fw_server_result", "fw_server_stats",
+            "fw_server_destroy")
+SERVER_STAT_NAMES = ("waiting", "active", "finished", "ticks", "walker_steps", "bytes_in_use", "peak_bytes",
+                     "alg_bytes")
 
 
 class FlexiWalkError(RuntimeError):
@@ -85,6 +89,14 @@ def _load():
         "fw_batch_capture": ([P, P, P], ctypes.c_int),
         "fw_batch_replay": ([P, P], ctypes.c_int),
         "fw_batch_destroy": ([P], ctypes.c_int),
+        "fw_server_create": ([P, ctypes.POINTER(fw_plan), I32, ctypes.c_uint64, I32, I32, I32,
+                              ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+        "fw_server_submit": ([P, ctypes.POINTER(fw_logic), P, I64, I32, ctypes.c_uint64,
+                              ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "fw_server_next_done": ([P, I32, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "fw_server_result": ([P, ctypes.c_uint64, P, P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "fw_server_stats": ([P, P], ctypes.c_int),
+        "fw_server_destroy": ([P], ctypes.c_int),
         "fw_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -232,3 +244,45 @@ def fw_batch_replay(b: int, stream=None):
 
 def fw_batch_destroy(b: int):
     _check(_lib.fw_batch_destroy(b))
+
+
+def fw_server_create(g: int, plan: fw_plan, strategy: int, hbm_budget: int, tick_steps: int = 16,
+                     max_active: int = 4096, max_pending: int = 1 << 16) -> int:
+    out = ctypes.c_void_p()
+    _check(_lib.fw_server_create(g, ctypes.byref(plan), strategy, hbm_budget, tick_steps, max_active, max_pending,
+                                 ctypes.byref(out)))
+    return out.value
+
+
+def fw_server_submit(s: int, logic: fw_logic, starts, L: int, seed: int) -> int:
+    """starts: host int32 array (copied).  Returns the request id."""
+    st = np.ascontiguousarray(starts, dtype=np.int32)
+    rid = ctypes.c_uint64()
+    _check(_lib.fw_server_submit(s, ctypes.byref(logic), st.ctypes.data, st.shape[0], L,
+                                 seed & 0xFFFFFFFFFFFFFFFF, ctypes.byref(rid)))
+    return rid.value
+
+
+def fw_server_next_done(s: int, timeout_ms: int = 100) -> int:
+    rid = ctypes.c_uint64()
+    _check(_lib.fw_server_next_done(s, timeout_ms, ctypes.byref(rid)))
+    return rid.value
+
+
+def fw_server_result(s: int, req_id: int, n: int, L: int):
+    """(paths (n, L+1), lengths (n,), latency seconds) of a finished request."""
+    paths = np.empty((n, L + 1), np.int32)
+    lengths = np.empty(n, np.int32)
+    lat = ctypes.c_double()
+    _check(_lib.fw_server_result(s, req_id, paths.ctypes.data, lengths.ctypes.data, ctypes.byref(lat)))
+    return paths, lengths, lat.value
+
+
+def fw_server_stats(s: int) -> dict:
+    out = np.zeros(8, np.uint64)
+    _check(_lib.fw_server_stats(s, out.ctypes.data))
+    return dict(zip(SERVER_STAT_NAMES, (int(x) for x in out)))
+
+
+def fw_server_destroy(s: int):
+    _check(_lib.fw_server_destroy(s))

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libflexiwalk.so")
-SOURCES = ["fw_kernels.hip", "fw_api.hip"]
+SOURCES = ["fw_kernels.hip", "fw_api.hip", "fw_server.hip"]
 
 # -ffp-contract=off: no fused multiply-add anywhere, so float32 results follow the
 #   stated operation order; denormals are kept; packed fp32 ops are disabled.
@@ -30,7 +30,7 @@ def build(verbose: bool = False) -> str:
         subprocess.check_call(cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

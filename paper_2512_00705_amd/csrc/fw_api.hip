@@ -13,8 +13,10 @@
 #include "../../include/flexiwalk.h"
 #include "fw_device.h"
 #include "fw_internal.h"
+#include "fw_host.h"
 
-namespace {
+namespace fw {
+namespace host {
 
 thread_local std::string g_err;
 
@@ -35,27 +37,16 @@ int ok()
     return FW_OK;
 }
 
-#define HIP_TRY(expr)                                                                               \
-    do {                                                                                            \
-        hipError_t e_ = (expr);                                                                     \
-        if (e_ != hipSuccess) return fail(FW_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));     \
-    } while (0)
+}  // namespace host
+}  // namespace fw
 
-}  // namespace
-
-struct fw_graph {
-    int device = 0;
-    int64_t nv = 0, ne = 0, max_deg = 0;
-    int64_t *row_ptr = nullptr;
-    int32_t *col = nullptr;
-    float *h = nullptr;
-    uint8_t *label = nullptr;
-    uint2 *edges = nullptr;                 // {col, bits(h)} per entry
-    uint4 *vrec = nullptr;                  // {start_lo, degree, bits(h_MAX), bits(h_SUM)} per vertex
-    uint32_t *start_hi = nullptr;           // high row-start bits, only when ne >= 2^32
-    unsigned long long *scratch = nullptr;  // [0] walker queue, [1] error flag (int)
-    bool prepped = false;
-};
+using fw::host::check_logic;
+using fw::host::check_plan;
+using fw::host::fail;
+using fw::host::fill_args;
+using fw::host::fill_query;
+using fw::host::ok;
+using fw::host::plan_args;
 
 static void graph_free(fw_graph *g)
 {
@@ -86,7 +77,7 @@ static int dev_copy(T **dst, const T *src, int64_t count, int on_device)
 
 extern "C" {
 
-const char *fw_last_error(void) { return g_err.c_str(); }
+const char *fw_last_error(void) { return fw::host::g_err.c_str(); }
 
 int fw_graph_create(const fw_csr *in, fw_graph **out)
 {
@@ -235,7 +226,9 @@ int fw_plan_default(fw_plan *out)
     return ok();
 }
 
-static int check_logic(const fw_graph *g, const fw_logic *lg)
+}  // extern "C"
+
+int fw::host::check_logic(const fw_graph *g, const fw_logic *lg)
 {
     if (lg->kind == FW_NODE2VEC) {
         if (!(lg->p > 0.0f) || !(lg->q > 0.0f) || isinf(lg->p) || isinf(lg->q))
@@ -251,7 +244,7 @@ static int check_logic(const fw_graph *g, const fw_logic *lg)
 }
 
 // Per-query float constants, computed in float32 exactly as the definition states.
-static void fill_query(const fw_logic *lg, fw::QueryDev &q)
+void fw::host::fill_query(const fw_logic *lg, fw::QueryDev &q)
 {
     memset(&q, 0, sizeof(q));
     if (lg->kind == FW_NODE2VEC) {
@@ -271,7 +264,7 @@ static void fill_query(const fw_logic *lg, fw::QueryDev &q)
     }
 }
 
-static void fill_args(const fw_graph *g, const fw_logic *lg, fw::WalkArgs &a)
+void fw::host::fill_args(const fw_graph *g, const fw_logic *lg, fw::WalkArgs &a)
 {
     memset(&a, 0, sizeof(a));
     a.edges = g->edges;
@@ -285,7 +278,7 @@ static void fill_args(const fw_graph *g, const fw_logic *lg, fw::WalkArgs &a)
     a.item_bytes = 4 + (weighted ? 4 : 0) + (lg->kind == FW_METAPATH ? 1 : 0);
 }
 
-static int check_plan(const fw_plan *pl)
+int fw::host::check_plan(const fw_plan *pl)
 {
     if (pl->lanes != 64) return fail(FW_E_INVALID, "plan.lanes must be 64");
     if (pl->rjs_cap < 1) return fail(FW_E_INVALID, "plan.rjs_cap must be >= 1");
@@ -296,7 +289,7 @@ static int check_plan(const fw_plan *pl)
     return FW_OK;
 }
 
-static void plan_args(const fw_plan *pl, int32_t strategy, fw::WalkArgs &a)
+void fw::host::plan_args(const fw_plan *pl, int32_t strategy, fw::WalkArgs &a)
 {
     a.rho = pl->rho;
     a.d_lo = pl->d_lo;
@@ -304,6 +297,8 @@ static void plan_args(const fw_plan *pl, int32_t strategy, fw::WalkArgs &a)
     a.strategy = strategy;
     a.lds_cap = pl->lds_cap;
 }
+
+extern "C" {
 
 int fw_walk(fw_graph *g, const fw_logic *lg, const fw_plan *pl, int32_t strategy, const int32_t *starts, int64_t n,
             int32_t L, uint64_t seed, int32_t *paths, int32_t *lengths, uint64_t *stats, void *stream)

@@ -1,0 +1,50 @@
+// Host-side internals shared by the C ABI (fw_api.hip) and the walk server
+// (fw_server.hip): the graph object, error reporting and launch-argument helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/flexiwalk.h"
+#include "fw_internal.h"
+
+// Library-owned device copy of a graph (opaque to callers).
+struct fw_graph {
+    int device = 0;
+    int64_t nv = 0, ne = 0, max_deg = 0;
+    int64_t *row_ptr = nullptr;
+    int32_t *col = nullptr;
+    float *h = nullptr;
+    uint8_t *label = nullptr;
+    uint2 *edges = nullptr;                 // {col, bits(h)} per entry
+    uint4 *vrec = nullptr;                  // {start_lo, degree, bits(h_MAX), bits(h_SUM)} per vertex
+    uint32_t *start_hi = nullptr;           // high row-start bits, only when ne >= 2^32
+    unsigned long long *scratch = nullptr;  // [0] walker queue, [1] error flag (int)
+    bool prepped = false;
+};
+
+namespace fw {
+namespace host {
+
+// Record a message for fw_last_error (this thread) and return `code`.
+int fail(int code, const char *fmt, ...);
+// Clear the message and return FW_OK.
+int ok();
+
+int check_logic(const fw_graph *g, const fw_logic *lg);
+int check_plan(const fw_plan *pl);
+// Per-query float constants of a logic, in float32 exactly as the definition states.
+void fill_query(const fw_logic *lg, QueryDev &q);
+// Graph fields and logic-derived fields of a launch.
+void fill_args(const fw_graph *g, const fw_logic *lg, WalkArgs &a);
+void plan_args(const fw_plan *pl, int32_t strategy, WalkArgs &a);
+
+}  // namespace host
+}  // namespace fw
+
+#define HIP_TRY(expr)                                                                               \
+    do {                                                                                            \
+        hipError_t e_ = (expr);                                                                     \
+        if (e_ != hipSuccess)                                                                       \
+            return fw::host::fail(FW_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_));             \
+    } while (0)

@@ -47,7 +47,13 @@ struct QueryDev {
     int32_t L;
     int32_t schema_len;
     uint8_t schema[64];
+    // resumable walks (served form): prog[i] = steps done so far, or kDone when the walk
+    // has finished; done counts finished walkers.  Null for one-shot launches.
+    int32_t *prog;
+    int32_t *done;
 };
+
+constexpr int32_t kDone = INT32_MIN;
 
 // Device layout of a graph.  Besides the caller's CSR the library keeps
 //   edges[k] = {col[k], bits(h[k])}: one 8-byte load per proposed or scanned edge;
@@ -73,6 +79,7 @@ struct WalkArgs {
     int32_t strategy;
     int32_t lds_cap;
     int32_t item_bytes;         // col (+ h) (+ label) per scanned or proposed edge
+    int32_t tick_steps;         // resumable walks: steps per walker per launch
 
     QueryDev q0;                // the query of a single-query launch
     const QueryDev *queries;    // batched launch: nq entries, ascending `first`
@@ -81,6 +88,7 @@ struct WalkArgs {
 
 hipError_t launch_walk(const WalkArgs &a, int kind, bool weighted, bool batch, int grid, hipStream_t s);
 hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_layout(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int64_t ne,
                          uint2 *edges, uint4 *vrec, uint32_t *start_hi, hipStream_t s);
 hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv, uint4 *vrec, hipStream_t s);

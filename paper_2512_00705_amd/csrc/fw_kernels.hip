@@ -219,6 +219,7 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
     int64_t base = 0, pbase = 0;
     int32_t deg = 0, pdeg = 0;  // degrees (nv < 2^31)
     int32_t trials = 0;
+    int32_t stop_j = 0;  // resumable walks: suspend when j reaches this step
     bool fell_back = false;
     float B = 0.0f;
     // per-lane counters (32-bit counts, 64-bit bytes), flushed before a count could wrap
@@ -247,21 +248,43 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
                     const int32_t wq = BATCH ? query_of(a, w) : 0;
                     const QueryDev &Q = query<BATCH>(a, wq);
                     const int64_t local = w - Q.first;
-                    const int32_t s = Q.starts[local];
                     int32_t *row = Q.paths + local * ((int64_t)Q.L + 1);
-                    row[0] = s;
-                    st_bytes += 12 + 4 * (uint64_t)Q.L;
-                    if (s < 0 || (int64_t)s >= a.nv) {
-                        atomicOr(a.err, 1);
-                        for (int r = 1; r <= Q.L; ++r) row[r] = -1;
-                        Q.lengths[local] = 0;
-                    } else {
+                    const int32_t pj = (BATCH && Q.prog) ? Q.prog[local] : 0;
+                    if (pj > 0) {
+                        // resume a walk suspended after pj steps: cur and prev are the last
+                        // two slots it wrote, and prev's row is N(prev)
                         q = wq;
                         wid = (int32_t)local;
-                        cur = s;
-                        prev = -1;
-                        j = 0;
+                        j = pj;
+                        cur = row[pj];
+                        prev = row[pj - 1];
+                        const uint4 pr = a.vrec[prev];
+                        pbase = row_start(a, pr, prev);
+                        pdeg = (int32_t)pr.y;
+                        stop_j = pj + a.tick_steps;
+                        st_bytes += 4 + 8 + 16;
                         mode = kSetup;
+                    } else if (pj == 0) {
+                        const int32_t s = Q.starts[local];
+                        row[0] = s;
+                        st_bytes += 12 + 4 * (uint64_t)Q.L;
+                        if (s < 0 || (int64_t)s >= a.nv) {
+                            atomicOr(a.err, 1);
+                            for (int r = 1; r <= Q.L; ++r) row[r] = -1;
+                            Q.lengths[local] = 0;
+                            if (BATCH && Q.prog) {
+                                Q.prog[local] = kDone;
+                                atomicAdd(Q.done, 1);
+                            }
+                        } else {
+                            q = wq;
+                            wid = (int32_t)local;
+                            cur = s;
+                            prev = -1;
+                            j = 0;
+                            stop_j = a.tick_steps;
+                            mode = kSetup;
+                        }
                     }
                 }
             }
@@ -276,6 +299,14 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
             const QueryDev &Q = query<BATCH>(a, q);
             if (j == Q.L) {
                 Q.lengths[wid] = j;
+                if (BATCH && Q.prog) {
+                    Q.prog[wid] = kDone;
+                    atomicAdd(Q.done, 1);
+                }
+                mode = kIdle;
+                wid = -1;
+            } else if (BATCH && Q.prog && j == stop_j) {
+                Q.prog[wid] = j;  // suspend until the next launch
                 mode = kIdle;
                 wid = -1;
             } else {
@@ -456,6 +487,10 @@ __global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
             if (nxt < 0) {
                 for (int r = j + 1; r <= Q.L; ++r) row[r] = -1;
                 Q.lengths[wid] = j;
+                if (BATCH && Q.prog) {
+                    Q.prog[wid] = kDone;
+                    atomicAdd(Q.done, 1);
+                }
                 st[kStEarly] += 1;
                 mode = kIdle;
                 wid = -1;
@@ -479,6 +514,12 @@ __global__ void zero_kernel(unsigned long long *p, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
+}
+
+__global__ void fill_i32_kernel(int32_t *p, int64_t n, int32_t v)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 // h_MAX and h_SUM per row (Section 4.2 preprocess()), one wave per row.  The sum is
@@ -663,6 +704,15 @@ int walk_grid(int kind, bool weighted, bool batch, int lds_cap, int64_t n)
 hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(zero_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(fill_i32_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

@@ -210,6 +210,7 @@ def workload_graph(name: str) -> dict:
     * ``rmat22_labels``: the scale-22 graph plus uint8 labels uniform in 0..4.
     * ``rmat24_skew``: scale 24, edge factor 16, heavier skew (a, b, c) = (0.6, 0.175,
       0.175).
+    * ``rmat25_labels``: scale 25, edge factor 16 (~1.07 B entries), labels 0..4.
     """
     if name == "rmat12":
         return rmat(12, 8 << 12, seed=1)
@@ -217,6 +218,8 @@ def workload_graph(name: str) -> dict:
         return rmat(22, 16 << 22, seed=1)
     if name == "rmat22_labels":
         return rmat(22, 16 << 22, seed=1, nlabels=5)
+    if name == "rmat25_labels":
+        return rmat(25, 16 << 25, seed=1, nlabels=5)
     if name == "rmat24_skew":
         return rmat(24, 16 << 24, a=0.6, b=0.175, c=0.175, seed=1)
     if name.startswith("rmat") and name[4:].isdigit():
