@@ -112,7 +112,12 @@ def test_budget_queues_and_busy(g12, gg12):
     try:
         with pytest.raises(fw.FlexiWalkError):  # can never fit the budget
             fw.fw_server_submit(srv, fw_logic(big[0]), np.zeros(5000, np.int32), 200, 0)
-        ids = [fw.fw_server_submit(srv, fw_logic(lg), st, L, sd) for lg, st, L, sd in [big] + small]
+        ids = [fw.fw_server_submit(srv, fw_logic(big[0]), big[1], big[2], big[3])]
+        for _ in range(2000):  # until the long request holds its block
+            if fw.fw_server_stats(srv)["active"] >= 1:
+                break
+            time.sleep(0.001)
+        ids += [fw.fw_server_submit(srv, fw_logic(lg), st, L, sd) for lg, st, L, sd in small]
         time.sleep(0.01)
         st = fw.fw_server_stats(srv)
         assert st["waiting"] >= 1  # held back by the budget while the long walk runs
