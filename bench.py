@@ -46,6 +46,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-scale", type=int, default=25)
     ap.add_argument("--tick-steps", type=int, default=16)
+    ap.add_argument("--plan", default="", help="rho,d_lo,lds_cap: use this plan instead of autotuning")
     ap.add_argument("--per-query", type=int, default=1, help="batched: also time one launch per query")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB: only run a plain device-to-device copy of this size 3 times (counter calibration)")
@@ -89,7 +90,11 @@ def main():
     prep_ms = e0.elapsed_time(e1)
     logic = fw.fw_logic_node2vec(args.p, args.q, True)
     t1 = time.time()
-    plan = fw.fw_plan_autotune(gh, logic)
+    if args.plan:
+        rho, d_lo, cap = args.plan.split(",")
+        plan = fw.fw_plan_default(rho=float(rho), d_lo=int(d_lo), lds_cap=int(cap))
+    else:
+        plan = fw.fw_plan_autotune(gh, logic)
     tune_ms = (time.time() - t1) * 1e3
     log(f"preprocess {prep_ms:.2f} ms, autotune {tune_ms:.1f} ms, rho={plan.rho:.3f}")
 
@@ -186,7 +191,8 @@ def main():
                                f"(a=0.57,b=0.19,c=0.19, edge factor 16, {g['ne']} CSR entries), one walker "
                                f"per vertex ({nv}), L={L}, strategy={args.strategy}",
                    "walker_steps_per_walk_job": steps_per_walk, "preprocess_ms": prep_ms,
-                   "autotune_ms": tune_ms, "rho": plan.rho, "stats": st, "modes": modes},
+                   "autotune_ms": tune_ms, "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap},
+                   "stats": st, "modes": modes},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None},
         "cpu_baseline": cpu,

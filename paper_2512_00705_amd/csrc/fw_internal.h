@@ -28,6 +28,10 @@ constexpr int kDefaultLdsCap = 2048; // int32 entries of N(prev) per wavefront
 #define FW_RJS_BATCH 4
 #endif
 constexpr int kRjsBatch = FW_RJS_BATCH; // eRJS proposals whose loads a lane issues together
+#ifndef FW_MIN_WAVES
+#define FW_MIN_WAVES 4
+#endif
+constexpr int kMinWaves = FW_MIN_WAVES;  // resident waves per SIMD the walk kernel is compiled for
 
 // Per-query constants of a walk job.  Float constants are prepared on the host in float32
 // exactly as the definition states, so every float32 evaluation agrees bit for bit.

@@ -205,7 +205,7 @@ __device__ __forceinline__ void flush_stats(const WalkArgs &a, uint32_t (&cnt)[k
 // starts and outputs) share one launch; walker i of a query draws from that query's
 // seed with counter (i, step, draw, tag), exactly as in a launch of its own.
 template <int KIND, bool W, bool BATCH>
-__global__ void __launch_bounds__(kBlock, 4) walk_kernel(WalkArgs a)
+__global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
 {
     extern __shared__ int32_t lds_all[];
     int32_t *lds = lds_all + (threadIdx.x / kWave) * a.lds_cap;
