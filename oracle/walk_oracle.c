@@ -21,6 +21,15 @@
  *     helper generation, Eq. sum_estimation);
  *   - cost model: choose eRJS iff (EdgeCost_RJS / EdgeCost_RVS) * max w~ < sum w~
  *     (Section 4.1, Eq. runtime).
+ *   - optional split bound for Node2Vec (plan.bound = 1, not in the paper; any bound
+ *     that dominates w~ keeps rejection sampling exact, Section 3.3): the return edge
+ *     is the only one weighted 1/p, so the proposal board is deg columns of height
+ *     Bn = max(1, 1/q) * h_MAX plus one extra column of height E = max(0, w~ret - Bn)
+ *     that belongs to the return edge.  A trial lands in the extra column with
+ *     probability E / (deg * Bn + E) and then takes the return edge; otherwise it is
+ *     the usual uniform proposal against height Bn.  Each edge's total acceptance
+ *     mass is min(w~, Bn) + [return] E = w~, so the distribution is unchanged; the
+ *     expected trials drop from deg * B / S to (deg * Bn + E) / S.
  *
  * Canonical stream.  To compare samples one by one with a GPU run the random numbers
  * are a fixed function of (seed, walker, step, draw): Philox4x32-10 (Salmon, Moraes,
@@ -34,7 +43,8 @@
  * OG_MUTANT (tests only) plants one known mistake so that the test-suite can show its
  * pins catch it: 1 swaps the Node2Vec return weight 1/p for 1/q, 2 drops the
  * conditioning of the jump key, 3 keeps the skip sum after a jump, 4 never proposes
- * the last neighbour in eRJS, 5 drops h_MAX from the eRJS bound.
+ * the last neighbour in eRJS, 5 drops h_MAX from the eRJS bound, 6 makes the split
+ * bound's extra column the full return weight instead of its excess over Bn.
  */
 #ifndef OG_MUTANT
 #define OG_MUTANT 0
@@ -114,6 +124,7 @@ typedef struct {
     int32_t lanes;       /* eRVS lanes P */
     int32_t jump;        /* 1: Eq. (jump); 0: a key for every item */
     float bound_scale;   /* multiplies the eRJS bound (>= 1 keeps it a bound) */
+    int32_t bound;       /* 0: max(w) * h_MAX (Section 3.3); 1: Node2Vec split bound */
 } og_plan;
 
 enum { OG_AUTO = 0, OG_RVS_ONLY = 1, OG_RJS_ONLY = 2, OG_ITS = 3 };
@@ -306,20 +317,28 @@ static int64_t rvs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
     return best > -INFINITY ? best_i : -1;
 }
 
-/* eRJS, Section 3.3.  Returns the row offset, or -2 when the cap is reached. */
+/* eRJS, Section 3.3.  Returns the row offset, or -2 when the cap is reached.  With
+ * E > 0 (split bound) a trial first decides between the extra column of height E,
+ * owned by the return edge at row offset ret, and the deg regular columns of height B. */
 static int64_t rjs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int64_t base, int64_t deg,
-                          float B, og_info *info)
+                          float B, float E, int64_t ret, og_info *info)
 {
     uint32_t x[4];
     const og_logic *lg = cx->lg;
+    const float area = (float)deg * B + E;
     for (int t = 0; t < cx->pl->rjs_cap; ++t) {
         draw(cx->seed, w, (uint32_t)j, (uint32_t)t, 0, x);
+        info->trials++;
+        if (E > 0.0f) {
+            float z = og_uniform(x[3]) * area;
+            note_margin(info, z, E);
+            if (z < E) return ret;
+        }
         uint64_t R = ((uint64_t)x[1] << 32) | x[0];
         int64_t idx = (int64_t)(((unsigned __int128)R * (unsigned __int128)(uint64_t)deg) >> 64);
         if (OG_MUTANT == 4 && deg > 1) idx = (int64_t)(((unsigned __int128)R * (unsigned __int128)(uint64_t)(deg - 1)) >> 64);
         float wt = transition_weight(cx, base + idx, j, prev);
         float y = og_uniform(x[2]) * B;
-        info->trials++;
         info->bytes += bytes_per_item(cx);
         /* a membership search is needed only when the accept test is not already
            decided by the smallest and largest weight u could have */
@@ -382,8 +401,23 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
     const int weighted = lg->weighted && g->h;
     const float hm = (weighted && OG_MUTANT != 5) ? cx->hmax[cur] : 1.0f;
     const float hs = weighted ? cx->hsum[cur] : (float)deg;
-    const float B = (w_max(lg, j) * hm) * cx->pl->bound_scale; /* upper bound of max w~ */
-    const float Shat = w_avg(lg, j) * hs;                      /* estimate of sum w~ */
+    float B = (w_max(lg, j) * hm) * cx->pl->bound_scale; /* upper bound of max w~ */
+    const float Shat = w_avg(lg, j) * hs;                /* estimate of sum w~ */
+
+    /* split bound: regular height over the non-return weights, extra column for the
+       return edge's excess (w~ret of the edge cur -> prev, 0 if there is none) */
+    const int split = cx->pl->bound == 1 && lg->kind == OG_NODE2VEC && j > 0;
+    float E = 0.0f;
+    int64_t ret = -1;
+    if (split) {
+        B = (fmaxf(1.0f, 1.0f / lg->q) * hm) * cx->pl->bound_scale;
+        for (int64_t i = 0; i < deg; ++i)
+            if (g->col[base + i] == prev) ret = i;
+        if (ret >= 0) {
+            float wret = transition_weight(cx, base + ret, j, prev);
+            E = OG_MUTANT == 6 ? wret : fmaxf(0.0f, wret - B);
+        }
+    }
 
     int use_rjs = 0;
     if (cx->strategy == OG_RJS_ONLY) {
@@ -392,9 +426,12 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
     } else if (cx->strategy == OG_AUTO) {
         if (weighted) info->bytes += 8.0;
         if (deg >= cx->pl->d_lo) {
-            float lhs = cx->pl->rho * B;
-            note_margin(info, lhs, Shat);
-            use_rjs = lhs < Shat;
+            /* Eq. (runtime) per edge; with the split the expected-trial cost is
+               (deg * Bn + E) / S, compared against the eRVS cost deg */
+            float lhs = split ? cx->pl->rho * ((float)deg * B + E) : cx->pl->rho * B;
+            float rhs = split ? (float)deg * Shat : Shat;
+            note_margin(info, lhs, rhs);
+            use_rjs = lhs < rhs;
         }
     }
 
@@ -405,7 +442,7 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
     } else {
         off = -2;
         if (use_rjs) {
-            off = rjs_sample(cx, w, j, prev, base, deg, B, info);
+            off = rjs_sample(cx, w, j, prev, base, deg, B, E, ret, info);
             info->kind = 1;
         }
         if (off == -2) {

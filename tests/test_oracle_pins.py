@@ -219,6 +219,94 @@ def test_rjs_mean_trials_and_known_bound():
         assert abs(trials.mean() - want) < 5 * se, (trials.mean(), want)
 
 
+# ------------------------------------------------------------------ split bound (plan.bound = 1)
+# p = 0.25 makes the return edge the heaviest (1/p = 4 > 1 > 1/q), so the extra column
+# of the split bound is non-empty in most states
+N2V_RET = dict(kind=oracle.NODE2VEC, weighted=True, p=0.25, q=2.0)
+SPLIT = [
+    ("rjs", oracle.RJS_ONLY, oracle.Plan(bound=1)),
+    ("rjs_x4", oracle.RJS_ONLY, oracle.Plan(bound=1, bound_scale=4.0)),
+    ("auto", oracle.AUTO, oracle.Plan(bound=1, rho=1.0, lanes=2)),
+    ("rjs_cap1", oracle.RJS_ONLY, oracle.Plan(bound=1, rjs_cap=1, lanes=2)),
+]
+
+
+@pytest.mark.parametrize("name,strategy,plan", SPLIT, ids=[s[0] for s in SPLIT])
+@pytest.mark.parametrize("logic", [N2V_RET, N2V, dict(N2V_RET, weighted=False)], ids=["ret", "n2v", "unweighted"])
+def test_split_bound_paths_chisquare(name, strategy, plan, logic):
+    """Any bound that dominates every w~ leaves the distribution of Eq. (prob) unchanged
+    (Section 3.3): the split bound's walks follow the exact path distribution."""
+    g = triangle_graph()
+    lg = oracle.Logic(**logic)
+    n = 60000
+    for start in (0, 4):
+        counts, _ = _walk_counts(g, lg, plan, strategy, start, 3, n, seed=11 + start)
+        probs = exact.path_distribution(g, lg, start, 3)
+        assert chisq_pvalue(counts, probs, n) > P_OK, (name, start)
+
+
+def test_split_bound_hub_distribution():
+    """Second step at the 600-neighbour hub, where the return edge is one column of 600."""
+    g = hub_ring_graph()
+    lg = oracle.Logic(**N2V_RET)
+    og = oracle.Graph(g)
+    n = 40000
+    r = oracle.walk(og, lg, oracle.Plan(bound=1), oracle.RJS_ONLY, np.full(n, 1, np.int32), 2, 5, diagnostics=False)
+    went_hub = r.paths[:, 1] == 0
+    counts = {}
+    for v, c in zip(*np.unique(r.paths[went_hub, 2], return_counts=True)):
+        counts[int(v)] = int(c)
+    assert chisq_pvalue(counts, exact.transition(g, lg, 1, 1, 0), int(went_hub.sum())) > P_OK
+
+
+def test_split_bound_mean_trials():
+    """Mean trials of the split board = (deg * Bn + E) / sum w~, against deg * B / sum w~
+    for the paper's bound.  State prev = 3, cur = 1 of the triangle graph: N(1) = {0, 2, 3}
+    with h = 1, 3, 4, so w~ = 0.5, 3, 16 (two hops, common neighbour, return), h_MAX = 4,
+    Bn = max(1, 1/q) * 4 = 4, E = 16 - 4 = 12: 24 / 19.5 trials against 3 * 16 / 19.5."""
+    g = triangle_graph()
+    lg = oracle.Logic(**N2V_RET)
+    og = oracle.Graph(g)
+    og.aux()
+    ws = [exact.transition_weight(g, lg, 1, 3, k) for k in range(int(g["row_ptr"][1]), int(g["row_ptr"][2]))]
+    assert sorted(float(w) for w in ws) == [0.5, 3.0, 16.0]
+    n = 40000
+    for plan, want in ((oracle.Plan(bound=1, rjs_cap=100000), 24.0 / 19.5),
+                       (oracle.Plan(bound=0, rjs_cap=100000), 48.0 / 19.5)):
+        trials = np.empty(n)
+        for i in range(n):
+            trials[i] = oracle.step_once(og, lg, plan, oracle.RJS_ONLY, 3, i, 1, 3, 1)[3]
+        se = math.sqrt(want * (want - 1) / n)
+        assert abs(trials.mean() - want) < 5 * se, (plan.bound, trials.mean(), want)
+
+
+def test_split_bound_is_paper_bound_without_excess():
+    """With 1/p <= max(1, 1/q) the extra column is empty and Bn is the paper's bound,
+    so eRJS-only walks draw exactly the same samples under both settings."""
+    g = synth.rmat(10, 8 << 10, seed=4)
+    og = oracle.Graph(g)
+    lg = oracle.Logic(**N2V)
+    st = np.arange(g["nv"], dtype=np.int32)
+    a = oracle.walk(og, lg, oracle.Plan(bound=0), oracle.RJS_ONLY, st, 12, 9, diagnostics=False)
+    b = oracle.walk(og, lg, oracle.Plan(bound=1), oracle.RJS_ONLY, st, 12, 9, diagnostics=False)
+    np.testing.assert_array_equal(a.paths, b.paths)
+    assert a.counters["rjs_trials"] == b.counters["rjs_trials"]
+
+
+def test_split_bound_fewer_trials_rmat():
+    """On a skewed graph the split board needs fewer trials per step than the paper's
+    bound when the return weight dominates (the reason it exists)."""
+    g = synth.rmat(12, 8 << 12, seed=2)
+    og = oracle.Graph(g)
+    lg = oracle.Logic(**N2V_RET)
+    st = np.arange(g["nv"], dtype=np.int32)
+    a = oracle.walk(og, lg, oracle.Plan(bound=0), oracle.RJS_ONLY, st, 20, 9, diagnostics=False)
+    b = oracle.walk(og, lg, oracle.Plan(bound=1), oracle.RJS_ONLY, st, 20, 9, diagnostics=False)
+    ta = a.counters["rjs_trials"] / a.counters["steps"]
+    tb = b.counters["rjs_trials"] / b.counters["steps"]
+    assert tb < 0.75 * ta, (ta, tb)
+
+
 # ------------------------------------------------------------------ closed form / invariants
 def test_stationary_visits_proportional_to_degree():
     """p = q = 1, h = 1 on a connected non-bipartite graph: visits -> deg / 2|E|."""
@@ -288,6 +376,7 @@ MUTANTS = {
     3: "skip sum not reset after a jump",
     4: "eRJS never proposes the last neighbour",
     5: "eRJS bound without h_MAX",
+    6: "split bound's extra column is the whole return weight",
 }
 
 
@@ -299,13 +388,14 @@ def mutant_libs(tmp_path_factory):
 
 @pytest.mark.parametrize("mut", sorted(MUTANTS), ids=[MUTANTS[k] for k in sorted(MUTANTS)])
 def test_planted_mistake_is_caught(mut, mutant_libs):
-    lg = oracle.Logic(**N2V)
     g = triangle_graph()
     caught = []
     with oracle.use_library(mutant_libs[mut]):
-        for name, strategy, plan in (("rvs_P2", oracle.RVS_ONLY, oracle.Plan(lanes=2)),
-                                     ("rvs_P1", oracle.RVS_ONLY, oracle.Plan(lanes=1)),
-                                     ("rjs", oracle.RJS_ONLY, oracle.Plan())):
+        for name, logic, strategy, plan in (("rvs_P2", N2V, oracle.RVS_ONLY, oracle.Plan(lanes=2)),
+                                            ("rvs_P1", N2V, oracle.RVS_ONLY, oracle.Plan(lanes=1)),
+                                            ("rjs", N2V, oracle.RJS_ONLY, oracle.Plan()),
+                                            ("rjs_split", N2V_RET, oracle.RJS_ONLY, oracle.Plan(bound=1))):
+            lg = oracle.Logic(**logic)
             n = 60000
             counts, _ = _walk_counts(g, lg, plan, strategy, 0, 3, n, seed=7)
             probs = exact.path_distribution(g, lg, 0, 3)
