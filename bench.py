@@ -20,6 +20,49 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2512_00705_amd/csrc/fw_kernels.hip", "paper_2512_00705_amd/csrc/fw_device.h",
+                  "paper_2512_00705_amd/csrc/fw_internal.h")
+TRAFFIC_FILE = "profiles/traffic_walk_kernel_node2vec_rmat22.txt"
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+TRAFFIC_STATS = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", "rvs_triggers")
+
+
+def measured_traffic(plan, st: dict) -> float | None:
+    """HBM bytes per launch from the committed counter summary, or None unless it was
+    taken on this kernel source and on a launch that made the same decisions (the same
+    step, trial and fall-back counts, and the same LDS cap when eRVS ran): FETCH_SIZE and
+    WRITE_SIZE scaled by what the same counters read for a plain device copy of known
+    size."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        if kv.get("kernel_sources_sha256") != kernel_sources_sha256():
+            return None
+        rec = dict(x.split("=") for x in kv["stats"].split(","))
+        if any(int(rec[k]) != int(st[k]) for k in TRAFFIC_STATS):
+            return None
+        if int(st["rvs_steps"]) + int(st["rjs_fallbacks"]) > 0 and int(kv["lds_cap"]) != plan.lds_cap:
+            return None
+        return 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["copy_fetch_factor"])
+                         + float(kv["write_kib_per_launch"]) * float(kv["copy_write_factor"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def log(*a):
@@ -46,7 +89,7 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-scale", type=int, default=25)
     ap.add_argument("--tick-steps", type=int, default=16)
-    ap.add_argument("--plan", default="", help="rho,d_lo,lds_cap: use this plan instead of autotuning")
+    ap.add_argument("--plan", default="", help="rho,d_lo,lds_cap[,bound]: use this plan instead of autotuning")
     ap.add_argument("--per-query", type=int, default=1, help="batched: also time one launch per query")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB: only run a plain device-to-device copy of this size 3 times (counter calibration)")
@@ -91,12 +134,14 @@ def main():
     logic = fw.fw_logic_node2vec(args.p, args.q, True)
     t1 = time.time()
     if args.plan:
-        rho, d_lo, cap = args.plan.split(",")
-        plan = fw.fw_plan_default(rho=float(rho), d_lo=int(d_lo), lds_cap=int(cap))
+        f = args.plan.split(",")
+        plan = fw.fw_plan_default(rho=float(f[0]), d_lo=int(f[1]), lds_cap=int(f[2]),
+                                  bound=int(f[3]) if len(f) > 3 else 0)
     else:
         plan = fw.fw_plan_autotune(gh, logic)
     tune_ms = (time.time() - t1) * 1e3
-    log(f"preprocess {prep_ms:.2f} ms, autotune {tune_ms:.1f} ms, rho={plan.rho:.3f}")
+    log(f"preprocess {prep_ms:.2f} ms, autotune {tune_ms:.1f} ms, rho={plan.rho:.3f} d_lo={plan.d_lo} "
+        f"lds_cap={plan.lds_cap} bound={plan.bound}")
 
     nv, L, seed = g["nv"], args.L, 42
     starts = torch.arange(nv, dtype=torch.int32, device=dev)
@@ -105,7 +150,7 @@ def main():
     stats = torch.zeros(fw.FW_NSTATS, dtype=torch.int64, device=dev)
     strat = {"auto": fw.FW_AUTO, "rvs": fw.FW_RVS_ONLY, "rjs": fw.FW_RJS_ONLY}
 
-    def run(mode: str, steps: int, warmup: int):
+    def run(mode: str, steps: int, warmup: int, plan=plan, paths=paths, lengths=lengths):
         for _ in range(warmup):
             fw.fw_walk(gh, logic, plan, strat[mode], starts, nv, L, seed, paths, lengths, None)
         torch.cuda.synchronize()
@@ -126,8 +171,6 @@ def main():
 
     ms, wall, st = run(args.strategy, args.steps, args.warmup)
     rng = np.random.default_rng(7)
-    probe = np.sort(rng.choice(nv, size=min(4096, nv), replace=False)).astype(np.int64)
-    probe_paths = paths[torch.from_numpy(probe).to(dev)].cpu().numpy()  # before other modes overwrite paths
     avg_ms = float(np.mean(ms))
     steps_per_walk = st["steps"]
     value = steps_per_walk / (avg_ms / 1e3)
@@ -136,15 +179,23 @@ def main():
 
     modes = {}
     if args.modes:
-        for m in ("rvs", "rjs"):
-            if m == args.strategy:
-                continue
-            mms, _, mst = run(m, 2, 1)
+        # own output buffers: the timed job's walks stay for the CPU comparison below
+        m_paths, m_lengths = torch.empty_like(paths), torch.empty_like(lengths)
+        # the single-kernel modes, and the same job under the other eRJS bound
+        other = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap, bound=1 - plan.bound)
+        sym = fw.fw_graph_info(gh)[3]
+        cases = [(m + "_only", m, plan) for m in ("rvs", "rjs") if m != args.strategy]
+        if sym or other.bound == 0:
+            cases.append((("split" if other.bound else "paper") + "_bound", args.strategy, other))
+        for name, m, pl in cases:
+            mms, _, mst = run(m, 2, 1, plan=pl, paths=m_paths, lengths=m_lengths)
             a = float(np.mean(mms))
-            modes[m + "_only"] = {"ms": round(a, 3), "walker_steps_per_s": mst["steps"] / (a / 1e3),
-                                  "alg_GBps": mst["alg_bytes"] / (a / 1e3) / 1e9,
-                                  "rjs_steps": mst["rjs_steps"], "rvs_steps": mst["rvs_steps"]}
-            log(f"{m}: ms {mms}, stats {mst}")
+            modes[name] = {"ms": round(a, 3), "walker_steps_per_s": mst["steps"] / (a / 1e3),
+                           "alg_GBps": mst["alg_bytes"] / (a / 1e3) / 1e9, "bound": pl.bound,
+                           "rjs_steps": mst["rjs_steps"], "rvs_steps": mst["rvs_steps"],
+                           "trials_per_rjs_step": mst["rjs_trials"] / max(1, mst["rjs_steps"] + mst["rjs_fallbacks"])}
+            log(f"{name}: ms {mms}, stats {mst}")
+        del m_paths, m_lengths
 
     cpu = None
     if args.cpu_baseline:
@@ -152,7 +203,7 @@ def main():
         og = oracle.Graph(g)
         og.aux()
         lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=args.p, q=args.q)
-        pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap)
+        pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap, bound=plan.bound)
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
         smode = {"auto": 0, "rvs": 1, "rjs": 2}[args.strategy]
         k = args.cpu_sample or 2048
@@ -174,6 +225,7 @@ def main():
         log(f"cpu oracle: {cpu}")
 
     fw.fw_graph_destroy(gh)
+    traffic = measured_traffic(plan, st)
     out = {
         "metric": "walker-steps/sec + achieved HBM GB/s, node2vec R-MAT s22; p99 latency served",
         "value": value,
@@ -191,10 +243,11 @@ def main():
                                f"(a=0.57,b=0.19,c=0.19, edge factor 16, {g['ne']} CSR entries), one walker "
                                f"per vertex ({nv}), L={L}, strategy={args.strategy}",
                    "walker_steps_per_walk_job": steps_per_walk, "preprocess_ms": prep_ms,
-                   "autotune_ms": tune_ms, "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap},
-                   "stats": st, "modes": modes},
+                   "autotune_ms": tune_ms, "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound},
+                   "stats": st, "modes": modes,
+                   "hbm_traffic_GBps": None if traffic is None else traffic / (avg_ms / 1e3) / 1e9},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None},
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

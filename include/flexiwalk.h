@@ -86,7 +86,18 @@ typedef struct fw_logic {
  *   rjs_cap  eRJS trials before an exact fall-back to eRVS, >= 1
  *   lanes    eRVS lanes per step; must be 64 (one wavefront)
  *   lds_cap  int32 entries of N(prev) staged in LDS per wavefront (0 = default)
- *   grid     persistent blocks (0 = fill the device) */
+ *   grid     persistent blocks (0 = fill the device)
+ *   bound    eRJS bound (changes the stream, never the distribution):
+ *            0  max(w) * h_MAX of Section 3.3;
+ *            1  Node2Vec split bound, an extension of Section 3.3 (any bound that
+ *               dominates every w~ keeps eRJS exact): columns of height
+ *               max(1, 1/q) * h_MAX plus one extra column holding the return edge's
+ *               excess (1/p) * h(cur, prev) - that height, taken with probability
+ *               excess / (deg * height + excess) per trial.  Needs a graph whose
+ *               reverse edges exist with equal h (fw_graph_info reports it); MetaPath
+ *               ignores it.  The cost model then compares rho * (deg * height +
+ *               excess) with deg * S^.
+ *   reserved must be 0 */
 typedef struct fw_plan {
     float rho;
     int32_t d_lo;
@@ -94,7 +105,8 @@ typedef struct fw_plan {
     int32_t lanes;
     int32_t lds_cap;
     int32_t grid;
-    int32_t reserved[2];
+    int32_t bound;
+    int32_t reserved;
 } fw_plan;
 
 /* Counters accumulated by fw_walk into a device array of FW_NSTATS uint64 values:
@@ -105,7 +117,7 @@ typedef struct fw_plan {
  *   membership probes, start/path/length I/O). */
 
 /* Copy a CSR graph into library-owned device memory (Section 2.1 graph G with N(v),
- * d(v), h, labels).  Validates row_ptr (monotone, row_ptr[0] = 0, row_ptr[nv] = ne), col
+ * d(v), h, labels); nv < 2^30.  Validates row_ptr (monotone, row_ptr[0] = 0, row_ptr[nv] = ne), col
  * (in range, strictly ascending per row) and h (finite, >= 0); on failure returns
  * FW_E_INVALID and allocates nothing.  Device-side inputs are validated on the device
  * before the call returns (synchronous).  *out is set only on FW_OK. */
@@ -124,8 +136,10 @@ int fw_graph_preprocess(fw_graph *g, void *stream);
 /* Copy h_MAX and h_SUM (nv floats each, host pointers) back to the host; synchronous. */
 int fw_graph_export_aux(const fw_graph *g, float *hmax, float *hsum);
 
-/* Sizes of a graph: vertices, edges, maximum degree (any pointer may be NULL). */
-int fw_graph_info(const fw_graph *g, int64_t *nv, int64_t *ne, int64_t *max_deg);
+/* Sizes of a graph: vertices, edges, maximum degree, and 1 if every edge (v, u) has a
+ * reverse edge (u, v) with the same h (checked on the device by fw_graph_create), else 0
+ * (any pointer may be NULL). */
+int fw_graph_info(const fw_graph *g, int64_t *nv, int64_t *ne, int64_t *max_deg, int32_t *symmetric);
 
 /* Build a Node2Vec logic; p, q finite and > 0. */
 int fw_logic_node2vec(float p, float q, int32_t weighted, fw_logic *out);
@@ -145,8 +159,9 @@ int fw_plan_default(fw_plan *out);
 int fw_plan_profile(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stream);
 
 /* fw_plan_profile, then a measured search: short seeded sample walks (up to 2^18 walkers,
- * 16 steps, AUTO) are timed for rho scaled by 1/16 .. 4 around the profiled value, then for
- * the degree gate d_lo in {0, 8, 32, 128} and the LDS budget for N(prev); the fastest plan
+ * 16 steps, AUTO) are timed for rho scaled by 1/16 .. 4 around the profiled value (with
+ * each eRJS bound: the split bound too for Node2Vec on a symmetric graph), then for the
+ * degree gate d_lo in {0, 8, 32, 128} and the LDS budget for N(prev); the fastest plan
  * is returned.  Every candidate samples the same distribution; only the choice of kernel
  * per step, and so the random stream, differs.  Allocates temporary device memory;
  * synchronous on `stream`. */

@@ -55,7 +55,7 @@ class fw_logic(ctypes.Structure):
 class fw_plan(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_float), ("d_lo", ctypes.c_int32), ("rjs_cap", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("lds_cap", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("bound", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class fw_query(ctypes.Structure):
@@ -74,7 +74,7 @@ def _load():
         "fw_graph_destroy": ([P], ctypes.c_int),
         "fw_graph_preprocess": ([P, P], ctypes.c_int),
         "fw_graph_export_aux": ([P, P, P], ctypes.c_int),
-        "fw_graph_info": ([P, P, P, P], ctypes.c_int),
+        "fw_graph_info": ([P, P, P, P, P], ctypes.c_int),
         "fw_logic_node2vec": ([ctypes.c_float, ctypes.c_float, I32, ctypes.POINTER(fw_logic)], ctypes.c_int),
         "fw_logic_metapath": ([P, I32, I32, ctypes.POINTER(fw_logic)], ctypes.c_int),
         "fw_plan_default": ([ctypes.POINTER(fw_plan)], ctypes.c_int),
@@ -161,9 +161,10 @@ def fw_graph_export_aux(g: int, nv: int):
 
 
 def fw_graph_info(g: int):
-    nv, ne, md = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-    _check(_lib.fw_graph_info(g, ctypes.byref(nv), ctypes.byref(ne), ctypes.byref(md)))
-    return nv.value, ne.value, md.value
+    """(nv, ne, max_deg, symmetric)"""
+    nv, ne, md, sym = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    _check(_lib.fw_graph_info(g, ctypes.byref(nv), ctypes.byref(ne), ctypes.byref(md), ctypes.byref(sym)))
+    return nv.value, ne.value, md.value, bool(sym.value)
 
 
 def fw_logic_node2vec(p: float, q: float, weighted: bool = True) -> fw_logic:

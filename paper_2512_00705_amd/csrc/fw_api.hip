@@ -41,6 +41,7 @@ int ok()
 }  // namespace fw
 
 using fw::host::check_logic;
+using fw::host::check_bound;
 using fw::host::check_plan;
 using fw::host::fail;
 using fw::host::fill_args;
@@ -83,7 +84,8 @@ int fw_graph_create(const fw_csr *in, fw_graph **out)
 {
     if (!in || !out) return fail(FW_E_INVALID, "fw_graph_create: null argument");
     if (in->nv < 0 || in->ne < 0) return fail(FW_E_INVALID, "fw_graph_create: negative size");
-    if (in->nv >= ((int64_t)1 << 31)) return fail(FW_E_INVALID, "fw_graph_create: nv must be < 2^31");
+    // vertex ids, degrees and search brackets are int32 on the device
+    if (in->nv >= ((int64_t)1 << 30)) return fail(FW_E_INVALID, "fw_graph_create: nv must be < 2^30");
     if (!in->row_ptr || (in->ne > 0 && !in->col))
         return fail(FW_E_INVALID, "fw_graph_create: row_ptr/col missing");
 
@@ -137,6 +139,14 @@ int fw_graph_create(const fw_csr *in, fw_graph **out)
                     "fw_graph_create: col must be in [0, nv) and strictly ascending per row; h finite and >= 0");
     }
     g->max_deg = (int64_t)host_chk[1];
+    // symmetry decides whether the split eRJS bound may be used; not an error
+    e = fw::launch_check_symmetry(g->row_ptr, g->col, g->h, g->nv, (int *)chk, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(host_chk, chk, sizeof(host_chk), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        graph_free(g);
+        return fail(FW_E_DEVICE, "fw_graph_create: %s", hipGetErrorString(e));
+    }
+    g->symmetric = (host_chk[0] & 16u) == 0;
     e = fw::launch_layout(g->row_ptr, g->col, g->h, g->nv, g->ne, g->edges, g->vrec, g->start_hi, nullptr);
     if (e == hipSuccess) e = hipMemset(g->scratch, 0, 4 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -179,12 +189,13 @@ int fw_graph_export_aux(const fw_graph *g, float *hmax, float *hsum)
     return ok();
 }
 
-int fw_graph_info(const fw_graph *g, int64_t *nv, int64_t *ne, int64_t *max_deg)
+int fw_graph_info(const fw_graph *g, int64_t *nv, int64_t *ne, int64_t *max_deg, int32_t *symmetric)
 {
     if (!g) return fail(FW_E_INVALID, "fw_graph_info: null graph");
     if (nv) *nv = g->nv;
     if (ne) *ne = g->ne;
     if (max_deg) *max_deg = g->max_deg;
+    if (symmetric) *symmetric = g->symmetric ? 1 : 0;
     return ok();
 }
 
@@ -223,6 +234,7 @@ int fw_plan_default(fw_plan *out)
     out->lanes = 64;
     out->lds_cap = fw::kDefaultLdsCap;
     out->grid = 0;
+    out->bound = 0;
     return ok();
 }
 
@@ -286,6 +298,15 @@ int fw::host::check_plan(const fw_plan *pl)
     if (pl->d_lo < 0) return fail(FW_E_INVALID, "plan.d_lo must be >= 0");
     if (pl->lds_cap < 0 || pl->lds_cap > 16384) return fail(FW_E_INVALID, "plan.lds_cap in [0, 16384]");
     if (pl->grid < 0) return fail(FW_E_INVALID, "plan.grid must be >= 0");
+    if (pl->bound < 0 || pl->bound > 1) return fail(FW_E_INVALID, "plan.bound must be 0 or 1");
+    if (pl->reserved != 0) return fail(FW_E_INVALID, "plan.reserved must be 0");
+    return FW_OK;
+}
+
+int fw::host::check_bound(const fw_graph *g, const fw_plan *pl, const fw_logic *lg)
+{
+    if (pl->bound == 1 && lg->kind == FW_NODE2VEC && !g->symmetric)
+        return fail(FW_E_INVALID, "plan.bound = 1 needs every edge's reverse with the same h (fw_graph_info)");
     return FW_OK;
 }
 
@@ -296,6 +317,7 @@ void fw::host::plan_args(const fw_plan *pl, int32_t strategy, fw::WalkArgs &a)
     a.rjs_cap = pl->rjs_cap;
     a.strategy = strategy;
     a.lds_cap = pl->lds_cap;
+    a.bound = pl->bound;
 }
 
 extern "C" {
@@ -311,6 +333,7 @@ int fw_walk(fw_graph *g, const fw_logic *lg, const fw_plan *pl, int32_t strategy
     int rc = check_logic(g, lg);
     if (rc != FW_OK) return rc;
     if ((rc = check_plan(pl)) != FW_OK) return rc;
+    if ((rc = check_bound(g, pl, lg)) != FW_OK) return rc;
     const bool weighted = lg->weighted && g->h;
     if (weighted && strategy != FW_RVS_ONLY && !g->prepped)
         return fail(FW_E_STATE, "fw_walk: call fw_graph_preprocess before a weighted eRJS/AUTO walk");
@@ -474,16 +497,21 @@ int fw_plan_autotune(fw_graph *g, const fw_logic *lg, fw_plan *out, void *stream
     };
     // cost-model constant around the profiled value, then the degree gate, then the LDS
     // budget for N(prev)
+    // (for each eRJS bound the graph and logic allow)
     fw_plan bestp = *out;
     float bestt = 1e30f;
     const float rho0 = out->rho;
     const float scales[] = {0.0625f, 0.25f, 0.5f, 1.0f, 2.0f, 4.0f};
-    for (float sc : scales) {
-        fw_plan p = *out;
-        p.rho = std::max(1e-3f, rho0 * sc);
-        float t;
-        if ((rc = time_plan(p, &t)) != FW_OK) return rc;
-        if (t < bestt) bestt = t, bestp = p;
+    const int nbound = (lg->kind == FW_NODE2VEC && g->symmetric) ? 2 : 1;
+    for (int32_t bound = 0; bound < nbound; ++bound) {
+        for (float sc : scales) {
+            fw_plan p = *out;
+            p.rho = std::max(1e-3f, rho0 * sc);
+            p.bound = bound;
+            float t;
+            if ((rc = time_plan(p, &t)) != FW_OK) return rc;
+            if (t < bestt) bestt = t, bestp = p;
+        }
     }
     for (int32_t d : {8, 32, 128}) {
         fw_plan p = bestp;
@@ -540,6 +568,7 @@ int fw_batch_create(fw_graph *g, const fw_query *qs, int64_t nq, const fw_plan *
     for (int64_t i = 0; i < nq; ++i) {
         const fw_query &q = qs[i];
         if ((rc = check_logic(g, &q.logic)) != FW_OK) return rc;
+        if ((rc = check_bound(g, pl, &q.logic)) != FW_OK) return rc;
         if (q.logic.kind != qs[0].logic.kind || (q.logic.weighted != 0) != (qs[0].logic.weighted != 0))
             return fail(FW_E_INVALID, "fw_batch_create: all queries of a batch share kind and weighting");
         if (q.n < 0 || q.n >= ((int64_t)1 << 31)) return fail(FW_E_INVALID, "query %lld: n out of range", (long long)i);

@@ -113,40 +113,39 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// Binary search for u in the ascending array a[0, n).
-template <typename IdxT>
-__device__ __forceinline__ bool sorted_contains(const int32_t *a, IdxT n, int32_t u)
+// Binary search for u in the ascending array a[0, n): its position, or -1.
+__device__ __forceinline__ int64_t sorted_find(const int32_t *a, int64_t n, int32_t u)
 {
-    const IdxT total = n;
-    IdxT lo = 0;
-    while (n > 0) {
-        const IdxT half = n >> 1;
+    int64_t lo = 0, len = n;
+    while (len > 0) {
+        const int64_t half = len >> 1;
         if (a[lo + half] < u) {
             lo += half + 1;
-            n -= half + 1;
+            len -= half + 1;
         } else {
-            n = half;
+            len = half;
         }
     }
-    return lo < total && a[lo] == u;
+    return (lo < n && a[lo] == u) ? lo : -1;
 }
 
 // Membership of u in the strictly ascending array a[0, n) whose values lie in [0, vend).
 // Interpolation search: the bracket (lo, hi) starts at the virtual ends a[-1] = -1 and
 // a[n] = vend; each probe guesses u's position from the bracket values.  Vertex ids of
 // a row are spread almost uniformly, so a few probes suffice; after three guesses the
-// search bisects, which bounds it by 3 + log2(n) probes for any input.
-template <typename IdxT>
-__device__ __forceinline__ bool sorted_contains_interp(const int32_t *a, IdxT n, int32_t u, int64_t vend)
+// search bisects, which bounds it by 3 + log2(n) probes for any input.  The guess is
+// only a position inside the bracket, so it uses a fast reciprocal: any value works.
+// Requires vend < 2^30 so that bracket widths fit int32.
+__device__ __forceinline__ bool sorted_contains_interp(const int32_t *a, int32_t n, int32_t u, int32_t vend)
 {
-    IdxT lo = -1, hi = n;
-    int64_t vlo = -1, vhi = vend;
+    int32_t lo = -1, hi = n;
+    int32_t vlo = -1, vhi = vend;
     int it = 0;
     while (hi - lo > 1) {
-        IdxT pos;
+        int32_t pos;
         if (it < 3) {
-            const float f = (float)(u - vlo) / (float)(vhi - vlo);
-            pos = lo + (IdxT)(f * (float)(hi - lo));
+            const float f = (float)(u - vlo) * __builtin_amdgcn_rcpf((float)(vhi - vlo));
+            pos = lo + (int32_t)(f * (float)(hi - lo));
         } else {
             pos = lo + ((hi - lo) >> 1);
         }

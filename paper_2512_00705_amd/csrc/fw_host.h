@@ -21,6 +21,7 @@ struct fw_graph {
     uint32_t *start_hi = nullptr;           // high row-start bits, only when ne >= 2^32
     unsigned long long *scratch = nullptr;  // [0] walker queue, [1] error flag (int)
     bool prepped = false;
+    bool symmetric = false;                 // every (v, u) has a reverse (u, v) with equal h
 };
 
 namespace fw {
@@ -33,6 +34,8 @@ int ok();
 
 int check_logic(const fw_graph *g, const fw_logic *lg);
 int check_plan(const fw_plan *pl);
+// plan.bound = 1 for Node2Vec needs a symmetric graph
+int check_bound(const fw_graph *g, const fw_plan *pl, const fw_logic *lg);
 // Per-query float constants of a logic, in float32 exactly as the definition states.
 void fill_query(const fw_logic *lg, QueryDev &q);
 // Graph fields and logic-derived fields of a launch.

@@ -25,7 +25,7 @@ constexpr int kBlock = 256;          // 4 wavefronts per block, each independent
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kDefaultLdsCap = 2048; // int32 entries of N(prev) per wavefront
 #ifndef FW_RJS_BATCH
-#define FW_RJS_BATCH 4
+#define FW_RJS_BATCH 2
 #endif
 constexpr int kRjsBatch = FW_RJS_BATCH; // eRJS proposals whose loads a lane issues together
 #ifndef FW_MIN_WAVES
@@ -84,6 +84,7 @@ struct WalkArgs {
     int32_t lds_cap;
     int32_t item_bytes;         // col (+ h) (+ label) per scanned or proposed edge
     int32_t tick_steps;         // resumable walks: steps per walker per launch
+    int32_t bound;              // 1: Node2Vec split eRJS bound (symmetric graphs only)
 
     QueryDev q0;                // the query of a single-query launch
     const QueryDev *queries;    // batched launch: nq entries, ascending `first`
@@ -96,6 +97,10 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_layout(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int64_t ne,
                          uint2 *edges, uint4 *vrec, uint32_t *start_hi, hipStream_t s);
 hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv, uint4 *vrec, hipStream_t s);
+// Sets bit 4 of *err unless every entry (v, u) has a reverse (u, v) with the same h.
+// Rows must already be validated (in range, strictly ascending).
+hipError_t launch_check_symmetry(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int *err,
+                                 hipStream_t s);
 hipError_t launch_validate_rows(const int64_t *row_ptr, int64_t nv, int64_t ne, int *err, hipStream_t s);
 hipError_t launch_validate_edges(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv,
                                  int *err, unsigned long long *max_deg, hipStream_t s);

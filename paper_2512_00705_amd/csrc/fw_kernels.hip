@@ -60,7 +60,7 @@ __device__ __forceinline__ float edge_weight(const WalkArgs &a, const QueryDev &
         if (j == 0) return hv;
         const int32_t u = (int32_t)e.x;
         if (u == prev) return Q.inv_p * hv;
-        return sorted_contains_interp(m.p, m.len, u, a.nv) ? hv : Q.inv_q * hv;
+        return sorted_contains_interp(m.p, (int32_t)m.len, u, (int32_t)a.nv) ? hv : Q.inv_q * hv;
     } else {
         return a.label[k] == want ? hv : 0.0f;
     }
@@ -72,11 +72,12 @@ __device__ __forceinline__ int64_t row_start(const WalkArgs &a, uint4 r, int32_t
 }
 
 // eRVS for one step, all 64 lanes cooperating.  Returns the next vertex or -1 when no
-// neighbour has positive weight.  `trig` receives the number of jump events.
+// neighbour has positive weight, with the h of the chosen edge in `hsel`.  `trig`
+// receives the number of jump events.
 template <int KIND, bool W>
 __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q, const Mem &mem, uint32_t wid,
                                             int j, int32_t prev, int64_t base, int64_t deg, uint8_t want,
-                                            uint32_t &trig)
+                                            uint32_t &trig, float &hsel)
 {
     const int lane = lane_id();
     const uint32_t k0 = Q.key0, k1 = Q.key1;
@@ -123,18 +124,22 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q
     }
     wave_argmax(key, bi);
     trig = (uint32_t)wave_sum_u64(nt);
-    return key > -INFINITY ? a.col[base + bi] : -1;
+    if (!(key > -INFINITY)) return -1;
+    const uint2 e = a.edges[base + bi];
+    hsel = W ? __uint_as_float(e.y) : 1.0f;
+    return (int32_t)e.x;
 }
 
 // eRVS for up to 64/G steps at once, one G-lane group per step, for rows of at most G
 // neighbours.  Such a step is decided by round 0 alone (every neighbour gets its key,
 // there is nothing to scan), so the result equals the one-wave eRVS bit for bit.
 // Takes its steps from `pool` (lanes in trial order of the ballot) and returns true
-// for the lanes that were served, with the next vertex (or -1) in `res`.
+// for the lanes that were served, with the next vertex (or -1) in `res` and the h of
+// the chosen edge in `hres`.
 template <int KIND, bool W, bool BATCH>
 __device__ __forceinline__ bool rvs_group_pass(const WalkArgs &a, int G, uint64_t &pool, int32_t q, int32_t wid,
                                                int32_t j, int32_t prev, int64_t base, int32_t deg, int64_t pbase,
-                                               int32_t pdeg, int32_t &res)
+                                               int32_t pdeg, int32_t &res, float &hres)
 {
     const int lane = lane_id();
     const int g = lane / G, r = lane % G;
@@ -180,9 +185,15 @@ __device__ __forceinline__ bool rvs_group_pass(const WalkArgs &a, int G, uint64_
             bi = i2;
         }
     }
-    const int32_t nx = key > -INFINITY ? a.col[s_base + bi] : -1;
-    const int32_t got = __shfl(nx, my_slot >= 0 ? my_slot * G : lane, kWave);
-    if (my_slot >= 0) res = got;
+    uint2 e = make_uint2(0xffffffffu, 0u);
+    if (key > -INFINITY) e = a.edges[s_base + bi];
+    const int from = my_slot >= 0 ? my_slot * G : lane;
+    const int32_t got = __shfl((int32_t)e.x, from, kWave);
+    const uint32_t got_h = (uint32_t)__shfl((int32_t)e.y, from, kWave);
+    if (my_slot >= 0) {
+        res = got;
+        hres = W ? __uint_as_float(got_h) : 1.0f;
+    }
     return my_slot >= 0;
 }
 
@@ -222,6 +233,9 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
     int32_t stop_j = 0;  // resumable walks: suspend when j reaches this step
     bool fell_back = false;
     float B = 0.0f;
+    // h of the edge prev -> cur, and of the edge the current step takes; on a symmetric
+    // graph the first is also h(cur, prev), the return edge's property weight
+    float hlast = 1.0f, hnext = 1.0f;
     // per-lane counters (32-bit counts, 64-bit bytes), flushed before a count could wrap
     uint32_t st[kStBytes];
 #pragma unroll
@@ -261,6 +275,11 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                         const uint4 pr = a.vrec[prev];
                         pbase = row_start(a, pr, prev);
                         pdeg = (int32_t)pr.y;
+                        hlast = 1.0f;
+                        if (KIND == kNode2Vec && W && a.bound != 0) {
+                            const int64_t pos = sorted_find(a.col + pbase, pdeg, cur);
+                            if (pos >= 0) hlast = __uint_as_float(a.edges[pbase + pos].y);
+                        }
                         stop_j = pj + a.tick_steps;
                         st_bytes += 4 + 8 + 16;
                         mode = kSetup;
@@ -281,6 +300,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                             wid = (int32_t)local;
                             cur = s;
                             prev = -1;
+                            hlast = 1.0f;
                             j = 0;
                             stop_j = a.tick_steps;
                             mode = kSetup;
@@ -322,7 +342,10 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                     if (a.strategy != kRvsOnly) {
                         const float wmax = (j == 0) ? Q.wmax0 : Q.wmax1;
                         const float hm = W ? __uint_as_float(r.z) : 1.0f;
-                        B = wmax * hm;  // get_weight_max: max(w) * h_MAX
+                        // get_weight_max: max(w) * h_MAX; the split bound's column height
+                        // leaves the return weight 1/p out
+                        const bool split = KIND == kNode2Vec && a.bound != 0 && j > 0;
+                        B = split ? Q.hi_w * hm : wmax * hm;
                         if (a.strategy == kRjsOnly) {
                             rjs = true;
                             st_bytes += W ? 4 : 0;
@@ -330,8 +353,14 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                             const float wavg = (j == 0) ? Q.wavg0 : Q.wavg1;
                             const float hs = W ? __uint_as_float(r.w) : (float)deg;
                             st_bytes += W ? 8 : 0;
-                            // Eq. (runtime) with get_weight_sum = mean(w) * h_SUM
-                            rjs = deg >= a.d_lo && (a.rho * B) < (wavg * hs);
+                            // Eq. (runtime) with get_weight_sum = mean(w) * h_SUM; with the
+                            // split board the eRJS cost is (deg * B + E) / S per step
+                            if (split) {
+                                const float E = fmaxf(0.0f, Q.inv_p * hlast - B);
+                                rjs = deg >= a.d_lo && (a.rho * ((float)deg * B + E)) < ((float)deg * (wavg * hs));
+                            } else {
+                                rjs = deg >= a.d_lo && (a.rho * B) < (wavg * hs);
+                            }
                         }
                     }
                     mode = rjs ? kRjs : kRvs;
@@ -350,16 +379,24 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
             // issue the loads of the next kRjsBatch proposals together, then decide them
             // in trial order; the first accepted trial is the sample, exactly as if the
             // trials ran one by one
+            // split bound: a trial first picks the return edge's extra column (height
+            // E) with probability E / (deg * B + E); such a trial reads no edge
+            const bool split = KIND == kNode2Vec && a.bound != 0 && j > 0;
+            const float E = split ? fmaxf(0.0f, Q.inv_p * hlast - B) : 0.0f;
+            const float area = (float)deg * B + E;
             uint32_t ux[kRjsBatch];
             uint2 ee[kRjsBatch];
             uint8_t ll[kRjsBatch];
+            bool ol[kRjsBatch];
             const uint32_t k0 = Q.key0, k1 = Q.key1;
 #pragma unroll
             for (int r = 0; r < kRjsBatch; ++r) {
                 const U4 x = philox((uint32_t)wid, (uint32_t)j, (uint32_t)(trials + r), 0u, k0, k1);
                 const int64_t k = base + scaled_index(x.x0, x.x1, deg);
+                ol[r] = E > 0.0f && unit_uniform(x.x3) * area < E;
                 ux[r] = x.x2;
-                ee[r] = a.edges[k];
+                if (ol[r]) ee[r] = make_uint2((uint32_t)prev, 0u);
+                else ee[r] = a.edges[k];
                 ll[r] = (KIND == kMetaPath) ? a.label[k] : (uint8_t)0;
             }
             const float inv_p = Q.inv_p, inv_q = Q.inv_q, lo_w = Q.lo_w, hi_w = Q.hi_w;
@@ -371,7 +408,9 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 const float hv = W ? __uint_as_float(ee[0].y) : 1.0f;
                 const float y = unit_uniform(ux[0]) * B;
                 bool acc;
-                if (KIND == kNode2Vec) {
+                if (ol[0]) {
+                    acc = true;  // the extra column belongs to the return edge
+                } else if (KIND == kNode2Vec) {
                     if (j == 0) {
                         acc = y < hv;
                     } else if (u == prev) {
@@ -385,7 +424,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                         } else {
                             st_bytes += 4 * (uint64_t)probes(pdeg);
                             const float wt =
-                                sorted_contains_interp(a.col + pbase, (int64_t)pdeg, u, a.nv) ? hv : inv_q * hv;
+                                sorted_contains_interp(a.col + pbase, pdeg, u, (int32_t)a.nv) ? hv : inv_q * hv;
                             acc = y < wt;
                         }
                     }
@@ -394,9 +433,10 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 }
                 ++trials;
                 st[kStTrials] += 1;
-                st_bytes += (uint64_t)a.item_bytes;
+                if (!ol[0]) st_bytes += (uint64_t)a.item_bytes;
                 if (acc) {
                     nxt = u;
+                    hnext = ol[0] ? hlast : hv;  // symmetric h: h(cur, prev) = h(prev, cur)
                     mode = kAdv;
                     st[kStRjs] += 1;
                     break;
@@ -411,6 +451,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                     ee[t] = ee[t + 1];
                     ux[t] = ux[t + 1];
                     ll[t] = ll[t + 1];
+                    ol[t] = ol[t + 1];
                 }
             }
         }
@@ -433,8 +474,9 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 s16 = 0;
             }
             // the per-step accounting is the same whichever lanes served the step
-            auto served = [&](int32_t res, uint32_t trig) {
+            auto served = [&](int32_t res, float hres, uint32_t trig) {
                 nxt = res;
+                hnext = hres;
                 mode = kAdv;
                 st[kStTriggers] += trig;
                 uint64_t by = (uint64_t)deg * (uint64_t)a.item_bytes;
@@ -447,11 +489,13 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 if (res >= 0) st[fell_back ? kStFallback : kStRvs] += 1;
             };
             int32_t res = -1;
+            float hres = 1.0f;
             for (int G = 8; G <= 32; G <<= 1) {
                 uint64_t &pool = G == 8 ? s8 : (G == 16 ? s16 : s32);
                 while (pool != 0)
-                    if (rvs_group_pass<KIND, W, BATCH>(a, G, pool, q, wid, j, prev, base, deg, pbase, pdeg, res))
-                        served(res, 0);
+                    if (rvs_group_pass<KIND, W, BATCH>(a, G, pool, q, wid, j, prev, base, deg, pbase, pdeg, res,
+                                                       hres))
+                        served(res, hres, 0);
             }
             while (big != 0) {
                 const int src = __ffsll((unsigned long long)big) - 1;
@@ -475,8 +519,8 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                     m.p = lds;
                 }
                 uint32_t trig = 0;
-                res = rvs_step<KIND, W>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, trig);
-                if (lane == src) served(res, trig);
+                res = rvs_step<KIND, W>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, trig, hres);
+                if (lane == src) served(res, hres, trig);
             }
         }
 
@@ -499,6 +543,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 st[kStSteps] += 1;
                 prev = cur;
                 cur = nxt;
+                hlast = hnext;
                 pbase = base;
                 pdeg = deg;
                 ++j;
@@ -595,6 +640,27 @@ __global__ void __launch_bounds__(kBlock) validate_edges_kernel(const int64_t *r
         if (bad) atomicOr(err, 2);
     }
     if (lane == 0 && dmax > 0) atomicMax(max_deg, dmax);
+}
+
+// One wave per row v: every entry (v, u) must have the reverse entry (u, v) with the
+// same h bits, else bit 4 of *err is set (one atomic per wave).
+__global__ void __launch_bounds__(kBlock) check_symmetry_kernel(const int64_t *row_ptr, const int32_t *col,
+                                                                const float *h, int64_t nv, int *err)
+{
+    const int lane = lane_id();
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    bool bad = false;
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; v < nv; v += nw) {
+        const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+        for (int64_t k = b + lane; k < e; k += kWave) {
+            const int32_t u = col[k];
+            const int64_t ub = row_ptr[u];
+            const int64_t pos = sorted_find(col + ub, row_ptr[u + 1] - ub, (int32_t)v);
+            if (pos < 0) bad = true;
+            else if (h && __float_as_uint(h[ub + pos]) != __float_as_uint(h[k])) bad = true;
+        }
+    }
+    if (__ballot(bad) != 0 && lane == 0) atomicOr(err, 16);
 }
 
 // Profiling kernels (Section 5, "Flexi-Runtime Profiling Kernels"): evaluate workload
@@ -753,6 +819,16 @@ hipError_t launch_validate_edges(const int64_t *row_ptr, const int32_t *col, con
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(validate_edges_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, nv, err,
                        max_deg);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_symmetry(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int *err,
+                                 hipStream_t s)
+{
+    int64_t blocks = (nv + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(check_symmetry_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, nv, err);
     return hipGetLastError();
 }
 

@@ -390,6 +390,7 @@ int fw_server_submit(fw_server *s, const fw_logic *logic, const int32_t *starts,
     if (!s || !logic || !req_id || (n > 0 && !starts)) return fail(FW_E_INVALID, "fw_server_submit: null argument");
     int rc = fw::host::check_logic(s->g, logic);
     if (rc != FW_OK) return rc;
+    if ((rc = fw::host::check_bound(s->g, &s->plan, logic)) != FW_OK) return rc;
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(FW_E_INVALID, "fw_server_submit: n must be in [0, 2^31)");
     if (L < 0 || L >= (1 << 20)) return fail(FW_E_INVALID, "fw_server_submit: L must be in [0, 2^20)");
     const size_t bytes = request_bytes(n, L);

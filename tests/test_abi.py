@@ -66,16 +66,20 @@ def test_host_only_argument_checks():
     lg = fw.fw_logic_node2vec(2.0, 0.5, True)
     assert (lg.kind, lg.weighted, lg.p, lg.q) == (fw.FW_NODE2VEC, 1, 2.0, 0.5)
     pl = fw.fw_plan_default()
-    assert (pl.rho, pl.d_lo, pl.rjs_cap, pl.lanes) == (8.0, 0, 1024, 64)
+    assert (pl.rho, pl.d_lo, pl.rjs_cap, pl.lanes, pl.bound, pl.reserved) == (8.0, 0, 1024, 64, 0, 0)
     with pytest.raises(fw.FlexiWalkError):
         fw.fw_graph_create(-1, 0, None, None)
 
 
 def test_struct_layouts_match_header():
-    """ctypes mirrors of the C structs have the sizes the C compiler gives them."""
+    """ctypes mirrors of the C structs have the sizes and field offsets the C compiler
+    gives them."""
     import paper_2512_00705_amd as fw
-    src = ("#include <stdio.h>\n#include \"flexiwalk.h\"\nint main(void){printf(\"%zu %zu %zu\\n\","
-           "sizeof(fw_csr), sizeof(fw_logic), sizeof(fw_plan));printf(\"%zu\\n\", sizeof(fw_query));return 0;}\n")
+    fields = [("fw_plan", f) for f, _ in fw.fw_plan._fields_] + [("fw_query", f) for f, _ in fw.fw_query._fields_]
+    offs = "".join(f'printf("%zu\\n", offsetof({s}, {f}));' for s, f in fields)
+    src = ("#include <stdio.h>\n#include <stddef.h>\n#include \"flexiwalk.h\"\nint main(void){printf(\"%zu %zu %zu\\n\","
+           "sizeof(fw_csr), sizeof(fw_logic), sizeof(fw_plan));printf(\"%zu\\n\", sizeof(fw_query));" + offs +
+           "return 0;}\n")
     d = os.path.join(ROOT, "_build")
     os.makedirs(d, exist_ok=True)
     c = os.path.join(d, "sizes.c")
@@ -83,5 +87,7 @@ def test_struct_layouts_match_header():
     open(c, "w").write(src)
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
     sizes = [int(x) for x in subprocess.check_output([exe]).split()]
-    assert sizes == [ctypes.sizeof(fw.fw_csr), ctypes.sizeof(fw.fw_logic), ctypes.sizeof(fw.fw_plan),
-                     ctypes.sizeof(fw.fw_query)]
+    want = [ctypes.sizeof(fw.fw_csr), ctypes.sizeof(fw.fw_logic), ctypes.sizeof(fw.fw_plan),
+            ctypes.sizeof(fw.fw_query)]
+    want += [getattr(fw.fw_plan if s == "fw_plan" else fw.fw_query, f).offset for s, f in fields]
+    assert sizes == want

@@ -172,3 +172,26 @@ def test_batch_argument_errors(g12, gg12):
     empty = fw.fw_batch_create(gg12.handle, [], fw.fw_plan_default(), 0, None, None, None)
     fw.fw_batch_launch(empty)
     fw.fw_batch_destroy(empty)
+
+
+def test_batch_split_bound(g12, gg12):
+    qd = _small_batch(g12["nv"], 24, 13)
+    logics = [oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=float(0.25 + (i % 4) * 0.5), q=2.0)
+              for i in range(24)]
+    pl = oracle.Plan(rho=1.0, bound=1)
+    b = Batch(gg12, qd, [fw.fw_logic_node2vec(l.p, l.q, True) for l in logics], fw_plan(pl), oracle.AUTO)
+    try:
+        fw.fw_batch_launch(b.h)
+        og = oracle.Graph(g12)
+        for i in range(24):
+            n = int(qd["n"][i])
+            if n == 0:
+                continue
+            p, ln = b.query(i)
+            st = qd["starts"][qd["start_off"][i]:qd["start_off"][i] + n]
+            alone = gpu_walk(gg12, logics[i], pl, oracle.AUTO, st, int(qd["L"][i]), int(qd["seed"][i]))
+            np.testing.assert_array_equal(p, alone[0])
+            ora = oracle.walk(og, logics[i], pl, oracle.AUTO, st, int(qd["L"][i]), int(qd["seed"][i]))
+            assert_parity(parity(p, ln, ora))
+    finally:
+        b.close()

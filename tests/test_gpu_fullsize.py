@@ -45,15 +45,25 @@ def og22(g22):
     return og
 
 
+@pytest.fixture(scope="module")
+def tuned22(gg22):
+    return fw.fw_plan_autotune(gg22.handle, fw.fw_logic_node2vec(0.5, 2.0, True))
+
+
 def _sample(n, k, seed):
     return np.sort(np.random.default_rng(seed).choice(n, size=min(k, n), replace=False)).astype(np.int64)
 
 
-@pytest.mark.parametrize("strategy,k", [(oracle.AUTO, 65536), (oracle.RJS_ONLY, 65536), (oracle.RVS_ONLY, 1024)],
-                         ids=["auto", "rjs", "rvs"])
-def test_node2vec_scale22(g22, gg22, og22, strategy, k):
-    tuned = fw.fw_plan_autotune(gg22.handle, fw.fw_logic_node2vec(0.5, 2.0, True))
-    pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap)
+@pytest.mark.parametrize("strategy,k,bound", [(oracle.AUTO, 65536, None), (oracle.RJS_ONLY, 65536, None),
+                                             (oracle.RVS_ONLY, 1024, None), (oracle.AUTO, 65536, 0),
+                                             (oracle.AUTO, 65536, 1), (oracle.RJS_ONLY, 65536, 1)],
+                         ids=["auto", "rjs", "rvs", "auto_paper_bound", "auto_split_bound", "rjs_split_bound"])
+def test_node2vec_scale22(g22, gg22, og22, tuned22, strategy, k, bound):
+    """bound None: the autotuned plan as the benchmark runs it; 0 / 1: that plan with
+    the paper's bound or the split bound forced."""
+    tuned = tuned22
+    pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap,
+                     bound=tuned.bound if bound is None else bound)
     starts = synth.all_vertices(g22["nv"])
     p, ln, st = gpu_walk(gg22, N2V, pl, strategy, starts, 80, 42)
     ok, pad_ok, _ = edge_check_torch(g22, p, ln)

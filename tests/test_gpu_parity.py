@@ -226,3 +226,78 @@ def test_chisquare_hub_second_step(strategy):
     counts = {int(v): int(c) for v, c in zip(*np.unique(nxt, return_counts=True))}
     probs = exact.transition(g, N2V, 1, 1, 0)
     assert chisq_pvalue(counts, probs, int(at_hub.sum())) > 1e-3
+
+
+# ------------------------------------------------------------------ split eRJS bound
+N2V_RET = oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=0.25, q=2.0)
+
+
+@pytest.mark.parametrize("strategy", ["auto", "rjs", "rvs"])
+@pytest.mark.parametrize("weighted", [True, False], ids=["weighted", "unweighted"])
+def test_split_bound_scale12(g12, gg12, strategy, weighted):
+    """plan.bound = 1 with a dominant return weight (1/p = 4): the extra column is taken
+    often; the walks and counters equal the oracle's split-bound walks."""
+    lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=weighted, p=0.25, q=2.0)
+    pl = oracle.Plan(rho=1.0, bound=1)
+    starts = synth.all_vertices(g12["nv"])
+    p, ln, st, ora = _run_both(gg12, g12, lg, pl, STRATS[strategy], starts, 20, 77)
+    rep = parity(p, ln, ora)
+    assert_parity(rep)
+    if rep["mismatch_walkers"] == 0:
+        _assert_counters(st, ora)
+    if strategy != "rvs":
+        assert st["rjs_steps"] > 0
+
+
+def test_split_bound_fewer_trials_on_gpu(g12, gg12):
+    starts = synth.all_vertices(g12["nv"])
+    a = gpu_walk(gg12, N2V_RET, oracle.Plan(bound=0), oracle.RJS_ONLY, starts, 20, 5)[2]
+    b = gpu_walk(gg12, N2V_RET, oracle.Plan(bound=1), oracle.RJS_ONLY, starts, 20, 5)[2]
+    assert b["rjs_trials"] / b["steps"] < 0.75 * a["rjs_trials"] / a["steps"]
+
+
+@pytest.mark.parametrize("strategy", ["auto", "rjs"])
+def test_split_bound_chisquare_hub(strategy):
+    g = hub_ring_graph(600)
+    gg = GpuGraph(g)
+    try:
+        assert fw.fw_graph_info(gg.handle)[3]
+        n = 300000
+        p, ln, st = gpu_walk(gg, N2V_RET, oracle.Plan(rho=1.0, bound=1), STRATS[strategy], np.ones(n, np.int32),
+                             2, 29)
+    finally:
+        gg.close()
+    at_hub = p[:, 1] == 0
+    counts = {int(v): int(c) for v, c in zip(*np.unique(p[at_hub, 2], return_counts=True))}
+    assert chisq_pvalue(counts, exact.transition(g, N2V_RET, 1, 1, 0), int(at_hub.sum())) > 1e-3
+
+
+def test_split_bound_needs_symmetric_graph(g12, gg12):
+    assert fw.fw_graph_info(gg12.handle)[3]
+    dev = torch.device("cuda:0")
+    s = torch.zeros(4, dtype=torch.int32, device=dev)
+    out = torch.zeros(4 * 6, dtype=torch.int32, device=dev)
+    ln = torch.zeros(4, dtype=torch.int32, device=dev)
+    split = fw.fw_plan_default(bound=1)
+    # a directed edge 0 -> 1 without its reverse
+    gd = synth.csr_from_edges(3, [(0, 1), (0, 2)], h=[1, 2], symmetric=False)
+    # reverse edges present but with different h
+    gh = synth.csr_from_edges(3, [(0, 1), (1, 2)], h=[1, 2])
+    gh["h"] = gh["h"].copy()
+    gh["h"][0] += 1.0
+    for g in (gd, gh):
+        gg = GpuGraph(g)
+        try:
+            assert not fw.fw_graph_info(gg.handle)[3]
+            with pytest.raises(fw.FlexiWalkError) as e:
+                fw.fw_walk(gg.handle, fw.fw_logic_node2vec(0.25, 2.0, True), split, 0, s, 4, 5, 1, out, ln)
+            assert e.value.code == fw.FW_E_INVALID
+            # the paper's bound needs no symmetry
+            fw.fw_walk(gg.handle, fw.fw_logic_node2vec(0.25, 2.0, True), fw.fw_plan_default(), 0, s, 4, 5, 1, out,
+                       ln)
+            torch.cuda.synchronize()
+        finally:
+            gg.close()
+    with pytest.raises(fw.FlexiWalkError):
+        fw.fw_walk(gg12.handle, fw.fw_logic_node2vec(0.25, 2.0, True), fw.fw_plan_default(bound=2), 0, s, 4, 5, 1,
+                   out, ln)

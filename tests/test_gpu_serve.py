@@ -163,3 +163,29 @@ def test_bad_start_and_teardown(g12, gg12):
             fw.fw_server_submit(srv, fw.fw_logic_node2vec(1.0, 1.0, True), np.arange(200, dtype=np.int32), 30, i)
     finally:
         fw.fw_server_destroy(srv)
+
+
+@pytest.mark.parametrize("tick_steps", [1, 5])
+def test_split_bound_resume(g12, gg12, tick_steps):
+    """Walks suspended every few steps under the split bound: a resumed walker recovers
+    h(prev, cur) from the graph, so its samples equal an uninterrupted walk's."""
+    pl = oracle.Plan(rho=1.0, rjs_cap=64, bound=1)
+    rng = np.random.default_rng(tick_steps)
+    reqs = []
+    for i in range(12):
+        lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=bool(i % 3), p=float(rng.choice([0.25, 0.5, 2.0])), q=2.0)
+        reqs.append((lg, rng.integers(0, g12["nv"], int(rng.integers(1, 400))).astype(np.int32),
+                     int(rng.integers(1, 30)), 500 + i))
+    srv = fw.fw_server_create(gg12.handle, fw.fw_plan_default(rho=pl.rho, rjs_cap=pl.rjs_cap, bound=1), fw.FW_AUTO,
+                              64 << 20, tick_steps=tick_steps, max_active=8)
+    try:
+        results = _serve_all(srv, reqs)
+    finally:
+        fw.fw_server_destroy(srv)
+    og = oracle.Graph(g12)
+    for k, (lg, st, L, seed) in enumerate(reqs):
+        p, ln, _ = results[k]
+        alone = gpu_walk(gg12, lg, pl, oracle.AUTO, st, L, seed)
+        np.testing.assert_array_equal(p, alone[0], err_msg=f"request {k}")
+        np.testing.assert_array_equal(ln, alone[1], err_msg=f"request {k}")
+        assert_parity(parity(p, ln, oracle.walk(og, lg, pl, oracle.AUTO, st, L, seed)))
