@@ -131,6 +131,11 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     prep_ms = e0.elapsed_time(e1)
+    e0.record()
+    fw.fw_graph_build_index(gh)
+    e1.record()
+    torch.cuda.synchronize()
+    index_ms = e0.elapsed_time(e1)
     logic = fw.fw_logic_node2vec(args.p, args.q, True)
     t1 = time.time()
     if args.plan:
@@ -203,7 +208,7 @@ def main():
         og = oracle.Graph(g)
         og.aux()
         lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=args.p, q=args.q)
-        pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap, bound=plan.bound)
+        pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap, bound=plan.bound, member_index=True)
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
         smode = {"auto": 0, "rvs": 1, "rjs": 2}[args.strategy]
         k = args.cpu_sample or 2048
@@ -243,6 +248,7 @@ def main():
                                f"(a=0.57,b=0.19,c=0.19, edge factor 16, {g['ne']} CSR entries), one walker "
                                f"per vertex ({nv}), L={L}, strategy={args.strategy}",
                    "walker_steps_per_walk_job": steps_per_walk, "preprocess_ms": prep_ms,
+                   "edge_index_ms": index_ms,
                    "autotune_ms": tune_ms, "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound},
                    "stats": st, "modes": modes,
                    "hbm_traffic_GBps": None if traffic is None else traffic / (avg_ms / 1e3) / 1e9},
@@ -269,6 +275,7 @@ def bench_batched(args):
     gh = fw.fw_graph_create(g["nv"], g["ne"], t["row_ptr"], t["col"], t["h"], None, on_device=True)
     del t
     fw.fw_graph_preprocess(gh)
+    fw.fw_graph_build_index(gh)
     plan = fw.fw_plan_autotune(gh, fw.fw_logic_node2vec(1.0, 1.0, True))
     qd = synth.batch_queries(g["nv"], 4096, 7)
     starts = torch.from_numpy(qd["starts"]).to(dev)
@@ -356,6 +363,7 @@ def bench_served(args):
     nv = g["nv"]
     del g
     fw.fw_graph_preprocess(gh)
+    fw.fw_graph_build_index(gh)
     plan = fw.fw_plan_autotune(gh, fw.fw_logic_node2vec(1.0, 1.0, True))
     budget = 32 << 30
     srv = fw.fw_server_create(gh, plan, fw.FW_AUTO, budget, tick_steps=args.tick_steps, max_active=8192,

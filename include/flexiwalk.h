@@ -136,6 +136,16 @@ int fw_graph_preprocess(fw_graph *g, void *stream);
 /* Copy h_MAX and h_SUM (nv floats each, host pointers) back to the host; synchronous. */
 int fw_graph_export_aux(const fw_graph *g, float *hmax, float *hsum);
 
+/* Build the edge index: an exact hash set of the entries (v, u) (64-byte buckets of eight
+ * 64-bit keys, at most half full; 16 bytes of device memory per entry, rounded up to a
+ * power-of-two bucket count).  Node2Vec's membership test u in N(prev) then reads one
+ * bucket instead of searching prev's sorted row; samples and counts of eRJS trials do not
+ * change (the algorithmic-byte counter charges 8 bytes per test instead of a binary
+ * search's).  Asynchronous on `stream`; idempotent.  Walks, batches and servers created
+ * afterwards use it; build it before creating batches or servers.  Returns FW_E_NOMEM if
+ * the table cannot be allocated (the graph stays usable without it). */
+int fw_graph_build_index(fw_graph *g, void *stream);
+
 /* Sizes of a graph: vertices, edges, maximum degree, and 1 if every edge (v, u) has a
  * reverse edge (u, v) with the same h (checked on the device by fw_graph_create), else 0
  * (any pointer may be NULL). */

@@ -125,6 +125,8 @@ typedef struct {
     int32_t jump;        /* 1: Eq. (jump); 0: a key for every item */
     float bound_scale;   /* multiplies the eRJS bound (>= 1 keeps it a bound) */
     int32_t bound;       /* 0: max(w) * h_MAX (Section 3.3); 1: Node2Vec split bound */
+    int32_t member_index; /* byte accounting only: a membership test reads one 8-byte key of
+                             an edge index (1) or binary-searches the sorted row (0) */
 } og_plan;
 
 enum { OG_AUTO = 0, OG_RVS_ONLY = 1, OG_RJS_ONLY = 2, OG_ITS = 3 };
@@ -347,7 +349,7 @@ static int64_t rjs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
             float lo = fminf(1.0f, 1.0f / lg->q) * hv, hi = fmaxf(1.0f, 1.0f / lg->q) * hv;
             if (!(y < lo) && y < hi) {
                 int64_t pdeg = cx->g->row_ptr[prev + 1] - cx->g->row_ptr[prev];
-                info->bytes += 4.0 * ceil_log2_plus1(pdeg);
+                info->bytes += cx->pl->member_index ? 8.0 : 4.0 * ceil_log2_plus1(pdeg);
             }
         }
         if (y < wt) return idx;
@@ -451,7 +453,7 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
             if (lg->kind == OG_NODE2VEC && j > 0) {
                 int64_t pdeg = g->row_ptr[prev + 1] - g->row_ptr[prev];
                 double stage = 4.0 * (double)pdeg;
-                double search = 4.0 * (double)deg * ceil_log2_plus1(pdeg);
+                double search = (double)deg * (cx->pl->member_index ? 8.0 : 4.0 * ceil_log2_plus1(pdeg));
                 info->bytes += stage < search ? stage : search;
             }
             off = rvs_sample(cx, w, j, prev, base, deg, info);

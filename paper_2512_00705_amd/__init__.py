@@ -24,8 +24,8 @@ FW_MAX_SCHEMA = 64
 FW_NSTATS = 8
 STAT_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", "rvs_triggers",
               "ended_early", "alg_bytes")
-EXPORTED = ("fw_graph_create", "fw_graph_destroy", "fw_graph_preprocess", "fw_graph_export_aux",
-            "fw_graph_info", "fw_logic_node2vec", "fw_logic_metapath", "fw_plan_default",
+EXPORTED = ("fw_graph_create", "fw_graph_destroy", "fw_graph_preprocess", "fw_graph_build_index",
+            "fw_graph_export_aux", "fw_graph_info", "fw_logic_node2vec", "fw_logic_metapath", "fw_plan_default",
             "fw_plan_profile", "fw_plan_autotune", "fw_walk", "fw_graph_check", "fw_last_error",
             "fw_batch_create", "fw_batch_launch", "fw_batch_capture", "fw_batch_replay", "fw_batch_destroy",
             "fw_server_create", "fw_server_submit", "fw_server_next_done", "fw_server_result", "fw_server_stats",
@@ -73,6 +73,7 @@ def _load():
         "fw_graph_create": ([ctypes.POINTER(fw_csr), ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
         "fw_graph_destroy": ([P], ctypes.c_int),
         "fw_graph_preprocess": ([P, P], ctypes.c_int),
+        "fw_graph_build_index": ([P, P], ctypes.c_int),
         "fw_graph_export_aux": ([P, P, P], ctypes.c_int),
         "fw_graph_info": ([P, P, P, P, P], ctypes.c_int),
         "fw_logic_node2vec": ([ctypes.c_float, ctypes.c_float, I32, ctypes.POINTER(fw_logic)], ctypes.c_int),
@@ -151,6 +152,10 @@ def fw_graph_destroy(g: int):
 
 def fw_graph_preprocess(g: int, stream=None):
     _check(_lib.fw_graph_preprocess(g, _stream(stream)))
+
+
+def fw_graph_build_index(g: int, stream=None):
+    _check(_lib.fw_graph_build_index(g, _stream(stream)))
 
 
 def fw_graph_export_aux(g: int, nv: int):

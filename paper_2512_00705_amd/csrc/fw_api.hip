@@ -60,6 +60,7 @@ static void graph_free(fw_graph *g)
     (void)hipFree(g->vrec);
     (void)hipFree(g->start_hi);
     (void)hipFree(g->scratch);
+    (void)hipFree(g->mtab);
     delete g;
 }
 
@@ -170,6 +171,30 @@ int fw_graph_preprocess(fw_graph *g, void *stream)
     HIP_TRY(hipSetDevice(g->device));
     HIP_TRY(fw::launch_preprocess(g->row_ptr, g->h, g->nv, g->vrec, (hipStream_t)stream));
     g->prepped = true;
+    return ok();
+}
+
+int fw_graph_build_index(fw_graph *g, void *stream)
+{
+    if (!g) return fail(FW_E_INVALID, "fw_graph_build_index: null graph");
+    if (g->mtab) return ok();
+    HIP_TRY(hipSetDevice(g->device));
+    // power-of-two bucket count with at least 16 slots per 8 keys (load <= 1/2)
+    uint64_t buckets = 1;
+    while (buckets * 8 < 2 * (uint64_t)g->ne) buckets <<= 1;
+    unsigned long long *tab = nullptr;
+    if (hipMalloc((void **)&tab, buckets * 64) != hipSuccess)
+        return fail(FW_E_NOMEM, "fw_graph_build_index: hipMalloc of %llu bytes failed",
+                    (unsigned long long)(buckets * 64));
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemsetAsync(tab, 0xFF, buckets * 64, s);  // every slot kEmptyKey
+    if (e == hipSuccess) e = fw::launch_build_index(g->row_ptr, g->col, g->nv, tab, buckets - 1, s);
+    if (e != hipSuccess) {
+        (void)hipFree(tab);
+        return fail(FW_E_DEVICE, "fw_graph_build_index: %s", hipGetErrorString(e));
+    }
+    g->mtab = tab;
+    g->mtab_mask = buckets - 1;
     return ok();
 }
 
@@ -285,6 +310,8 @@ void fw::host::fill_args(const fw_graph *g, const fw_logic *lg, fw::WalkArgs &a)
     a.col = g->col;
     a.label = g->label;
     a.nv = g->nv;
+    a.mtab = (const uint4 *)g->mtab;
+    a.mtab_mask = g->mtab_mask;
     fill_query(lg, a.q0);
     const bool weighted = lg->weighted && g->h;
     a.item_bytes = 4 + (weighted ? 4 : 0) + (lg->kind == FW_METAPATH ? 1 : 0);

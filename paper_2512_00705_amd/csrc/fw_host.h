@@ -22,6 +22,8 @@ struct fw_graph {
     unsigned long long *scratch = nullptr;  // [0] walker queue, [1] error flag (int)
     bool prepped = false;
     bool symmetric = false;                 // every (v, u) has a reverse (u, v) with equal h
+    unsigned long long *mtab = nullptr;     // edge index: buckets of 8 keys v << 32 | u, or null
+    uint64_t mtab_mask = 0;                 // buckets - 1
 };
 
 namespace fw {

@@ -85,6 +85,8 @@ struct WalkArgs {
     int32_t item_bytes;         // col (+ h) (+ label) per scanned or proposed edge
     int32_t tick_steps;         // resumable walks: steps per walker per launch
     int32_t bound;              // 1: Node2Vec split eRJS bound (symmetric graphs only)
+    const uint4 *mtab;          // edge index (4 uint4 per bucket) or null: search the sorted rows
+    uint64_t mtab_mask;         // buckets - 1
 
     QueryDev q0;                // the query of a single-query launch
     const QueryDev *queries;    // batched launch: nq entries, ascending `first`
@@ -97,6 +99,10 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_layout(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int64_t ne,
                          uint2 *edges, uint4 *vrec, uint32_t *start_hi, hipStream_t s);
 hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv, uint4 *vrec, hipStream_t s);
+// Edge index: inserts every entry (v, col[k]) of the rows into `tab` (buckets * 8 keys, all
+// kEmptyKey on entry; buckets = mask + 1, a power of two, at least a quarter of ne).
+hipError_t launch_build_index(const int64_t *row_ptr, const int32_t *col, int64_t nv, unsigned long long *tab,
+                              uint64_t mask, hipStream_t s);
 // Sets bit 4 of *err unless every entry (v, u) has a reverse (u, v) with the same h.
 // Rows must already be validated (in range, strictly ascending).
 hipError_t launch_check_symmetry(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int *err,

@@ -23,11 +23,20 @@ namespace fw {
 enum Mode : int { kIdle = 0, kSetup = 1, kRjs = 2, kRvs = 3, kAdv = 4 };
 
 // N(prev) for the membership test: a copy in this wave's LDS or the row of prev in col,
-// read through one flat pointer either way.
+// read through one flat pointer either way.  An unstaged row is tested through the edge
+// index when the graph has one.
 struct Mem {
     const int32_t *p;
     int64_t len;
+    bool staged;
 };
+
+// u in N(prev): LDS copy, else the edge index, else a search of prev's sorted row.
+__device__ __forceinline__ bool in_prev_row(const WalkArgs &a, const Mem &m, int32_t prev, int32_t u)
+{
+    if (!m.staged && a.mtab != nullptr) return index_contains(a.mtab, a.mtab_mask, prev, u);
+    return sorted_contains_interp(m.p, (int32_t)m.len, u, (int32_t)a.nv);
+}
 
 // The constants of query q: a device table for batched launches, the kernel argument
 // block otherwise.
@@ -60,7 +69,7 @@ __device__ __forceinline__ float edge_weight(const WalkArgs &a, const QueryDev &
         if (j == 0) return hv;
         const int32_t u = (int32_t)e.x;
         if (u == prev) return Q.inv_p * hv;
-        return sorted_contains_interp(m.p, (int32_t)m.len, u, (int32_t)a.nv) ? hv : Q.inv_q * hv;
+        return in_prev_row(a, m, prev, u) ? hv : Q.inv_q * hv;
     } else {
         return a.label[k] == want ? hv : 0.0f;
     }
@@ -171,7 +180,7 @@ __device__ __forceinline__ bool rvs_group_pass(const WalkArgs &a, int G, uint64_
         const QueryDev &Q = query<BATCH>(a, s_q);
         const int64_t k = s_base + r;
         const uint8_t want = (KIND == kMetaPath) ? Q.schema[s_j % Q.schema_len] : (uint8_t)0;
-        const Mem m = {a.col + s_pbase, s_pdeg};
+        const Mem m = {a.col + s_pbase, s_pdeg, false};
         const float wt = edge_weight<KIND, W>(a, Q, k, a.edges[k], s_j, s_prev, m, want);
         const U4 x = philox(s_wid, (uint32_t)s_j, (uint32_t)r, 1u, Q.key0, Q.key1);
         key = wt > 0.0f ? ln_f(unit_uniform(x.x0)) / wt : -INFINITY;
@@ -422,9 +431,10 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                         } else if (!(y < hi)) {
                             acc = false;
                         } else {
-                            st_bytes += 4 * (uint64_t)probes(pdeg);
-                            const float wt =
-                                sorted_contains_interp(a.col + pbase, pdeg, u, (int32_t)a.nv) ? hv : inv_q * hv;
+                            st_bytes += a.mtab ? 8 : 4 * (uint64_t)probes(pdeg);
+                            const bool member = a.mtab ? index_contains(a.mtab, a.mtab_mask, prev, u)
+                                                       : sorted_contains_interp(a.col + pbase, pdeg, u, (int32_t)a.nv);
+                            const float wt = member ? hv : inv_q * hv;
                             acc = y < wt;
                         }
                     }
@@ -482,7 +492,9 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 uint64_t by = (uint64_t)deg * (uint64_t)a.item_bytes;
                 if (KIND == kNode2Vec && j > 0) {
                     const uint64_t stage = 4 * (uint64_t)pdeg;
-                    const uint64_t search = 4 * (uint64_t)deg * (uint64_t)probes(pdeg);
+                    // a membership test: one 8-byte key of the edge index, else a binary search
+                    const uint64_t search =
+                        (uint64_t)deg * (a.mtab ? 8 : 4 * (uint64_t)probes(pdeg));
                     by += stage < search ? stage : search;
                 }
                 st_bytes += by;
@@ -511,12 +523,15 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 const QueryDev &Q = query<BATCH>(a, s_q);
                 const uint8_t want = (KIND == kMetaPath) ? Q.schema[s_j % Q.schema_len] : (uint8_t)0;
                 const bool member_test = (KIND == kNode2Vec) && s_j > 0;
-                Mem m = {a.col + s_pbase, s_pdeg};
-                if (member_test && s_pdeg <= a.lds_cap && (int64_t)s_pdeg <= (int64_t)s_deg * probes(s_pdeg)) {
+                Mem m = {a.col + s_pbase, s_pdeg, false};
+                // stage N(prev) when copying it costs fewer memory requests than the tests
+                const int64_t per_test = a.mtab ? 16 : probes(s_pdeg);
+                if (member_test && s_pdeg <= a.lds_cap && (int64_t)s_pdeg <= (int64_t)s_deg * per_test) {
                     wave_lds_sync();
                     for (int32_t i = lane; i < s_pdeg; i += kWave) lds[i] = a.col[s_pbase + i];
                     wave_lds_sync();
                     m.p = lds;
+                    m.staged = true;
                 }
                 uint32_t trig = 0;
                 res = rvs_step<KIND, W>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, trig, hres);
@@ -642,6 +657,31 @@ __global__ void __launch_bounds__(kBlock) validate_edges_kernel(const int64_t *r
     if (lane == 0 && dmax > 0) atomicMax(max_deg, dmax);
 }
 
+// Edge index build: one wave per row, each lane inserts its entries' keys with a 64-bit
+// compare-and-swap into the first free slot from the key's bucket on.  The table holds
+// at least twice as many slots as keys, so every insert finds a slot within the scan.
+__global__ void __launch_bounds__(kBlock) build_index_kernel(const int64_t *row_ptr, const int32_t *col, int64_t nv,
+                                                             unsigned long long *tab, uint64_t mask)
+{
+    const int lane = lane_id();
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; v < nv; v += nw) {
+        const int64_t b = row_ptr[v], e = row_ptr[v + 1];
+        for (int64_t k = b + lane; k < e; k += kWave) {
+            const unsigned long long key = edge_key((int32_t)v, col[k]);
+            uint64_t bk = mix64(key) & mask;
+            bool done = false;
+            for (uint64_t t = 0; t <= mask && !done; ++t) {
+                for (int s = 0; s < 8 && !done; ++s) {
+                    const unsigned long long old = atomicCAS(&tab[bk * 8 + s], kEmptyKey, key);
+                    done = old == kEmptyKey || old == key;
+                }
+                bk = (bk + 1) & mask;
+            }
+        }
+    }
+}
+
 // One wave per row v: every entry (v, u) must have the reverse entry (u, v) with the
 // same h bits, else bit 4 of *err is set (one atomic per wave).
 __global__ void __launch_bounds__(kBlock) check_symmetry_kernel(const int64_t *row_ptr, const int32_t *col,
@@ -683,7 +723,7 @@ __global__ void __launch_bounds__(kBlock) profile_rvs_kernel(WalkArgs a, const i
         const uint4 rp = a.vrec[prev];
         const int64_t pb = row_start(a, rp, prev), pd = (int64_t)rp.y;
         for (int64_t i = lane; i < m; i += kWave)
-            acc += edge_weight<KIND, W>(a, a.q0, b + i, a.edges[b + i], 1, prev, Mem{a.col + pb, pd},
+            acc += edge_weight<KIND, W>(a, a.q0, b + i, a.edges[b + i], 1, prev, Mem{a.col + pb, pd, false},
                                         a.q0.schema[0]);
     }
     acc = wave_max(acc);
@@ -706,7 +746,7 @@ __global__ void __launch_bounds__(kBlock) profile_rjs_kernel(WalkArgs a, const i
         for (int t = 0; t < per_node; ++t) {
             const U4 x = philox((uint32_t)s, 0u, (uint32_t)t, 2u, a.q0.key0, a.q0.key1);
             const int64_t k = b + scaled_index(x.x0, x.x1, d);
-            acc += edge_weight<KIND, W>(a, a.q0, k, a.edges[k], 1, prev, Mem{a.col + pb, pd}, a.q0.schema[0]);
+            acc += edge_weight<KIND, W>(a, a.q0, k, a.edges[k], 1, prev, Mem{a.col + pb, pd, false}, a.q0.schema[0]);
         }
     }
     if (acc < 0.0f) sink[0] = acc;
@@ -819,6 +859,16 @@ hipError_t launch_validate_edges(const int64_t *row_ptr, const int32_t *col, con
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(validate_edges_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, nv, err,
                        max_deg);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_index(const int64_t *row_ptr, const int32_t *col, int64_t nv, unsigned long long *tab,
+                              uint64_t mask, hipStream_t s)
+{
+    int64_t blocks = (nv + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(build_index_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, nv, tab, mask);
     return hipGetLastError();
 }
 

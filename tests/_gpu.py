@@ -12,7 +12,7 @@ MARGIN = 1e-6  # a float decision within this relative gap is a flagged boundary
 
 
 class GpuGraph:
-    def __init__(self, g: dict, on_device: bool = True, preprocess: bool = True):
+    def __init__(self, g: dict, on_device: bool = True, preprocess: bool = True, index: bool = False):
         self.g = g
         self.nv, self.ne = int(g["nv"]), int(g["ne"])
         dev = torch.device("cuda:0")
@@ -28,7 +28,9 @@ class GpuGraph:
                                          on_device=on_device)
         if preprocess:
             fw.fw_graph_preprocess(self.handle)
-            torch.cuda.synchronize()
+        if index:
+            fw.fw_graph_build_index(self.handle)
+        torch.cuda.synchronize()
 
     def close(self):
         if self.handle:

@@ -33,7 +33,7 @@ def g22():
 
 @pytest.fixture(scope="module")
 def gg22(g22):
-    gg = GpuGraph(g22)
+    gg = GpuGraph(g22, index=True)  # as the benchmark runs it
     yield gg
     gg.close()
 
@@ -63,7 +63,7 @@ def test_node2vec_scale22(g22, gg22, og22, tuned22, strategy, k, bound):
     the paper's bound or the split bound forced."""
     tuned = tuned22
     pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap,
-                     bound=tuned.bound if bound is None else bound)
+                     bound=tuned.bound if bound is None else bound, member_index=True)
     starts = synth.all_vertices(g22["nv"])
     p, ln, st = gpu_walk(gg22, N2V, pl, strategy, starts, 80, 42)
     ok, pad_ok, _ = edge_check_torch(g22, p, ln)
@@ -80,7 +80,7 @@ def test_node2vec_scale22(g22, gg22, og22, tuned22, strategy, k, bound):
 
 def test_metapath_scale22(g22, gg22, og22):
     tuned = fw.fw_plan_autotune(gg22.handle, fw.fw_logic_metapath([0, 1, 2, 3, 4], True))
-    pl = oracle.Plan(rho=tuned.rho, rjs_cap=tuned.rjs_cap)
+    pl = oracle.Plan(rho=tuned.rho, rjs_cap=tuned.rjs_cap, member_index=True)
     starts = synth.uniform_starts(g22["nv"], 1 << 20, 42)
     p, ln, st = gpu_walk(gg22, MP, pl, oracle.AUTO, starts, 40, 42)
     ok, pad_ok, (pos, taken) = edge_check_torch(g22, p, ln)
@@ -102,7 +102,7 @@ def test_batched_scale24():
     5..200) on the skewed scale-24 R-MAT in one launch; 32 queries replayed by the oracle
     on up to 256 walkers each, and every walk of 256 queries checked to follow edges."""
     g = synth.cached("rmat24_skew")
-    gg = GpuGraph(g)
+    gg = GpuGraph(g, index=True)
     try:
         qd = synth.batch_queries(g["nv"], 4096, 7)
         dev = torch.device("cuda:0")
@@ -111,7 +111,8 @@ def test_batched_scale24():
         lengths = torch.full((int(qd["n"].sum()),), -7, dtype=torch.int32, device=dev)
         stats = torch.zeros(fw.FW_NSTATS, dtype=torch.int64, device=dev)
         tuned = fw.fw_plan_autotune(gg.handle, fw.fw_logic_node2vec(1.0, 1.0, True))
-        pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap)
+        pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap, bound=tuned.bound,
+                         member_index=True)
         qs = []
         for i in range(4096):
             q = fw.fw_query()

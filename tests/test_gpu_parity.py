@@ -301,3 +301,65 @@ def test_split_bound_needs_symmetric_graph(g12, gg12):
     with pytest.raises(fw.FlexiWalkError):
         fw.fw_walk(gg12.handle, fw.fw_logic_node2vec(0.25, 2.0, True), fw.fw_plan_default(bound=2), 0, s, 4, 5, 1,
                    out, ln)
+
+
+# ------------------------------------------------------------------ edge index
+@pytest.fixture(scope="module")
+def gi12(g12):
+    gg = GpuGraph(g12, index=True)
+    yield gg
+    gg.close()
+
+
+@pytest.mark.parametrize("strategy", list(STRATS), ids=list(STRATS))
+@pytest.mark.parametrize("bound", [0, 1])
+def test_edge_index_same_walks(g12, gg12, gi12, strategy, bound):
+    """The edge index answers u in N(prev) exactly: walks and every counter but the
+    algorithmic bytes equal the searched rows'; all counters equal the oracle's with
+    indexed byte accounting."""
+    lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=0.5, q=2.0)
+    pl = oracle.Plan(rho=1.0, bound=bound)
+    starts = synth.all_vertices(g12["nv"])
+    a = gpu_walk(gg12, lg, pl, STRATS[strategy], starts, 20, 3)
+    b = gpu_walk(gi12, lg, pl, STRATS[strategy], starts, 20, 3, lds_cap=16)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+    for k in COUNTERS[:-1]:
+        assert a[2][k] == b[2][k], k
+    ora = oracle.walk(oracle.Graph(g12), lg, oracle.Plan(rho=1.0, bound=bound, member_index=True),
+                      STRATS[strategy], starts, 20, 3)
+    rep = parity(b[0], b[1], ora)
+    assert_parity(rep)
+    if rep["mismatch_walkers"] == 0:
+        _assert_counters(b[2], ora)
+
+
+@pytest.mark.parametrize("strategy", ["rvs", "auto", "rjs"])
+def test_edge_index_hub_rows(strategy):
+    """Hub rows of 3000 neighbours with N(prev) never staged: every membership test of
+    the eRVS scan goes through the index."""
+    g = hub_ring_graph(3000)
+    gg = GpuGraph(g, index=True)
+    try:
+        starts = np.arange(1, 3001, dtype=np.int32)
+        pl = oracle.Plan(rho=1.0, member_index=True)
+        p, ln, st, ora = _run_both(gg, g, N2V, pl, STRATS[strategy], starts, 6, 11, lds_cap=0)
+        rep = parity(p, ln, ora)
+        assert_parity(rep)
+        if rep["mismatch_walkers"] == 0:
+            _assert_counters(st, ora)
+    finally:
+        gg.close()
+
+
+def test_edge_index_idempotent_and_tiny_graphs():
+    for g in (synth.csr_from_edges(3, [(0, 1)], h=[2]), synth.csr_from_edges(2, [], h=[])):
+        gg = GpuGraph(g, index=True)
+        try:
+            fw.fw_graph_build_index(gg.handle)  # second call is a no-op
+            p, ln, st = gpu_walk(gg, N2V, oracle.Plan(), oracle.AUTO, np.zeros(3, np.int32), 4, 1)
+            ora = oracle.walk(oracle.Graph(g), N2V, oracle.Plan(member_index=True), oracle.AUTO,
+                              np.zeros(3, np.int32), 4, 1)
+            np.testing.assert_array_equal(p, ora.paths)
+        finally:
+            gg.close()
