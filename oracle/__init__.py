@@ -36,7 +36,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 AUTO, RVS_ONLY, RJS_ONLY, ITS = 0, 1, 2, 3
-NODE2VEC, METAPATH = 1, 2
+NODE2VEC, METAPATH, SECOND_PR = 1, 2, 3
 COUNTER_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", "rvs_triggers",
                  "ended_early", "alg_bytes", "flagged_steps")
 
@@ -48,7 +48,8 @@ class _Graph(ctypes.Structure):
 
 class _Logic(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("weighted", ctypes.c_int32), ("p", ctypes.c_float),
-                ("q", ctypes.c_float), ("schema_len", ctypes.c_int32), ("schema", ctypes.c_uint8 * 64)]
+                ("q", ctypes.c_float), ("gamma", ctypes.c_float), ("schema_len", ctypes.c_int32),
+                ("schema", ctypes.c_uint8 * 64)]
 
 
 class _Plan(ctypes.Structure):
@@ -59,16 +60,19 @@ class _Plan(ctypes.Structure):
 
 @dataclass
 class Logic:
-    """Walk logic: Node2Vec (p = the paper's a, q = b) or MetaPath (label schema)."""
+    """Walk logic: Node2Vec (p = the paper's a, q = b), MetaPath (label schema) or
+    second-order PageRank (gamma)."""
     kind: int = NODE2VEC
     weighted: bool = True
     p: float = 1.0
     q: float = 1.0
     schema: tuple = ()
+    gamma: float = 0.2
 
     def _c(self):
         s = _Logic()
         s.kind, s.weighted, s.p, s.q = self.kind, int(self.weighted), self.p, self.q
+        s.gamma = self.gamma
         s.schema_len = len(self.schema)
         for i, v in enumerate(self.schema):
             s.schema[i] = v

@@ -11,7 +11,10 @@ rational arithmetic:
   neighbour of the previous vertex (dist 1), 1/b otherwise (dist 2); a, b are called
   p, q here.  The first step has no previous vertex and uses w = 1;
 * MetaPath: w = 1 when the edge label equals the schema label of the current step
-  (schema repeated along the walk), else 0.
+  (schema repeated along the walk), else 0;
+* second-order PageRank (Eq. 2ndpr): with max_d = max(d(v), d(v')),
+  w = ((1 - gamma)/d(v) + gamma/d(v')) * max_d if u is a neighbour of v' (dist 1),
+  else ((1 - gamma)/d(v)) * max_d; the first step has no v' and uses w = 1.
 
 A walk ends early when the current vertex has no neighbour of positive weight.
 Float inputs (p, q, h) are converted to fractions exactly.
@@ -22,7 +25,7 @@ from fractions import Fraction
 
 import numpy as np
 
-NODE2VEC, METAPATH = 1, 2
+NODE2VEC, METAPATH, SECOND_PR = 1, 2, 3
 
 
 def _row(g, v):
@@ -42,6 +45,16 @@ def workload_weight(g, logic, j: int, prev: int, k: int) -> Fraction:
         return 1 / Fraction(float(logic.q))
     if logic.kind == METAPATH:
         return Fraction(1) if int(g["label"][k]) == logic.schema[j % len(logic.schema)] else Fraction(0)
+    if logic.kind == SECOND_PR:
+        if j == 0:
+            return Fraction(1)
+        cur = int(np.searchsorted(g["row_ptr"], k, side="right")) - 1  # the row holding position k
+        dv, dvp = len(_row(g, cur)), len(_row(g, prev))
+        gamma = Fraction(float(logic.gamma))
+        max_d = max(dv, dvp)
+        if u != prev and any(int(g["col"][t]) == u for t in _row(g, prev)):
+            return ((1 - gamma) / dv + gamma / dvp) * max_d
+        return (1 - gamma) / dv * max_d
     raise ValueError(logic.kind)
 
 

@@ -12,6 +12,9 @@
  *     a and b are called p and q here;
  *   - MetaPath: weight 1 when the edge label matches the schema position, else 0
  *     (Section 2.1);
+ *   - Second-order PageRank (Eq. 2ndpr): with max_d = max(d(v), d(v')), weight
+ *     ((1-g)/d(v) + g/d(v')) * max_d when u is a neighbour of v', ((1-g)/d(v)) * max_d
+ *     otherwise; the first step has no v' and uses weight 1;
  *   - eRVS: exponential keys k_i = u_i^(1/w~_i), argmax wins, ">=" so later items win
  *     ties (Section 3.2, Algorithm 1), plus the jump of Eq. (jump) run per lane with a
  *     shared initial maximum (Section 3.2, parallel description);
@@ -44,7 +47,8 @@
  * pins catch it: 1 swaps the Node2Vec return weight 1/p for 1/q, 2 drops the
  * conditioning of the jump key, 3 keeps the skip sum after a jump, 4 never proposes
  * the last neighbour in eRJS, 5 drops h_MAX from the eRJS bound, 6 makes the split
- * bound's extra column the full return weight instead of its excess over Bn.
+ * bound's extra column the full return weight instead of its excess over Bn, 7 divides
+ * the second-order PageRank term g by d(v) instead of d(v').
  */
 #ifndef OG_MUTANT
 #define OG_MUTANT 0
@@ -108,11 +112,12 @@ typedef struct {
     const uint8_t *label; /* NULL unless MetaPath */
 } og_graph;
 
-enum { OG_NODE2VEC = 1, OG_METAPATH = 2 };
+enum { OG_NODE2VEC = 1, OG_METAPATH = 2, OG_SECOND_PR = 3 };
 typedef struct {
     int32_t kind;
     int32_t weighted;
     float p, q;          /* Node2Vec a, b */
+    float gamma;         /* second-order PageRank */
     int32_t schema_len;  /* MetaPath */
     uint8_t schema[64];
 } og_logic;
@@ -193,10 +198,31 @@ static int ceil_log2_plus1(int64_t m) /* ceil(log2(m + 1)): probes of a binary s
     return c;
 }
 
-/* Workload weight w(v, u) for the edge at CSR position k (u = col[k]) at step j. */
-static float workload_weight(const og_ctx *cx, int64_t k, int j, int32_t prev)
+/* The two values of the second-order PageRank weight at a step with d(v) = dv and
+ * d(v') = dvp, in float32 in the order Eq. (2ndpr) writes them: in = for u in N(v'),
+ * out = otherwise. */
+static void second_pr_weights(const og_logic *lg, int64_t dv, int64_t dvp, float *in, float *out)
+{
+    const float a = 1.0f - lg->gamma;
+    const float t1 = a / (float)dv;
+    const float t2 = lg->gamma / (float)(OG_MUTANT == 7 ? dv : dvp);
+    const float md = (float)(dv > dvp ? dv : dvp);
+    *in = (t1 + t2) * md;
+    *out = t1 * md;
+}
+
+/* Workload weight w(v, u) for the edge at CSR position k (u = col[k]) at step j, where
+ * v has degree dv and the previous vertex prev has degree dvp. */
+static float workload_weight(const og_ctx *cx, int64_t k, int j, int32_t prev, int64_t dv, int64_t dvp)
 {
     const og_logic *lg = cx->lg;
+    if (lg->kind == OG_SECOND_PR) {
+        if (j == 0) return 1.0f;                     /* no previous vertex yet */
+        float in, out;
+        second_pr_weights(lg, dv, dvp, &in, &out);
+        int32_t u = cx->g->col[k];
+        return (u != prev && is_neighbour(cx->g, prev, u)) ? in : out; /* dist(v', u) = 1 or not */
+    }
     if (lg->kind == OG_NODE2VEC) {
         if (j == 0) return 1.0f;                     /* no previous vertex yet */
         int32_t u = cx->g->col[k];
@@ -208,22 +234,33 @@ static float workload_weight(const og_ctx *cx, int64_t k, int j, int32_t prev)
     return cx->g->label[k] == lg->schema[j % lg->schema_len] ? 1.0f : 0.0f;
 }
 
-static float transition_weight(const og_ctx *cx, int64_t k, int j, int32_t prev)
+static float transition_weight(const og_ctx *cx, int64_t k, int j, int32_t prev, int64_t dv, int64_t dvp)
 {
-    float w = workload_weight(cx, k, j, prev);
+    float w = workload_weight(cx, k, j, prev, dv, dvp);
     if (cx->lg->weighted && cx->g->h) return w * cx->g->h[k];
     return w;
 }
 
 /* max over the workload's return values, and their mean (Section 4.2 helpers) */
-static float w_max(const og_logic *lg, int j)
+static float w_max(const og_logic *lg, int j, int64_t dv, int64_t dvp)
 {
     if (lg->kind == OG_NODE2VEC && j > 0) return fmaxf(fmaxf(1.0f / lg->p, 1.0f), 1.0f / lg->q);
+    if (lg->kind == OG_SECOND_PR && j > 0) {
+        float in, out;
+        second_pr_weights(lg, dv, dvp, &in, &out);
+        return fmaxf(in, out);
+    }
     return 1.0f;
 }
 
-static float w_avg(const og_logic *lg, int j)
+static float w_avg(const og_logic *lg, int j, int64_t dv, int64_t dvp)
 {
+    if (lg->kind == OG_SECOND_PR) {
+        if (j == 0) return 1.0f;
+        float in, out;
+        second_pr_weights(lg, dv, dvp, &in, &out);
+        return (in + out) / 2.0f;
+    }
     if (lg->kind == OG_NODE2VEC) {
         if (j == 0) return 1.0f;
         return ((1.0f / lg->p + 1.0f) + 1.0f / lg->q) / 3.0f;
@@ -241,7 +278,7 @@ static double bytes_per_item(const og_ctx *cx)
 
 /* eRVS over the row of `cur`, Section 3.2.  Returns the CSR offset within the row or -1. */
 static int64_t rvs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int64_t base, int64_t deg,
-                          og_info *info)
+                          int64_t dvp, og_info *info)
 {
     const int64_t P = cx->pl->lanes;
     uint32_t x[4];
@@ -251,7 +288,7 @@ static int64_t rvs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
         float best = -INFINITY;
         int64_t best_i = -1;
         for (int64_t i = 0; i < deg; ++i) {
-            float wt = transition_weight(cx, base + i, j, prev);
+            float wt = transition_weight(cx, base + i, j, prev, deg, dvp);
             if (!(wt > 0.0f)) continue;
             draw(cx->seed, w, (uint32_t)j, (uint32_t)i, 1, x);
             float k = ln_f(og_uniform(x[0])) / wt;
@@ -267,7 +304,7 @@ static int64_t rvs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
     float *thr_u = (float *)malloc(sizeof(float) * (size_t)n0);
     float lkg = -INFINITY;
     for (int64_t l = 0; l < n0; ++l) {
-        float wt = transition_weight(cx, base + l, j, prev);
+        float wt = transition_weight(cx, base + l, j, prev, deg, dvp);
         draw(cx->seed, w, (uint32_t)j, (uint32_t)l, 1, x);
         key0[l] = wt > 0.0f ? ln_f(og_uniform(x[0])) / wt : -INFINITY;
         thr_u[l] = og_uniform(x[1]);
@@ -284,7 +321,7 @@ static int64_t rvs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
         float T = thr == -INFINITY ? 0.0f : (thr >= 0.0f ? INFINITY : ln_f(thr_u[l]) / thr);
         float S = 0.0f;
         for (int64_t i = l + P; i < deg; i += P) {
-            float wt = transition_weight(cx, base + i, j, prev);
+            float wt = transition_weight(cx, base + i, j, prev, deg, dvp);
             S = S + wt;
             if (T > 0.0f && T < INFINITY) note_margin(info, S, T);
             if (S > T) {
@@ -323,7 +360,7 @@ static int64_t rvs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
  * E > 0 (split bound) a trial first decides between the extra column of height E,
  * owned by the return edge at row offset ret, and the deg regular columns of height B. */
 static int64_t rjs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int64_t base, int64_t deg,
-                          float B, float E, int64_t ret, og_info *info)
+                          int64_t dvp, float B, float E, int64_t ret, og_info *info)
 {
     uint32_t x[4];
     const og_logic *lg = cx->lg;
@@ -339,14 +376,16 @@ static int64_t rjs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
         uint64_t R = ((uint64_t)x[1] << 32) | x[0];
         int64_t idx = (int64_t)(((unsigned __int128)R * (unsigned __int128)(uint64_t)deg) >> 64);
         if (OG_MUTANT == 4 && deg > 1) idx = (int64_t)(((unsigned __int128)R * (unsigned __int128)(uint64_t)(deg - 1)) >> 64);
-        float wt = transition_weight(cx, base + idx, j, prev);
+        float wt = transition_weight(cx, base + idx, j, prev, deg, dvp);
         float y = og_uniform(x[2]) * B;
         info->bytes += bytes_per_item(cx);
         /* a membership search is needed only when the accept test is not already
            decided by the smallest and largest weight u could have */
-        if (lg->kind == OG_NODE2VEC && j > 0 && cx->g->col[base + idx] != prev) {
+        if ((lg->kind == OG_NODE2VEC || lg->kind == OG_SECOND_PR) && j > 0 && cx->g->col[base + idx] != prev) {
             float hv = (lg->weighted && cx->g->h) ? cx->g->h[base + idx] : 1.0f;
-            float lo = fminf(1.0f, 1.0f / lg->q) * hv, hi = fmaxf(1.0f, 1.0f / lg->q) * hv;
+            float wa = 1.0f, wb = 1.0f / lg->q;
+            if (lg->kind == OG_SECOND_PR) second_pr_weights(lg, deg, dvp, &wa, &wb);
+            float lo = fminf(wa, wb) * hv, hi = fmaxf(wa, wb) * hv;
             if (!(y < lo) && y < hi) {
                 int64_t pdeg = cx->g->row_ptr[prev + 1] - cx->g->row_ptr[prev];
                 info->bytes += cx->pl->member_index ? 8.0 : 4.0 * ceil_log2_plus1(pdeg);
@@ -359,12 +398,12 @@ static int64_t rjs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
 
 /* Inverse transform sampling over the exact weights (plain CPU sampler). */
 static int64_t its_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int64_t base, int64_t deg,
-                          og_info *info)
+                          int64_t dvp, og_info *info)
 {
     double *cum = (double *)malloc(sizeof(double) * (size_t)deg);
     double run = 0.0;
     for (int64_t i = 0; i < deg; ++i) {
-        run += (double)transition_weight(cx, base + i, j, prev);
+        run += (double)transition_weight(cx, base + i, j, prev, deg, dvp);
         cum[i] = run;
     }
     int64_t res = -1;
@@ -400,11 +439,12 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
     const int64_t base = g->row_ptr[cur], deg = g->row_ptr[cur + 1] - base;
     if (deg == 0) return -1;
 
+    const int64_t dvp = j > 0 ? g->row_ptr[prev + 1] - g->row_ptr[prev] : 0; /* d(v') */
     const int weighted = lg->weighted && g->h;
     const float hm = (weighted && OG_MUTANT != 5) ? cx->hmax[cur] : 1.0f;
     const float hs = weighted ? cx->hsum[cur] : (float)deg;
-    float B = (w_max(lg, j) * hm) * cx->pl->bound_scale; /* upper bound of max w~ */
-    const float Shat = w_avg(lg, j) * hs;                /* estimate of sum w~ */
+    float B = (w_max(lg, j, deg, dvp) * hm) * cx->pl->bound_scale; /* upper bound of max w~ */
+    const float Shat = w_avg(lg, j, deg, dvp) * hs;                /* estimate of sum w~ */
 
     /* split bound: regular height over the non-return weights, extra column for the
        return edge's excess (w~ret of the edge cur -> prev, 0 if there is none) */
@@ -416,7 +456,7 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
         for (int64_t i = 0; i < deg; ++i)
             if (g->col[base + i] == prev) ret = i;
         if (ret >= 0) {
-            float wret = transition_weight(cx, base + ret, j, prev);
+            float wret = transition_weight(cx, base + ret, j, prev, deg, dvp);
             E = OG_MUTANT == 6 ? wret : fmaxf(0.0f, wret - B);
         }
     }
@@ -440,23 +480,23 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
     int64_t off;
     if (cx->strategy == OG_ITS) {
         info->kind = 3;
-        off = its_sample(cx, w, j, prev, base, deg, info);
+        off = its_sample(cx, w, j, prev, base, deg, dvp, info);
     } else {
         off = -2;
         if (use_rjs) {
-            off = rjs_sample(cx, w, j, prev, base, deg, B, E, ret, info);
+            off = rjs_sample(cx, w, j, prev, base, deg, dvp, B, E, ret, info);
             info->kind = 1;
         }
         if (off == -2) {
             info->kind = use_rjs ? 2 : 0;
             info->bytes += (double)deg * bytes_per_item(cx);
-            if (lg->kind == OG_NODE2VEC && j > 0) {
-                int64_t pdeg = g->row_ptr[prev + 1] - g->row_ptr[prev];
+            if ((lg->kind == OG_NODE2VEC || lg->kind == OG_SECOND_PR) && j > 0) {
+                int64_t pdeg = dvp;
                 double stage = 4.0 * (double)pdeg;
                 double search = (double)deg * (cx->pl->member_index ? 8.0 : 4.0 * ceil_log2_plus1(pdeg));
                 info->bytes += stage < search ? stage : search;
             }
-            off = rvs_sample(cx, w, j, prev, base, deg, info);
+            off = rvs_sample(cx, w, j, prev, base, deg, dvp, info);
         }
     }
     if (off < 0) {

@@ -307,6 +307,65 @@ def test_split_bound_fewer_trials_rmat():
     assert tb < 0.75 * ta, (ta, tb)
 
 
+# ------------------------------------------------------------------ second-order PageRank
+PR2 = dict(kind=oracle.SECOND_PR, weighted=True, gamma=0.25)
+
+
+def test_second_pr_hand_worked_state():
+    """Eq. (2ndpr) at prev = 2 (degree 4), cur = 1 (degree 3) of the triangle graph with
+    gamma = 1/4: max_d = 4, weight (3/4 / 3 + 1/4 / 4) * 4 = 5/4 for u in N(2) and
+    (3/4 / 3) * 4 = 1 otherwise (the return edge to 2 included).  N(1) = {0, 2, 3} with
+    h = 1, 3, 4 gives w~ = 5/4, 3, 5 and probabilities 5/37, 12/37, 20/37."""
+    g = triangle_graph()
+    lg = oracle.Logic(**PR2)
+    t = exact.transition(g, lg, 1, 2, 1)
+    assert t == {0: Fraction(5, 37), 2: Fraction(12, 37), 3: Fraction(20, 37)}
+    assert exact.transition(g, lg, 0, -1, 1) == {0: Fraction(1, 8), 2: Fraction(3, 8), 3: Fraction(4, 8)}
+
+
+@pytest.mark.parametrize("name,strategy,plan", STRATS, ids=[s[0] for s in STRATS])
+@pytest.mark.parametrize("gamma", [0.25, 0.7])
+def test_second_pr_paths_chisquare(name, strategy, plan, gamma):
+    g = triangle_graph()
+    lg = oracle.Logic(**dict(PR2, gamma=gamma))
+    n = 60000
+    for start in (0, 4):
+        counts, _ = _walk_counts(g, lg, plan, strategy, start, 3, n, seed=31 + start)
+        probs = exact.path_distribution(g, lg, start, 3)
+        assert chisq_pvalue(counts, probs, n) > P_OK, (name, start)
+
+
+def test_second_pr_gamma0_is_first_order():
+    """gamma = 0 makes both branches (1/d(v)) * max_d: the step is the static walk
+    p(u) = h(v, u) / sum h, i.e. a row of the first-order transition matrix."""
+    g = hub_ring_graph(40)
+    lg = oracle.Logic(**dict(PR2, gamma=0.0))
+    og = oracle.Graph(g)
+    P = exact.first_order_matrix(g)
+    n = 80000
+    for strategy in (oracle.RJS_ONLY, oracle.RVS_ONLY):
+        r = oracle.walk(og, lg, oracle.Plan(), strategy, np.full(n, 3, np.int32), 2, 17, diagnostics=False)
+        at_hub = r.paths[:, 1] == 0
+        counts = {int(v): int(c) for v, c in zip(*np.unique(r.paths[at_hub, 2], return_counts=True))}
+        probs = {u: Fraction(float(P[0, u])) for u in range(g["nv"]) if P[0, u] > 0}
+        assert chisq_pvalue(counts, probs, int(at_hub.sum())) > P_OK
+
+
+def test_second_pr_mean_trials():
+    """State prev = 2, cur = 1 (gamma = 1/4): B = max(w) * h_MAX = 5/4 * 4 = 5, so the mean
+    eRJS trial count is deg * B / sum w~ = 3 * 5 / (37/4) = 60/37."""
+    g = triangle_graph()
+    lg = oracle.Logic(**PR2)
+    og = oracle.Graph(g)
+    og.aux()
+    n = 40000
+    trials = np.array([oracle.step_once(og, lg, oracle.Plan(rjs_cap=100000), oracle.RJS_ONLY, 3, i, 1, 2, 1)[3]
+                       for i in range(n)], dtype=np.float64)
+    want = 60.0 / 37.0
+    se = math.sqrt(want * (want - 1) / n)
+    assert abs(trials.mean() - want) < 5 * se, (trials.mean(), want)
+
+
 # ------------------------------------------------------------------ closed form / invariants
 def test_stationary_visits_proportional_to_degree():
     """p = q = 1, h = 1 on a connected non-bipartite graph: visits -> deg / 2|E|."""
@@ -377,6 +436,7 @@ MUTANTS = {
     4: "eRJS never proposes the last neighbour",
     5: "eRJS bound without h_MAX",
     6: "split bound's extra column is the whole return weight",
+    7: "second-order PageRank divides gamma by d(v) instead of d(v')",
 }
 
 
@@ -394,7 +454,9 @@ def test_planted_mistake_is_caught(mut, mutant_libs):
         for name, logic, strategy, plan in (("rvs_P2", N2V, oracle.RVS_ONLY, oracle.Plan(lanes=2)),
                                             ("rvs_P1", N2V, oracle.RVS_ONLY, oracle.Plan(lanes=1)),
                                             ("rjs", N2V, oracle.RJS_ONLY, oracle.Plan()),
-                                            ("rjs_split", N2V_RET, oracle.RJS_ONLY, oracle.Plan(bound=1))):
+                                            ("rjs_split", N2V_RET, oracle.RJS_ONLY, oracle.Plan(bound=1)),
+                                            ("rjs_2ndpr", PR2, oracle.RJS_ONLY, oracle.Plan()),
+                                            ("rvs_2ndpr", PR2, oracle.RVS_ONLY, oracle.Plan(lanes=2))):
             lg = oracle.Logic(**logic)
             n = 60000
             counts, _ = _walk_counts(g, lg, plan, strategy, 0, 3, n, seed=7)
