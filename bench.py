@@ -78,6 +78,9 @@ def main():
     ap.add_argument("--L", type=int, default=80)
     ap.add_argument("--p", type=float, default=0.5)
     ap.add_argument("--q", type=float, default=2.0)
+    ap.add_argument("--logic", default="node2vec", choices=["node2vec", "secondpr"],
+                    help="walk logic of the scale-22 job (node2vec p, q or second-order PageRank gamma)")
+    ap.add_argument("--gamma", type=float, default=0.2)
     ap.add_argument("--strategy", default="auto", choices=["auto", "rvs", "rjs"])
     ap.add_argument("--modes", type=int, default=1, help="also time the single-kernel modes")
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -93,7 +96,29 @@ def main():
     ap.add_argument("--per-query", type=int, default=1, help="batched: also time one launch per query")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB: only run a plain device-to-device copy of this size 3 times (counter calibration)")
+    ap.add_argument("--calibrate-random", type=int, default=0,
+                    help="MiB: only gather 2^25 random float32 from an array of this size 3 times (counter "
+                         "calibration for random reads) and print the gather rate")
     args = ap.parse_args()
+    if args.calibrate_random:
+        import torch
+        dev = torch.device("cuda:0")
+        a = torch.ones((args.calibrate_random << 20) // 4, dtype=torch.float32, device=dev)
+        g = torch.Generator(device=dev)
+        g.manual_seed(5)
+        idx = torch.randint(0, a.numel(), (1 << 25,), device=dev, generator=g)
+        out = torch.empty(1 << 25, dtype=torch.float32, device=dev)
+        ms = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            torch.index_select(a, 0, idx, out=out)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        print(json.dumps({"random_reads": 1 << 25, "array_bytes": a.numel() * 4, "launches": 3, "ms": ms,
+                          "random_reads_per_s": (1 << 25) / (min(ms) / 1e3)}))
+        return
     if args.calibrate_copy:
         import torch
         n = args.calibrate_copy << 20
@@ -136,7 +161,12 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     index_ms = e0.elapsed_time(e1)
-    logic = fw.fw_logic_node2vec(args.p, args.q, True)
+    if args.logic == "secondpr":
+        logic = fw.fw_logic_second_pr(args.gamma, True)
+        logic_text = f"second-order PageRank gamma={args.gamma}"
+    else:
+        logic = fw.fw_logic_node2vec(args.p, args.q, True)
+        logic_text = f"node2vec p={args.p} q={args.q}"
     t1 = time.time()
     if args.plan:
         f = args.plan.split(",")
@@ -190,7 +220,7 @@ def main():
         other = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap, bound=1 - plan.bound)
         sym = fw.fw_graph_info(gh)[3]
         cases = [(m + "_only", m, plan) for m in ("rvs", "rjs") if m != args.strategy]
-        if sym or other.bound == 0:
+        if args.logic == "node2vec" and (sym or other.bound == 0):
             cases.append((("split" if other.bound else "paper") + "_bound", args.strategy, other))
         for name, m, pl in cases:
             mms, _, mst = run(m, 2, 1, plan=pl, paths=m_paths, lengths=m_lengths)
@@ -207,7 +237,8 @@ def main():
         import oracle
         og = oracle.Graph(g)
         og.aux()
-        lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=args.p, q=args.q)
+        lg = (oracle.Logic(kind=oracle.SECOND_PR, weighted=True, gamma=args.gamma) if args.logic == "secondpr"
+              else oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=args.p, q=args.q))
         pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap, bound=plan.bound, member_index=True)
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
         smode = {"auto": 0, "rvs": 1, "rjs": 2}[args.strategy]
@@ -244,7 +275,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"node2vec p={args.p} q={args.q} weighted h~U(1,10), R-MAT scale 22 "
+        "config": {"workload": f"{logic_text} weighted h~U(1,10), R-MAT scale 22 "
                                f"(a=0.57,b=0.19,c=0.19, edge factor 16, {g['ne']} CSR entries), one walker "
                                f"per vertex ({nv}), L={L}, strategy={args.strategy}",
                    "walker_steps_per_walk_job": steps_per_walk, "preprocess_ms": prep_ms,

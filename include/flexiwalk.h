@@ -38,11 +38,15 @@ typedef enum fw_status {
     FW_E_BUSY = 5     /* the server's waiting queue is full; retry later */
 } fw_status;
 
-/* Sampling strategy per step (Section 4.1; single-kernel modes of the ablation). */
-enum { FW_AUTO = 0, FW_RVS_ONLY = 1, FW_RJS_ONLY = 2 };
+/* Sampling strategy per step: the cost model of Section 4.1 (AUTO), the single-kernel
+ * modes of the ablation, and the two selection policies the evaluation compares the cost
+ * model with (sensitivity on selection strategy): a fair coin per step drawn from the
+ * walker's stream (Philox counter (walker, step, 0, 4), eRJS iff U(x0) < 1/2), and eRVS
+ * below the degree plan.d_lo (1K in the paper) with eRJS at or above it. */
+enum { FW_AUTO = 0, FW_RVS_ONLY = 1, FW_RJS_ONLY = 2, FW_RANDOM_SELECT = 4, FW_DEGREE_SELECT = 5 };
 
 /* Walk logics (Section 2.1). */
-enum { FW_NODE2VEC = 1, FW_METAPATH = 2 };
+enum { FW_NODE2VEC = 1, FW_METAPATH = 2, FW_SECOND_PR = 3 };
 
 #define FW_MAX_SCHEMA 64
 #define FW_NSTATS 8
@@ -70,11 +74,16 @@ typedef struct fw_graph fw_graph; /* opaque, library-owned device copy of a grap
  * FW_METAPATH (Section 2.1): w = 1 if the label of edge (v,u) equals
  *   schema[j mod schema_len] at step j, else 0; a walk ends when no neighbour has
  *   positive weight.
+ * FW_SECOND_PR (Eq. 2ndpr): with max_d = max(d(v), d(v')), w = ((1 - gamma)/d(v) +
+ *   gamma/d(v')) * max_d if u is a neighbour of the previous vertex v', else
+ *   ((1 - gamma)/d(v)) * max_d (the return to v' included); evaluated in float32 in that
+ *   order.  The first step has no previous vertex and uses w = 1.
  * weighted: 1 uses w~ = w * h, 0 uses w~ = w. */
 typedef struct fw_logic {
     int32_t kind;
     int32_t weighted;
     float p, q;
+    float gamma;
     int32_t schema_len;
     uint8_t schema[FW_MAX_SCHEMA];
 } fw_logic;
@@ -138,10 +147,11 @@ int fw_graph_export_aux(const fw_graph *g, float *hmax, float *hsum);
 
 /* Build the edge index: an exact hash set of the entries (v, u) (64-byte buckets of eight
  * 64-bit keys, at most half full; 16 bytes of device memory per entry, rounded up to a
- * power-of-two bucket count).  Node2Vec's membership test u in N(prev) then reads one
- * bucket instead of searching prev's sorted row; samples and counts of eRJS trials do not
- * change (the algorithmic-byte counter charges 8 bytes per test instead of a binary
- * search's).  Asynchronous on `stream`; idempotent.  Walks, batches and servers created
+ * power-of-two bucket count).  The membership test u in N(prev) of an eRJS proposal
+ * (Node2Vec, second-order PageRank) then reads one bucket instead of searching prev's
+ * sorted row; eRVS steps keep searching the row, which all lanes of the step share.
+ * Samples and counts of eRJS trials do not change (the algorithmic-byte counter charges
+ * 8 bytes per eRJS test instead of a binary search's).  Asynchronous on `stream`; idempotent.  Walks, batches and servers created
  * afterwards use it; build it before creating batches or servers.  Returns FW_E_NOMEM if
  * the table cannot be allocated (the graph stays usable without it). */
 int fw_graph_build_index(fw_graph *g, void *stream);
@@ -156,6 +166,9 @@ int fw_logic_node2vec(float p, float q, int32_t weighted, fw_logic *out);
 
 /* Build a MetaPath logic from `m` labels (1 <= m <= FW_MAX_SCHEMA, host pointer). */
 int fw_logic_metapath(const uint8_t *schema, int32_t m, int32_t weighted, fw_logic *out);
+
+/* Build a second-order PageRank logic; 0 <= gamma <= 1. */
+int fw_logic_second_pr(float gamma, int32_t weighted, fw_logic *out);
 
 /* Default plan: rho = 8, d_lo = 0, rjs_cap = 1024, lanes = 64, lds_cap and grid chosen
  * by the library. */

@@ -35,7 +35,7 @@ _SRC = os.path.join(_HERE, "walk_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-AUTO, RVS_ONLY, RJS_ONLY, ITS = 0, 1, 2, 3
+AUTO, RVS_ONLY, RJS_ONLY, ITS, RANDOM_SELECT, DEGREE_SELECT = 0, 1, 2, 3, 4, 5
 NODE2VEC, METAPATH, SECOND_PR = 1, 2, 3
 COUNTER_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", "rvs_triggers",
                  "ended_early", "alg_bytes", "flagged_steps")

@@ -37,7 +37,8 @@
  * Canonical stream.  To compare samples one by one with a GPU run the random numbers
  * are a fixed function of (seed, walker, step, draw): Philox4x32-10 (Salmon, Moraes,
  * Dror, Shaw, "Parallel Random Numbers: As Easy as 1, 2, 3", SC'11) with key = seed and
- * counter = (walker, step, draw, tag); tag 0 = eRJS trial, 1 = eRVS item, 3 = ITS.
+ * counter = (walker, step, draw, tag); tag 0 = eRJS trial, 1 = eRVS item, 3 = ITS,
+ * 4 = random selection.
  * All sampling arithmetic is IEEE float32 with round-to-nearest and no contraction;
  * logarithms are evaluated in double and rounded once to float32.
  *
@@ -130,11 +131,16 @@ typedef struct {
     int32_t jump;        /* 1: Eq. (jump); 0: a key for every item */
     float bound_scale;   /* multiplies the eRJS bound (>= 1 keeps it a bound) */
     int32_t bound;       /* 0: max(w) * h_MAX (Section 3.3); 1: Node2Vec split bound */
-    int32_t member_index; /* byte accounting only: a membership test reads one 8-byte key of
-                             an edge index (1) or binary-searches the sorted row (0) */
+    int32_t member_index; /* byte accounting only: an eRJS membership test reads one 8-byte
+                             key of an edge index (1) or binary-searches the sorted row (0);
+                             eRVS always searches the row (all its tests share N(prev)) */
 } og_plan;
 
-enum { OG_AUTO = 0, OG_RVS_ONLY = 1, OG_RJS_ONLY = 2, OG_ITS = 3 };
+/* OG_RANDOM_SELECT and OG_DEGREE_SELECT are the two selection policies the paper compares
+ * its cost model against (Section 6, sensitivity on selection strategy): a fair coin per
+ * step (draw tag 4), and eRVS below a degree threshold (plan.d_lo, 1K in the paper) with
+ * eRJS above it. */
+enum { OG_AUTO = 0, OG_RVS_ONLY = 1, OG_RJS_ONLY = 2, OG_ITS = 3, OG_RANDOM_SELECT = 4, OG_DEGREE_SELECT = 5 };
 
 /* Per-node preprocessing: h_MAX is the row maximum of h; h_SUM is the row sum of h,
  * accumulated in double and rounded once to float32 (Section 4.2, preprocess()). */
@@ -475,6 +481,14 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
             note_margin(info, lhs, rhs);
             use_rjs = lhs < rhs;
         }
+    } else if (cx->strategy == OG_RANDOM_SELECT) {
+        if (weighted) info->bytes += 4.0;
+        uint32_t x[4];
+        draw(cx->seed, w, (uint32_t)j, 0, 4, x);
+        use_rjs = og_uniform(x[0]) < 0.5f;
+    } else if (cx->strategy == OG_DEGREE_SELECT) {
+        if (weighted) info->bytes += 4.0;
+        use_rjs = deg >= cx->pl->d_lo;
     }
 
     int64_t off;
@@ -493,7 +507,7 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
             if ((lg->kind == OG_NODE2VEC || lg->kind == OG_SECOND_PR) && j > 0) {
                 int64_t pdeg = dvp;
                 double stage = 4.0 * (double)pdeg;
-                double search = (double)deg * (cx->pl->member_index ? 8.0 : 4.0 * ceil_log2_plus1(pdeg));
+                double search = 4.0 * (double)deg * ceil_log2_plus1(pdeg);
                 info->bytes += stage < search ? stage : search;
             }
             off = rvs_sample(cx, w, j, prev, base, deg, dvp, info);

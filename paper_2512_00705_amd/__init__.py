@@ -18,14 +18,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libflexiwalk.so")
 
 FW_OK, FW_E_INVALID, FW_E_NOMEM, FW_E_DEVICE, FW_E_STATE, FW_E_BUSY = 0, 1, 2, 3, 4, 5
-FW_AUTO, FW_RVS_ONLY, FW_RJS_ONLY = 0, 1, 2
-FW_NODE2VEC, FW_METAPATH = 1, 2
+FW_AUTO, FW_RVS_ONLY, FW_RJS_ONLY, FW_RANDOM_SELECT, FW_DEGREE_SELECT = 0, 1, 2, 4, 5
+FW_NODE2VEC, FW_METAPATH, FW_SECOND_PR = 1, 2, 3
 FW_MAX_SCHEMA = 64
 FW_NSTATS = 8
 STAT_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", "rvs_triggers",
               "ended_early", "alg_bytes")
 EXPORTED = ("fw_graph_create", "fw_graph_destroy", "fw_graph_preprocess", "fw_graph_build_index",
-            "fw_graph_export_aux", "fw_graph_info", "fw_logic_node2vec", "fw_logic_metapath", "fw_plan_default",
+            "fw_graph_export_aux", "fw_graph_info", "fw_logic_node2vec", "fw_logic_metapath", "fw_logic_second_pr",
+            "fw_plan_default",
             "fw_plan_profile", "fw_plan_autotune", "fw_walk", "fw_graph_check", "fw_last_error",
             "fw_batch_create", "fw_batch_launch", "fw_batch_capture", "fw_batch_replay", "fw_batch_destroy",
             "fw_server_create", "fw_server_submit", "fw_server_next_done", "fw_server_result", "fw_server_stats",
@@ -48,7 +49,7 @@ class fw_csr(ctypes.Structure):
 
 class fw_logic(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("weighted", ctypes.c_int32), ("p", ctypes.c_float),
-                ("q", ctypes.c_float), ("schema_len", ctypes.c_int32),
+                ("q", ctypes.c_float), ("gamma", ctypes.c_float), ("schema_len", ctypes.c_int32),
                 ("schema", ctypes.c_uint8 * FW_MAX_SCHEMA)]
 
 
@@ -78,6 +79,7 @@ def _load():
         "fw_graph_info": ([P, P, P, P, P], ctypes.c_int),
         "fw_logic_node2vec": ([ctypes.c_float, ctypes.c_float, I32, ctypes.POINTER(fw_logic)], ctypes.c_int),
         "fw_logic_metapath": ([P, I32, I32, ctypes.POINTER(fw_logic)], ctypes.c_int),
+        "fw_logic_second_pr": ([ctypes.c_float, I32, ctypes.POINTER(fw_logic)], ctypes.c_int),
         "fw_plan_default": ([ctypes.POINTER(fw_plan)], ctypes.c_int),
         "fw_plan_profile": ([P, ctypes.POINTER(fw_logic), ctypes.POINTER(fw_plan), P], ctypes.c_int),
         "fw_plan_autotune": ([P, ctypes.POINTER(fw_logic), ctypes.POINTER(fw_plan), P], ctypes.c_int),
@@ -182,6 +184,12 @@ def fw_logic_metapath(schema, weighted: bool = True) -> fw_logic:
     arr = np.ascontiguousarray(np.asarray(schema, dtype=np.uint8))
     out = fw_logic()
     _check(_lib.fw_logic_metapath(arr.ctypes.data, len(arr), int(weighted), ctypes.byref(out)))
+    return out
+
+
+def fw_logic_second_pr(gamma: float, weighted: bool = True) -> fw_logic:
+    out = fw_logic()
+    _check(_lib.fw_logic_second_pr(float(gamma), int(weighted), ctypes.byref(out)))
     return out
 
 

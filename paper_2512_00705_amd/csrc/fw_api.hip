@@ -249,6 +249,17 @@ int fw_logic_metapath(const uint8_t *schema, int32_t m, int32_t weighted, fw_log
     return ok();
 }
 
+int fw_logic_second_pr(float gamma, int32_t weighted, fw_logic *out)
+{
+    if (!out) return fail(FW_E_INVALID, "fw_logic_second_pr: null output");
+    if (!(gamma >= 0.0f && gamma <= 1.0f)) return fail(FW_E_INVALID, "second-order PageRank gamma must be in [0, 1]");
+    memset(out, 0, sizeof(*out));
+    out->kind = FW_SECOND_PR;
+    out->weighted = weighted ? 1 : 0;
+    out->gamma = gamma;
+    return ok();
+}
+
 int fw_plan_default(fw_plan *out)
 {
     if (!out) return fail(FW_E_INVALID, "fw_plan_default: null output");
@@ -274,6 +285,9 @@ int fw::host::check_logic(const fw_graph *g, const fw_logic *lg)
         if (lg->schema_len < 1 || lg->schema_len > FW_MAX_SCHEMA)
             return fail(FW_E_INVALID, "metapath schema length must be in [1, %d]", FW_MAX_SCHEMA);
         if (!g->label) return fail(FW_E_INVALID, "metapath needs edge labels");
+    } else if (lg->kind == FW_SECOND_PR) {
+        if (!(lg->gamma >= 0.0f && lg->gamma <= 1.0f))
+            return fail(FW_E_INVALID, "second-order PageRank gamma must be in [0, 1]");
     } else {
         return fail(FW_E_INVALID, "unknown logic kind %d", lg->kind);
     }
@@ -293,6 +307,13 @@ void fw::host::fill_query(const fw_logic *lg, fw::QueryDev &q)
         q.wavg0 = 1.0f;
         q.wmax1 = fmaxf(fmaxf(q.inv_p, 1.0f), q.inv_q);      // max over the three return values
         q.wavg1 = ((q.inv_p + 1.0f) + q.inv_q) / 3.0f;       // their mean (Section 4.2)
+    } else if (lg->kind == FW_SECOND_PR) {
+        // step 0 uses w = 1; later steps take max and mean of the two branches of
+        // Eq. (2ndpr), which depend on the step's degrees (computed in the kernel)
+        q.gamma = lg->gamma;
+        q.omg = 1.0f - lg->gamma;
+        q.wmax0 = q.wavg0 = 1.0f;
+        q.wmax1 = q.wavg1 = 1.0f;
     } else {
         q.wmax0 = q.wmax1 = 1.0f;
         q.wavg0 = q.wavg1 = (1.0f + 0.0f) / 2.0f;
@@ -353,7 +374,7 @@ int fw_walk(fw_graph *g, const fw_logic *lg, const fw_plan *pl, int32_t strategy
             int32_t L, uint64_t seed, int32_t *paths, int32_t *lengths, uint64_t *stats, void *stream)
 {
     if (!g || !lg || !pl) return fail(FW_E_INVALID, "fw_walk: null graph, logic or plan");
-    if (strategy < FW_AUTO || strategy > FW_RJS_ONLY) return fail(FW_E_INVALID, "fw_walk: bad strategy %d", strategy);
+    if (!fw::valid_strategy(strategy)) return fail(FW_E_INVALID, "fw_walk: bad strategy %d", strategy);
     if (n < 0 || n >= ((int64_t)1 << 31)) return fail(FW_E_INVALID, "fw_walk: n must be in [0, 2^31)");
     if (L < 0 || L >= (1 << 20)) return fail(FW_E_INVALID, "fw_walk: L must be in [0, 2^20)");
     if (n > 0 && (!starts || !paths || !lengths)) return fail(FW_E_INVALID, "fw_walk: null starts/paths/lengths");
@@ -586,7 +607,7 @@ int fw_batch_create(fw_graph *g, const fw_query *qs, int64_t nq, const fw_plan *
 {
     if (!g || !pl || !out || (nq > 0 && !qs)) return fail(FW_E_INVALID, "fw_batch_create: null argument");
     if (nq < 0 || nq >= ((int64_t)1 << 31)) return fail(FW_E_INVALID, "fw_batch_create: nq must be in [0, 2^31)");
-    if (strategy < FW_AUTO || strategy > FW_RJS_ONLY)
+    if (!fw::valid_strategy(strategy))
         return fail(FW_E_INVALID, "fw_batch_create: bad strategy %d", strategy);
     int rc = check_plan(pl);
     if (rc != FW_OK) return rc;

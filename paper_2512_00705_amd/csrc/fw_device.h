@@ -184,22 +184,25 @@ __device__ __forceinline__ uint64_t edge_key(int32_t v, int32_t u)
     return ((uint64_t)(uint32_t)v << 32) | (uint64_t)(uint32_t)u;
 }
 
-// tab: 4 uint4 per bucket, mask = buckets - 1 (buckets a power of two).  Scans at most
-// every bucket once, so it ends even on a full table.
+// tab: 4 uint4 per bucket, mask = buckets - 1 (buckets a power of two).  The bucket's
+// four 16-byte parts are loaded before any is tested, so they go out together as one
+// 64-byte request instead of one dependent load after another.  Scans at most every
+// bucket once, so it ends even on a full table.
 __device__ __forceinline__ bool index_contains(const uint4 *tab, uint64_t mask, int32_t v, int32_t u)
 {
     const uint64_t key = edge_key(v, u);
     uint64_t b = mix64(key) & mask;
     for (uint64_t t = 0; t <= mask; ++t) {
         const uint4 *p = tab + b * 4;
-        bool empty = false;
+        const uint4 x[4] = {p[0], p[1], p[2], p[3]};
+        bool hit = false, empty = false;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const uint4 x = p[i];
-            const uint64_t k0 = ((uint64_t)x.y << 32) | x.x, k1 = ((uint64_t)x.w << 32) | x.z;
-            if (k0 == key || k1 == key) return true;
+            const uint64_t k0 = ((uint64_t)x[i].y << 32) | x[i].x, k1 = ((uint64_t)x[i].w << 32) | x[i].z;
+            hit = hit || k0 == key || k1 == key;
             empty = empty || k0 == kEmptyKey || k1 == kEmptyKey;
         }
+        if (hit) return true;
         if (empty) return false;
         b = (b + 1) & mask;
     }

@@ -7,8 +7,17 @@
 
 namespace fw {
 
-enum Kind : int { kNode2Vec = 1, kMetaPath = 2 };
-enum Strategy : int { kAuto = 0, kRvsOnly = 1, kRjsOnly = 2 };
+enum Kind : int { kNode2Vec = 1, kMetaPath = 2, kSecondPR = 3 };
+constexpr int kNumKinds = 3;
+
+// Logics whose weight depends on u in N(prev) (the membership test).
+__host__ __device__ constexpr bool uses_membership(int kind) { return kind == kNode2Vec || kind == kSecondPR; }
+enum Strategy : int { kAuto = 0, kRvsOnly = 1, kRjsOnly = 2, kRandomSelect = 4, kDegreeSelect = 5 };
+
+__host__ __device__ constexpr bool valid_strategy(int s)
+{
+    return s == kAuto || s == kRvsOnly || s == kRjsOnly || s == kRandomSelect || s == kDegreeSelect;
+}
 enum Stat : int {
     kStSteps = 0,
     kStRjs = 1,
@@ -47,7 +56,8 @@ struct QueryDev {
     float inv_p, inv_q;         // 1/p, 1/q
     float lo_w, hi_w;           // min(1, 1/q), max(1, 1/q)
     float wmax0, wavg0;         // max and mean workload weight at step 0
-    float wmax1, wavg1;         // ... at steps >= 1
+    float wmax1, wavg1;         // ... at steps >= 1 (Node2Vec, MetaPath)
+    float gamma, omg;           // second-order PageRank: gamma and 1 - gamma
     int32_t L;
     int32_t schema_len;
     uint8_t schema[64];

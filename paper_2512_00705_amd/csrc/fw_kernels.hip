@@ -23,18 +23,21 @@ namespace fw {
 enum Mode : int { kIdle = 0, kSetup = 1, kRjs = 2, kRvs = 3, kAdv = 4 };
 
 // N(prev) for the membership test: a copy in this wave's LDS or the row of prev in col,
-// read through one flat pointer either way.  An unstaged row is tested through the edge
-// index when the graph has one.
+// read through one flat pointer either way.  `indexed`: test an unstaged row through the
+// edge index when the graph has one.  That pays where lanes test different rows (eRJS);
+// where a whole wave tests one row (an eRVS step) its probes hit the cache and the
+// search is cheaper than scattered bucket reads.
 struct Mem {
     const int32_t *p;
     int64_t len;
     bool staged;
+    bool indexed;
 };
 
-// u in N(prev): LDS copy, else the edge index, else a search of prev's sorted row.
+// u in N(prev): LDS copy, else the edge index if asked for, else a search of the row.
 __device__ __forceinline__ bool in_prev_row(const WalkArgs &a, const Mem &m, int32_t prev, int32_t u)
 {
-    if (!m.staged && a.mtab != nullptr) return index_contains(a.mtab, a.mtab_mask, prev, u);
+    if (!m.staged && m.indexed && a.mtab != nullptr) return index_contains(a.mtab, a.mtab_mask, prev, u);
     return sorted_contains_interp(m.p, (int32_t)m.len, u, (int32_t)a.nv);
 }
 
@@ -58,13 +61,42 @@ __device__ __forceinline__ int32_t query_of(const WalkArgs &a, int64_t w)
     return lo;
 }
 
+// The workload weights of a step that depend on u only through u in N(prev): `mem` for
+// u in N(prev), `oth` otherwise, `ret` for u = prev, and their smallest and largest
+// (Node2Vec: 1, 1/q, 1/p from the query; second-order PageRank: the two branches of
+// Eq. (2ndpr) at this step's d(v), d(v'), the return taking the second).
+struct StepW {
+    float mem, oth, ret, lo, hi;
+};
+
+template <int KIND>
+__device__ __forceinline__ StepW step_weights(const QueryDev &Q, int32_t dv, int32_t dvp)
+{
+    if (KIND == kSecondPR) {
+        // in float32 in the order of Eq. (2ndpr): ((1-g)/d(v) + g/d(v')) * max_d, ((1-g)/d(v)) * max_d
+        const float t1 = Q.omg / (float)dv;
+        const float t2 = Q.gamma / (float)(dvp > 0 ? dvp : 1);
+        const float md = (float)(dv > dvp ? dv : dvp);
+        const float in = (t1 + t2) * md, out = t1 * md;
+        return StepW{in, out, out, fminf(in, out), fmaxf(in, out)};
+    }
+    return StepW{1.0f, Q.inv_q, Q.inv_p, Q.lo_w, Q.hi_w};
+}
+
 // Transition weight w~ = w * h of the edge at CSR position k (record e) at step j
-// (Section 2.1, Eq. prob; Eq. node2vec; MetaPath rule).  `m` holds N(prev) sorted.
+// (Section 2.1, Eq. prob; Eq. node2vec; MetaPath rule; Eq. 2ndpr).  `m` holds N(prev)
+// sorted; `sw` the step's weights.
 template <int KIND, bool W>
 __device__ __forceinline__ float edge_weight(const WalkArgs &a, const QueryDev &Q, int64_t k, uint2 e, int j,
-                                             int32_t prev, const Mem &m, uint8_t want)
+                                             int32_t prev, const Mem &m, uint8_t want, const StepW &sw)
 {
     const float hv = W ? __uint_as_float(e.y) : 1.0f;
+    if (KIND == kSecondPR) {
+        if (j == 0) return hv;
+        const int32_t u = (int32_t)e.x;
+        if (u == prev) return sw.ret * hv;
+        return in_prev_row(a, m, prev, u) ? sw.mem * hv : sw.oth * hv;
+    }
     if (KIND == kNode2Vec) {
         if (j == 0) return hv;
         const int32_t u = (int32_t)e.x;
@@ -86,7 +118,7 @@ __device__ __forceinline__ int64_t row_start(const WalkArgs &a, uint4 r, int32_t
 template <int KIND, bool W>
 __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q, const Mem &mem, uint32_t wid,
                                             int j, int32_t prev, int64_t base, int64_t deg, uint8_t want,
-                                            uint32_t &trig, float &hsel)
+                                            const StepW &sw, uint32_t &trig, float &hsel)
 {
     const int lane = lane_id();
     const uint32_t k0 = Q.key0, k1 = Q.key1;
@@ -96,7 +128,7 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q
     // round 0: lane l keys neighbour l, k = u^(1/w~) kept as log(u) / w~
     if (lane < deg) {
         const int64_t k = base + lane;
-        const float wt = edge_weight<KIND, W>(a, Q, k, a.edges[k], j, prev, mem, want);
+        const float wt = edge_weight<KIND, W>(a, Q, k, a.edges[k], j, prev, mem, want, sw);
         const U4 x = philox(wid, (uint32_t)j, (uint32_t)lane, 1u, k0, k1);
         key = wt > 0.0f ? ln_f(unit_uniform(x.x0)) / wt : -INFINITY;
         ru = unit_uniform(x.x1);
@@ -113,7 +145,7 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q
         const int64_t i = i0 + lane;
         if (i < deg) {
             const int64_t k = base + i;
-            const float wt = edge_weight<KIND, W>(a, Q, k, a.edges[k], j, prev, mem, want);
+            const float wt = edge_weight<KIND, W>(a, Q, k, a.edges[k], j, prev, mem, want, sw);
             S = S + wt;
             if (S > T) {
                 // key conditioned to beat thr: log u' = log1p(expm1(w~ * thr) * V)
@@ -180,8 +212,9 @@ __device__ __forceinline__ bool rvs_group_pass(const WalkArgs &a, int G, uint64_
         const QueryDev &Q = query<BATCH>(a, s_q);
         const int64_t k = s_base + r;
         const uint8_t want = (KIND == kMetaPath) ? Q.schema[s_j % Q.schema_len] : (uint8_t)0;
-        const Mem m = {a.col + s_pbase, s_pdeg, false};
-        const float wt = edge_weight<KIND, W>(a, Q, k, a.edges[k], s_j, s_prev, m, want);
+        const Mem m = {a.col + s_pbase, s_pdeg, false, false};
+        const StepW sw = step_weights<KIND>(Q, s_deg, s_pdeg);
+        const float wt = edge_weight<KIND, W>(a, Q, k, a.edges[k], s_j, s_prev, m, want, sw);
         const U4 x = philox(s_wid, (uint32_t)s_j, (uint32_t)r, 1u, Q.key0, Q.key1);
         key = wt > 0.0f ? ln_f(unit_uniform(x.x0)) / wt : -INFINITY;
         bi = r;
@@ -349,7 +382,14 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 } else {
                     bool rjs = false;
                     if (a.strategy != kRvsOnly) {
-                        const float wmax = (j == 0) ? Q.wmax0 : Q.wmax1;
+                        float wmax = (j == 0) ? Q.wmax0 : Q.wmax1;
+                        float wavg = (j == 0) ? Q.wavg0 : Q.wavg1;
+                        if (KIND == kSecondPR && j > 0) {
+                            // max and mean over the two branches of Eq. (2ndpr) at this step
+                            const StepW sw = step_weights<KIND>(Q, deg, pdeg);
+                            wmax = fmaxf(sw.mem, sw.oth);
+                            wavg = (sw.mem + sw.oth) / 2.0f;
+                        }
                         const float hm = W ? __uint_as_float(r.z) : 1.0f;
                         // get_weight_max: max(w) * h_MAX; the split bound's column height
                         // leaves the return weight 1/p out
@@ -358,8 +398,15 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                         if (a.strategy == kRjsOnly) {
                             rjs = true;
                             st_bytes += W ? 4 : 0;
+                        } else if (a.strategy == kRandomSelect) {
+                            // comparison policy: a fair coin from the walker's own stream
+                            const U4 x = philox((uint32_t)wid, (uint32_t)j, 0u, 4u, Q.key0, Q.key1);
+                            rjs = unit_uniform(x.x0) < 0.5f;
+                            st_bytes += W ? 4 : 0;
+                        } else if (a.strategy == kDegreeSelect) {
+                            rjs = deg >= a.d_lo;  // comparison policy: eRJS at high degree
+                            st_bytes += W ? 4 : 0;
                         } else {
-                            const float wavg = (j == 0) ? Q.wavg0 : Q.wavg1;
                             const float hs = W ? __uint_as_float(r.w) : (float)deg;
                             st_bytes += W ? 8 : 0;
                             // Eq. (runtime) with get_weight_sum = mean(w) * h_SUM; with the
@@ -408,7 +455,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 else ee[r] = a.edges[k];
                 ll[r] = (KIND == kMetaPath) ? a.label[k] : (uint8_t)0;
             }
-            const float inv_p = Q.inv_p, inv_q = Q.inv_q, lo_w = Q.lo_w, hi_w = Q.hi_w;
+            const StepW sw = step_weights<KIND>(Q, deg, pdeg);
             // decide proposals in order; the batch shifts down one slot per trial so the
             // decision code appears once
 #pragma unroll 1
@@ -419,13 +466,13 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 bool acc;
                 if (ol[0]) {
                     acc = true;  // the extra column belongs to the return edge
-                } else if (KIND == kNode2Vec) {
+                } else if (uses_membership(KIND)) {
                     if (j == 0) {
                         acc = y < hv;
                     } else if (u == prev) {
-                        acc = y < inv_p * hv;
+                        acc = y < sw.ret * hv;
                     } else {
-                        const float lo = lo_w * hv, hi = hi_w * hv;
+                        const float lo = sw.lo * hv, hi = sw.hi * hv;
                         if (y < lo) {
                             acc = true;
                         } else if (!(y < hi)) {
@@ -434,7 +481,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                             st_bytes += a.mtab ? 8 : 4 * (uint64_t)probes(pdeg);
                             const bool member = a.mtab ? index_contains(a.mtab, a.mtab_mask, prev, u)
                                                        : sorted_contains_interp(a.col + pbase, pdeg, u, (int32_t)a.nv);
-                            const float wt = member ? hv : inv_q * hv;
+                            const float wt = member ? sw.mem * hv : sw.oth * hv;
                             acc = y < wt;
                         }
                     }
@@ -490,11 +537,9 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 mode = kAdv;
                 st[kStTriggers] += trig;
                 uint64_t by = (uint64_t)deg * (uint64_t)a.item_bytes;
-                if (KIND == kNode2Vec && j > 0) {
+                if (uses_membership(KIND) && j > 0) {
                     const uint64_t stage = 4 * (uint64_t)pdeg;
-                    // a membership test: one 8-byte key of the edge index, else a binary search
-                    const uint64_t search =
-                        (uint64_t)deg * (a.mtab ? 8 : 4 * (uint64_t)probes(pdeg));
+                    const uint64_t search = 4 * (uint64_t)deg * (uint64_t)probes(pdeg);
                     by += stage < search ? stage : search;
                 }
                 st_bytes += by;
@@ -522,11 +567,9 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 const int32_t s_pdeg = bcast_i32(pdeg, src);
                 const QueryDev &Q = query<BATCH>(a, s_q);
                 const uint8_t want = (KIND == kMetaPath) ? Q.schema[s_j % Q.schema_len] : (uint8_t)0;
-                const bool member_test = (KIND == kNode2Vec) && s_j > 0;
-                Mem m = {a.col + s_pbase, s_pdeg, false};
-                // stage N(prev) when copying it costs fewer memory requests than the tests
-                const int64_t per_test = a.mtab ? 16 : probes(s_pdeg);
-                if (member_test && s_pdeg <= a.lds_cap && (int64_t)s_pdeg <= (int64_t)s_deg * per_test) {
+                const bool member_test = uses_membership(KIND) && s_j > 0;
+                Mem m = {a.col + s_pbase, s_pdeg, false, false};
+                if (member_test && s_pdeg <= a.lds_cap && (int64_t)s_pdeg <= (int64_t)s_deg * probes(s_pdeg)) {
                     wave_lds_sync();
                     for (int32_t i = lane; i < s_pdeg; i += kWave) lds[i] = a.col[s_pbase + i];
                     wave_lds_sync();
@@ -534,7 +577,8 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                     m.staged = true;
                 }
                 uint32_t trig = 0;
-                res = rvs_step<KIND, W>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, trig, hres);
+                const StepW sw = step_weights<KIND>(Q, s_deg, s_pdeg);
+                res = rvs_step<KIND, W>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, sw, trig, hres);
                 if (lane == src) served(res, hres, trig);
             }
         }
@@ -723,8 +767,8 @@ __global__ void __launch_bounds__(kBlock) profile_rvs_kernel(WalkArgs a, const i
         const uint4 rp = a.vrec[prev];
         const int64_t pb = row_start(a, rp, prev), pd = (int64_t)rp.y;
         for (int64_t i = lane; i < m; i += kWave)
-            acc += edge_weight<KIND, W>(a, a.q0, b + i, a.edges[b + i], 1, prev, Mem{a.col + pb, pd, false},
-                                        a.q0.schema[0]);
+            acc += edge_weight<KIND, W>(a, a.q0, b + i, a.edges[b + i], 1, prev, Mem{a.col + pb, pd, false, false},
+                                        a.q0.schema[0], step_weights<KIND>(a.q0, (int32_t)d, (int32_t)pd));
     }
     acc = wave_max(acc);
     if (lane == 0 && acc < 0.0f) sink[0] = acc;  // never true; keeps the loads alive
@@ -746,7 +790,8 @@ __global__ void __launch_bounds__(kBlock) profile_rjs_kernel(WalkArgs a, const i
         for (int t = 0; t < per_node; ++t) {
             const U4 x = philox((uint32_t)s, 0u, (uint32_t)t, 2u, a.q0.key0, a.q0.key1);
             const int64_t k = b + scaled_index(x.x0, x.x1, d);
-            acc += edge_weight<KIND, W>(a, a.q0, k, a.edges[k], 1, prev, Mem{a.col + pb, pd, false}, a.q0.schema[0]);
+            acc += edge_weight<KIND, W>(a, a.q0, k, a.edges[k], 1, prev, Mem{a.col + pb, pd, false, true}, a.q0.schema[0],
+                                        step_weights<KIND>(a.q0, (int32_t)d, (int32_t)pd));
         }
     }
     if (acc < 0.0f) sink[0] = acc;
@@ -766,6 +811,8 @@ static hipError_t launch_walk_b(const WalkArgs &a, int kind, bool weighted, int 
 {
     if (kind == kNode2Vec) return weighted ? launch_walk_t<kNode2Vec, true, BATCH>(a, grid, s)
                                            : launch_walk_t<kNode2Vec, false, BATCH>(a, grid, s);
+    if (kind == kSecondPR) return weighted ? launch_walk_t<kSecondPR, true, BATCH>(a, grid, s)
+                                           : launch_walk_t<kSecondPR, false, BATCH>(a, grid, s);
     return weighted ? launch_walk_t<kMetaPath, true, BATCH>(a, grid, s)
                     : launch_walk_t<kMetaPath, false, BATCH>(a, grid, s);
 }
@@ -790,6 +837,8 @@ static int occupancy_b(int kind, bool weighted, int lds_cap)
 {
     if (kind == kNode2Vec) return weighted ? occupancy_blocks<kNode2Vec, true, BATCH>(lds_cap)
                                            : occupancy_blocks<kNode2Vec, false, BATCH>(lds_cap);
+    if (kind == kSecondPR) return weighted ? occupancy_blocks<kSecondPR, true, BATCH>(lds_cap)
+                                           : occupancy_blocks<kSecondPR, false, BATCH>(lds_cap);
     return weighted ? occupancy_blocks<kMetaPath, true, BATCH>(lds_cap)
                     : occupancy_blocks<kMetaPath, false, BATCH>(lds_cap);
 }
@@ -903,6 +952,9 @@ hipError_t launch_profile(const WalkArgs &a, int kind, bool weighted, bool rjs_s
     if (kind == kNode2Vec)
         return weighted ? launch_profile_t<kNode2Vec, true>(a, rjs_style, nodes, nsample, per_node, sink, s)
                         : launch_profile_t<kNode2Vec, false>(a, rjs_style, nodes, nsample, per_node, sink, s);
+    if (kind == kSecondPR)
+        return weighted ? launch_profile_t<kSecondPR, true>(a, rjs_style, nodes, nsample, per_node, sink, s)
+                        : launch_profile_t<kSecondPR, false>(a, rjs_style, nodes, nsample, per_node, sink, s);
     return weighted ? launch_profile_t<kMetaPath, true>(a, rjs_style, nodes, nsample, per_node, sink, s)
                     : launch_profile_t<kMetaPath, false>(a, rjs_style, nodes, nsample, per_node, sink, s);
 }

@@ -114,6 +114,9 @@ size_t request_bytes(int64_t n, int32_t L)
 
 }  // namespace
 
+// one batched launch per (logic kind, weighting)
+constexpr int kGroups = 2 * fw::kNumKinds;
+
 struct fw_server {
     fw_graph *g = nullptr;
     fw_plan plan{};
@@ -126,7 +129,7 @@ struct fw_server {
     Arena arena;
     hipStream_t stream = nullptr;
     int32_t *d_done = nullptr;                 // finished walkers per slot
-    fw::QueryDev *d_table = nullptr;           // 4 groups x max_active entries
+    fw::QueryDev *d_table = nullptr;           // kGroups groups x max_active entries
     fw::QueryDev *h_table = nullptr;           // pinned staging of the same
     unsigned long long *d_queue = nullptr;     // one walker counter per group
     unsigned long long *d_stats = nullptr;     // FW_NSTATS counters
@@ -212,8 +215,8 @@ int admit(fw_server *s, std::vector<Request *> &picked)
 // One tick: a batched launch per group of admitted requests.
 int tick(fw_server *s)
 {
-    for (int grp = 0; grp < 4; ++grp) {
-        const int kind = grp < 2 ? FW_NODE2VEC : FW_METAPATH;
+    for (int grp = 0; grp < kGroups; ++grp) {
+        const int kind = 1 + grp / 2;  // FW_NODE2VEC, FW_METAPATH, FW_SECOND_PR
         const bool weighted_logic = (grp & 1) != 0;
         fw::QueryDev *tab = s->h_table + (size_t)grp * s->max_active;
         int32_t nq = 0;
@@ -342,7 +345,7 @@ int fw_server_create(fw_graph *g, const fw_plan *plan, int32_t strategy, uint64_
     if (!g || !plan || !out) return fail(FW_E_INVALID, "fw_server_create: null argument");
     int rc = fw::host::check_plan(plan);
     if (rc != FW_OK) return rc;
-    if (strategy < FW_AUTO || strategy > FW_RJS_ONLY)
+    if (!fw::valid_strategy(strategy))
         return fail(FW_E_INVALID, "fw_server_create: bad strategy %d", strategy);
     if (tick_steps < 1) return fail(FW_E_INVALID, "fw_server_create: tick_steps must be >= 1");
     if (max_active < 1 || max_active > (1 << 20)) return fail(FW_E_INVALID, "fw_server_create: max_active in [1, 2^20]");
@@ -363,10 +366,10 @@ int fw_server_create(fw_graph *g, const fw_plan *plan, int32_t strategy, uint64_
     for (int32_t i = max_active - 1; i >= 0; --i) s->free_slots.push_back(i);
     if (hipMalloc((void **)&s->arena_base, s->budget) != hipSuccess ||
         hipMalloc((void **)&s->d_done, sizeof(int32_t) * (size_t)max_active) != hipSuccess ||
-        hipMalloc((void **)&s->d_table, sizeof(fw::QueryDev) * 4 * (size_t)max_active) != hipSuccess ||
-        hipMalloc((void **)&s->d_queue, 4 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void **)&s->d_table, sizeof(fw::QueryDev) * kGroups * (size_t)max_active) != hipSuccess ||
+        hipMalloc((void **)&s->d_queue, kGroups * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void **)&s->d_stats, FW_NSTATS * sizeof(unsigned long long)) != hipSuccess ||
-        hipHostMalloc((void **)&s->h_table, sizeof(fw::QueryDev) * 4 * (size_t)max_active, hipHostMallocDefault) !=
+        hipHostMalloc((void **)&s->h_table, sizeof(fw::QueryDev) * kGroups * (size_t)max_active, hipHostMallocDefault) !=
             hipSuccess) {
         server_free(s);
         return fail(FW_E_NOMEM, "fw_server_create: allocation failed");

@@ -112,6 +112,19 @@ def edge_props(row_ptr: np.ndarray, col: np.ndarray, seed: int, wlo: float = 1.0
     return h, lab
 
 
+def pareto_weights(row_ptr: np.ndarray, col: np.ndarray, alpha: float, seed: int) -> np.ndarray:
+    """Power-law property weights as numpy.random.pareto draws them (Lomax: (1 - U)^(-1/alpha) - 1),
+    with U hashed from the unordered vertex pair so both directions of an edge agree."""
+    u, _ = edge_props(row_ptr, col, seed, 0.0, 1.0)
+    return ((1.0 - u.astype(np.float64)) ** (-1.0 / alpha) - 1.0).astype(np.float32)
+
+
+def degree_weights(row_ptr: np.ndarray, col: np.ndarray) -> np.ndarray:
+    """Property weight of edge (v, u) = d(u), the neighbouring vertex's degree (not symmetric)."""
+    deg = np.diff(np.asarray(row_ptr, dtype=np.int64))
+    return deg[np.asarray(col)].astype(np.float32)
+
+
 def csr_from_edges(nv: int, edges, h=None, label=None, symmetric: bool = True) -> dict:
     """Small hand-built graphs: CSR from an edge list with optional per-edge values.
 

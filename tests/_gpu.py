@@ -48,6 +48,8 @@ class GpuGraph:
 def fw_logic(lg: oracle.Logic):
     if lg.kind == oracle.NODE2VEC:
         return fw.fw_logic_node2vec(lg.p, lg.q, lg.weighted)
+    if lg.kind == oracle.SECOND_PR:
+        return fw.fw_logic_second_pr(lg.gamma, lg.weighted)
     return fw.fw_logic_metapath(list(lg.schema), lg.weighted)
 
 

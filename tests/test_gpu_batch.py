@@ -195,3 +195,27 @@ def test_batch_split_bound(g12, gg12):
             assert_parity(parity(p, ln, ora))
     finally:
         b.close()
+
+
+def test_batch_second_pr(g12, gg12):
+    """A batch of second-order PageRank queries with their own gamma, L, seed and starts."""
+    qd = _small_batch(g12["nv"], 20, 17)
+    gammas = [0.05 * (i % 20) for i in range(20)]
+    logics = [oracle.Logic(kind=oracle.SECOND_PR, weighted=True, gamma=g) for g in gammas]
+    pl = oracle.Plan(rho=1.0)
+    b = Batch(gg12, qd, [fw.fw_logic_second_pr(l.gamma, True) for l in logics], fw_plan(pl), oracle.AUTO)
+    try:
+        fw.fw_batch_launch(b.h)
+        og = oracle.Graph(g12)
+        for i in range(20):
+            n = int(qd["n"][i])
+            if n == 0:
+                continue
+            p, ln = b.query(i)
+            st = qd["starts"][qd["start_off"][i]:qd["start_off"][i] + n]
+            alone = gpu_walk(gg12, logics[i], pl, oracle.AUTO, st, int(qd["L"][i]), int(qd["seed"][i]))
+            np.testing.assert_array_equal(p, alone[0])
+            ora = oracle.walk(og, logics[i], pl, oracle.AUTO, st, int(qd["L"][i]), int(qd["seed"][i]))
+            assert_parity(parity(p, ln, ora))
+    finally:
+        b.close()

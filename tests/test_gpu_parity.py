@@ -363,3 +363,86 @@ def test_edge_index_idempotent_and_tiny_graphs():
             np.testing.assert_array_equal(p, ora.paths)
         finally:
             gg.close()
+
+
+# ------------------------------------------------------------------ second-order PageRank
+PR2 = oracle.Logic(kind=oracle.SECOND_PR, weighted=True, gamma=0.2)
+
+
+@pytest.mark.parametrize("strategy", list(STRATS), ids=list(STRATS))
+@pytest.mark.parametrize("weighted", [True, False], ids=["weighted", "unweighted"])
+@pytest.mark.parametrize("indexed", [False, True], ids=["search", "index"])
+def test_second_pr_scale12(g12, gg12, gi12, strategy, weighted, indexed):
+    """Eq. (2ndpr) with gamma = 0.2, one walker per vertex, L = 20: walks and counters
+    equal the oracle's, with the sorted-row search and with the edge index."""
+    lg = oracle.Logic(kind=oracle.SECOND_PR, weighted=weighted, gamma=0.2)
+    pl = oracle.Plan(rho=1.0, member_index=indexed)
+    starts = synth.all_vertices(g12["nv"])
+    gg = gi12 if indexed else gg12
+    p, ln, st = gpu_walk(gg, lg, pl, STRATS[strategy], starts, 20, 42)
+    ora = oracle.walk(oracle.Graph(g12), lg, pl, STRATS[strategy], starts, 20, 42)
+    rep = parity(p, ln, ora)
+    assert_parity(rep)
+    if rep["mismatch_walkers"] == 0:
+        _assert_counters(st, ora)
+    if strategy == "auto":
+        assert st["rjs_steps"] > 0 and st["rvs_steps"] > 0
+
+
+@pytest.mark.parametrize("strategy", list(STRATS), ids=list(STRATS))
+def test_second_pr_hub_rows(strategy):
+    """Hub rows (eRVS jump scan, N(prev) staged or not) with degrees 2 and 3001 meeting
+    in max_d."""
+    g = hub_ring_graph(3000)
+    gg = GpuGraph(g)
+    try:
+        starts = np.arange(1, 3001, dtype=np.int32)
+        for cap in (2048, 16):
+            p, ln, st, ora = _run_both(gg, g, PR2, oracle.Plan(rho=1.0), STRATS[strategy], starts, 6, 13,
+                                       lds_cap=cap)
+            rep = parity(p, ln, ora)
+            assert_parity(rep)
+            if rep["mismatch_walkers"] == 0:
+                _assert_counters(st, ora)
+    finally:
+        gg.close()
+
+
+@pytest.mark.parametrize("strategy", list(STRATS), ids=list(STRATS))
+def test_second_pr_chisquare_hub(strategy):
+    """Second step at the 600-neighbour hub from leaf 1 against the exact transition."""
+    g = hub_ring_graph(600)
+    gg = GpuGraph(g)
+    try:
+        n = 300000
+        p, ln, st = gpu_walk(gg, PR2, oracle.Plan(rho=1.0), STRATS[strategy], np.ones(n, np.int32), 2, 41)
+    finally:
+        gg.close()
+    at_hub = p[:, 1] == 0
+    counts = {int(v): int(c) for v, c in zip(*np.unique(p[at_hub, 2], return_counts=True))}
+    assert chisq_pvalue(counts, exact.transition(g, PR2, 1, 1, 0), int(at_hub.sum())) > 1e-3
+
+
+def test_second_pr_logic_errors():
+    with pytest.raises(fw.FlexiWalkError):
+        fw.fw_logic_second_pr(-0.1)
+    with pytest.raises(fw.FlexiWalkError):
+        fw.fw_logic_second_pr(float("nan"))
+    lg = fw.fw_logic_second_pr(0.3, False)
+    assert lg.kind == fw.FW_SECOND_PR and abs(lg.gamma - 0.3) < 1e-7 and lg.weighted == 0
+
+
+# ------------------------------------------------------------------ comparison selection policies
+@pytest.mark.parametrize("strategy", [oracle.RANDOM_SELECT, oracle.DEGREE_SELECT], ids=["random", "degree"])
+@pytest.mark.parametrize("logic", [N2V, PR2, MP], ids=["node2vec", "2ndpr", "metapath"])
+def test_selection_policies_scale12(g12, gg12, strategy, logic):
+    """The fair-coin and degree-threshold policies the paper compares its cost model with:
+    walks and counters equal the oracle's."""
+    pl = oracle.Plan(rho=1.0, d_lo=24, rjs_cap=256)
+    starts = synth.uniform_starts(g12["nv"], 5000, 9)
+    p, ln, st, ora = _run_both(gg12, g12, logic, pl, strategy, starts, 20, 77)
+    rep = parity(p, ln, ora)
+    assert_parity(rep)
+    if rep["mismatch_walkers"] == 0:
+        _assert_counters(st, ora)
+    assert st["rjs_steps"] > 0 and st["rvs_steps"] > 0

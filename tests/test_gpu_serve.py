@@ -43,6 +43,8 @@ def _requests(nv, k, seed):
         if i % 3 == 2:
             lg = oracle.Logic(kind=oracle.METAPATH, weighted=bool(i % 2),
                               schema=tuple(int(x) for x in rng.integers(0, 5, 1 + i % 5)))
+        elif i % 6 == 1:
+            lg = oracle.Logic(kind=oracle.SECOND_PR, weighted=bool(i % 4 != 1), gamma=float(rng.choice([0.0, 0.2, 0.9])))
         else:
             lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=bool(i % 4 != 1), p=float(rng.choice([0.25, 1, 4])),
                               q=float(rng.choice([0.5, 2])))

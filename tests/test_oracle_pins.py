@@ -366,6 +366,38 @@ def test_second_pr_mean_trials():
     assert abs(trials.mean() - want) < 5 * se, (trials.mean(), want)
 
 
+# ------------------------------------------------------------------ comparison selection policies
+@pytest.mark.parametrize("strategy", [oracle.RANDOM_SELECT, oracle.DEGREE_SELECT], ids=["random", "degree"])
+@pytest.mark.parametrize("logic", [N2V, PR2], ids=["node2vec", "2ndpr"])
+def test_selection_policies_exact(strategy, logic):
+    """Any per-step choice between two exact samplers is exact: paths follow Eq. (prob)."""
+    g = triangle_graph()
+    lg = oracle.Logic(**logic)
+    n = 60000
+    for start in (0, 4):
+        counts, _ = _walk_counts(g, lg, oracle.Plan(d_lo=3, lanes=2), strategy, start, 3, n, seed=51 + start)
+        assert chisq_pvalue(counts, exact.path_distribution(g, lg, start, 3), n) > P_OK
+
+
+def test_selection_policy_ratios():
+    """The fair coin picks eRJS for about half the steps; the degree policy picks eRJS for
+    exactly the steps taken from vertices of degree >= d_lo."""
+    g = synth.rmat(12, 8 << 12, seed=2)
+    og = oracle.Graph(g)
+    lg = oracle.Logic(**N2V)
+    st = np.arange(g["nv"], dtype=np.int32)
+    r = oracle.walk(og, lg, oracle.Plan(rjs_cap=1 << 20), oracle.RANDOM_SELECT, st, 20, 3, diagnostics=False)
+    n = r.counters["steps"]
+    assert abs(r.counters["rjs_steps"] / n - 0.5) < 5 * math.sqrt(0.25 / n)
+    pl = oracle.Plan(d_lo=40, rjs_cap=1 << 20)
+    r = oracle.walk(og, lg, pl, oracle.DEGREE_SELECT, st, 20, 3)
+    deg = np.diff(g["row_ptr"])
+    taken = np.arange(20)[None, :] < r.lengths[:, None]
+    from_high = (deg[np.where(taken, r.paths[:, :-1], 0)] >= 40) & taken
+    assert r.counters["rjs_steps"] == int(from_high.sum())
+    assert (r.kinds[taken] == np.where(from_high[taken], 1, 0)).all()
+
+
 # ------------------------------------------------------------------ closed form / invariants
 def test_stationary_visits_proportional_to_degree():
     """p = q = 1, h = 1 on a connected non-bipartite graph: visits -> deg / 2|E|."""
