@@ -37,12 +37,11 @@ def kernel_sources_sha256() -> str:
 TRAFFIC_STATS = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", "rvs_triggers")
 
 
-def measured_traffic(plan, st: dict) -> float | None:
-    """HBM bytes per launch from the committed counter summary, or None unless it was
+def measured_traffic(plan, st: dict) -> dict | None:
+    """HBM traffic of one launch from the committed counter summary, or None unless it was
     taken on this kernel source and on a launch that made the same decisions (the same
-    step, trial and fall-back counts, and the same LDS cap when eRVS ran): FETCH_SIZE and
-    WRITE_SIZE scaled by what the same counters read for a plain device copy of known
-    size."""
+    step, trial and fall-back counts, and the same LDS cap when eRVS ran).  Reads are the
+    size-resolved TCC->memory read requests (32/64/128 B), writes WRITE_SIZE."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
@@ -59,8 +58,8 @@ def measured_traffic(plan, st: dict) -> float | None:
             return None
         if int(st["rvs_steps"]) + int(st["rjs_fallbacks"]) > 0 and int(kv["lds_cap"]) != plan.lds_cap:
             return None
-        return 1024.0 * (float(kv["fetch_kib_per_launch"]) * float(kv["copy_fetch_factor"])
-                         + float(kv["write_kib_per_launch"]) * float(kv["copy_write_factor"]))
+        return {"bytes": 1024.0 * (float(kv["read_kib_per_launch"]) + float(kv["write_kib_per_launch"])),
+                "read_requests": float(kv["read_requests_per_launch"])}
     except (KeyError, ValueError):
         return None
 
@@ -262,6 +261,10 @@ def main():
 
     fw.fw_graph_destroy(gh)
     traffic = measured_traffic(plan, st)
+    ceiling = fw.fw_calibrate_random_reads(4 << 30)  # random 8-byte reads/s, 128 B moved each
+    random_access = {"ceiling_reads_per_s": ceiling,
+                     "achieved_reads_per_s": None if traffic is None else traffic["read_requests"] / (avg_ms / 1e3),
+                     "frac": None if traffic is None else traffic["read_requests"] / (avg_ms / 1e3) / ceiling}
     out = {
         "metric": "walker-steps/sec + achieved HBM GB/s, node2vec R-MAT s22; p99 latency served",
         "value": value,
@@ -282,9 +285,10 @@ def main():
                    "edge_index_ms": index_ms,
                    "autotune_ms": tune_ms, "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound},
                    "stats": st, "modes": modes,
-                   "hbm_traffic_GBps": None if traffic is None else traffic / (avg_ms / 1e3) / 1e9},
+                   "hbm_traffic_GBps": None if traffic is None else traffic["bytes"] / (avg_ms / 1e3) / 1e9,
+                   "random_access": random_access},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic},
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None if traffic is None else traffic["bytes"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

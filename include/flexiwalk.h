@@ -156,6 +156,13 @@ int fw_graph_export_aux(const fw_graph *g, float *hmax, float *hsum);
  * the table cannot be allocated (the graph stays usable without it). */
 int fw_graph_build_index(fw_graph *g, void *stream);
 
+/* Roofline calibration (not part of the method): time random 8-byte reads from a device
+ * array of `bytes` (a power of two >= 1 MiB), 2^20 lanes each issuing four independent
+ * loads per round, and store the best rate in *reads_per_s.  Each such read moves one
+ * 128-byte line from HBM, so this is the ceiling for the walk kernel's proposal, vertex
+ * and membership reads.  Allocates and frees its array; synchronous on `stream`. */
+int fw_calibrate_random_reads(int64_t bytes, double *reads_per_s, void *stream);
+
 /* Sizes of a graph: vertices, edges, maximum degree, and 1 if every edge (v, u) has a
  * reverse edge (u, v) with the same h (checked on the device by fw_graph_create), else 0
  * (any pointer may be NULL). */

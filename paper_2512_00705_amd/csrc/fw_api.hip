@@ -440,6 +440,35 @@ struct Events {
     }
 };
 
+int fw_calibrate_random_reads(int64_t bytes, double *reads_per_s, void *stream)
+{
+    if (!reads_per_s) return fail(FW_E_INVALID, "fw_calibrate_random_reads: null output");
+    if (bytes < (1 << 20) || (bytes & (bytes - 1)) != 0)
+        return fail(FW_E_INVALID, "fw_calibrate_random_reads: bytes must be a power of two >= 1 MiB");
+    hipStream_t s = (hipStream_t)stream;
+    DevBuf arr, sink;
+    HIP_TRY(hipMalloc(&arr.p, (size_t)bytes));
+    HIP_TRY(hipMalloc(&sink.p, sizeof(unsigned)));
+    HIP_TRY(hipMemsetAsync(arr.p, 1, (size_t)bytes, s));
+    const uint64_t mask = (uint64_t)bytes / 8 - 1;
+    const int blocks = 4096, rounds = 64;
+    Events ev;
+    HIP_TRY(hipEventCreate(&ev.a));
+    HIP_TRY(hipEventCreate(&ev.b));
+    float best = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {  // the first launch warms up; the fastest counts
+        HIP_TRY(hipEventRecord(ev.a, s));
+        HIP_TRY(fw::launch_random_reads((const uint2 *)arr.p, mask, blocks, rounds, (unsigned *)sink.p, s));
+        HIP_TRY(hipEventRecord(ev.b, s));
+        HIP_TRY(hipEventSynchronize(ev.b));
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+        if (rep > 0) best = std::min(best, ms);
+    }
+    *reads_per_s = (double)blocks * fw::kBlock * rounds * 4 / (best / 1e3);
+    return ok();
+}
+
 int fw_plan_profile(fw_graph *g, const fw_logic *lg, fw_plan *out, void *stream)
 {
     if (!g || !lg || !out) return fail(FW_E_INVALID, "fw_plan_profile: null argument");

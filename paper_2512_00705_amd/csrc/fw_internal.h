@@ -113,6 +113,9 @@ hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv,
 // kEmptyKey on entry; buckets = mask + 1, a power of two, at least a quarter of ne).
 hipError_t launch_build_index(const int64_t *row_ptr, const int32_t *col, int64_t nv, unsigned long long *tab,
                               uint64_t mask, hipStream_t s);
+// blocks * kBlock lanes each read 4 * rounds random 8-byte records of a[0, mask] (mask + 1 a
+// power of two).
+hipError_t launch_random_reads(const uint2 *a, uint64_t mask, int blocks, int rounds, unsigned *sink, hipStream_t s);
 // Sets bit 4 of *err unless every entry (v, u) has a reverse (u, v) with the same h.
 // Rows must already be validated (in range, strictly ascending).
 hipError_t launch_check_symmetry(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int *err,

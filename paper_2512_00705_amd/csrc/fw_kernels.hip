@@ -797,7 +797,31 @@ __global__ void __launch_bounds__(kBlock) profile_rjs_kernel(WalkArgs a, const i
     if (acc < 0.0f) sink[0] = acc;
 }
 
+// Random-read ceiling: each lane issues four independent 8-byte loads per round at
+// addresses hashed from (lane, round), masked into a power-of-two array.  Its rate is the
+// memory system's limit for the access pattern the walk kernel's proposals make.
+__global__ void __launch_bounds__(kBlock) random_reads_kernel(const uint2 *a, uint64_t mask, int rounds,
+                                                              unsigned *sink)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned acc = 0;
+    for (int it = 0; it < rounds; ++it) {
+        uint2 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = a[mix64(t * 1315423911ull + (uint64_t)it * 64 + (uint64_t)k) & mask];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc += v[k].x ^ v[k].y;
+    }
+    if (acc == 0x9E3779B9u) sink[0] = acc;  // keeps the loads; practically never true
+}
+
 // ---------------------------------------------------------------- launchers
+hipError_t launch_random_reads(const uint2 *a, uint64_t mask, int blocks, int rounds, unsigned *sink, hipStream_t s)
+{
+    hipLaunchKernelGGL(random_reads_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, a, mask, rounds, sink);
+    return hipGetLastError();
+}
+
 template <int KIND, bool W, bool BATCH>
 static hipError_t launch_walk_t(const WalkArgs &a, int grid, hipStream_t s)
 {
