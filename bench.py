@@ -84,13 +84,15 @@ def main():
     ap.add_argument("--modes", type=int, default=1, help="also time the single-kernel modes")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample", type=int, default=0, help="walkers for the CPU baseline (0: sized to ~15 s)")
-    ap.add_argument("--workload", default="node2vec", choices=["node2vec", "batched", "served"],
+    ap.add_argument("--workload", default="node2vec", choices=["node2vec", "batched", "served", "skew"],
                     help="node2vec: the headline scale-22 job; batched: 4096 queries on skewed scale 24; "
                          "served: Poisson request stream against a resident scale-25 graph")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-scale", type=int, default=25)
     ap.add_argument("--tick-steps", type=int, default=16)
+    ap.add_argument("--skew-scale", type=int, default=20, help="skew: R-MAT scale of the topology")
+    ap.add_argument("--skew-L", type=int, default=20, help="skew: walk length")
     ap.add_argument("--plan", default="", help="rho,d_lo,lds_cap[,bound]: use this plan instead of autotuning")
     ap.add_argument("--per-query", type=int, default=1, help="batched: also time one launch per query")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -141,6 +143,8 @@ def main():
         return bench_batched(args)
     if args.workload == "served":
         return bench_served(args)
+    if args.workload == "skew":
+        return bench_skew(args)
     t0 = time.time()
     g = synth.cached(args.graph)
     log(f"graph {args.graph}: nv={g['nv']} ne={g['ne']} ({time.time() - t0:.1f}s)")
@@ -292,6 +296,85 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_skew(args):
+    """Property-weight skew and selection policy (the paper's power-law / degree-based
+    weight study and its selection-strategy comparison): one R-MAT topology, weights
+    uniform U(1,10), Pareto(alpha) as numpy.random.pareto draws them for alpha in
+    {1, 1.5, 2, 3, 4}, and h(v,u) = d(u); Node2Vec p=0.5 q=2, one walker per vertex.  Each
+    setting is autotuned, then timed under the cost model (AUTO), the fair-coin and the
+    degree-threshold (1K) selection policies, and the two single-kernel modes."""
+    import torch
+    import paper_2512_00705_amd as fw
+    import synth
+
+    dev = torch.device("cuda:0")
+    s = args.skew_scale
+    topo = synth.rmat(s, 16 << s, seed=1, weighted=False)
+    rp, col = topo["row_ptr"], topo["col"]
+    settings = [("uniform", None)] + [(f"pareto{a:g}", a) for a in (1.0, 1.5, 2.0, 3.0, 4.0)] + [("degree", "deg")]
+    L, seed, nv = args.skew_L, 42, topo["nv"]
+    logic = fw.fw_logic_node2vec(0.5, 2.0, True)
+    starts = torch.arange(nv, dtype=torch.int32, device=dev)
+    paths = torch.empty((nv, L + 1), dtype=torch.int32, device=dev)
+    lengths = torch.empty(nv, dtype=torch.int32, device=dev)
+    stats = torch.zeros(fw.FW_NSTATS, dtype=torch.int64, device=dev)
+    rows = []
+    t_rp, t_col = torch.from_numpy(rp).to(dev), torch.from_numpy(col).to(dev)
+    for name, a in settings:
+        if a is None:
+            h, _ = synth.edge_props(rp, col, 1)
+        elif a == "deg":
+            h = synth.degree_weights(rp, col)
+        else:
+            h = synth.pareto_weights(rp, col, a, 7)
+        t_h = torch.from_numpy(h).to(dev)
+        gh = fw.fw_graph_create(nv, topo["ne"], t_rp, t_col, t_h, None, on_device=True)
+        fw.fw_graph_preprocess(gh)
+        fw.fw_graph_build_index(gh)
+        plan = fw.fw_plan_autotune(gh, logic)
+        modes = {"auto": (fw.FW_AUTO, plan),
+                 "random": (fw.FW_RANDOM_SELECT, plan),
+                 "degree": (fw.FW_DEGREE_SELECT, fw.fw_plan_default(d_lo=1000, bound=plan.bound)),
+                 "rjs_only": (fw.FW_RJS_ONLY, plan),
+                 "rvs_only": (fw.FW_RVS_ONLY, plan)}
+        row = {"weights": name, "h_max": float(h.max()), "h_median": float(np.median(h)), "plan_rho": plan.rho,
+               "plan_bound": plan.bound}
+        for m, (strat, pl) in modes.items():
+            fw.fw_walk(gh, logic, pl, strat, starts, nv, L, seed, paths, lengths, None)  # warm-up
+            stats.zero_()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fw.fw_walk(gh, logic, pl, strat, starts, nv, L, seed, paths, lengths, stats)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            st = dict(zip(fw.STAT_NAMES, stats.cpu().numpy().tolist()))
+            row[m] = {"ms": round(ms, 3), "steps_per_s": st["steps"] / (ms / 1e3),
+                      "rjs_share": (st["rjs_steps"] + st["rjs_fallbacks"]) / max(1, st["steps"]),
+                      "trials_per_rjs_step": st["rjs_trials"] / max(1, st["rjs_steps"] + st["rjs_fallbacks"])}
+        fw.fw_graph_check(gh)
+        fw.fw_graph_destroy(gh)
+        del t_h
+        for m in ("random", "degree", "rjs_only", "rvs_only"):
+            row["auto_speedup_vs_" + m] = row[m]["ms"] / row["auto"]["ms"]
+        log(f"{name}: " + ", ".join(f"{m} {row[m]['ms']:.2f} ms" for m in modes) +
+            f", auto eRJS share {row['auto']['rjs_share']:.3f}")
+        rows.append(row)
+    gm = lambda key: float(np.exp(np.mean([np.log(r[key]) for r in rows])))
+    steps_auto = [r["auto"]["steps_per_s"] for r in rows]
+    print(json.dumps({
+        "metric": "walker-steps/sec under property-weight skew (geometric mean over weight settings), AUTO",
+        "value": float(np.exp(np.mean(np.log(steps_auto)))), "unit": "walker-steps/s", "n_gpus": 1,
+        "steps": 1, "warmup": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"node2vec p=0.5 q=2 on R-MAT scale {s} (edge factor 16, {topo['ne']} CSR entries), "
+                               f"one walker per vertex, L={L}; weights uniform U(1,10), numpy-style Pareto "
+                               f"alpha in {{1,1.5,2,3,4}}, and h(v,u)=d(u)",
+                   "geomean_auto_speedup_vs_random": gm("auto_speedup_vs_random"),
+                   "geomean_auto_speedup_vs_degree": gm("auto_speedup_vs_degree"),
+                   "rows": rows}}), flush=True)
 
 
 def bench_batched(args):

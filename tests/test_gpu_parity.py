@@ -446,3 +446,29 @@ def test_selection_policies_scale12(g12, gg12, strategy, logic):
     if rep["mismatch_walkers"] == 0:
         _assert_counters(st, ora)
     assert st["rjs_steps"] > 0 and st["rvs_steps"] > 0
+
+
+# ------------------------------------------------------------------ skewed property weights
+@pytest.mark.parametrize("strategy", list(STRATS), ids=list(STRATS))
+@pytest.mark.parametrize("weights", ["pareto1", "pareto3", "degree"])
+def test_skewed_weights_scale12(g12, strategy, weights):
+    """Power-law (numpy-style Pareto, alpha 1 and 3) and degree-based property weights:
+    heavy tails stress the bound, the cost model and the float keys; walks and counters
+    equal the oracle's."""
+    g = dict(g12)
+    if weights == "degree":
+        g["h"] = synth.degree_weights(g["row_ptr"], g["col"])
+    else:
+        g["h"] = synth.pareto_weights(g["row_ptr"], g["col"], float(weights[6:]), 7)
+    gg = GpuGraph(g)
+    try:
+        assert fw.fw_graph_info(gg.handle)[3] == (weights != "degree")
+        pl = oracle.Plan(rho=1.0, rjs_cap=256)
+        starts = synth.all_vertices(g["nv"])
+        p, ln, st, ora = _run_both(gg, g, N2V, pl, STRATS[strategy], starts, 15, 5)
+        rep = parity(p, ln, ora)
+        assert_parity(rep)
+        if rep["mismatch_walkers"] == 0:
+            _assert_counters(st, ora)
+    finally:
+        gg.close()
