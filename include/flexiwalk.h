@@ -94,7 +94,7 @@ typedef struct fw_logic {
  *   d_lo     steps at vertices of degree < d_lo always use eRVS (0 disables)
  *   rjs_cap  eRJS trials before an exact fall-back to eRVS, >= 1
  *   lanes    eRVS lanes per step; must be 64 (one wavefront)
- *   lds_cap  int32 entries of N(prev) staged in LDS per wavefront (0 = default)
+ *   lds_cap  int32 entries of N(prev) staged in LDS per wavefront, 0..8192 (0: never stage)
  *   grid     persistent blocks (0 = fill the device)
  *   bound    eRJS bound (changes the stream, never the distribution):
  *            0  max(w) * h_MAX of Section 3.3;

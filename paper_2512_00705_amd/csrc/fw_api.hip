@@ -344,7 +344,8 @@ int fw::host::check_plan(const fw_plan *pl)
     if (pl->rjs_cap < 1) return fail(FW_E_INVALID, "plan.rjs_cap must be >= 1");
     if (!(pl->rho > 0.0f) || isinf(pl->rho)) return fail(FW_E_INVALID, "plan.rho must be finite and > 0");
     if (pl->d_lo < 0) return fail(FW_E_INVALID, "plan.d_lo must be >= 0");
-    if (pl->lds_cap < 0 || pl->lds_cap > 16384) return fail(FW_E_INVALID, "plan.lds_cap in [0, 16384]");
+    if (pl->lds_cap < 0 || pl->lds_cap > fw::kMaxLdsCap)
+        return fail(FW_E_INVALID, "plan.lds_cap in [0, %d]", fw::kMaxLdsCap);
     if (pl->grid < 0) return fail(FW_E_INVALID, "plan.grid must be >= 0");
     if (pl->bound < 0 || pl->bound > 1) return fail(FW_E_INVALID, "plan.bound must be 0 or 1");
     if (pl->reserved != 0) return fail(FW_E_INVALID, "plan.reserved must be 0");

@@ -27,6 +27,8 @@ struct fw_graph {
 };
 
 namespace fw {
+constexpr int kMaxLdsCap = 8192;  // four waves' N(prev) staging stays within a CU's 160 KB of LDS
+
 namespace host {
 
 // Record a message for fw_last_error (this thread) and return `code`.
