@@ -43,7 +43,8 @@ COUNTER_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials
 
 class _Graph(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
-                ("col", ctypes.c_void_p), ("h", ctypes.c_void_p), ("label", ctypes.c_void_p)]
+                ("col", ctypes.c_void_p), ("h", ctypes.c_void_p), ("label", ctypes.c_void_p),
+                ("alias_thr", ctypes.c_void_p), ("alias_idx", ctypes.c_void_p)]
 
 
 class _Logic(ctypes.Structure):
@@ -55,7 +56,7 @@ class _Logic(ctypes.Structure):
 class _Plan(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_float), ("d_lo", ctypes.c_int32), ("rjs_cap", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("jump", ctypes.c_int32), ("bound_scale", ctypes.c_float),
-                ("bound", ctypes.c_int32), ("member_index", ctypes.c_int32)]
+                ("bound", ctypes.c_int32), ("proposal", ctypes.c_int32), ("member_index", ctypes.c_int32)]
 
 
 @dataclass
@@ -89,6 +90,7 @@ class Plan:
     jump: bool = True
     bound_scale: float = 1.0
     bound: int = 0  # 0: max(w) * h_MAX (Section 3.3); 1: Node2Vec split bound (return edge apart)
+    proposal: int = 0  # 0: uniform eRJS proposals (Section 3.3); 1: proportional to h (alias tables)
     member_index: bool = False  # byte accounting only: membership tests read an edge index
 
     def _c(self):
@@ -96,6 +98,7 @@ class Plan:
         s.rho, s.d_lo, s.rjs_cap, s.lanes = self.rho, self.d_lo, self.rjs_cap, self.lanes
         s.jump, s.bound_scale, s.bound = int(self.jump), self.bound_scale, self.bound
         s.member_index = int(self.member_index)
+        s.proposal = self.proposal
         return s
 
 
@@ -117,6 +120,8 @@ def _configure(lib):
     lib.og_uniform.argtypes = [ctypes.c_uint32]
     lib.og_uniform.restype = ctypes.c_float
     lib.og_preprocess.argtypes = [ctypes.POINTER(_Graph), P, P]
+    lib.og_build_alias.argtypes = [ctypes.POINTER(_Graph), P, P]
+    lib.og_build_alias.restype = None
     lib.og_preprocess.restype = None
     lib.og_walk.argtypes = [ctypes.POINTER(_Graph), P, P, ctypes.POINTER(_Logic), ctypes.POINTER(_Plan),
                             ctypes.c_int, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
@@ -181,6 +186,7 @@ class Graph:
         s.label = self.label.ctypes.data if self.label is not None else None
         self._s = s
         self._aux = None
+        self._alias = None
 
     def aux(self):
         """(h_MAX, h_SUM) per node, computed by the oracle."""
@@ -190,6 +196,17 @@ class Graph:
             _load().og_preprocess(ctypes.byref(self._s), hmax.ctypes.data, hsum.ctypes.data)
             self._aux = (hmax, hsum)
         return self._aux
+
+    def alias(self):
+        """(threshold, alias offset) per CSR entry: the alias tables of the static weights h
+        used by h-proportional eRJS proposals (og_build_alias)."""
+        if self._alias is None:
+            thr = np.empty(max(self.ne, 1), np.uint32)
+            idx = np.empty(max(self.ne, 1), np.int32)
+            _load().og_build_alias(ctypes.byref(self._s), thr.ctypes.data, idx.ctypes.data)
+            self._alias = (thr, idx)
+            self._s.alias_thr, self._s.alias_idx = thr.ctypes.data, idx.ctypes.data
+        return self._alias
 
 
 def philox(ctr, key) -> np.ndarray:
@@ -222,6 +239,8 @@ def walk(graph: Graph, logic: Logic, plan: Plan, strategy: int, starts, L: int, 
     n = starts.shape[0]
     wid = None if walker_ids is None else np.ascontiguousarray(walker_ids, np.int64)
     hmax, hsum = graph.aux()
+    if plan.proposal:
+        graph.alias()
     paths = np.empty((n, L + 1), np.int32)
     lengths = np.empty(n, np.int32)
     margins = np.empty((n, L), np.float32) if diagnostics else None
@@ -243,6 +262,8 @@ def step_once(graph: Graph, logic: Logic, plan: Plan, strategy: int, seed: int, 
     """One transition from (prev, cur) at step j; returns (next, margin, kind, trials)."""
     lib = _load()
     hmax, hsum = graph.aux()
+    if plan.proposal:
+        graph.alias()
     m = ctypes.c_float()
     k = ctypes.c_int32()
     t = ctypes.c_int32()

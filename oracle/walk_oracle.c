@@ -24,6 +24,12 @@
  *     helper generation, Eq. sum_estimation);
  *   - cost model: choose eRJS iff (EdgeCost_RJS / EdgeCost_RVS) * max w~ < sum w~
  *     (Section 4.1, Eq. runtime).
+ *   - optional h-proportional proposals (plan.proposal = 1, not in the paper): eRJS
+ *     proposes u with probability h(v,u) / sum h from a per-row alias table of the static
+ *     property weights (Walker's alias method, Vose's construction) and accepts with
+ *     w(u) / W for W >= every workload weight; the mass of u is then h * w / (W * sum h),
+ *     proportional to w~, so the distribution is unchanged and the expected trials drop
+ *     from deg * max(w) * h_MAX / S to W * sum h / S;
  *   - optional split bound for Node2Vec (plan.bound = 1, not in the paper; any bound
  *     that dominates w~ keeps rejection sampling exact, Section 3.3): the return edge
  *     is the only one weighted 1/p, so the proposal board is deg columns of height
@@ -49,7 +55,8 @@
  * conditioning of the jump key, 3 keeps the skip sum after a jump, 4 never proposes
  * the last neighbour in eRJS, 5 drops h_MAX from the eRJS bound, 6 makes the split
  * bound's extra column the full return weight instead of its excess over Bn, 7 divides
- * the second-order PageRank term g by d(v) instead of d(v').
+ * the second-order PageRank term g by d(v) instead of d(v'), 8 never takes an alias
+ * table's alias (every slot keeps itself).
  */
 #ifndef OG_MUTANT
 #define OG_MUTANT 0
@@ -111,6 +118,8 @@ typedef struct {
     const int32_t *col;
     const float *h;       /* NULL: unweighted (h = 1) */
     const uint8_t *label; /* NULL unless MetaPath */
+    const uint32_t *alias_thr; /* per entry: keep-threshold of its alias slot (og_build_alias), or NULL */
+    const int32_t *alias_idx;  /* per entry: row offset of its alias */
 } og_graph;
 
 enum { OG_NODE2VEC = 1, OG_METAPATH = 2, OG_SECOND_PR = 3 };
@@ -131,6 +140,7 @@ typedef struct {
     int32_t jump;        /* 1: Eq. (jump); 0: a key for every item */
     float bound_scale;   /* multiplies the eRJS bound (>= 1 keeps it a bound) */
     int32_t bound;       /* 0: max(w) * h_MAX (Section 3.3); 1: Node2Vec split bound */
+    int32_t proposal;    /* 0: uniform eRJS proposals (Section 3.3); 1: proportional to h */
     int32_t member_index; /* byte accounting only: an eRJS membership test reads one 8-byte
                              key of an edge index (1) or binary-searches the sorted row (0);
                              eRVS always searches the row (all its tests share N(prev)) */
@@ -157,6 +167,51 @@ void og_preprocess(const og_graph *g, float *hmax, float *hsum)
         }
         hmax[v] = mx;
         hsum[v] = (float)sm;
+    }
+}
+
+/* Alias tables of the static weights h (Walker, "An efficient method for generating
+ * discrete random variables with general distributions", ACM TOMS 1977; construction of
+ * Vose, IEEE TSE 1991).  Row v with n entries: scaled_k = h_k * n / H (double, H the sum
+ * of h in index order); slots below 1 ("small") and at or above 1 ("large") are stacked in
+ * index order and paired last in, first out: the small slot keeps probability scaled_s
+ * with the large one as its alias, and the large one gives up 1 - scaled_s.  Leftover
+ * slots keep themselves.  A slot's probability is stored as the threshold
+ * min(floor(p * 2^32), 2^32 - 1): a proposal draws a 64-bit R, takes slot
+ * floor(R * n / 2^64) and keeps it when the high 32 bits of the fraction (R * n mod 2^64)
+ * lie below the threshold, else takes its alias; index k then has probability h_k / H.
+ * A row whose h are all zero keeps every slot (eRJS never proposes there, see og_step). */
+void og_build_alias(const og_graph *g, uint32_t *thr, int32_t *alias)
+{
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t v = 0; v < g->nv; ++v) {
+        const int64_t b = g->row_ptr[v], n = g->row_ptr[v + 1] - b;
+        if (n == 0) continue;
+        double H = 0.0;
+        for (int64_t k = 0; k < n; ++k) H += g->h ? (double)g->h[b + k] : 1.0;
+        double *sc = (double *)malloc(sizeof(double) * (size_t)n);
+        int64_t *small = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+        int64_t *large = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+        double *p = (double *)malloc(sizeof(double) * (size_t)n);
+        int64_t ns = 0, nl = 0;
+        for (int64_t k = 0; k < n; ++k) {
+            alias[b + k] = (int32_t)k;
+            p[k] = 1.0;
+            sc[k] = H > 0.0 ? ((g->h ? (double)g->h[b + k] : 1.0) * (double)n) / H : 1.0;
+            if (sc[k] < 1.0) small[ns++] = k; else large[nl++] = k;
+        }
+        while (ns > 0 && nl > 0) {
+            const int64_t s = small[--ns], l = large[--nl];
+            p[s] = sc[s];
+            alias[b + s] = (int32_t)l;
+            sc[l] = (sc[l] + sc[s]) - 1.0;
+            if (sc[l] < 1.0) small[ns++] = l; else large[nl++] = l;
+        }
+        for (int64_t k = 0; k < n; ++k) {
+            const double t = floor(p[k] * 4294967296.0);
+            thr[b + k] = (OG_MUTANT == 8 || t >= 4294967295.0) ? 0xFFFFFFFFu : (uint32_t)t;
+        }
+        free(sc); free(small); free(large); free(p);
     }
 }
 
@@ -366,11 +421,10 @@ static int64_t rvs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
  * E > 0 (split bound) a trial first decides between the extra column of height E,
  * owned by the return edge at row offset ret, and the deg regular columns of height B. */
 static int64_t rjs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int64_t base, int64_t deg,
-                          int64_t dvp, float B, float E, int64_t ret, og_info *info)
+                          int64_t dvp, float B, float E, int64_t ret, float area, int hprop, og_info *info)
 {
     uint32_t x[4];
     const og_logic *lg = cx->lg;
-    const float area = (float)deg * B + E;
     for (int t = 0; t < cx->pl->rjs_cap; ++t) {
         draw(cx->seed, w, (uint32_t)j, (uint32_t)t, 0, x);
         info->trials++;
@@ -380,15 +434,23 @@ static int64_t rjs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
             if (z < E) return ret;
         }
         uint64_t R = ((uint64_t)x[1] << 32) | x[0];
-        int64_t idx = (int64_t)(((unsigned __int128)R * (unsigned __int128)(uint64_t)deg) >> 64);
+        const unsigned __int128 P = (unsigned __int128)R * (unsigned __int128)(uint64_t)deg;
+        int64_t idx = (int64_t)(P >> 64);
         if (OG_MUTANT == 4 && deg > 1) idx = (int64_t)(((unsigned __int128)R * (unsigned __int128)(uint64_t)(deg - 1)) >> 64);
-        float wt = transition_weight(cx, base + idx, j, prev, deg, dvp);
+        if (hprop) {
+            /* alias coin: the high 32 bits of the fraction against the slot's threshold */
+            const uint32_t f = (uint32_t)((uint64_t)P >> 32);
+            if (!(f < cx->g->alias_thr[base + idx])) idx = cx->g->alias_idx[base + idx];
+        }
+        /* uniform proposals test U * B against w~; h-proportional ones U * B against w */
+        float wt = hprop ? workload_weight(cx, base + idx, j, prev, deg, dvp)
+                         : transition_weight(cx, base + idx, j, prev, deg, dvp);
         float y = og_uniform(x[2]) * B;
-        info->bytes += bytes_per_item(cx);
+        info->bytes += bytes_per_item(cx) + (hprop ? 12.0 : 0.0);
         /* a membership search is needed only when the accept test is not already
            decided by the smallest and largest weight u could have */
         if ((lg->kind == OG_NODE2VEC || lg->kind == OG_SECOND_PR) && j > 0 && cx->g->col[base + idx] != prev) {
-            float hv = (lg->weighted && cx->g->h) ? cx->g->h[base + idx] : 1.0f;
+            float hv = (!hprop && lg->weighted && cx->g->h) ? cx->g->h[base + idx] : 1.0f;
             float wa = 1.0f, wb = 1.0f / lg->q;
             if (lg->kind == OG_SECOND_PR) second_pr_weights(lg, deg, dvp, &wa, &wb);
             float lo = fminf(wa, wb) * hv, hi = fmaxf(wa, wb) * hv;
@@ -449,7 +511,11 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
     const int weighted = lg->weighted && g->h;
     const float hm = (weighted && OG_MUTANT != 5) ? cx->hmax[cur] : 1.0f;
     const float hs = weighted ? cx->hsum[cur] : (float)deg;
-    float B = (w_max(lg, j, deg, dvp) * hm) * cx->pl->bound_scale; /* upper bound of max w~ */
+    /* h-proportional proposals: the eRJS test compares U * B with w (not w~), so B bounds
+       the workload weights alone */
+    const int hprop = cx->pl->proposal == 1 && weighted;
+    const float hB = hprop ? 1.0f : hm;
+    float B = (w_max(lg, j, deg, dvp) * hB) * cx->pl->bound_scale; /* upper bound of max w~ (or w) */
     const float Shat = w_avg(lg, j, deg, dvp) * hs;                /* estimate of sum w~ */
 
     /* split bound: regular height over the non-return weights, extra column for the
@@ -458,14 +524,19 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
     float E = 0.0f;
     int64_t ret = -1;
     if (split) {
-        B = (fmaxf(1.0f, 1.0f / lg->q) * hm) * cx->pl->bound_scale;
+        B = (fmaxf(1.0f, 1.0f / lg->q) * hB) * cx->pl->bound_scale;
         for (int64_t i = 0; i < deg; ++i)
             if (g->col[base + i] == prev) ret = i;
         if (ret >= 0) {
             float wret = transition_weight(cx, base + ret, j, prev, deg, dvp);
-            E = OG_MUTANT == 6 ? wret : fmaxf(0.0f, wret - B);
+            /* the return edge's column has width 1 (uniform) or h(v, prev) (h-proportional) */
+            float cell = hprop ? B * g->h[base + ret] : B;
+            E = OG_MUTANT == 6 ? wret : fmaxf(0.0f, wret - cell);
         }
     }
+    /* area of the proposal board: deg columns of height B (uniform) or total width
+       sum h = h_SUM at height B (h-proportional), plus the return edge's extra column */
+    const float area = hprop ? B * hs + E : (float)deg * B + E;
 
     int use_rjs = 0;
     if (cx->strategy == OG_RJS_ONLY) {
@@ -474,10 +545,11 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
     } else if (cx->strategy == OG_AUTO) {
         if (weighted) info->bytes += 8.0;
         if (deg >= cx->pl->d_lo) {
-            /* Eq. (runtime) per edge; with the split the expected-trial cost is
-               (deg * Bn + E) / S, compared against the eRVS cost deg */
-            float lhs = split ? cx->pl->rho * ((float)deg * B + E) : cx->pl->rho * B;
-            float rhs = split ? (float)deg * Shat : Shat;
+            /* Eq. (runtime) per edge; with the split or h-proportional proposals the
+               expected-trial cost is area / S, compared against the eRVS cost deg */
+            const int board = split || hprop;
+            float lhs = board ? cx->pl->rho * area : cx->pl->rho * B;
+            float rhs = board ? (float)deg * Shat : Shat;
             note_margin(info, lhs, rhs);
             use_rjs = lhs < rhs;
         }
@@ -497,8 +569,9 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
         off = its_sample(cx, w, j, prev, base, deg, dvp, info);
     } else {
         off = -2;
-        if (use_rjs) {
-            off = rjs_sample(cx, w, j, prev, base, deg, dvp, B, E, ret, info);
+        /* h-proportional proposals need some positive h; a row without goes to eRVS */
+        if (use_rjs && !(hprop && !(hs > 0.0f))) {
+            off = rjs_sample(cx, w, j, prev, base, deg, dvp, B, E, ret, area, hprop, info);
             info->kind = 1;
         }
         if (off == -2) {

@@ -366,6 +366,103 @@ def test_second_pr_mean_trials():
     assert abs(trials.mean() - want) < 5 * se, (trials.mean(), want)
 
 
+# ------------------------------------------------------------------ h-proportional proposals
+def _alias_distribution(g, thr, idx, v):
+    """Exact probabilities with which a uniform slot plus the alias coin yields each
+    offset of row v: slot s keeps itself with thr_s / 2^32, else yields idx_s."""
+    b, n = int(g["row_ptr"][v]), int(g["row_ptr"][v + 1] - g["row_ptr"][v])
+    P = [Fraction(0)] * n
+    for s in range(n):
+        keep = Fraction(int(thr[b + s]), 1 << 32)
+        P[s] += keep / n
+        P[int(idx[b + s])] += (1 - keep) / n
+    return P
+
+
+@pytest.mark.parametrize("weights", ["triangle", "hub", "pareto1", "pareto3"])
+def test_alias_tables_realise_h(weights):
+    """Each row's alias table draws offset k with probability h_k / sum h, to within the
+    2^-32 granularity of the thresholds (Walker's alias method)."""
+    if weights == "triangle":
+        g = triangle_graph()
+    elif weights == "hub":
+        g = hub_ring_graph(600)
+    else:
+        g = synth.rmat(9, 8 << 9, seed=3)
+        g["h"] = synth.pareto_weights(g["row_ptr"], g["col"], float(weights[6:]), 5)
+    og = oracle.Graph(g)
+    thr, idx = og.alias()
+    rows = range(g["nv"]) if g["nv"] <= 700 else np.random.default_rng(0).choice(g["nv"], 120, replace=False)
+    for v in rows:
+        b, e = int(g["row_ptr"][v]), int(g["row_ptr"][v + 1])
+        if e == b:
+            continue
+        h = [Fraction(float(x)) for x in g["h"][b:e]]
+        H = sum(h)
+        got = _alias_distribution(g, thr, idx, int(v))
+        assert sum(got) == 1
+        for k in range(e - b):
+            assert abs(got[k] - h[k] / H) <= Fraction(e - b + 2, 1 << 31), (v, k)
+
+
+N2V_H = [("rjs", oracle.RJS_ONLY, oracle.Plan(proposal=1)),
+         ("rjs_split", oracle.RJS_ONLY, oracle.Plan(proposal=1, bound=1)),
+         ("auto_split", oracle.AUTO, oracle.Plan(proposal=1, bound=1, rho=1.0, lanes=2)),
+         ("rjs_cap1", oracle.RJS_ONLY, oracle.Plan(proposal=1, rjs_cap=1, lanes=2))]
+
+
+@pytest.mark.parametrize("name,strategy,plan", N2V_H, ids=[s[0] for s in N2V_H])
+@pytest.mark.parametrize("logic", [N2V, N2V_RET, PR2, dict(kind=oracle.METAPATH, weighted=True, schema=(0, 1, 2))],
+                         ids=["n2v", "n2v_ret", "2ndpr", "metapath"])
+def test_h_proposals_paths_chisquare(name, strategy, plan, logic):
+    g = triangle_graph(labels=True)
+    lg = oracle.Logic(**logic)
+    n = 60000
+    for start in (0, 4):
+        counts, _ = _walk_counts(g, lg, plan, strategy, start, 3, n, seed=61 + start)
+        assert chisq_pvalue(counts, exact.path_distribution(g, lg, start, 3), n) > P_OK, (name, start)
+
+
+def test_h_proposals_hub_and_skew():
+    """The 600-neighbour hub, and Pareto(1) weights where uniform proposals need hundreds
+    of trials per step: same exact distribution, far fewer trials."""
+    g = hub_ring_graph(600)
+    lg = oracle.Logic(**N2V_RET)
+    og = oracle.Graph(g)
+    n = 40000
+    r = oracle.walk(og, lg, oracle.Plan(proposal=1, bound=1), oracle.RJS_ONLY, np.full(n, 1, np.int32), 2, 5,
+                    diagnostics=False)
+    at_hub = r.paths[:, 1] == 0
+    counts = {int(v): int(c) for v, c in zip(*np.unique(r.paths[at_hub, 2], return_counts=True))}
+    assert chisq_pvalue(counts, exact.transition(g, lg, 1, 1, 0), int(at_hub.sum())) > P_OK
+    g = synth.rmat(12, 8 << 12, seed=2)
+    g["h"] = synth.pareto_weights(g["row_ptr"], g["col"], 1.0, 3)
+    og = oracle.Graph(g)
+    st = np.arange(g["nv"], dtype=np.int32)
+    u = oracle.walk(og, oracle.Logic(**N2V), oracle.Plan(rjs_cap=1 << 20), oracle.RJS_ONLY, st, 10, 9, diagnostics=False)
+    a = oracle.walk(og, oracle.Logic(**N2V), oracle.Plan(proposal=1, rjs_cap=1 << 20), oracle.RJS_ONLY, st, 10, 9,
+                    diagnostics=False)
+    tu, ta = (x.counters["rjs_trials"] / x.counters["steps"] for x in (u, a))
+    assert ta < 0.05 * tu and ta < 4.0, (tu, ta)
+
+
+def test_h_proposals_mean_trials():
+    """State prev = 3, cur = 1 of the triangle graph, p = 1/4, q = 2: w = 1/2, 1, 4 for
+    u = 0, 2, 3 with h = 1, 3, 4 (sum 8), so sum w~ = 19.5.  With the split bound W = 1 and
+    the return edge's extra column (4 - 1) * 4 = 12: trials = (1 * 8 + 12) / 19.5; with the
+    paper's bound W = 4: trials = 4 * 8 / 19.5."""
+    g = triangle_graph()
+    lg = oracle.Logic(**N2V_RET)
+    og = oracle.Graph(g)
+    n = 40000
+    for plan, want in ((oracle.Plan(proposal=1, bound=1, rjs_cap=100000), 20.0 / 19.5),
+                       (oracle.Plan(proposal=1, bound=0, rjs_cap=100000), 32.0 / 19.5)):
+        trials = np.array([oracle.step_once(og, lg, plan, oracle.RJS_ONLY, 3, i, 1, 3, 1)[3] for i in range(n)],
+                          dtype=np.float64)
+        se = math.sqrt(max(want * (want - 1), 1e-12) / n)
+        assert abs(trials.mean() - want) < 5 * se + 1e-9, (plan.bound, trials.mean(), want)
+
+
 # ------------------------------------------------------------------ comparison selection policies
 @pytest.mark.parametrize("strategy", [oracle.RANDOM_SELECT, oracle.DEGREE_SELECT], ids=["random", "degree"])
 @pytest.mark.parametrize("logic", [N2V, PR2], ids=["node2vec", "2ndpr"])
@@ -469,6 +566,7 @@ MUTANTS = {
     5: "eRJS bound without h_MAX",
     6: "split bound's extra column is the whole return weight",
     7: "second-order PageRank divides gamma by d(v) instead of d(v')",
+    8: "alias tables never take the alias",
 }
 
 
@@ -488,7 +586,8 @@ def test_planted_mistake_is_caught(mut, mutant_libs):
                                             ("rjs", N2V, oracle.RJS_ONLY, oracle.Plan()),
                                             ("rjs_split", N2V_RET, oracle.RJS_ONLY, oracle.Plan(bound=1)),
                                             ("rjs_2ndpr", PR2, oracle.RJS_ONLY, oracle.Plan()),
-                                            ("rvs_2ndpr", PR2, oracle.RVS_ONLY, oracle.Plan(lanes=2))):
+                                            ("rvs_2ndpr", PR2, oracle.RVS_ONLY, oracle.Plan(lanes=2)),
+                                            ("rjs_hprop", N2V, oracle.RJS_ONLY, oracle.Plan(proposal=1))):
             lg = oracle.Logic(**logic)
             n = 60000
             counts, _ = _walk_counts(g, lg, plan, strategy, 0, 3, n, seed=7)
