@@ -93,7 +93,8 @@ def main():
     ap.add_argument("--tick-steps", type=int, default=16)
     ap.add_argument("--skew-scale", type=int, default=20, help="skew: R-MAT scale of the topology")
     ap.add_argument("--skew-L", type=int, default=20, help="skew: walk length")
-    ap.add_argument("--plan", default="", help="rho,d_lo,lds_cap[,bound]: use this plan instead of autotuning")
+    ap.add_argument("--plan", default="",
+                    help="rho,d_lo,lds_cap[,bound[,proposal]]: use this plan instead of autotuning")
     ap.add_argument("--per-query", type=int, default=1, help="batched: also time one launch per query")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB: only run a plain device-to-device copy of this size 3 times (counter calibration)")
@@ -164,6 +165,9 @@ def main():
     e1.record()
     torch.cuda.synchronize()
     index_ms = e0.elapsed_time(e1)
+    a0 = time.perf_counter()
+    fw.fw_graph_build_alias(gh)
+    alias_ms = (time.perf_counter() - a0) * 1e3
     if args.logic == "secondpr":
         logic = fw.fw_logic_second_pr(args.gamma, True)
         logic_text = f"second-order PageRank gamma={args.gamma}"
@@ -174,12 +178,12 @@ def main():
     if args.plan:
         f = args.plan.split(",")
         plan = fw.fw_plan_default(rho=float(f[0]), d_lo=int(f[1]), lds_cap=int(f[2]),
-                                  bound=int(f[3]) if len(f) > 3 else 0)
+                                  bound=int(f[3]) if len(f) > 3 else 0, proposal=int(f[4]) if len(f) > 4 else 0)
     else:
         plan = fw.fw_plan_autotune(gh, logic)
     tune_ms = (time.time() - t1) * 1e3
     log(f"preprocess {prep_ms:.2f} ms, autotune {tune_ms:.1f} ms, rho={plan.rho:.3f} d_lo={plan.d_lo} "
-        f"lds_cap={plan.lds_cap} bound={plan.bound}")
+        f"lds_cap={plan.lds_cap} bound={plan.bound} proposal={plan.proposal}")
 
     nv, L, seed = g["nv"], args.L, 42
     starts = torch.arange(nv, dtype=torch.int32, device=dev)
@@ -220,11 +224,17 @@ def main():
         # own output buffers: the timed job's walks stay for the CPU comparison below
         m_paths, m_lengths = torch.empty_like(paths), torch.empty_like(lengths)
         # the single-kernel modes, and the same job under the other eRJS bound
-        other = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap, bound=1 - plan.bound)
+        other = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap, bound=1 - plan.bound,
+                                   proposal=plan.proposal)
         sym = fw.fw_graph_info(gh)[3]
         cases = [(m + "_only", m, plan) for m in ("rvs", "rjs") if m != args.strategy]
         if args.logic == "node2vec" and (sym or other.bound == 0):
             cases.append((("split" if other.bound else "paper") + "_bound", args.strategy, other))
+        flip = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap, bound=plan.bound,
+                                  proposal=1 - plan.proposal)
+        cases.append((("h" if flip.proposal else "uniform") + "_proposals", args.strategy, flip))
+        paper = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap)
+        cases.append(("paper_eRJS", args.strategy, paper))  # uniform proposals, bound max(w) * h_MAX
         for name, m, pl in cases:
             mms, _, mst = run(m, 2, 1, plan=pl, paths=m_paths, lengths=m_lengths)
             a = float(np.mean(mms))
@@ -242,7 +252,8 @@ def main():
         og.aux()
         lg = (oracle.Logic(kind=oracle.SECOND_PR, weighted=True, gamma=args.gamma) if args.logic == "secondpr"
               else oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=args.p, q=args.q))
-        pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap, bound=plan.bound, member_index=True)
+        pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap, bound=plan.bound, proposal=plan.proposal,
+                         member_index=True)
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
         smode = {"auto": 0, "rvs": 1, "rjs": 2}[args.strategy]
         k = args.cpu_sample or 2048
@@ -286,8 +297,9 @@ def main():
                                f"(a=0.57,b=0.19,c=0.19, edge factor 16, {g['ne']} CSR entries), one walker "
                                f"per vertex ({nv}), L={L}, strategy={args.strategy}",
                    "walker_steps_per_walk_job": steps_per_walk, "preprocess_ms": prep_ms,
-                   "edge_index_ms": index_ms,
-                   "autotune_ms": tune_ms, "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound},
+                   "edge_index_ms": index_ms, "alias_build_ms": alias_ms,
+                   "autotune_ms": tune_ms, "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound,
+                            "proposal": plan.proposal},
                    "stats": st, "modes": modes,
                    "hbm_traffic_GBps": None if traffic is None else traffic["bytes"] / (avg_ms / 1e3) / 1e9,
                    "random_access": random_access},
@@ -333,14 +345,18 @@ def bench_skew(args):
         gh = fw.fw_graph_create(nv, topo["ne"], t_rp, t_col, t_h, None, on_device=True)
         fw.fw_graph_preprocess(gh)
         fw.fw_graph_build_index(gh)
+        fw.fw_graph_build_alias(gh)
         plan = fw.fw_plan_autotune(gh, logic)
+        uni = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap, bound=plan.bound)
         modes = {"auto": (fw.FW_AUTO, plan),
+                 "auto_uniform_proposals": (fw.FW_AUTO, uni),
                  "random": (fw.FW_RANDOM_SELECT, plan),
-                 "degree": (fw.FW_DEGREE_SELECT, fw.fw_plan_default(d_lo=1000, bound=plan.bound)),
+                 "degree": (fw.FW_DEGREE_SELECT, fw.fw_plan_default(d_lo=1000, bound=plan.bound,
+                                                                   proposal=plan.proposal)),
                  "rjs_only": (fw.FW_RJS_ONLY, plan),
                  "rvs_only": (fw.FW_RVS_ONLY, plan)}
         row = {"weights": name, "h_max": float(h.max()), "h_median": float(np.median(h)), "plan_rho": plan.rho,
-               "plan_bound": plan.bound}
+               "plan_bound": plan.bound, "plan_proposal": plan.proposal}
         for m, (strat, pl) in modes.items():
             fw.fw_walk(gh, logic, pl, strat, starts, nv, L, seed, paths, lengths, None)  # warm-up
             stats.zero_()
@@ -394,6 +410,7 @@ def bench_batched(args):
     del t
     fw.fw_graph_preprocess(gh)
     fw.fw_graph_build_index(gh)
+    fw.fw_graph_build_alias(gh)
     plan = fw.fw_plan_autotune(gh, fw.fw_logic_node2vec(1.0, 1.0, True))
     qd = synth.batch_queries(g["nv"], 4096, 7)
     starts = torch.from_numpy(qd["starts"]).to(dev)
@@ -482,6 +499,7 @@ def bench_served(args):
     del g
     fw.fw_graph_preprocess(gh)
     fw.fw_graph_build_index(gh)
+    fw.fw_graph_build_alias(gh)
     plan = fw.fw_plan_autotune(gh, fw.fw_logic_node2vec(1.0, 1.0, True))
     budget = 32 << 30
     srv = fw.fw_server_create(gh, plan, fw.FW_AUTO, budget, tick_steps=args.tick_steps, max_active=8192,

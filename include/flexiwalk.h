@@ -106,7 +106,15 @@ typedef struct fw_logic {
  *               reverse edges exist with equal h (fw_graph_info reports it); MetaPath
  *               ignores it.  The cost model then compares rho * (deg * height +
  *               excess) with deg * S^.
- *   reserved must be 0 */
+ *   proposal eRJS proposal distribution (changes the stream, never the distribution):
+ *            0  uniform over N(v) (Section 3.3), tested as U * B < w~;
+ *            1  proportional to the static weight h(v,u) through per-row alias tables
+ *               (fw_graph_build_alias), tested as U * W < w with W >= every workload
+ *               weight: the mass of u is h * w / (W * sum h), proportional to w~, and the
+ *               expected trials drop from deg * B / S to W * h_SUM / S.  Applies to
+ *               weighted logics; a row whose h are all zero goes to eRVS.  With
+ *               bound = 1 the return edge's extra column is (1/p - W) * h(v, prev) wide.
+ *            The cost model compares rho * (board area) with deg * S^ for 1 (and bound 1). */
 typedef struct fw_plan {
     float rho;
     int32_t d_lo;
@@ -115,7 +123,7 @@ typedef struct fw_plan {
     int32_t lds_cap;
     int32_t grid;
     int32_t bound;
-    int32_t reserved;
+    int32_t proposal;
 } fw_plan;
 
 /* Counters accumulated by fw_walk into a device array of FW_NSTATS uint64 values:
@@ -156,6 +164,17 @@ int fw_graph_export_aux(const fw_graph *g, float *hmax, float *hsum);
  * the table cannot be allocated (the graph stays usable without it). */
 int fw_graph_build_index(fw_graph *g, void *stream);
 
+/* Build the proposal records of h-proportional eRJS (plan.proposal = 1): per CSR entry k
+ * of row v, 32 bytes {col[k], h[k], col[a], h[a], threshold, labels of k and a, 0, 0} where
+ * a and the threshold form Walker's alias table of the row's h (Vose's construction in
+ * double precision in index order; threshold = min(floor(p * 2^32), 2^32 - 1) of the slot's
+ * keep probability p).  A proposal takes slot floor(R * deg / 2^64) of a 64-bit draw R and
+ * keeps it when the high 32 bits of the fraction lie below the threshold, else takes a.
+ * One record is one 32-byte read.  Device memory: 32 bytes per entry, plus 20 bytes per
+ * entry of scratch while building.  Synchronous; idempotent.  Walks, batches and servers
+ * created afterwards can use it. */
+int fw_graph_build_alias(fw_graph *g, void *stream);
+
 /* Roofline calibration (not part of the method): time random 8-byte reads from a device
  * array of `bytes` (a power of two >= 1 MiB), 2^20 lanes each issuing four independent
  * loads per round, and store the best rate in *reads_per_s.  Each such read moves one
@@ -190,7 +209,8 @@ int fw_plan_profile(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stre
 
 /* fw_plan_profile, then a measured search: short seeded sample walks (up to 2^18 walkers,
  * 16 steps, AUTO) are timed for rho scaled by 1/16 .. 4 around the profiled value (with
- * each eRJS bound: the split bound too for Node2Vec on a symmetric graph), then for the
+ * each eRJS bound: the split bound too for Node2Vec on a symmetric graph; and each
+ * proposal: h-proportional too for a weighted logic once fw_graph_build_alias ran), then for the
  * degree gate d_lo in {0, 8, 32, 128} and the LDS budget for N(prev); the fastest plan
  * is returned.  Every candidate samples the same distribution; only the choice of kernel
  * per step, and so the random stream, differs.  Allocates temporary device memory;

@@ -25,11 +25,11 @@ FW_NSTATS = 8
 STAT_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", "rvs_triggers",
               "ended_early", "alg_bytes")
 EXPORTED = ("fw_graph_create", "fw_graph_destroy", "fw_graph_preprocess", "fw_graph_build_index",
-            "fw_graph_export_aux", "fw_graph_info", "fw_calibrate_random_reads", "fw_logic_node2vec",
-            "fw_logic_metapath", "fw_logic_second_pr", "fw_plan_default", "fw_plan_profile", "fw_plan_autotune",
-            "fw_walk", "fw_graph_check", "fw_last_error", "fw_batch_create", "fw_batch_launch", "fw_batch_capture",
-            "fw_batch_replay", "fw_batch_destroy", "fw_server_create", "fw_server_submit", "fw_server_next_done",
-            "fw_server_result", "fw_server_stats", "fw_server_destroy")
+            "fw_graph_export_aux", "fw_graph_info", "fw_calibrate_random_reads", "fw_graph_build_alias",
+            "fw_logic_node2vec", "fw_logic_metapath", "fw_logic_second_pr", "fw_plan_default", "fw_plan_profile",
+            "fw_plan_autotune", "fw_walk", "fw_graph_check", "fw_last_error", "fw_batch_create", "fw_batch_launch",
+            "fw_batch_capture", "fw_batch_replay", "fw_batch_destroy", "fw_server_create", "fw_server_submit",
+            "fw_server_next_done", "fw_server_result", "fw_server_stats", "fw_server_destroy")
 SERVER_STAT_NAMES = ("waiting", "active", "finished", "ticks", "walker_steps", "bytes_in_use", "peak_bytes",
                      "alg_bytes")
 
@@ -55,7 +55,7 @@ class fw_logic(ctypes.Structure):
 class fw_plan(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_float), ("d_lo", ctypes.c_int32), ("rjs_cap", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("lds_cap", ctypes.c_int32), ("grid", ctypes.c_int32),
-                ("bound", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bound", ctypes.c_int32), ("proposal", ctypes.c_int32)]
 
 
 class fw_query(ctypes.Structure):
@@ -74,6 +74,7 @@ def _load():
         "fw_graph_destroy": ([P], ctypes.c_int),
         "fw_graph_preprocess": ([P, P], ctypes.c_int),
         "fw_graph_build_index": ([P, P], ctypes.c_int),
+        "fw_graph_build_alias": ([P, P], ctypes.c_int),
         "fw_calibrate_random_reads": ([ctypes.c_int64, ctypes.POINTER(ctypes.c_double), P], ctypes.c_int),
         "fw_graph_export_aux": ([P, P, P], ctypes.c_int),
         "fw_graph_info": ([P, P, P, P, P], ctypes.c_int),
@@ -158,6 +159,10 @@ def fw_graph_preprocess(g: int, stream=None):
 
 def fw_graph_build_index(g: int, stream=None):
     _check(_lib.fw_graph_build_index(g, _stream(stream)))
+
+
+def fw_graph_build_alias(g: int, stream=None):
+    _check(_lib.fw_graph_build_alias(g, _stream(stream)))
 
 
 def fw_calibrate_random_reads(nbytes: int = 4 << 30, stream=None) -> float:

@@ -61,6 +61,7 @@ static void graph_free(fw_graph *g)
     (void)hipFree(g->start_hi);
     (void)hipFree(g->scratch);
     (void)hipFree(g->mtab);
+    (void)hipFree(g->prop);
     delete g;
 }
 
@@ -333,6 +334,7 @@ void fw::host::fill_args(const fw_graph *g, const fw_logic *lg, fw::WalkArgs &a)
     a.nv = g->nv;
     a.mtab = (const uint4 *)g->mtab;
     a.mtab_mask = g->mtab_mask;
+    a.prop = g->prop;
     fill_query(lg, a.q0);
     const bool weighted = lg->weighted && g->h;
     a.item_bytes = 4 + (weighted ? 4 : 0) + (lg->kind == FW_METAPATH ? 1 : 0);
@@ -348,12 +350,14 @@ int fw::host::check_plan(const fw_plan *pl)
         return fail(FW_E_INVALID, "plan.lds_cap in [0, %d]", fw::kMaxLdsCap);
     if (pl->grid < 0) return fail(FW_E_INVALID, "plan.grid must be >= 0");
     if (pl->bound < 0 || pl->bound > 1) return fail(FW_E_INVALID, "plan.bound must be 0 or 1");
-    if (pl->reserved != 0) return fail(FW_E_INVALID, "plan.reserved must be 0");
+    if (pl->proposal < 0 || pl->proposal > 1) return fail(FW_E_INVALID, "plan.proposal must be 0 or 1");
     return FW_OK;
 }
 
 int fw::host::check_bound(const fw_graph *g, const fw_plan *pl, const fw_logic *lg)
 {
+    if (pl->proposal == 1 && lg->weighted && g->h && !g->prop)
+        return fail(FW_E_STATE, "plan.proposal = 1 needs fw_graph_build_alias first");
     if (pl->bound == 1 && lg->kind == FW_NODE2VEC && !g->symmetric)
         return fail(FW_E_INVALID, "plan.bound = 1 needs every edge's reverse with the same h (fw_graph_info)");
     return FW_OK;
@@ -367,6 +371,7 @@ void fw::host::plan_args(const fw_plan *pl, int32_t strategy, fw::WalkArgs &a)
     a.strategy = strategy;
     a.lds_cap = pl->lds_cap;
     a.bound = pl->bound;
+    a.proposal = pl->proposal;
 }
 
 extern "C" {
@@ -440,6 +445,33 @@ struct Events {
         if (b) (void)hipEventDestroy(b);
     }
 };
+
+int fw_graph_build_alias(fw_graph *g, void *stream)
+{
+    if (!g) return fail(FW_E_INVALID, "fw_graph_build_alias: null graph");
+    if (g->prop) return ok();
+    HIP_TRY(hipSetDevice(g->device));
+    const size_t ne = (size_t)(g->ne > 0 ? g->ne : 1);
+    uint4 *prop = nullptr;
+    if (hipMalloc((void **)&prop, 32 * ne) != hipSuccess)
+        return fail(FW_E_NOMEM, "fw_graph_build_alias: hipMalloc of %zu bytes failed", 32 * ne);
+    DevBuf sc, ss, sl, al;
+    if (hipMalloc(&sc.p, 8 * ne) != hipSuccess || hipMalloc(&ss.p, 4 * ne) != hipSuccess ||
+        hipMalloc(&sl.p, 4 * ne) != hipSuccess || hipMalloc(&al.p, 4 * ne) != hipSuccess) {
+        (void)hipFree(prop);
+        return fail(FW_E_NOMEM, "fw_graph_build_alias: scratch of %zu bytes failed", 20 * ne);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = fw::launch_build_alias(g->row_ptr, g->col, g->h, g->label, g->nv, (double *)sc.p,
+                                          (int32_t *)ss.p, (int32_t *)sl.p, (int32_t *)al.p, prop, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(prop);
+        return fail(FW_E_DEVICE, "fw_graph_build_alias: %s", hipGetErrorString(e));
+    }
+    g->prop = prop;
+    return ok();
+}
 
 int fw_calibrate_random_reads(int64_t bytes, double *reads_per_s, void *stream)
 {
@@ -581,14 +613,18 @@ int fw_plan_autotune(fw_graph *g, const fw_logic *lg, fw_plan *out, void *stream
     const float rho0 = out->rho;
     const float scales[] = {0.0625f, 0.25f, 0.5f, 1.0f, 2.0f, 4.0f};
     const int nbound = (lg->kind == FW_NODE2VEC && g->symmetric) ? 2 : 1;
-    for (int32_t bound = 0; bound < nbound; ++bound) {
-        for (float sc : scales) {
-            fw_plan p = *out;
-            p.rho = std::max(1e-3f, rho0 * sc);
-            p.bound = bound;
-            float t;
-            if ((rc = time_plan(p, &t)) != FW_OK) return rc;
-            if (t < bestt) bestt = t, bestp = p;
+    const int nprop = (lg->weighted && g->h && g->prop) ? 2 : 1;
+    for (int32_t prop = 0; prop < nprop; ++prop) {
+        for (int32_t bound = 0; bound < nbound; ++bound) {
+            for (float sc : scales) {
+                fw_plan p = *out;
+                p.rho = std::max(1e-3f, rho0 * sc);
+                p.bound = bound;
+                p.proposal = prop;
+                float t;
+                if ((rc = time_plan(p, &t)) != FW_OK) return rc;
+                if (t < bestt) bestt = t, bestp = p;
+            }
         }
     }
     for (int32_t d : {8, 32, 128}) {

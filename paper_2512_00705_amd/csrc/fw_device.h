@@ -47,6 +47,14 @@ __device__ __forceinline__ int64_t scaled_index(uint32_t lo, uint32_t hi, int64_
     return (int64_t)__umul64hi(r, (uint64_t)n);
 }
 
+// The high 32 bits of the fraction R * n mod 2^64 left by scaled_index: a second draw,
+// independent of the index to within 2^-32, from the same 64 random bits.
+__device__ __forceinline__ uint32_t scaled_fraction_hi(uint32_t lo, uint32_t hi, int64_t n)
+{
+    const uint64_t r = ((uint64_t)hi << 32) | lo;
+    return (uint32_t)((r * (uint64_t)n) >> 32);
+}
+
 // Logarithms rounded once to float32 from a double-precision evaluation, so the value
 // is the correctly rounded one except within ~1e-16 of a rounding tie.
 __device__ __forceinline__ float ln_f(float x) { return (float)log((double)x); }

@@ -96,6 +96,8 @@ struct WalkArgs {
     int32_t tick_steps;         // resumable walks: steps per walker per launch
     int32_t bound;              // 1: Node2Vec split eRJS bound (symmetric graphs only)
     const uint4 *mtab;          // edge index (4 uint4 per bucket) or null: search the sorted rows
+    const uint4 *prop;          // proposal records (2 uint4 per entry) or null
+    int32_t proposal;           // 1: h-proportional eRJS proposals through `prop`
     uint64_t mtab_mask;         // buckets - 1
 
     QueryDev q0;                // the query of a single-query launch
@@ -109,6 +111,13 @@ hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 hipError_t launch_layout(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int64_t ne,
                          uint2 *edges, uint4 *vrec, uint32_t *start_hi, hipStream_t s);
 hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv, uint4 *vrec, hipStream_t s);
+// Proposal records of h-proportional eRJS: Walker's alias table per row (Vose's
+// construction, one lane per row, in double precision in index order) written as
+// prop[2k] = {col[k], h[k], col[a], h[a]}, prop[2k+1] = {threshold, lab[k] | lab[a] << 8, 0, 0}.
+// sc, stk_s, stk_l and alias are ne-long scratch arrays.
+hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
+                              int64_t nv, double *sc, int32_t *stk_s, int32_t *stk_l, int32_t *alias, uint4 *prop,
+                              hipStream_t s);
 // Edge index: inserts every entry (v, col[k]) of the rows into `tab` (buckets * 8 keys, all
 // kEmptyKey on entry; buckets = mask + 1, a power of two, at least a quarter of ne).
 hipError_t launch_build_index(const int64_t *row_ptr, const int32_t *col, int64_t nv, unsigned long long *tab,

@@ -275,6 +275,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
     int32_t stop_j = 0;  // resumable walks: suspend when j reaches this step
     bool fell_back = false;
     float B = 0.0f;
+    float area = 0.0f;  // eRJS proposal board: deg * B (uniform) or B * h_SUM (h-proportional), plus E
     // h of the edge prev -> cur, and of the edge the current step takes; on a symmetric
     // graph the first is also h(cur, prev), the return edge's property weight
     float hlast = 1.0f, hnext = 1.0f;
@@ -381,6 +382,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                     mode = kAdv;
                 } else {
                     bool rjs = false;
+                    fell_back = false;
                     if (a.strategy != kRvsOnly) {
                         float wmax = (j == 0) ? Q.wmax0 : Q.wmax1;
                         float wavg = (j == 0) ? Q.wavg0 : Q.wavg1;
@@ -391,10 +393,16 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                             wavg = (sw.mem + sw.oth) / 2.0f;
                         }
                         const float hm = W ? __uint_as_float(r.z) : 1.0f;
+                        const float hs = W ? __uint_as_float(r.w) : (float)deg;
                         // get_weight_max: max(w) * h_MAX; the split bound's column height
-                        // leaves the return weight 1/p out
+                        // leaves the return weight 1/p out; h-proportional proposals bound
+                        // w alone
                         const bool split = KIND == kNode2Vec && a.bound != 0 && j > 0;
-                        B = split ? Q.hi_w * hm : wmax * hm;
+                        const bool hprop = W && a.proposal != 0;
+                        const float hB = hprop ? 1.0f : hm;
+                        B = split ? Q.hi_w * hB : wmax * hB;
+                        const float E = split ? fmaxf(0.0f, Q.inv_p * hlast - (hprop ? B * hlast : B)) : 0.0f;
+                        area = hprop ? B * hs + E : (float)deg * B + E;
                         if (a.strategy == kRjsOnly) {
                             rjs = true;
                             st_bytes += W ? 4 : 0;
@@ -407,21 +415,24 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                             rjs = deg >= a.d_lo;  // comparison policy: eRJS at high degree
                             st_bytes += W ? 4 : 0;
                         } else {
-                            const float hs = W ? __uint_as_float(r.w) : (float)deg;
                             st_bytes += W ? 8 : 0;
                             // Eq. (runtime) with get_weight_sum = mean(w) * h_SUM; with the
-                            // split board the eRJS cost is (deg * B + E) / S per step
-                            if (split) {
-                                const float E = fmaxf(0.0f, Q.inv_p * hlast - B);
-                                rjs = deg >= a.d_lo && (a.rho * ((float)deg * B + E)) < ((float)deg * (wavg * hs));
+                            // split board or h-proportional proposals the eRJS cost is
+                            // area / S per step against deg for eRVS
+                            if (split || hprop) {
+                                rjs = deg >= a.d_lo && (a.rho * area) < ((float)deg * (wavg * hs));
                             } else {
                                 rjs = deg >= a.d_lo && (a.rho * B) < (wavg * hs);
                             }
                         }
+                        // h-proportional proposals need some positive h: else eRVS
+                        if (rjs && hprop && !(hs > 0.0f)) {
+                            rjs = false;
+                            fell_back = true;
+                        }
                     }
                     mode = rjs ? kRjs : kRvs;
                     trials = 0;
-                    fell_back = false;
                 }
             }
         }
@@ -437,9 +448,11 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
             // trials ran one by one
             // split bound: a trial first picks the return edge's extra column (height
             // E) with probability E / (deg * B + E); such a trial reads no edge
+            // h-proportional proposals: a record of the row's alias table gives the slot
+            // and its alias; the coin is the fraction of the index draw
             const bool split = KIND == kNode2Vec && a.bound != 0 && j > 0;
-            const float E = split ? fmaxf(0.0f, Q.inv_p * hlast - B) : 0.0f;
-            const float area = (float)deg * B + E;
+            const bool hprop = W && a.proposal != 0;
+            const float E = split ? fmaxf(0.0f, Q.inv_p * hlast - (hprop ? B * hlast : B)) : 0.0f;
             uint32_t ux[kRjsBatch];
             uint2 ee[kRjsBatch];
             uint8_t ll[kRjsBatch];
@@ -451,9 +464,19 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 const int64_t k = base + scaled_index(x.x0, x.x1, deg);
                 ol[r] = E > 0.0f && unit_uniform(x.x3) * area < E;
                 ux[r] = x.x2;
-                if (ol[r]) ee[r] = make_uint2((uint32_t)prev, 0u);
-                else ee[r] = a.edges[k];
-                ll[r] = (KIND == kMetaPath) ? a.label[k] : (uint8_t)0;
+                if (ol[r]) {
+                    ee[r] = make_uint2((uint32_t)prev, 0u);
+                    ll[r] = 0;
+                } else if (hprop) {
+                    const uint32_t f = scaled_fraction_hi(x.x0, x.x1, deg);
+                    const uint4 r0 = a.prop[2 * k], r1 = a.prop[2 * k + 1];
+                    const bool keep = f < r1.x;
+                    ee[r] = keep ? make_uint2(r0.x, r0.y) : make_uint2(r0.z, r0.w);
+                    ll[r] = (KIND == kMetaPath) ? (uint8_t)(keep ? r1.y : r1.y >> 8) : (uint8_t)0;
+                } else {
+                    ee[r] = a.edges[k];
+                    ll[r] = (KIND == kMetaPath) ? a.label[k] : (uint8_t)0;
+                }
             }
             const StepW sw = step_weights<KIND>(Q, deg, pdeg);
             // decide proposals in order; the batch shifts down one slot per trial so the
@@ -462,17 +485,18 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
             for (int r = 0; r < kRjsBatch; ++r) {
                 const int32_t u = (int32_t)ee[0].x;
                 const float hv = W ? __uint_as_float(ee[0].y) : 1.0f;
+                const float hw = hprop ? 1.0f : hv;  // the test is on w~ (uniform) or w (h-proportional)
                 const float y = unit_uniform(ux[0]) * B;
                 bool acc;
                 if (ol[0]) {
                     acc = true;  // the extra column belongs to the return edge
                 } else if (uses_membership(KIND)) {
                     if (j == 0) {
-                        acc = y < hv;
+                        acc = y < hw;
                     } else if (u == prev) {
-                        acc = y < sw.ret * hv;
+                        acc = y < sw.ret * hw;
                     } else {
-                        const float lo = sw.lo * hv, hi = sw.hi * hv;
+                        const float lo = sw.lo * hw, hi = sw.hi * hw;
                         if (y < lo) {
                             acc = true;
                         } else if (!(y < hi)) {
@@ -481,16 +505,16 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                             st_bytes += a.mtab ? 8 : 4 * (uint64_t)probes(pdeg);
                             const bool member = a.mtab ? index_contains(a.mtab, a.mtab_mask, prev, u)
                                                        : sorted_contains_interp(a.col + pbase, pdeg, u, (int32_t)a.nv);
-                            const float wt = member ? sw.mem * hv : sw.oth * hv;
+                            const float wt = member ? sw.mem * hw : sw.oth * hw;
                             acc = y < wt;
                         }
                     }
                 } else {
-                    acc = y < (ll[0] == want ? hv : 0.0f);
+                    acc = y < (ll[0] == want ? hw : 0.0f);
                 }
                 ++trials;
                 st[kStTrials] += 1;
-                if (!ol[0]) st_bytes += (uint64_t)a.item_bytes;
+                if (!ol[0]) st_bytes += (uint64_t)a.item_bytes + (hprop ? 12 : 0);
                 if (acc) {
                     nxt = u;
                     hnext = ol[0] ? hlast : hv;  // symmetric h: h(cur, prev) = h(prev, cur)
@@ -699,6 +723,50 @@ __global__ void __launch_bounds__(kBlock) validate_edges_kernel(const int64_t *r
         if (bad) atomicOr(err, 2);
     }
     if (lane == 0 && dmax > 0) atomicMax(max_deg, dmax);
+}
+
+// Proposal records: one lane per row runs Vose's alias construction in index order, in
+// double precision, with the row's stretch of the scratch arrays as its two stacks.
+__global__ void __launch_bounds__(kBlock) build_alias_kernel(const int64_t *row_ptr, const int32_t *col,
+                                                             const float *h, const uint8_t *label, int64_t nv,
+                                                             double *sc, int32_t *stk_s, int32_t *stk_l,
+                                                             int32_t *alias, uint4 *prop)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += stride) {
+        const int64_t b = row_ptr[v];
+        const int32_t n = (int32_t)(row_ptr[v + 1] - b);
+        if (n == 0) continue;
+        double H = 0.0;
+        for (int32_t k = 0; k < n; ++k) H += h ? (double)h[b + k] : 1.0;
+        int32_t ns = 0, nl = 0;
+        for (int32_t k = 0; k < n; ++k) {
+            alias[b + k] = k;
+            const double x = H > 0.0 ? ((h ? (double)h[b + k] : 1.0) * (double)n) / H : 1.0;
+            sc[b + k] = x;
+            if (x < 1.0) stk_s[b + ns++] = k;
+            else stk_l[b + nl++] = k;
+        }
+        while (ns > 0 && nl > 0) {
+            const int32_t s = stk_s[b + --ns], l = stk_l[b + --nl];
+            alias[b + s] = l;
+            const double x = (sc[b + l] + sc[b + s]) - 1.0;
+            sc[b + l] = x;
+            if (x < 1.0) stk_s[b + ns++] = l;
+            else stk_l[b + nl++] = l;
+        }
+        for (int32_t k = 0; k < n; ++k) {
+            const int32_t al = alias[b + k];
+            const double p = al != k ? sc[b + k] : 1.0;  // paired slots keep their scaled weight
+            const double t = floor(p * 4294967296.0);
+            const uint32_t thr = t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
+            const uint32_t hk = h ? __float_as_uint(h[b + k]) : __float_as_uint(1.0f);
+            const uint32_t ha = h ? __float_as_uint(h[b + al]) : __float_as_uint(1.0f);
+            const uint32_t lab = label ? ((uint32_t)label[b + k] | ((uint32_t)label[b + al] << 8)) : 0u;
+            prop[2 * (b + k)] = make_uint4((uint32_t)col[b + k], hk, (uint32_t)col[b + al], ha);
+            prop[2 * (b + k) + 1] = make_uint4(thr, lab, 0u, 0u);
+        }
+    }
 }
 
 // Edge index build: one wave per row, each lane inserts its entries' keys with a 64-bit
@@ -932,6 +1000,18 @@ hipError_t launch_validate_edges(const int64_t *row_ptr, const int32_t *col, con
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(validate_edges_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, nv, err,
                        max_deg);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
+                              int64_t nv, double *sc, int32_t *stk_s, int32_t *stk_l, int32_t *alias, uint4 *prop,
+                              hipStream_t s)
+{
+    int64_t blocks = (nv + kBlock - 1) / kBlock;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(build_alias_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, label, nv,
+                       sc, stk_s, stk_l, alias, prop);
     return hipGetLastError();
 }
 

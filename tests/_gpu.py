@@ -12,7 +12,8 @@ MARGIN = 1e-6  # a float decision within this relative gap is a flagged boundary
 
 
 class GpuGraph:
-    def __init__(self, g: dict, on_device: bool = True, preprocess: bool = True, index: bool = False):
+    def __init__(self, g: dict, on_device: bool = True, preprocess: bool = True, index: bool = False,
+                 alias: bool = False):
         self.g = g
         self.nv, self.ne = int(g["nv"]), int(g["ne"])
         dev = torch.device("cuda:0")
@@ -30,6 +31,8 @@ class GpuGraph:
             fw.fw_graph_preprocess(self.handle)
         if index:
             fw.fw_graph_build_index(self.handle)
+        if alias:
+            fw.fw_graph_build_alias(self.handle)
         torch.cuda.synchronize()
 
     def close(self):
@@ -55,7 +58,8 @@ def fw_logic(lg: oracle.Logic):
 
 def fw_plan(pl: oracle.Plan, **speed):
     assert pl.lanes == 64 and pl.jump and pl.bound_scale == 1.0
-    return fw.fw_plan_default(rho=pl.rho, d_lo=pl.d_lo, rjs_cap=pl.rjs_cap, bound=pl.bound, **speed)
+    return fw.fw_plan_default(rho=pl.rho, d_lo=pl.d_lo, rjs_cap=pl.rjs_cap, bound=pl.bound, proposal=pl.proposal,
+                              **speed)
 
 
 def gpu_walk(gg: GpuGraph, lg: oracle.Logic, pl: oracle.Plan, strategy: int, starts: np.ndarray, L: int,

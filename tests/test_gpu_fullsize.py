@@ -33,7 +33,7 @@ def g22():
 
 @pytest.fixture(scope="module")
 def gg22(g22):
-    gg = GpuGraph(g22, index=True)  # as the benchmark runs it
+    gg = GpuGraph(g22, index=True, alias=True)  # as the benchmark runs it
     yield gg
     gg.close()
 
@@ -54,16 +54,17 @@ def _sample(n, k, seed):
     return np.sort(np.random.default_rng(seed).choice(n, size=min(k, n), replace=False)).astype(np.int64)
 
 
-@pytest.mark.parametrize("strategy,k,bound", [(oracle.AUTO, 65536, None), (oracle.RJS_ONLY, 65536, None),
-                                             (oracle.RVS_ONLY, 1024, None), (oracle.AUTO, 65536, 0),
-                                             (oracle.AUTO, 65536, 1), (oracle.RJS_ONLY, 65536, 1)],
-                         ids=["auto", "rjs", "rvs", "auto_paper_bound", "auto_split_bound", "rjs_split_bound"])
-def test_node2vec_scale22(g22, gg22, og22, tuned22, strategy, k, bound):
-    """bound None: the autotuned plan as the benchmark runs it; 0 / 1: that plan with
-    the paper's bound or the split bound forced."""
+@pytest.mark.parametrize("strategy,k,bound,proposal", [
+    (oracle.AUTO, 65536, None, None), (oracle.RJS_ONLY, 65536, None, None), (oracle.RVS_ONLY, 1024, None, None),
+    (oracle.AUTO, 65536, 0, 0), (oracle.AUTO, 65536, 1, 0), (oracle.RJS_ONLY, 65536, 1, 1)],
+    ids=["auto", "rjs", "rvs", "auto_paper", "auto_split_uniform", "rjs_split_h_proposals"])
+def test_node2vec_scale22(g22, gg22, og22, tuned22, strategy, k, bound, proposal):
+    """None: the autotuned plan as the benchmark runs it; otherwise that plan with the
+    bound (paper's / split) and the proposal (uniform / h-proportional) forced."""
     tuned = tuned22
     pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap,
-                     bound=tuned.bound if bound is None else bound, member_index=True)
+                     bound=tuned.bound if bound is None else bound,
+                     proposal=tuned.proposal if proposal is None else proposal, member_index=True)
     starts = synth.all_vertices(g22["nv"])
     p, ln, st = gpu_walk(gg22, N2V, pl, strategy, starts, 80, 42)
     ok, pad_ok, _ = edge_check_torch(g22, p, ln)
@@ -102,7 +103,7 @@ def test_batched_scale24():
     5..200) on the skewed scale-24 R-MAT in one launch; 32 queries replayed by the oracle
     on up to 256 walkers each, and every walk of 256 queries checked to follow edges."""
     g = synth.cached("rmat24_skew")
-    gg = GpuGraph(g, index=True)
+    gg = GpuGraph(g, index=True, alias=True)
     try:
         qd = synth.batch_queries(g["nv"], 4096, 7)
         dev = torch.device("cuda:0")
@@ -112,7 +113,7 @@ def test_batched_scale24():
         stats = torch.zeros(fw.FW_NSTATS, dtype=torch.int64, device=dev)
         tuned = fw.fw_plan_autotune(gg.handle, fw.fw_logic_node2vec(1.0, 1.0, True))
         pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap, bound=tuned.bound,
-                         member_index=True)
+                         proposal=tuned.proposal, member_index=True)
         qs = []
         for i in range(4096):
             q = fw.fw_query()

@@ -472,3 +472,84 @@ def test_skewed_weights_scale12(g12, strategy, weights):
             _assert_counters(st, ora)
     finally:
         gg.close()
+
+
+# ------------------------------------------------------------------ h-proportional proposals
+@pytest.fixture(scope="module")
+def ga12(g12):
+    gg = GpuGraph(g12, index=True, alias=True)
+    yield gg
+    gg.close()
+
+
+HP_LOGICS = {"n2v": N2V, "n2v_ret": N2V_RET, "2ndpr": PR2, "metapath": MP,
+             "n2v_unweighted": oracle.Logic(kind=oracle.NODE2VEC, weighted=False, p=0.25, q=2.0)}
+
+
+@pytest.mark.parametrize("strategy", ["auto", "rjs"])
+@pytest.mark.parametrize("bound", [0, 1])
+@pytest.mark.parametrize("logic", list(HP_LOGICS), ids=list(HP_LOGICS))
+def test_h_proposals_scale12(g12, ga12, strategy, bound, logic):
+    """plan.proposal = 1: alias-table proposals, the test on w; walks and counters equal
+    the oracle's (which builds its alias tables independently)."""
+    lg = HP_LOGICS[logic]
+    pl = oracle.Plan(rho=1.0, bound=bound if lg.kind == oracle.NODE2VEC else 0, proposal=1, rjs_cap=256,
+                     member_index=True)
+    starts = synth.all_vertices(g12["nv"])
+    p, ln, st, ora = _run_both(ga12, g12, lg, pl, STRATS[strategy], starts, 20, 31)
+    rep = parity(p, ln, ora)
+    assert_parity(rep)
+    if rep["mismatch_walkers"] == 0:
+        _assert_counters(st, ora)
+    assert st["rjs_steps"] > 0
+
+
+@pytest.mark.parametrize("weights", ["pareto1", "pareto2"])
+def test_h_proposals_skewed(g12, weights):
+    """Heavy-tailed weights, where uniform proposals need hundreds of trials per step."""
+    g = dict(g12)
+    g["h"] = synth.pareto_weights(g["row_ptr"], g["col"], float(weights[6:]), 7)
+    gg = GpuGraph(g, alias=True)
+    try:
+        starts = synth.all_vertices(g["nv"])
+        for prop in (0, 1):
+            pl = oracle.Plan(rho=1.0, proposal=prop, rjs_cap=4096)
+            p, ln, st, ora = _run_both(gg, g, N2V, pl, oracle.RJS_ONLY, starts, 12, 19)
+            rep = parity(p, ln, ora)
+            assert_parity(rep)
+            if rep["mismatch_walkers"] == 0:
+                _assert_counters(st, ora)
+            if prop == 0:
+                uniform_trials = st["rjs_trials"]
+        assert st["rjs_trials"] < 0.1 * uniform_trials
+    finally:
+        gg.close()
+
+
+def test_h_proposals_chisquare_hub():
+    g = hub_ring_graph(600)
+    gg = GpuGraph(g, alias=True)
+    try:
+        n = 300000
+        p, ln, st = gpu_walk(gg, N2V_RET, oracle.Plan(rho=1.0, bound=1, proposal=1), oracle.RJS_ONLY,
+                             np.ones(n, np.int32), 2, 43)
+    finally:
+        gg.close()
+    at_hub = p[:, 1] == 0
+    counts = {int(v): int(c) for v, c in zip(*np.unique(p[at_hub, 2], return_counts=True))}
+    assert chisq_pvalue(counts, exact.transition(g, N2V_RET, 1, 1, 0), int(at_hub.sum())) > 1e-3
+
+
+def test_h_proposals_need_alias(g12, gg12):
+    dev = torch.device("cuda:0")
+    s = torch.zeros(4, dtype=torch.int32, device=dev)
+    out = torch.zeros(4 * 6, dtype=torch.int32, device=dev)
+    ln = torch.zeros(4, dtype=torch.int32, device=dev)
+    with pytest.raises(fw.FlexiWalkError) as e:
+        fw.fw_walk(gg12.handle, fw.fw_logic_node2vec(0.5, 2.0, True), fw.fw_plan_default(proposal=1), 0, s, 4, 5, 1,
+                   out, ln)
+    assert e.value.code == fw.FW_E_STATE
+    # unweighted logics ignore it
+    fw.fw_walk(gg12.handle, fw.fw_logic_node2vec(0.5, 2.0, False), fw.fw_plan_default(proposal=1), 0, s, 4, 5, 1,
+               out, ln)
+    torch.cuda.synchronize()

@@ -191,3 +191,28 @@ def test_split_bound_resume(g12, gg12, tick_steps):
         np.testing.assert_array_equal(p, alone[0], err_msg=f"request {k}")
         np.testing.assert_array_equal(ln, alone[1], err_msg=f"request {k}")
         assert_parity(parity(p, ln, oracle.walk(og, lg, pl, oracle.AUTO, st, L, seed)))
+
+
+def test_h_proposals_served(g12):
+    """Served walks under h-proportional proposals and the split bound, suspended every
+    3 steps, equal the same walks run alone."""
+    gg = GpuGraph(g12, index=True, alias=True)
+    pl = oracle.Plan(rho=1.0, rjs_cap=64, bound=1, proposal=1)
+    rng = np.random.default_rng(9)
+    reqs = [(oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=float(rng.choice([0.25, 2.0])), q=2.0),
+             rng.integers(0, g12["nv"], int(rng.integers(1, 300))).astype(np.int32), int(rng.integers(1, 25)), 700 + i)
+            for i in range(10)]
+    srv = fw.fw_server_create(gg.handle, fw.fw_plan_default(rho=pl.rho, rjs_cap=pl.rjs_cap, bound=1, proposal=1),
+                              fw.FW_AUTO, 64 << 20, tick_steps=3, max_active=8)
+    try:
+        results = _serve_all(srv, reqs)
+    finally:
+        fw.fw_server_destroy(srv)
+    try:
+        for k, (lg, st, L, seed) in enumerate(reqs):
+            p, ln, _ = results[k]
+            alone = gpu_walk(gg, lg, pl, oracle.AUTO, st, L, seed)
+            np.testing.assert_array_equal(p, alone[0], err_msg=f"request {k}")
+            np.testing.assert_array_equal(ln, alone[1], err_msg=f"request {k}")
+    finally:
+        gg.close()
