@@ -132,8 +132,8 @@ def main():
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}))
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "walkers shard across GPUs with no exchange, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): walkers are independent, so a "
+              "multi-GPU run is this job on each GPU's share of the walkers with no exchange", file=sys.stderr)
         sys.exit(2)
 
     import torch
