@@ -30,6 +30,13 @@
  *     w(u) / W for W >= every workload weight; the mass of u is then h * w / (W * sum h),
  *     proportional to w~, so the distribution is unchanged and the expected trials drop
  *     from deg * max(w) * h_MAX / S to W * sum h / S;
+ *   - optional member board (plan.bound = 2, not in the paper) for logics whose weight is
+ *     larger on N(v') than off it (Node2Vec with q > 1, second-order PageRank with g > 0):
+ *     regular columns at the lower weight w_oth take every proposal (members included),
+ *     a member region of area (w_mem - w_oth) * h_MAX * d(v') picks a neighbour x of v'
+ *     uniformly and keeps it when x is in N(v) with probability h(v,x) / h_MAX, so each
+ *     member gets the extra mass (w_mem - w_oth) * h(v,x); the return edge keeps its own
+ *     column.  Per step the smaller of this board and the split/plain board is used;
  *   - optional split bound for Node2Vec (plan.bound = 1, not in the paper; any bound
  *     that dominates w~ keeps rejection sampling exact, Section 3.3): the return edge
  *     is the only one weighted 1/p, so the proposal board is deg columns of height
@@ -56,7 +63,8 @@
  * the last neighbour in eRJS, 5 drops h_MAX from the eRJS bound, 6 makes the split
  * bound's extra column the full return weight instead of its excess over Bn, 7 divides
  * the second-order PageRank term g by d(v) instead of d(v'), 8 never takes an alias
- * table's alias (every slot keeps itself).
+ * table's alias (every slot keeps itself), 9 lets the member region keep a member without
+ * its h(v, x) / h_MAX test.
  */
 #ifndef OG_MUTANT
 #define OG_MUTANT 0
@@ -139,10 +147,12 @@ typedef struct {
     int32_t lanes;       /* eRVS lanes P */
     int32_t jump;        /* 1: Eq. (jump); 0: a key for every item */
     float bound_scale;   /* multiplies the eRJS bound (>= 1 keeps it a bound) */
-    int32_t bound;       /* 0: max(w) * h_MAX (Section 3.3); 1: Node2Vec split bound */
+    int32_t bound;       /* 0: max(w) * h_MAX (Section 3.3); 1: Node2Vec split bound; 2: split and
+                            member board, the smaller per step */
     int32_t proposal;    /* 0: uniform eRJS proposals (Section 3.3); 1: proportional to h */
-    int32_t member_index; /* byte accounting only: an eRJS membership test reads one 8-byte
-                             key of an edge index (1) or binary-searches the sorted row (0);
+    int32_t member_index; /* byte accounting only: an eRJS membership test reads one 8-byte key
+                             of an edge index (1), a member-region test its key and its 4-byte h,
+                             or each binary-searches the sorted row (0);
                              eRVS always searches the row (all its tests share N(prev)) */
 } og_plan;
 
@@ -464,6 +474,63 @@ static int64_t rjs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
     return -2;
 }
 
+/* Offset of u in the sorted row of v, or -1. */
+static int64_t row_find(const og_graph *g, int32_t v, int32_t u)
+{
+    int64_t b = g->row_ptr[v], n = g->row_ptr[v + 1] - b;
+    const int32_t *p = n > 0 ? (const int32_t *)bsearch(&u, g->col + b, (size_t)n, sizeof(int32_t), cmp_i32) : NULL;
+    return p ? (int64_t)(p - (g->col + b)) : -1;
+}
+
+/* eRJS on the member board (plan.bound = 2).  z = U(x3) * A picks the return column
+ * [0, E), the member region [E, E + R) or the regular columns; a member-region trial takes
+ * x = N(v')[floor(R64 * d(v') / 2^64)] and keeps it iff x != v', x in N(v) and
+ * U(x2) * h_MAX < h(v, x); a regular trial proposes as usual (uniform or h-proportional)
+ * and keeps u with min(w_u, w_oth) / w_oth of the usual test, members counted at w_oth. */
+static int64_t rjs_sample_member(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, int64_t base,
+                                 int64_t deg, int64_t dvp, float woth, float wret, float hm, float E, float R,
+                                 float area, int64_t ret, int hprop, og_info *info)
+{
+    const og_graph *g = cx->g;
+    const int64_t pbase = g->row_ptr[prev];
+    uint32_t x[4];
+    const float zm = E + R;
+    for (int t = 0; t < cx->pl->rjs_cap; ++t) {
+        draw(cx->seed, w, (uint32_t)j, (uint32_t)t, 0, x);
+        info->trials++;
+        const float z = og_uniform(x[3]) * area;
+        if (E > 0.0f) {
+            note_margin(info, z, E);
+            if (z < E) return ret;
+        }
+        const uint64_t R64 = ((uint64_t)x[1] << 32) | x[0];
+        note_margin(info, z, zm);
+        if (z < zm) {
+            const int32_t xv = g->col[pbase + (int64_t)(((unsigned __int128)R64 * (unsigned __int128)(uint64_t)dvp) >> 64)];
+            info->bytes += 4.0 + (cx->pl->member_index ? 12.0 : 4.0 * ceil_log2_plus1(deg));
+            if (xv == prev) continue;
+            const int64_t pos = row_find(g, cur, xv);
+            if (pos < 0) continue;
+            const float hx = (cx->lg->weighted && g->h) ? g->h[base + pos] : 1.0f;
+            const float y = og_uniform(x[2]) * hm;
+            if (y < hx || OG_MUTANT == 9) return pos;
+            continue;
+        }
+        const unsigned __int128 P = (unsigned __int128)R64 * (unsigned __int128)(uint64_t)deg;
+        int64_t idx = (int64_t)(P >> 64);
+        if (hprop) {
+            const uint32_t f = (uint32_t)((uint64_t)P >> 32);
+            if (!(f < g->alias_thr[base + idx])) idx = g->alias_idx[base + idx];
+        }
+        info->bytes += bytes_per_item(cx) + (hprop ? 12.0 : 0.0);
+        const float wu = g->col[base + idx] == prev ? fminf(wret, woth) : woth;
+        const float hu = (!hprop && cx->lg->weighted && g->h) ? g->h[base + idx] : 1.0f;
+        const float y = og_uniform(x[2]) * (hprop ? woth : woth * hm);
+        if (y < wu * hu) return idx;
+    }
+    return -2;
+}
+
 /* Inverse transform sampling over the exact weights (plain CPU sampler). */
 static int64_t its_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int64_t base, int64_t deg,
                           int64_t dvp, og_info *info)
@@ -520,7 +587,7 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
 
     /* split bound: regular height over the non-return weights, extra column for the
        return edge's excess (w~ret of the edge cur -> prev, 0 if there is none) */
-    const int split = cx->pl->bound == 1 && lg->kind == OG_NODE2VEC && j > 0;
+    const int split = (cx->pl->bound == 1 || cx->pl->bound == 2) && lg->kind == OG_NODE2VEC && j > 0;
     float E = 0.0f;
     int64_t ret = -1;
     if (split) {
@@ -536,7 +603,38 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
     }
     /* area of the proposal board: deg columns of height B (uniform) or total width
        sum h = h_SUM at height B (h-proportional), plus the return edge's extra column */
-    const float area = hprop ? B * hs + E : (float)deg * B + E;
+    float area = hprop ? B * hs + E : (float)deg * B + E;
+
+    /* member board: w_mem on N(v') above w_oth elsewhere; used when its area is smaller */
+    int member = 0;
+    float woth = 0.0f, wmem = 0.0f, wret = 0.0f, Em = 0.0f, Rm = 0.0f;
+    if (cx->pl->bound == 2 && j > 0 && dvp > 0 && (lg->kind == OG_NODE2VEC || lg->kind == OG_SECOND_PR)) {
+        if (lg->kind == OG_NODE2VEC) {
+            woth = 1.0f / lg->q;
+            wmem = 1.0f;
+            wret = 1.0f / lg->p;
+        } else {
+            second_pr_weights(lg, deg, dvp, &wmem, &woth);
+            wret = woth;
+        }
+        if (wmem > woth) {
+            const float hmx = weighted ? cx->hmax[cur] : 1.0f;
+            const float areg = hprop ? woth * hs : ((float)deg * woth) * hmx;
+            Rm = ((wmem - woth) * hmx) * (float)dvp;
+            if (lg->kind == OG_NODE2VEC && ret < 0)
+                for (int64_t i = 0; i < deg; ++i)
+                    if (g->col[base + i] == prev) ret = i;
+            if (lg->kind == OG_NODE2VEC && ret >= 0) {
+                const float hr = weighted ? g->h[base + ret] : 1.0f;
+                Em = fmaxf(0.0f, transition_weight(cx, base + ret, j, prev, deg, dvp) - woth * hr);
+            }
+            const float am = (areg + Rm) + Em;
+            if (am < area) {
+                member = 1;
+                area = am;
+            }
+        }
+    }
 
     int use_rjs = 0;
     if (cx->strategy == OG_RJS_ONLY) {
@@ -547,7 +645,7 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
         if (deg >= cx->pl->d_lo) {
             /* Eq. (runtime) per edge; with the split or h-proportional proposals the
                expected-trial cost is area / S, compared against the eRVS cost deg */
-            const int board = split || hprop;
+            const int board = split || hprop || member;
             float lhs = board ? cx->pl->rho * area : cx->pl->rho * B;
             float rhs = board ? (float)deg * Shat : Shat;
             note_margin(info, lhs, rhs);
@@ -571,7 +669,9 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
         off = -2;
         /* h-proportional proposals need some positive h; a row without goes to eRVS */
         if (use_rjs && !(hprop && !(hs > 0.0f))) {
-            off = rjs_sample(cx, w, j, prev, base, deg, dvp, B, E, ret, area, hprop, info);
+            off = member ? rjs_sample_member(cx, w, j, prev, cur, base, deg, dvp, woth, wret,
+                                             weighted ? cx->hmax[cur] : 1.0f, Em, Rm, area, ret, hprop, info)
+                         : rjs_sample(cx, w, j, prev, base, deg, dvp, B, E, ret, area, hprop, info);
             info->kind = 1;
         }
         if (off == -2) {

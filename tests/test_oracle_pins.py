@@ -463,6 +463,79 @@ def test_h_proposals_mean_trials():
         assert abs(trials.mean() - want) < 5 * se + 1e-9, (plan.bound, trials.mean(), want)
 
 
+# ------------------------------------------------------------------ member board (plan.bound = 2)
+MB = [("rjs", oracle.RJS_ONLY, oracle.Plan(bound=2)),
+      ("rjs_h", oracle.RJS_ONLY, oracle.Plan(bound=2, proposal=1)),
+      ("auto_h", oracle.AUTO, oracle.Plan(bound=2, proposal=1, rho=1.0, lanes=2)),
+      ("rjs_cap1", oracle.RJS_ONLY, oracle.Plan(bound=2, rjs_cap=1, lanes=2))]
+
+
+@pytest.mark.parametrize("name,strategy,plan", MB, ids=[s[0] for s in MB])
+@pytest.mark.parametrize("logic", [dict(kind=oracle.NODE2VEC, weighted=True, p=0.25, q=2.0),
+                                   dict(kind=oracle.NODE2VEC, weighted=True, p=4.0, q=2.0),
+                                   dict(kind=oracle.NODE2VEC, weighted=False, p=1.0, q=4.0), PR2,
+                                   dict(PR2, gamma=0.7), dict(kind=oracle.NODE2VEC, weighted=True, p=2.0, q=0.5)],
+                         ids=["n2v_ret", "n2v_p4", "n2v_unweighted", "2ndpr", "2ndpr_g07", "n2v_q05"])
+def test_member_board_paths_chisquare(name, strategy, plan, logic):
+    """The member board keeps the exact distribution: every proposal in the regular
+    columns is taken at the lower weight, members get their excess from the member region
+    and the return edge from its column (q <= 1 falls back to the split board)."""
+    g = triangle_graph()
+    lg = oracle.Logic(**logic)
+    n = 60000
+    for start in (0, 4):
+        counts, _ = _walk_counts(g, lg, plan, strategy, start, 3, n, seed=71 + start)
+        assert chisq_pvalue(counts, exact.path_distribution(g, lg, start, 3), n) > P_OK, (name, start)
+
+
+def test_member_board_hub():
+    g = hub_ring_graph(600)
+    og = oracle.Graph(g)
+    n = 40000
+    for logic in (N2V_RET, PR2):
+        lg = oracle.Logic(**logic)
+        for prop in (0, 1):
+            r = oracle.walk(og, lg, oracle.Plan(bound=2, proposal=prop), oracle.RJS_ONLY, np.full(n, 1, np.int32), 2,
+                            5, diagnostics=False)
+            at_hub = r.paths[:, 1] == 0
+            counts = {int(v): int(c) for v, c in zip(*np.unique(r.paths[at_hub, 2], return_counts=True))}
+            assert chisq_pvalue(counts, exact.transition(g, lg, 1, 1, 0), int(at_hub.sum())) > P_OK, (logic, prop)
+
+
+def test_member_board_mean_trials():
+    """Fan graph: v = 0 joined to 1..6 with h(0, u) = u, v' = 1 joined to 0 and 2.
+    Second-order PageRank with gamma = 1/4 at d(v) = 6, d(v') = 2: w_in = 3/2, w_out = 3/4,
+    one member (vertex 2), sum w~ = (3/4) * 21 + (3/4) * 2 = 69/4, h_MAX = 6.
+    h-proportional: regular area (3/4) * 21 plus member region (3/4) * 6 * 2 = 99/4, so
+    33/23 trials per step (the single-bound board, (3/2) * 21, would take 42/23);
+    uniform: 6 * (3/4) * 6 + 9 = 36, 48/23 trials (single bound 54, 72/23)."""
+    g = synth.csr_from_edges(7, [(0, 1), (0, 2), (0, 3), (0, 4), (0, 5), (0, 6), (1, 2)],
+                             h=[1, 2, 3, 4, 5, 6, 1])
+    lg = oracle.Logic(**PR2)
+    og = oracle.Graph(g)
+    n = 40000
+    for bound, prop, want in ((2, 1, 33.0 / 23.0), (2, 0, 48.0 / 23.0), (0, 1, 42.0 / 23.0), (0, 0, 72.0 / 23.0)):
+        plan = oracle.Plan(bound=bound, proposal=prop, rjs_cap=100000)
+        trials = np.array([oracle.step_once(og, lg, plan, oracle.RJS_ONLY, 3, i, 1, 1, 0)[3] for i in range(n)],
+                          dtype=np.float64)
+        se = math.sqrt(want * (want - 1) / n)
+        assert abs(trials.mean() - want) < 5 * se, (bound, prop, trials.mean(), want)
+
+
+def test_member_board_fewer_trials_second_pr():
+    """On a skewed graph second-order PageRank's bound (the larger branch) is loose when
+    d(v) >> d(v'); the member board's area does not grow with d(v) / d(v')."""
+    g = synth.rmat(12, 8 << 12, seed=2)
+    og = oracle.Graph(g)
+    lg = oracle.Logic(**PR2)
+    st = np.arange(g["nv"], dtype=np.int32)
+    a = oracle.walk(og, lg, oracle.Plan(proposal=1, rjs_cap=1 << 20), oracle.RJS_ONLY, st, 20, 9, diagnostics=False)
+    b = oracle.walk(og, lg, oracle.Plan(proposal=1, bound=2, rjs_cap=1 << 20), oracle.RJS_ONLY, st, 20, 9,
+                    diagnostics=False)
+    ta, tb = (x.counters["rjs_trials"] / x.counters["steps"] for x in (a, b))
+    assert tb < 0.4 * ta and tb < 2.0, (ta, tb)
+
+
 # ------------------------------------------------------------------ comparison selection policies
 @pytest.mark.parametrize("strategy", [oracle.RANDOM_SELECT, oracle.DEGREE_SELECT], ids=["random", "degree"])
 @pytest.mark.parametrize("logic", [N2V, PR2], ids=["node2vec", "2ndpr"])
@@ -567,6 +640,7 @@ MUTANTS = {
     6: "split bound's extra column is the whole return weight",
     7: "second-order PageRank divides gamma by d(v) instead of d(v')",
     8: "alias tables never take the alias",
+    9: "member region keeps a member without its h test",
 }
 
 
@@ -587,7 +661,8 @@ def test_planted_mistake_is_caught(mut, mutant_libs):
                                             ("rjs_split", N2V_RET, oracle.RJS_ONLY, oracle.Plan(bound=1)),
                                             ("rjs_2ndpr", PR2, oracle.RJS_ONLY, oracle.Plan()),
                                             ("rvs_2ndpr", PR2, oracle.RVS_ONLY, oracle.Plan(lanes=2)),
-                                            ("rjs_hprop", N2V, oracle.RJS_ONLY, oracle.Plan(proposal=1))):
+                                            ("rjs_hprop", N2V, oracle.RJS_ONLY, oracle.Plan(proposal=1)),
+                                            ("rjs_member", PR2, oracle.RJS_ONLY, oracle.Plan(bound=2))):
             lg = oracle.Logic(**logic)
             n = 60000
             counts, _ = _walk_counts(g, lg, plan, strategy, 0, 3, n, seed=7)
