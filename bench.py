@@ -223,13 +223,16 @@ def main():
     if args.modes:
         # own output buffers: the timed job's walks stay for the CPU comparison below
         m_paths, m_lengths = torch.empty_like(paths), torch.empty_like(lengths)
-        # the single-kernel modes, and the same job under the other eRJS bound
-        other = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap, bound=1 - plan.bound,
-                                   proposal=plan.proposal)
+        # the single-kernel modes, and the same job under the other eRJS bounds the logic
+        # and graph allow (Node2Vec's split bound and member board need a symmetric graph)
         sym = fw.fw_graph_info(gh)[3]
         cases = [(m + "_only", m, plan) for m in ("rvs", "rjs") if m != args.strategy]
-        if args.logic == "node2vec" and (sym or other.bound == 0):
-            cases.append((("split" if other.bound else "paper") + "_bound", args.strategy, other))
+        bounds = [0, 1, 2] if (args.logic == "node2vec" and sym) else ([0] if args.logic == "node2vec" else [0, 2])
+        for b in bounds:
+            if b != plan.bound:
+                other = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap, bound=b,
+                                           proposal=plan.proposal)
+                cases.append((("paper_bound", "split_bound", "member_board")[b], args.strategy, other))
         flip = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap, bound=plan.bound,
                                   proposal=1 - plan.proposal)
         cases.append((("h" if flip.proposal else "uniform") + "_proposals", args.strategy, flip))

@@ -114,7 +114,17 @@ typedef struct fw_logic {
  *               expected trials drop from deg * B / S to W * h_SUM / S.  Applies to
  *               weighted logics; a row whose h are all zero goes to eRVS.  With
  *               bound = 1 the return edge's extra column is (1/p - W) * h(v, prev) wide.
- *            The cost model compares rho * (board area) with deg * S^ for 1 (and bound 1). */
+ *            The cost model compares rho * (board area) with deg * S^ for 1 (and bound 1).
+ *            2  member board (extension of Section 3.3), Node2Vec with q > 1 and
+ *               second-order PageRank with gamma > 0, where members of N(prev) weigh
+ *               w_mem above everyone else's w_oth: regular columns at w_oth take every
+ *               proposal (no membership test; the return edge at min(w_ret, w_oth)),
+ *               the return edge keeps an extra column (w_ret - w_oth) * h(v, prev), and
+ *               a member region of area (w_mem - w_oth) * h_MAX * d(prev) proposes a
+ *               neighbour x of prev uniformly and keeps it when (v, x) is an edge, with
+ *               probability h(v, x) / h_MAX (the edge index, else a search of v's row,
+ *               finds it).  Per step the smaller of this board and bound 1's (Node2Vec)
+ *               or bound 0's is used.  Node2Vec needs a symmetric graph as for 1. */
 typedef struct fw_plan {
     float rho;
     int32_t d_lo;
@@ -153,13 +163,15 @@ int fw_graph_preprocess(fw_graph *g, void *stream);
 /* Copy h_MAX and h_SUM (nv floats each, host pointers) back to the host; synchronous. */
 int fw_graph_export_aux(const fw_graph *g, float *hmax, float *hsum);
 
-/* Build the edge index: an exact hash set of the entries (v, u) (64-byte buckets of eight
- * 64-bit keys, at most half full; 16 bytes of device memory per entry, rounded up to a
- * power-of-two bucket count).  The membership test u in N(prev) of an eRJS proposal
- * (Node2Vec, second-order PageRank) then reads one bucket instead of searching prev's
- * sorted row; eRVS steps keep searching the row, which all lanes of the step share.
- * Samples and counts of eRJS trials do not change (the algorithmic-byte counter charges
- * 8 bytes per eRJS test instead of a binary search's).  Asynchronous on `stream`; idempotent.  Walks, batches and servers created
+/* Build the edge index: an exact hash map of the entries (v, u) to h(v, u) (128-byte
+ * buckets of eight 64-bit keys and their eight float h, at most half full; 32 bytes of
+ * device memory per entry, rounded up to a power-of-two bucket count).  The membership
+ * test u in N(prev) of an eRJS proposal (Node2Vec, second-order PageRank) then reads one
+ * bucket instead of searching prev's sorted row, and so does a member-board trial's
+ * lookup of (cur, x) with its h; eRVS steps keep searching the row, which all lanes of the
+ * step share.  Samples and counts of eRJS trials do not change (the algorithmic-byte
+ * counter charges 8 bytes per membership test and 12 per member lookup instead of a
+ * binary search's).  Asynchronous on `stream`; idempotent.  Walks, batches and servers created
  * afterwards use it; build it before creating batches or servers.  Returns FW_E_NOMEM if
  * the table cannot be allocated (the graph stays usable without it). */
 int fw_graph_build_index(fw_graph *g, void *stream);
@@ -207,9 +219,10 @@ int fw_plan_default(fw_plan *out);
  * the graph must be preprocessed for a weighted logic. */
 int fw_plan_profile(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stream);
 
-/* fw_plan_profile, then a measured search: short seeded sample walks (up to 2^18 walkers,
+/* fw_plan_profile, then a measured search: short seeded sample walks (up to 2^20 walkers,
  * 16 steps, AUTO) are timed for rho scaled by 1/16 .. 4 around the profiled value (with
- * each eRJS bound: the split bound too for Node2Vec on a symmetric graph; and each
+ * each eRJS bound: the split bound and the member board too for Node2Vec on a symmetric
+ * graph, the member board for second-order PageRank; and each
  * proposal: h-proportional too for a weighted logic once fw_graph_build_alias ran), then for the
  * degree gate d_lo in {0, 8, 32, 128} and the LDS budget for N(prev); the fastest plan
  * is returned.  Every candidate samples the same distribution; only the choice of kernel

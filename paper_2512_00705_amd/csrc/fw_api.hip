@@ -180,16 +180,16 @@ int fw_graph_build_index(fw_graph *g, void *stream)
     if (!g) return fail(FW_E_INVALID, "fw_graph_build_index: null graph");
     if (g->mtab) return ok();
     HIP_TRY(hipSetDevice(g->device));
-    // power-of-two bucket count with at least 16 slots per 8 keys (load <= 1/2)
+    // power-of-two count of 128-byte buckets with at least 16 slots per 8 keys (load <= 1/2)
     uint64_t buckets = 1;
     while (buckets * 8 < 2 * (uint64_t)g->ne) buckets <<= 1;
     unsigned long long *tab = nullptr;
-    if (hipMalloc((void **)&tab, buckets * 64) != hipSuccess)
+    if (hipMalloc((void **)&tab, buckets * 128) != hipSuccess)
         return fail(FW_E_NOMEM, "fw_graph_build_index: hipMalloc of %llu bytes failed",
-                    (unsigned long long)(buckets * 64));
+                    (unsigned long long)(buckets * 128));
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMemsetAsync(tab, 0xFF, buckets * 64, s);  // every slot kEmptyKey
-    if (e == hipSuccess) e = fw::launch_build_index(g->row_ptr, g->col, g->nv, tab, buckets - 1, s);
+    hipError_t e = hipMemsetAsync(tab, 0xFF, buckets * 128, s);  // every key kEmptyKey
+    if (e == hipSuccess) e = fw::launch_build_index(g->row_ptr, g->col, g->h, g->nv, tab, buckets - 1, s);
     if (e != hipSuccess) {
         (void)hipFree(tab);
         return fail(FW_E_DEVICE, "fw_graph_build_index: %s", hipGetErrorString(e));
@@ -349,7 +349,7 @@ int fw::host::check_plan(const fw_plan *pl)
     if (pl->lds_cap < 0 || pl->lds_cap > fw::kMaxLdsCap)
         return fail(FW_E_INVALID, "plan.lds_cap in [0, %d]", fw::kMaxLdsCap);
     if (pl->grid < 0) return fail(FW_E_INVALID, "plan.grid must be >= 0");
-    if (pl->bound < 0 || pl->bound > 1) return fail(FW_E_INVALID, "plan.bound must be 0 or 1");
+    if (pl->bound < 0 || pl->bound > 2) return fail(FW_E_INVALID, "plan.bound must be 0, 1 or 2");
     if (pl->proposal < 0 || pl->proposal > 1) return fail(FW_E_INVALID, "plan.proposal must be 0 or 1");
     return FW_OK;
 }
@@ -358,8 +358,9 @@ int fw::host::check_bound(const fw_graph *g, const fw_plan *pl, const fw_logic *
 {
     if (pl->proposal == 1 && lg->weighted && g->h && !g->prop)
         return fail(FW_E_STATE, "plan.proposal = 1 needs fw_graph_build_alias first");
-    if (pl->bound == 1 && lg->kind == FW_NODE2VEC && !g->symmetric)
-        return fail(FW_E_INVALID, "plan.bound = 1 needs every edge's reverse with the same h (fw_graph_info)");
+    if (pl->bound >= 1 && lg->kind == FW_NODE2VEC && !g->symmetric)
+        return fail(FW_E_INVALID, "plan.bound = %d needs every edge's reverse with the same h (fw_graph_info)",
+                    (int)pl->bound);
     return FW_OK;
 }
 
@@ -569,9 +570,10 @@ int fw_plan_autotune(fw_graph *g, const fw_logic *lg, fw_plan *out, void *stream
     if (g->nv == 0 || g->ne == 0) return ok();
     hipStream_t s = (hipStream_t)stream;
 
-    // sample walks: seeded walkers spread over all vertices, as many as fill the device a
-    // few times, long enough for the walk's degree bias to set in
-    const int64_t n = std::min<int64_t>(g->nv, 1 << 18);
+    // sample walks: seeded walkers spread over all vertices, enough to keep the device busy
+    // for milliseconds per candidate (shorter runs time the launch and the tail), long
+    // enough for the walk's degree bias to set in
+    const int64_t n = std::min<int64_t>(g->nv, 1 << 20);
     const int32_t L = 16;
     std::vector<int32_t> starts((size_t)n);
     uint64_t x = 0x9E3779B97F4A7C15ull;
@@ -612,10 +614,20 @@ int fw_plan_autotune(fw_graph *g, const fw_logic *lg, fw_plan *out, void *stream
     float bestt = 1e30f;
     const float rho0 = out->rho;
     const float scales[] = {0.0625f, 0.25f, 0.5f, 1.0f, 2.0f, 4.0f};
-    const int nbound = (lg->kind == FW_NODE2VEC && g->symmetric) ? 2 : 1;
+    // bounds: 0 always; 1 and 2 for Node2Vec on a symmetric graph; 2 for second-order
+    // PageRank (bound 1 is the same board there)
+    int32_t bounds[3] = {0, 0, 0};
+    int nbound = 1;
+    if (lg->kind == FW_NODE2VEC && g->symmetric) {
+        bounds[nbound++] = 1;
+        bounds[nbound++] = 2;
+    } else if (lg->kind == FW_SECOND_PR) {
+        bounds[nbound++] = 2;
+    }
     const int nprop = (lg->weighted && g->h && g->prop) ? 2 : 1;
     for (int32_t prop = 0; prop < nprop; ++prop) {
-        for (int32_t bound = 0; bound < nbound; ++bound) {
+        for (int ib = 0; ib < nbound; ++ib) {
+            const int32_t bound = bounds[ib];
             for (float sc : scales) {
                 fw_plan p = *out;
                 p.rho = std::max(1e-3f, rho0 * sc);

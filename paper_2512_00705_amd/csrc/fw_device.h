@@ -173,12 +173,14 @@ __device__ __forceinline__ bool sorted_contains_interp(const int32_t *a, int32_t
     return false;
 }
 
-// Exact set of the graph's entries (v, u): open addressing over 64-byte buckets of eight
-// 64-bit keys v << 32 | u, the first bucket chosen by the SplitMix64 finaliser (Steele,
-// Lea, Flood, OOPSLA'14), then linear probing bucket by bucket.  At most half the slots
-// are used, so a query almost always reads one bucket: one memory request where a search
-// of the sorted row needs several dependent ones.
+// Exact map of the graph's entries (v, u) to their h: open addressing over 128-byte
+// buckets (one DRAM line) of eight 64-bit keys v << 32 | u followed by their eight h
+// values, the first bucket chosen by the SplitMix64 finaliser (Steele, Lea, Flood,
+// OOPSLA'14), then linear probing bucket by bucket.  At most half the slots are used, so
+// a query almost always reads one bucket: one memory request where a search of the
+// sorted row needs several dependent ones.
 constexpr unsigned long long kEmptyKey = ~0ull;
+constexpr int kIndexBucketU4 = 8;  // uint4 per bucket: keys in parts 0..3, h in parts 4..5
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z)
 {
@@ -192,29 +194,47 @@ __device__ __forceinline__ uint64_t edge_key(int32_t v, int32_t u)
     return ((uint64_t)(uint32_t)v << 32) | (uint64_t)(uint32_t)u;
 }
 
-// tab: 4 uint4 per bucket, mask = buckets - 1 (buckets a power of two).  The bucket's
-// four 16-byte parts are loaded before any is tested, so they go out together as one
-// 64-byte request instead of one dependent load after another.  Scans at most every
-// bucket once, so it ends even on a full table.
-__device__ __forceinline__ bool index_contains(const uint4 *tab, uint64_t mask, int32_t v, int32_t u)
+// tab: kIndexBucketU4 uint4 per bucket, mask = buckets - 1 (buckets a power of two).  The
+// key parts of a bucket are loaded before any is tested, so they go out together as one
+// request instead of one dependent load after another.  Scans at most every bucket
+// once, so it ends even on a full table.  Returns the slot of (v, u) in [0, 8), or -1.
+// With H the hit's h is read from the bucket's h part (the same DRAM line, so a cache
+// hit) and stored in *h.
+template <bool H>
+__device__ __forceinline__ int index_probe(const uint4 *tab, uint64_t mask, int32_t v, int32_t u, float *h)
 {
     const uint64_t key = edge_key(v, u);
     uint64_t b = mix64(key) & mask;
     for (uint64_t t = 0; t <= mask; ++t) {
-        const uint4 *p = tab + b * 4;
+        const uint4 *p = tab + b * kIndexBucketU4;
         const uint4 x[4] = {p[0], p[1], p[2], p[3]};
-        bool hit = false, empty = false;
+        int slot = -1;
+        bool empty = false;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const uint64_t k0 = ((uint64_t)x[i].y << 32) | x[i].x, k1 = ((uint64_t)x[i].w << 32) | x[i].z;
-            hit = hit || k0 == key || k1 == key;
+            slot = k0 == key ? 2 * i : (k1 == key ? 2 * i + 1 : slot);
             empty = empty || k0 == kEmptyKey || k1 == kEmptyKey;
         }
-        if (hit) return true;
-        if (empty) return false;
+        if (slot >= 0) {
+            if (H) *h = reinterpret_cast<const float *>(p + 4)[slot];
+            return slot;
+        }
+        if (empty) return -1;
         b = (b + 1) & mask;
     }
-    return false;
+    return -1;
+}
+
+__device__ __forceinline__ bool index_contains(const uint4 *tab, uint64_t mask, int32_t v, int32_t u)
+{
+    return index_probe<false>(tab, mask, v, u, nullptr) >= 0;
+}
+
+// (v, u) in the graph, with h(v, u) in *h when it is.
+__device__ __forceinline__ bool index_find_h(const uint4 *tab, uint64_t mask, int32_t v, int32_t u, float *h)
+{
+    return index_probe<true>(tab, mask, v, u, h) >= 0;
 }
 
 // ceil(log2(m + 1)): probes of a binary search over m entries.

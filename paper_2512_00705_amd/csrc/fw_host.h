@@ -22,7 +22,7 @@ struct fw_graph {
     unsigned long long *scratch = nullptr;  // [0] walker queue, [1] error flag (int)
     bool prepped = false;
     bool symmetric = false;                 // every (v, u) has a reverse (u, v) with equal h
-    unsigned long long *mtab = nullptr;     // edge index: buckets of 8 keys v << 32 | u, or null
+    unsigned long long *mtab = nullptr;     // edge index: 128-byte buckets of 8 keys v << 32 | u and their h, or null
     uint4 *prop = nullptr;                  // h-proportional proposal records (2 uint4 per entry), or null
     uint64_t mtab_mask = 0;                 // buckets - 1
 };
@@ -39,7 +39,7 @@ int ok();
 
 int check_logic(const fw_graph *g, const fw_logic *lg);
 int check_plan(const fw_plan *pl);
-// plan.bound = 1 for Node2Vec needs a symmetric graph
+// plan.bound = 1 or 2 for Node2Vec needs a symmetric graph
 int check_bound(const fw_graph *g, const fw_plan *pl, const fw_logic *lg);
 // Per-query float constants of a logic, in float32 exactly as the definition states.
 void fill_query(const fw_logic *lg, QueryDev &q);

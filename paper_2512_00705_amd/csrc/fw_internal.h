@@ -118,10 +118,11 @@ hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv,
 hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
                               int64_t nv, double *sc, int32_t *stk_s, int32_t *stk_l, int32_t *alias, uint4 *prop,
                               hipStream_t s);
-// Edge index: inserts every entry (v, col[k]) of the rows into `tab` (buckets * 8 keys, all
-// kEmptyKey on entry; buckets = mask + 1, a power of two, at least a quarter of ne).
-hipError_t launch_build_index(const int64_t *row_ptr, const int32_t *col, int64_t nv, unsigned long long *tab,
-                              uint64_t mask, hipStream_t s);
+// Edge index: inserts every entry (v, col[k]) of the rows with its h (1 when h is null) into
+// `tab` (buckets of 8 keys and 8 h, 128 bytes each, keys all kEmptyKey on entry;
+// buckets = mask + 1, a power of two, at least a quarter of ne).
+hipError_t launch_build_index(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv,
+                              unsigned long long *tab, uint64_t mask, hipStream_t s);
 // blocks * kBlock lanes each read 4 * rounds random 8-byte records of a[0, mask] (mask + 1 a
 // power of two).
 hipError_t launch_random_reads(const uint2 *a, uint64_t mask, int blocks, int rounds, unsigned *sink, hipStream_t s);

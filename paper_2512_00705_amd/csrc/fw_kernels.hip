@@ -257,7 +257,9 @@ __device__ __forceinline__ void flush_stats(const WalkArgs &a, uint32_t (&cnt)[k
 // BATCH: walkers of many queries (each with its own logic constants, length, seed,
 // starts and outputs) share one launch; walker i of a query draws from that query's
 // seed with counter (i, step, draw, tag), exactly as in a launch of its own.
-template <int KIND, bool W, bool BATCH>
+// MB: the member board of plan.bound = 2 (Node2Vec, second-order PageRank); a variant of
+// its own so that the lane state it needs costs the other plans no registers.
+template <int KIND, bool W, bool BATCH, bool MB>
 __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
 {
     extern __shared__ int32_t lds_all[];
@@ -276,6 +278,10 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
     bool fell_back = false;
     float B = 0.0f;
     float area = 0.0f;  // eRJS proposal board: deg * B (uniform) or B * h_SUM (h-proportional), plus E
+    // the board's return column [0, bE) and member region [bE, bZ) of U * area; the
+    // member board's h_MAX for the member test; mb: the step uses the member board
+    float bE = 0.0f, bZ = 0.0f, hmx = 1.0f;
+    bool mb = false;
     // h of the edge prev -> cur, and of the edge the current step takes; on a symmetric
     // graph the first is also h(cur, prev), the return edge's property weight
     float hlast = 1.0f, hnext = 1.0f;
@@ -403,6 +409,32 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                         B = split ? Q.hi_w * hB : wmax * hB;
                         const float E = split ? fmaxf(0.0f, Q.inv_p * hlast - (hprop ? B * hlast : B)) : 0.0f;
                         area = hprop ? B * hs + E : (float)deg * B + E;
+                        bE = E;
+                        bZ = E;
+                        mb = false;
+                        hmx = hm;
+                        // member board: regular columns at the lower weight w_oth take every
+                        // proposal, a region of area (w_mem - w_oth) * h_MAX * d(v') adds the
+                        // members' excess, the return edge keeps a column for its own; used
+                        // when its area is the smaller
+                        if (MB && uses_membership(KIND) && j > 0 && pdeg > 0) {
+                            const StepW sw = step_weights<KIND>(Q, deg, pdeg);
+                            if (sw.mem > sw.oth) {
+                                const float areg = hprop ? sw.oth * hs : ((float)deg * sw.oth) * hm;
+                                const float Rm = ((sw.mem - sw.oth) * hm) * (float)pdeg;
+                                const float Em = KIND == kNode2Vec
+                                                     ? fmaxf(0.0f, Q.inv_p * hlast - sw.oth * (W ? hlast : 1.0f))
+                                                     : 0.0f;
+                                const float am = (areg + Rm) + Em;
+                                if (am < area) {
+                                    mb = true;
+                                    area = am;
+                                    bE = Em;
+                                    bZ = Em + Rm;
+                                    B = hprop ? sw.oth : sw.oth * hm;
+                                }
+                            }
+                        }
                         if (a.strategy == kRjsOnly) {
                             rjs = true;
                             st_bytes += W ? 4 : 0;
@@ -419,7 +451,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                             // Eq. (runtime) with get_weight_sum = mean(w) * h_SUM; with the
                             // split board or h-proportional proposals the eRJS cost is
                             // area / S per step against deg for eRVS
-                            if (split || hprop) {
+                            if (split || hprop || (MB && mb)) {
                                 rjs = deg >= a.d_lo && (a.rho * area) < ((float)deg * (wavg * hs));
                             } else {
                                 rjs = deg >= a.d_lo && (a.rho * B) < (wavg * hs);
@@ -450,22 +482,30 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
             // E) with probability E / (deg * B + E); such a trial reads no edge
             // h-proportional proposals: a record of the row's alias table gives the slot
             // and its alias; the coin is the fraction of the index draw
-            const bool split = KIND == kNode2Vec && a.bound != 0 && j > 0;
+            // member board: a trial in the member region proposes a neighbour x of prev
+            // (the index draw over d(v')); the entry (cur, x) and its h come from the edge
+            // index or a search of cur's row
             const bool hprop = W && a.proposal != 0;
-            const float E = split ? fmaxf(0.0f, Q.inv_p * hlast - (hprop ? B * hlast : B)) : 0.0f;
+            const bool split = KIND == kNode2Vec && a.bound != 0 && j > 0;
+            const float E = MB ? bE : (split ? fmaxf(0.0f, Q.inv_p * hlast - (hprop ? B * hlast : B)) : 0.0f);
             uint32_t ux[kRjsBatch];
             uint2 ee[kRjsBatch];
             uint8_t ll[kRjsBatch];
-            bool ol[kRjsBatch];
+            bool ol[kRjsBatch], mr[kRjsBatch];
             const uint32_t k0 = Q.key0, k1 = Q.key1;
 #pragma unroll
             for (int r = 0; r < kRjsBatch; ++r) {
                 const U4 x = philox((uint32_t)wid, (uint32_t)j, (uint32_t)(trials + r), 0u, k0, k1);
                 const int64_t k = base + scaled_index(x.x0, x.x1, deg);
-                ol[r] = E > 0.0f && unit_uniform(x.x3) * area < E;
+                const float z = unit_uniform(x.x3) * area;
+                ol[r] = E > 0.0f && z < E;
+                mr[r] = MB && uses_membership(KIND) && mb && !ol[r] && z < bZ;
                 ux[r] = x.x2;
                 if (ol[r]) {
                     ee[r] = make_uint2((uint32_t)prev, 0u);
+                    ll[r] = 0;
+                } else if (mr[r]) {
+                    ee[r] = make_uint2((uint32_t)a.col[pbase + scaled_index(x.x0, x.x1, pdeg)], 0u);
                     ll[r] = 0;
                 } else if (hprop) {
                     const uint32_t f = scaled_fraction_hi(x.x0, x.x1, deg);
@@ -487,9 +527,32 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 const float hv = W ? __uint_as_float(ee[0].y) : 1.0f;
                 const float hw = hprop ? 1.0f : hv;  // the test is on w~ (uniform) or w (h-proportional)
                 const float y = unit_uniform(ux[0]) * B;
+                float hsel = ol[0] ? hlast : hv;  // symmetric h: h(cur, prev) = h(prev, cur)
                 bool acc;
                 if (ol[0]) {
                     acc = true;  // the extra column belongs to the return edge
+                } else if (MB && uses_membership(KIND) && mr[0]) {
+                    // member region: keep x = u when it is a neighbour of cur (not prev),
+                    // with probability h(cur, x) / h_MAX
+                    st_bytes += 4 + (a.mtab ? 12 : 4 * (uint64_t)probes(deg));
+                    bool found = false;
+                    float hx = 1.0f;
+                    if (u != prev) {
+                        if (a.mtab) {
+                            found = index_find_h(a.mtab, a.mtab_mask, cur, u, &hx);
+                        } else {
+                            const int64_t pos = sorted_find(a.col + base, deg, u);
+                            found = pos >= 0;
+                            if (found && W) hx = __uint_as_float(a.edges[base + pos].y);
+                        }
+                    }
+                    if (!W) hx = 1.0f;
+                    hsel = hx;
+                    acc = found && unit_uniform(ux[0]) * hmx < hx;
+                } else if (MB && uses_membership(KIND) && mb) {
+                    // regular columns of the member board: every proposal at w_oth, the
+                    // return edge at min(w_ret, w_oth)
+                    acc = y < (u == prev ? fminf(sw.ret, sw.oth) : sw.oth) * hw;
                 } else if (uses_membership(KIND)) {
                     if (j == 0) {
                         acc = y < hw;
@@ -514,10 +577,10 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 }
                 ++trials;
                 st[kStTrials] += 1;
-                if (!ol[0]) st_bytes += (uint64_t)a.item_bytes + (hprop ? 12 : 0);
+                if (!ol[0] && !mr[0]) st_bytes += (uint64_t)a.item_bytes + (hprop ? 12 : 0);
                 if (acc) {
                     nxt = u;
-                    hnext = ol[0] ? hlast : hv;  // symmetric h: h(cur, prev) = h(prev, cur)
+                    hnext = hsel;
                     mode = kAdv;
                     st[kStRjs] += 1;
                     break;
@@ -533,6 +596,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                     ux[t] = ux[t + 1];
                     ll[t] = ll[t + 1];
                     ol[t] = ol[t + 1];
+                    mr[t] = mr[t + 1];
                 }
             }
         }
@@ -770,10 +834,13 @@ __global__ void __launch_bounds__(kBlock) build_alias_kernel(const int64_t *row_
 }
 
 // Edge index build: one wave per row, each lane inserts its entries' keys with a 64-bit
-// compare-and-swap into the first free slot from the key's bucket on.  The table holds
-// at least twice as many slots as keys, so every insert finds a slot within the scan.
-__global__ void __launch_bounds__(kBlock) build_index_kernel(const int64_t *row_ptr, const int32_t *col, int64_t nv,
-                                                             unsigned long long *tab, uint64_t mask)
+// compare-and-swap into the first free slot from the key's bucket on, then stores the
+// entry's h in the slot's h part (rows are strictly ascending, so a key is inserted once).
+// The table holds at least twice as many slots as keys, so every insert finds a slot
+// within the scan.  tab: 16 uint64 per bucket (8 keys, then 8 h as float pairs).
+__global__ void __launch_bounds__(kBlock) build_index_kernel(const int64_t *row_ptr, const int32_t *col,
+                                                             const float *h, int64_t nv, unsigned long long *tab,
+                                                             uint64_t mask)
 {
     const int lane = lane_id();
     const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
@@ -785,8 +852,10 @@ __global__ void __launch_bounds__(kBlock) build_index_kernel(const int64_t *row_
             bool done = false;
             for (uint64_t t = 0; t <= mask && !done; ++t) {
                 for (int s = 0; s < 8 && !done; ++s) {
-                    const unsigned long long old = atomicCAS(&tab[bk * 8 + s], kEmptyKey, key);
+                    unsigned long long *bucket = tab + bk * (2 * kIndexBucketU4);
+                    const unsigned long long old = atomicCAS(&bucket[s], kEmptyKey, key);
                     done = old == kEmptyKey || old == key;
+                    if (old == kEmptyKey) reinterpret_cast<float *>(bucket + 8)[s] = h ? h[k] : 1.0f;
                 }
                 bk = (bk + 1) & mask;
             }
@@ -894,7 +963,10 @@ template <int KIND, bool W, bool BATCH>
 static hipError_t launch_walk_t(const WalkArgs &a, int grid, hipStream_t s)
 {
     const size_t lds = (size_t)kWavesPerBlock * (size_t)a.lds_cap * sizeof(int32_t);
-    hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH>), dim3(grid), dim3(kBlock), lds, s, a);
+    if (uses_membership(KIND) && a.bound == 2)
+        hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, uses_membership(KIND)>), dim3(grid), dim3(kBlock), lds, s, a);
+    else
+        hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, false>), dim3(grid), dim3(kBlock), lds, s, a);
     return hipGetLastError();
 }
 
@@ -919,7 +991,8 @@ static int occupancy_blocks(int lds_cap)
 {
     int nb = 0;
     const size_t lds = (size_t)kWavesPerBlock * (size_t)lds_cap * sizeof(int32_t);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<KIND, W, BATCH>, kBlock, lds) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<KIND, W, BATCH, false>, kBlock, lds) !=
+        hipSuccess)
         nb = 1;
     return nb > 0 ? nb : 1;
 }
@@ -1015,13 +1088,14 @@ hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const 
     return hipGetLastError();
 }
 
-hipError_t launch_build_index(const int64_t *row_ptr, const int32_t *col, int64_t nv, unsigned long long *tab,
-                              uint64_t mask, hipStream_t s)
+hipError_t launch_build_index(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv,
+                              unsigned long long *tab, uint64_t mask, hipStream_t s)
 {
     int64_t blocks = (nv + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(build_index_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, nv, tab, mask);
+    hipLaunchKernelGGL(build_index_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, nv, tab,
+                       mask);
     return hipGetLastError();
 }
 

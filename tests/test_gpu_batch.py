@@ -174,11 +174,12 @@ def test_batch_argument_errors(g12, gg12):
     fw.fw_batch_destroy(empty)
 
 
-def test_batch_split_bound(g12, gg12):
+@pytest.mark.parametrize("bound", [1, 2], ids=["split", "member"])
+def test_batch_split_bound(g12, gg12, bound):
     qd = _small_batch(g12["nv"], 24, 13)
     logics = [oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=float(0.25 + (i % 4) * 0.5), q=2.0)
               for i in range(24)]
-    pl = oracle.Plan(rho=1.0, bound=1)
+    pl = oracle.Plan(rho=1.0, bound=bound)
     b = Batch(gg12, qd, [fw.fw_logic_node2vec(l.p, l.q, True) for l in logics], fw_plan(pl), oracle.AUTO)
     try:
         fw.fw_batch_launch(b.h)
@@ -197,12 +198,13 @@ def test_batch_split_bound(g12, gg12):
         b.close()
 
 
-def test_batch_second_pr(g12, gg12):
+@pytest.mark.parametrize("bound", [0, 2], ids=["paper", "member"])
+def test_batch_second_pr(g12, gg12, bound):
     """A batch of second-order PageRank queries with their own gamma, L, seed and starts."""
     qd = _small_batch(g12["nv"], 20, 17)
     gammas = [0.05 * (i % 20) for i in range(20)]
     logics = [oracle.Logic(kind=oracle.SECOND_PR, weighted=True, gamma=g) for g in gammas]
-    pl = oracle.Plan(rho=1.0)
+    pl = oracle.Plan(rho=1.0, bound=bound)
     b = Batch(gg12, qd, [fw.fw_logic_second_pr(l.gamma, True) for l in logics], fw_plan(pl), oracle.AUTO)
     try:
         fw.fw_batch_launch(b.h)

@@ -56,11 +56,14 @@ def _sample(n, k, seed):
 
 @pytest.mark.parametrize("strategy,k,bound,proposal", [
     (oracle.AUTO, 65536, None, None), (oracle.RJS_ONLY, 65536, None, None), (oracle.RVS_ONLY, 1024, None, None),
-    (oracle.AUTO, 65536, 0, 0), (oracle.AUTO, 65536, 1, 0), (oracle.RJS_ONLY, 65536, 1, 1)],
-    ids=["auto", "rjs", "rvs", "auto_paper", "auto_split_uniform", "rjs_split_h_proposals"])
+    (oracle.AUTO, 65536, 0, 0), (oracle.AUTO, 65536, 1, 0), (oracle.RJS_ONLY, 65536, 1, 1),
+    (oracle.AUTO, 65536, 2, 0), (oracle.RJS_ONLY, 65536, 2, 1)],
+    ids=["auto", "rjs", "rvs", "auto_paper", "auto_split_uniform", "rjs_split_h_proposals", "auto_member_uniform",
+         "rjs_member_h_proposals"])
 def test_node2vec_scale22(g22, gg22, og22, tuned22, strategy, k, bound, proposal):
     """None: the autotuned plan as the benchmark runs it; otherwise that plan with the
-    bound (paper's / split) and the proposal (uniform / h-proportional) forced."""
+    bound (paper's / split / member board) and the proposal (uniform / h-proportional)
+    forced."""
     tuned = tuned22
     pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap,
                      bound=tuned.bound if bound is None else bound,
@@ -77,6 +80,26 @@ def test_node2vec_scale22(g22, gg22, og22, tuned22, strategy, k, bound, proposal
     print("scale22", strategy, {k2: (v if not isinstance(v, list) else len(v)) for k2, v in rep.items()}, st)
     assert_parity(rep)
     assert rep["steps"] >= min(k, 65536) * 40
+
+
+@pytest.mark.parametrize("bound", [None, 0], ids=["tuned", "paper"])
+def test_second_pr_scale22(g22, gg22, og22, bound):
+    """Second-order PageRank (gamma = 0.2), one walker per vertex, L = 80, the autotuned
+    plan (the member board where it wins) and the paper's bound; sampled walkers replayed
+    by the oracle, every walk checked to follow edges."""
+    lg = oracle.Logic(kind=oracle.SECOND_PR, weighted=True, gamma=0.2)
+    tuned = fw.fw_plan_autotune(gg22.handle, fw.fw_logic_second_pr(0.2, True))
+    pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap,
+                     bound=tuned.bound if bound is None else bound, proposal=tuned.proposal, member_index=True)
+    starts = synth.all_vertices(g22["nv"])
+    p, ln, st = gpu_walk(gg22, lg, pl, oracle.AUTO, starts, 80, 42)
+    ok, pad_ok, _ = edge_check_torch(g22, p, ln)
+    assert ok and pad_ok
+    sub = _sample(g22["nv"], 16384, 4321)
+    ora = oracle.walk(og22, lg, pl, oracle.AUTO, starts[sub], 80, 42, walker_ids=sub)
+    rep = parity(p[sub], ln[sub], ora)
+    print("secondpr22", pl, {k2: (v if not isinstance(v, list) else len(v)) for k2, v in rep.items()}, st)
+    assert_parity(rep)
 
 
 def test_metapath_scale22(g22, gg22, og22):

@@ -278,7 +278,6 @@ def test_split_bound_needs_symmetric_graph(g12, gg12):
     s = torch.zeros(4, dtype=torch.int32, device=dev)
     out = torch.zeros(4 * 6, dtype=torch.int32, device=dev)
     ln = torch.zeros(4, dtype=torch.int32, device=dev)
-    split = fw.fw_plan_default(bound=1)
     # a directed edge 0 -> 1 without its reverse
     gd = synth.csr_from_edges(3, [(0, 1), (0, 2)], h=[1, 2], symmetric=False)
     # reverse edges present but with different h
@@ -289,9 +288,13 @@ def test_split_bound_needs_symmetric_graph(g12, gg12):
         gg = GpuGraph(g)
         try:
             assert not fw.fw_graph_info(gg.handle)[3]
-            with pytest.raises(fw.FlexiWalkError) as e:
-                fw.fw_walk(gg.handle, fw.fw_logic_node2vec(0.25, 2.0, True), split, 0, s, 4, 5, 1, out, ln)
-            assert e.value.code == fw.FW_E_INVALID
+            for split in (fw.fw_plan_default(bound=1), fw.fw_plan_default(bound=2)):
+                with pytest.raises(fw.FlexiWalkError) as e:
+                    fw.fw_walk(gg.handle, fw.fw_logic_node2vec(0.25, 2.0, True), split, 0, s, 4, 5, 1, out, ln)
+                assert e.value.code == fw.FW_E_INVALID
+            # second-order PageRank's member board needs no symmetry
+            fw.fw_walk(gg.handle, fw.fw_logic_second_pr(0.2, True), fw.fw_plan_default(bound=2), 0, s, 4, 5, 1, out,
+                       ln)
             # the paper's bound needs no symmetry
             fw.fw_walk(gg.handle, fw.fw_logic_node2vec(0.25, 2.0, True), fw.fw_plan_default(), 0, s, 4, 5, 1, out,
                        ln)
@@ -299,7 +302,7 @@ def test_split_bound_needs_symmetric_graph(g12, gg12):
         finally:
             gg.close()
     with pytest.raises(fw.FlexiWalkError):
-        fw.fw_walk(gg12.handle, fw.fw_logic_node2vec(0.25, 2.0, True), fw.fw_plan_default(bound=2), 0, s, 4, 5, 1,
+        fw.fw_walk(gg12.handle, fw.fw_logic_node2vec(0.25, 2.0, True), fw.fw_plan_default(bound=3), 0, s, 4, 5, 1,
                    out, ln)
 
 
@@ -312,7 +315,7 @@ def gi12(g12):
 
 
 @pytest.mark.parametrize("strategy", list(STRATS), ids=list(STRATS))
-@pytest.mark.parametrize("bound", [0, 1])
+@pytest.mark.parametrize("bound", [0, 1, 2])
 def test_edge_index_same_walks(g12, gg12, gi12, strategy, bound):
     """The edge index answers u in N(prev) exactly: walks and every counter but the
     algorithmic bytes equal the searched rows'; all counters equal the oracle's with
@@ -487,13 +490,13 @@ HP_LOGICS = {"n2v": N2V, "n2v_ret": N2V_RET, "2ndpr": PR2, "metapath": MP,
 
 
 @pytest.mark.parametrize("strategy", ["auto", "rjs"])
-@pytest.mark.parametrize("bound", [0, 1])
+@pytest.mark.parametrize("bound", [0, 1, 2])
 @pytest.mark.parametrize("logic", list(HP_LOGICS), ids=list(HP_LOGICS))
 def test_h_proposals_scale12(g12, ga12, strategy, bound, logic):
     """plan.proposal = 1: alias-table proposals, the test on w; walks and counters equal
     the oracle's (which builds its alias tables independently)."""
     lg = HP_LOGICS[logic]
-    pl = oracle.Plan(rho=1.0, bound=bound if lg.kind == oracle.NODE2VEC else 0, proposal=1, rjs_cap=256,
+    pl = oracle.Plan(rho=1.0, bound=bound if lg.kind != oracle.METAPATH else 0, proposal=1, rjs_cap=256,
                      member_index=True)
     starts = synth.all_vertices(g12["nv"])
     p, ln, st, ora = _run_both(ga12, g12, lg, pl, STRATS[strategy], starts, 20, 31)
@@ -553,3 +556,65 @@ def test_h_proposals_need_alias(g12, gg12):
     fw.fw_walk(gg12.handle, fw.fw_logic_node2vec(0.5, 2.0, False), fw.fw_plan_default(proposal=1), 0, s, 4, 5, 1,
                out, ln)
     torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------------ member board (plan.bound = 2)
+@pytest.fixture(scope="module")
+def gn12(g12):
+    gg = GpuGraph(g12, alias=True)  # alias records without the edge index
+    yield gg
+    gg.close()
+
+
+MB_LOGICS = {"n2v_q2": oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=0.5, q=2.0), "n2v_ret": N2V_RET,
+             "n2v_q05": N2V, "2ndpr": PR2, "2ndpr_g07": oracle.Logic(kind=oracle.SECOND_PR, weighted=True, gamma=0.7),
+             "n2v_unweighted": oracle.Logic(kind=oracle.NODE2VEC, weighted=False, p=0.25, q=4.0),
+             "2ndpr_unweighted": oracle.Logic(kind=oracle.SECOND_PR, weighted=False, gamma=0.2)}
+
+
+@pytest.mark.parametrize("strategy", ["auto", "rjs"])
+@pytest.mark.parametrize("proposal", [0, 1], ids=["uniform", "hprop"])
+@pytest.mark.parametrize("indexed", [False, True], ids=["search", "index"])
+@pytest.mark.parametrize("logic", list(MB_LOGICS), ids=list(MB_LOGICS))
+def test_member_board_scale12(g12, gn12, ga12, strategy, proposal, indexed, logic):
+    """plan.bound = 2: per step the smaller of the member board and the split (Node2Vec)
+    or plain board; a member-region trial finds (cur, x) and its h through the edge index
+    or a search of cur's row.  Walks and counters equal the oracle's."""
+    lg = MB_LOGICS[logic]
+    pl = oracle.Plan(rho=1.0, bound=2, proposal=proposal, rjs_cap=256, member_index=indexed)
+    starts = synth.all_vertices(g12["nv"])
+    p, ln, st, ora = _run_both(ga12 if indexed else gn12, g12, lg, pl, STRATS[strategy], starts, 20, 53)
+    rep = parity(p, ln, ora)
+    assert_parity(rep)
+    if rep["mismatch_walkers"] == 0:
+        _assert_counters(st, ora)
+    assert st["rjs_steps"] > 0
+
+
+def test_member_board_fewer_trials_on_gpu(g12, ga12):
+    """Second-order PageRank: the plain bound is loose where d(v) >> d(v'); the member
+    board's area does not grow with d(v) / d(v')."""
+    starts = synth.all_vertices(g12["nv"])
+    for prop in (0, 1):
+        a = gpu_walk(ga12, PR2, oracle.Plan(bound=0, proposal=prop), oracle.RJS_ONLY, starts, 20, 5)[2]
+        b = gpu_walk(ga12, PR2, oracle.Plan(bound=2, proposal=prop), oracle.RJS_ONLY, starts, 20, 5)[2]
+        assert b["rjs_trials"] / b["steps"] < 0.5 * a["rjs_trials"] / a["steps"], prop
+
+
+@pytest.mark.parametrize("logic", ["n2v_ret", "2ndpr"])
+@pytest.mark.parametrize("proposal", [0, 1], ids=["uniform", "hprop"])
+def test_member_board_chisquare_hub(logic, proposal):
+    """Second step at the 600-neighbour hub from leaf 1 (two members, the ring neighbours
+    of leaf 1) against the exact transition."""
+    lg = MB_LOGICS[logic]
+    g = hub_ring_graph(600)
+    gg = GpuGraph(g, index=True, alias=True)
+    try:
+        n = 300000
+        p, ln, st = gpu_walk(gg, lg, oracle.Plan(rho=1.0, bound=2, proposal=proposal), oracle.RJS_ONLY,
+                             np.ones(n, np.int32), 2, 47)
+    finally:
+        gg.close()
+    at_hub = p[:, 1] == 0
+    counts = {int(v): int(c) for v, c in zip(*np.unique(p[at_hub, 2], return_counts=True))}
+    assert chisq_pvalue(counts, exact.transition(g, lg, 1, 1, 0), int(at_hub.sum())) > 1e-3

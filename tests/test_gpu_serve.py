@@ -168,18 +168,20 @@ def test_bad_start_and_teardown(g12, gg12):
 
 
 @pytest.mark.parametrize("tick_steps", [1, 5])
-def test_split_bound_resume(g12, gg12, tick_steps):
-    """Walks suspended every few steps under the split bound: a resumed walker recovers
-    h(prev, cur) from the graph, so its samples equal an uninterrupted walk's."""
-    pl = oracle.Plan(rho=1.0, rjs_cap=64, bound=1)
+@pytest.mark.parametrize("bound", [1, 2], ids=["split", "member"])
+def test_split_bound_resume(g12, gg12, tick_steps, bound):
+    """Walks suspended every few steps under the split bound (or the member board): a
+    resumed walker recovers h(prev, cur) from the graph, so its samples equal an
+    uninterrupted walk's."""
+    pl = oracle.Plan(rho=1.0, rjs_cap=64, bound=bound)
     rng = np.random.default_rng(tick_steps)
     reqs = []
     for i in range(12):
         lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=bool(i % 3), p=float(rng.choice([0.25, 0.5, 2.0])), q=2.0)
         reqs.append((lg, rng.integers(0, g12["nv"], int(rng.integers(1, 400))).astype(np.int32),
                      int(rng.integers(1, 30)), 500 + i))
-    srv = fw.fw_server_create(gg12.handle, fw.fw_plan_default(rho=pl.rho, rjs_cap=pl.rjs_cap, bound=1), fw.FW_AUTO,
-                              64 << 20, tick_steps=tick_steps, max_active=8)
+    srv = fw.fw_server_create(gg12.handle, fw.fw_plan_default(rho=pl.rho, rjs_cap=pl.rjs_cap, bound=bound),
+                              fw.FW_AUTO, 64 << 20, tick_steps=tick_steps, max_active=8)
     try:
         results = _serve_all(srv, reqs)
     finally:
@@ -193,16 +195,18 @@ def test_split_bound_resume(g12, gg12, tick_steps):
         assert_parity(parity(p, ln, oracle.walk(og, lg, pl, oracle.AUTO, st, L, seed)))
 
 
-def test_h_proposals_served(g12):
-    """Served walks under h-proportional proposals and the split bound, suspended every
-    3 steps, equal the same walks run alone."""
+@pytest.mark.parametrize("bound", [1, 2], ids=["split", "member"])
+def test_h_proposals_served(g12, bound):
+    """Served walks under h-proportional proposals and the split bound (or the member
+    board), suspended every 3 steps, equal the same walks run alone."""
     gg = GpuGraph(g12, index=True, alias=True)
-    pl = oracle.Plan(rho=1.0, rjs_cap=64, bound=1, proposal=1)
+    pl = oracle.Plan(rho=1.0, rjs_cap=64, bound=bound, proposal=1)
     rng = np.random.default_rng(9)
     reqs = [(oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=float(rng.choice([0.25, 2.0])), q=2.0),
              rng.integers(0, g12["nv"], int(rng.integers(1, 300))).astype(np.int32), int(rng.integers(1, 25)), 700 + i)
             for i in range(10)]
-    srv = fw.fw_server_create(gg.handle, fw.fw_plan_default(rho=pl.rho, rjs_cap=pl.rjs_cap, bound=1, proposal=1),
+    srv = fw.fw_server_create(gg.handle,
+                              fw.fw_plan_default(rho=pl.rho, rjs_cap=pl.rjs_cap, bound=bound, proposal=1),
                               fw.FW_AUTO, 64 << 20, tick_steps=3, max_active=8)
     try:
         results = _serve_all(srv, reqs)
