@@ -414,8 +414,14 @@ def bench_batched(args):
     fw.fw_graph_preprocess(gh)
     fw.fw_graph_build_index(gh)
     fw.fw_graph_build_alias(gh)
-    plan = fw.fw_plan_autotune(gh, fw.fw_logic_node2vec(1.0, 1.0, True))
     qd = synth.batch_queries(g["nv"], 4096, 7)
+    # one plan for the batch: tuned over the distinct logics its queries use
+    mix = sorted({(float(p), float(q)) for p, q in zip(qd["p"], qd["q"])})
+    t0 = time.perf_counter()
+    plan = fw.fw_plan_autotune_mix(gh, [fw.fw_logic_node2vec(p, q, True) for p, q in mix])
+    tune_ms = (time.perf_counter() - t0) * 1e3
+    log(f"autotune over {len(mix)} logics {tune_ms:.0f} ms: rho={plan.rho:.3f} d_lo={plan.d_lo} "
+        f"lds_cap={plan.lds_cap} bound={plan.bound} proposal={plan.proposal}")
     starts = torch.from_numpy(qd["starts"]).to(dev)
     paths = torch.empty((qd["total_paths"],), dtype=torch.int32, device=dev)
     lengths = torch.empty((int(qd["n"].sum()),), dtype=torch.int32, device=dev)
@@ -472,6 +478,8 @@ def bench_batched(args):
                                f"({int(qd['n'].sum())} walkers), L in 5..200, one captured HIP-graph launch, "
                                f"R-MAT scale 24 (0.6,0.175,0.175), {g['ne']} CSR entries",
                    "stats": st, "rho": plan.rho, "d_lo": plan.d_lo,
+                   "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound,
+                            "proposal": plan.proposal}, "autotune_ms": tune_ms,
                    "per_query_launches_ms": per_q,
                    "per_query_walker_steps_per_s": (st["steps"] / (per_q / 1e3)) if per_q else None},
         "roofline": {"bound": "hbm", "achieved": st["alg_bytes"] / (avg / 1e3) / 1e9, "peak": PEAK_HBM_GBS,
@@ -503,7 +511,13 @@ def bench_served(args):
     fw.fw_graph_preprocess(gh)
     fw.fw_graph_build_index(gh)
     fw.fw_graph_build_alias(gh)
-    plan = fw.fw_plan_autotune(gh, fw.fw_logic_node2vec(1.0, 1.0, True))
+    # one plan for the server: tuned over every logic the requests may carry
+    pq = np.array([0.25, 0.5, 1.0, 2.0, 4.0], np.float32)
+    mix = [fw.fw_logic_node2vec(float(p), float(q), True) for p in pq for q in pq]
+    mix.append(fw.fw_logic_metapath([0, 1, 2, 3, 4], True))
+    plan = fw.fw_plan_autotune_mix(gh, mix)
+    log(f"plan: rho={plan.rho:.3f} d_lo={plan.d_lo} lds_cap={plan.lds_cap} bound={plan.bound} "
+        f"proposal={plan.proposal}")
     budget = 32 << 30
     srv = fw.fw_server_create(gh, plan, fw.FW_AUTO, budget, tick_steps=args.tick_steps, max_active=8192,
                               max_pending=1 << 16)
@@ -511,7 +525,6 @@ def bench_served(args):
     T, lam = args.serve_seconds, args.serve_rate
     arrivals = np.cumsum(rng.exponential(1.0 / lam, int(lam * T * 1.2) + 16))
     arrivals = arrivals[arrivals < T]
-    pq = np.array([0.25, 0.5, 1.0, 2.0, 4.0], np.float32)
     reqs = []
     for i in range(len(arrivals)):
         n = int(np.clip(np.floor(np.exp(rng.uniform(0, np.log(65536)))), 1, 65536))
@@ -581,6 +594,8 @@ def bench_served(args):
                                f"batching (tick {args.tick_steps} steps), budget {budget >> 30} GiB",
                    "p50_ms": p50, "p99_ms": p99, "requests": len(reqs), "completed": len(lat),
                    "sustained": sustained, "offered_walker_steps_per_s": offered_steps / T, "server": st,
+                   "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound,
+                            "proposal": plan.proposal},
                    "busy_retries": busy[0], "rho": plan.rho},
         "roofline": None, "cpu_baseline": None,
     }

@@ -27,7 +27,7 @@ STAT_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", 
 EXPORTED = ("fw_graph_create", "fw_graph_destroy", "fw_graph_preprocess", "fw_graph_build_index",
             "fw_graph_export_aux", "fw_graph_info", "fw_calibrate_random_reads", "fw_graph_build_alias",
             "fw_logic_node2vec", "fw_logic_metapath", "fw_logic_second_pr", "fw_plan_default", "fw_plan_profile",
-            "fw_plan_autotune", "fw_walk", "fw_graph_check", "fw_last_error", "fw_batch_create", "fw_batch_launch",
+            "fw_plan_autotune", "fw_plan_autotune_mix", "fw_walk", "fw_graph_check", "fw_last_error", "fw_batch_create", "fw_batch_launch",
             "fw_batch_capture", "fw_batch_replay", "fw_batch_destroy", "fw_server_create", "fw_server_submit",
             "fw_server_next_done", "fw_server_result", "fw_server_stats", "fw_server_destroy")
 SERVER_STAT_NAMES = ("waiting", "active", "finished", "ticks", "walker_steps", "bytes_in_use", "peak_bytes",
@@ -84,6 +84,8 @@ def _load():
         "fw_plan_default": ([ctypes.POINTER(fw_plan)], ctypes.c_int),
         "fw_plan_profile": ([P, ctypes.POINTER(fw_logic), ctypes.POINTER(fw_plan), P], ctypes.c_int),
         "fw_plan_autotune": ([P, ctypes.POINTER(fw_logic), ctypes.POINTER(fw_plan), P], ctypes.c_int),
+        "fw_plan_autotune_mix": ([P, ctypes.POINTER(fw_logic), ctypes.c_int32, ctypes.POINTER(fw_plan), P],
+                                 ctypes.c_int),
         "fw_walk": ([P, ctypes.POINTER(fw_logic), ctypes.POINTER(fw_plan), I32, P, I64, I32, ctypes.c_uint64,
                      P, P, P, P], ctypes.c_int),
         "fw_graph_check": ([P, P], ctypes.c_int),
@@ -222,6 +224,14 @@ def fw_plan_profile(g: int, logic: fw_logic, stream=None) -> fw_plan:
 def fw_plan_autotune(g: int, logic: fw_logic, stream=None) -> fw_plan:
     out = fw_plan()
     _check(_lib.fw_plan_autotune(g, ctypes.byref(logic), ctypes.byref(out), _stream(stream)))
+    return out
+
+
+def fw_plan_autotune_mix(g: int, logics, stream=None) -> fw_plan:
+    """One plan for a mix of logics (a batch or a server's requests)."""
+    arr = (fw_logic * len(logics))(*logics)
+    out = fw_plan()
+    _check(_lib.fw_plan_autotune_mix(g, arr, len(logics), ctypes.byref(out), _stream(stream)))
     return out
 
 

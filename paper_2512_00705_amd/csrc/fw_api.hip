@@ -565,15 +565,25 @@ int fw_plan_profile(fw_graph *g, const fw_logic *lg, fw_plan *out, void *stream)
 
 int fw_plan_autotune(fw_graph *g, const fw_logic *lg, fw_plan *out, void *stream)
 {
-    int rc = fw_plan_profile(g, lg, out, stream);
+    return fw_plan_autotune_mix(g, lg, 1, out, stream);
+}
+
+int fw_plan_autotune_mix(fw_graph *g, const fw_logic *logics, int32_t n_logics, fw_plan *out, void *stream)
+{
+    if (!g || !logics || !out || n_logics < 1 || n_logics > 64)
+        return fail(FW_E_INVALID, "fw_plan_autotune_mix: null argument or n_logics outside 1..64");
+    int rc = fw_plan_profile(g, &logics[0], out, stream);
     if (rc != FW_OK) return rc;
+    for (int32_t i = 1; i < n_logics; ++i)
+        if ((rc = check_logic(g, &logics[i])) != FW_OK) return rc;
     if (g->nv == 0 || g->ne == 0) return ok();
     hipStream_t s = (hipStream_t)stream;
 
     // sample walks: seeded walkers spread over all vertices, enough to keep the device busy
     // for milliseconds per candidate (shorter runs time the launch and the tail), long
-    // enough for the walk's degree bias to set in
-    const int64_t n = std::min<int64_t>(g->nv, 1 << 20);
+    // enough for the walk's degree bias to set in; with several logics each gets an equal
+    // share of the walkers and a candidate's time is the sum over the logics
+    const int64_t n = std::min<int64_t>(g->nv, std::max<int64_t>(1 << 16, (1 << 20) / n_logics));
     const int32_t L = 16;
     std::vector<int32_t> starts((size_t)n);
     uint64_t x = 0x9E3779B97F4A7C15ull;
@@ -592,46 +602,51 @@ int fw_plan_autotune(fw_graph *g, const fw_logic *lg, fw_plan *out, void *stream
     HIP_TRY(hipEventCreate(&ev.a));
     HIP_TRY(hipEventCreate(&ev.b));
     auto time_plan = [&](const fw_plan &p, float *ms) -> int {
-        float best = 1e30f;
-        for (int rep = 0; rep < 2; ++rep) {
-            HIP_TRY(hipEventRecord(ev.a, s));
-            int r = fw_walk(g, lg, &p, FW_AUTO, (const int32_t *)d_starts.p, n, L, 7, (int32_t *)d_paths.p,
-                            (int32_t *)d_len.p, nullptr, stream);
-            if (r != FW_OK) return r;
-            HIP_TRY(hipEventRecord(ev.b, s));
-            HIP_TRY(hipEventSynchronize(ev.b));
-            float t = 0;
-            HIP_TRY(hipEventElapsedTime(&t, ev.a, ev.b));
-            best = std::min(best, t);
+        float total = 0;
+        for (int32_t i = 0; i < n_logics; ++i) {
+            float best = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                HIP_TRY(hipEventRecord(ev.a, s));
+                int r = fw_walk(g, &logics[i], &p, FW_AUTO, (const int32_t *)d_starts.p, n, L, 7 + (uint64_t)i,
+                                (int32_t *)d_paths.p, (int32_t *)d_len.p, nullptr, stream);
+                if (r != FW_OK) return r;
+                HIP_TRY(hipEventRecord(ev.b, s));
+                HIP_TRY(hipEventSynchronize(ev.b));
+                float t = 0;
+                HIP_TRY(hipEventElapsedTime(&t, ev.a, ev.b));
+                best = std::min(best, t);
+            }
+            total += best;
         }
-        *ms = best;
+        *ms = total;
         return FW_OK;
     };
-    // cost-model constant around the profiled value, then the degree gate, then the LDS
-    // budget for N(prev)
-    // (for each eRJS bound the graph and logic allow)
+    // bounds every logic accepts: 0 always; the split bound (1) when a Node2Vec logic is
+    // present and the graph is symmetric; the member board (2) then, or for second-order
+    // PageRank when no Node2Vec logic needs a symmetric graph that is missing
+    bool any_n2v = false, any_pr = false, any_weighted = false;
+    for (int32_t i = 0; i < n_logics; ++i) {
+        any_n2v = any_n2v || logics[i].kind == FW_NODE2VEC;
+        any_pr = any_pr || logics[i].kind == FW_SECOND_PR;
+        any_weighted = any_weighted || logics[i].weighted;
+    }
+    int32_t bounds[3] = {0, 0, 0};
+    int nbound = 1;
+    if (any_n2v && g->symmetric) bounds[nbound++] = 1;
+    if ((any_n2v && g->symmetric) || (any_pr && !any_n2v)) bounds[nbound++] = 2;
+    const int nprop = (any_weighted && g->h && g->prop) ? 2 : 1;
+    // cost-model constant around the profiled value for each bound and proposal, then the
+    // degree gate, then the LDS budget for N(prev)
     fw_plan bestp = *out;
     float bestt = 1e30f;
     const float rho0 = out->rho;
     const float scales[] = {0.0625f, 0.25f, 0.5f, 1.0f, 2.0f, 4.0f};
-    // bounds: 0 always; 1 and 2 for Node2Vec on a symmetric graph; 2 for second-order
-    // PageRank (bound 1 is the same board there)
-    int32_t bounds[3] = {0, 0, 0};
-    int nbound = 1;
-    if (lg->kind == FW_NODE2VEC && g->symmetric) {
-        bounds[nbound++] = 1;
-        bounds[nbound++] = 2;
-    } else if (lg->kind == FW_SECOND_PR) {
-        bounds[nbound++] = 2;
-    }
-    const int nprop = (lg->weighted && g->h && g->prop) ? 2 : 1;
     for (int32_t prop = 0; prop < nprop; ++prop) {
         for (int ib = 0; ib < nbound; ++ib) {
-            const int32_t bound = bounds[ib];
             for (float sc : scales) {
                 fw_plan p = *out;
                 p.rho = std::max(1e-3f, rho0 * sc);
-                p.bound = bound;
+                p.bound = bounds[ib];
                 p.proposal = prop;
                 float t;
                 if ((rc = time_plan(p, &t)) != FW_OK) return rc;
