@@ -137,7 +137,7 @@ __device__ __forceinline__ int64_t sorted_find(const int32_t *a, int64_t n, int3
     return (lo < n && a[lo] == u) ? lo : -1;
 }
 
-// Membership of u in the strictly ascending array a[0, n) whose values lie in [0, vend).
+// Position of u in the strictly ascending array a[0, n) whose values lie in [0, vend), or -1.
 // Interpolation search: the bracket (lo, hi) starts at the virtual ends a[-1] = -1 and
 // a[n] = vend; each probe guesses u's position from the bracket values.  Vertex ids of
 // a row are spread almost uniformly, so a few probes suffice; after eight guesses the
@@ -145,7 +145,7 @@ __device__ __forceinline__ int64_t sorted_find(const int32_t *a, int64_t n, int3
 // only a position inside the bracket, so it uses a fast reciprocal: any value works.
 // Requires vend < 2^30 so that bracket widths fit int32.  Eight guesses before bisecting
 // measured fewest probes on skewed graphs (about 3.9 per miss on a row of ~4500 ids).
-__device__ __forceinline__ bool sorted_contains_interp(const int32_t *a, int32_t n, int32_t u, int32_t vend)
+__device__ __forceinline__ int32_t sorted_find_interp(const int32_t *a, int32_t n, int32_t u, int32_t vend)
 {
     int32_t lo = -1, hi = n;
     int32_t vlo = -1, vhi = vend;
@@ -161,7 +161,7 @@ __device__ __forceinline__ bool sorted_contains_interp(const int32_t *a, int32_t
         pos = pos <= lo ? lo + 1 : (pos >= hi ? hi - 1 : pos);
         const int32_t v = a[pos];
         ++it;
-        if (v == u) return true;
+        if (v == u) return pos;
         if (v < u) {
             lo = pos;
             vlo = v;
@@ -170,7 +170,12 @@ __device__ __forceinline__ bool sorted_contains_interp(const int32_t *a, int32_t
             vhi = v;
         }
     }
-    return false;
+    return -1;
+}
+
+__device__ __forceinline__ bool sorted_contains_interp(const int32_t *a, int32_t n, int32_t u, int32_t vend)
+{
+    return sorted_find_interp(a, n, u, vend) >= 0;
 }
 
 // Exact map of the graph's entries (v, u) to their h: open addressing over 128-byte
@@ -229,12 +234,6 @@ __device__ __forceinline__ int index_probe(const uint4 *tab, uint64_t mask, int3
 __device__ __forceinline__ bool index_contains(const uint4 *tab, uint64_t mask, int32_t v, int32_t u)
 {
     return index_probe<false>(tab, mask, v, u, nullptr) >= 0;
-}
-
-// (v, u) in the graph, with h(v, u) in *h when it is.
-__device__ __forceinline__ bool index_find_h(const uint4 *tab, uint64_t mask, int32_t v, int32_t u, float *h)
-{
-    return index_probe<true>(tab, mask, v, u, h) >= 0;
 }
 
 // ceil(log2(m + 1)): probes of a binary search over m entries.

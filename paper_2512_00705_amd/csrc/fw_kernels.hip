@@ -528,27 +528,17 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 const float hw = hprop ? 1.0f : hv;  // the test is on w~ (uniform) or w (h-proportional)
                 const float y = unit_uniform(ux[0]) * B;
                 float hsel = ol[0] ? hlast : hv;  // symmetric h: h(cur, prev) = h(prev, cur)
-                bool acc;
+                bool acc = false;
+                // a test left open by the bounds of w~ looks (lv, u) up once: in N(prev)
+                // for the membership test, in N(cur) with its h for a member trial
+                bool look = false;
                 if (ol[0]) {
                     acc = true;  // the extra column belongs to the return edge
                 } else if (MB && uses_membership(KIND) && mr[0]) {
                     // member region: keep x = u when it is a neighbour of cur (not prev),
                     // with probability h(cur, x) / h_MAX
                     st_bytes += 4 + (a.mtab ? 12 : 4 * (uint64_t)probes(deg));
-                    bool found = false;
-                    float hx = 1.0f;
-                    if (u != prev) {
-                        if (a.mtab) {
-                            found = index_find_h(a.mtab, a.mtab_mask, cur, u, &hx);
-                        } else {
-                            const int64_t pos = sorted_find(a.col + base, deg, u);
-                            found = pos >= 0;
-                            if (found && W) hx = __uint_as_float(a.edges[base + pos].y);
-                        }
-                    }
-                    if (!W) hx = 1.0f;
-                    hsel = hx;
-                    acc = found && unit_uniform(ux[0]) * hmx < hx;
+                    look = u != prev;
                 } else if (MB && uses_membership(KIND) && mb) {
                     // regular columns of the member board: every proposal at w_oth, the
                     // return edge at min(w_ret, w_oth)
@@ -560,20 +550,33 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                         acc = y < sw.ret * hw;
                     } else {
                         const float lo = sw.lo * hw, hi = sw.hi * hw;
-                        if (y < lo) {
-                            acc = true;
-                        } else if (!(y < hi)) {
-                            acc = false;
-                        } else {
-                            st_bytes += a.mtab ? 8 : 4 * (uint64_t)probes(pdeg);
-                            const bool member = a.mtab ? index_contains(a.mtab, a.mtab_mask, prev, u)
-                                                       : sorted_contains_interp(a.col + pbase, pdeg, u, (int32_t)a.nv);
-                            const float wt = member ? sw.mem * hw : sw.oth * hw;
-                            acc = y < wt;
-                        }
+                        acc = y < lo;
+                        look = !acc && y < hi;
+                        if (look) st_bytes += a.mtab ? 8 : 4 * (uint64_t)probes(pdeg);
                     }
                 } else {
                     acc = y < (ll[0] == want ? hw : 0.0f);
+                }
+                if (uses_membership(KIND) && look) {
+                    const bool mem_trial = MB && mr[0];
+                    const int32_t lv = mem_trial ? cur : prev;
+                    float hx = 1.0f;
+                    bool found;
+                    if (a.mtab) {
+                        found = MB ? index_probe<true>(a.mtab, a.mtab_mask, lv, u, &hx) >= 0
+                                   : index_contains(a.mtab, a.mtab_mask, lv, u);
+                    } else {
+                        const int64_t rb = mem_trial ? base : pbase;
+                        const int32_t pos = sorted_find_interp(a.col + rb, mem_trial ? deg : pdeg, u, (int32_t)a.nv);
+                        found = pos >= 0;
+                        if (MB && found && W) hx = __uint_as_float(a.edges[rb + pos].y);
+                    }
+                    if (mem_trial) {
+                        hsel = W ? hx : 1.0f;
+                        acc = found && unit_uniform(ux[0]) * hmx < hsel;
+                    } else {
+                        acc = y < (found ? sw.mem * hw : sw.oth * hw);
+                    }
                 }
                 ++trials;
                 st[kStTrials] += 1;
