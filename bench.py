@@ -80,6 +80,8 @@ def main():
     ap.add_argument("--logic", default="node2vec", choices=["node2vec", "secondpr"],
                     help="walk logic of the scale-22 job (node2vec p, q or second-order PageRank gamma)")
     ap.add_argument("--gamma", type=float, default=0.2)
+    ap.add_argument("--weights", default="f32", choices=["f32", "q8"],
+                    help="edge property weights as float32, or as 8-bit codes (scale 10/255) of the same weights")
     ap.add_argument("--strategy", default="auto", choices=["auto", "rvs", "rjs"])
     ap.add_argument("--modes", type=int, default=1, help="also time the single-kernel modes")
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -150,8 +152,13 @@ def main():
     g = synth.cached(args.graph)
     log(f"graph {args.graph}: nv={g['nv']} ne={g['ne']} ({time.time() - t0:.1f}s)")
     dev = torch.device("cuda:0")
-    t = {k: torch.from_numpy(g[k]).to(dev) for k in ("row_ptr", "col", "h") if g.get(k) is not None}
-    gh = fw.fw_graph_create(g["nv"], g["ne"], t["row_ptr"], t["col"], t.get("h"), None, on_device=True)
+    if args.weights == "q8":  # the same weights stored as 8-bit codes
+        g = dict(g)
+        g["h8"], g["h_scale"] = synth.quantize_u8(g["h"])
+        g["h"] = None
+    t = {k: torch.from_numpy(g[k]).to(dev) for k in ("row_ptr", "col", "h", "h8") if g.get(k) is not None}
+    gh = fw.fw_graph_create(g["nv"], g["ne"], t["row_ptr"], t["col"], t.get("h"), None, on_device=True,
+                            h8=t.get("h8"), h_scale=float(g.get("h_scale", 0.0)))
     del t
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -278,7 +285,8 @@ def main():
         log(f"cpu oracle: {cpu}")
 
     fw.fw_graph_destroy(gh)
-    traffic = measured_traffic(plan, st)
+    # the recorded counters cover the float32-weight Node2Vec job only
+    traffic = measured_traffic(plan, st) if (args.weights == "f32" and args.logic == "node2vec") else None
     ceiling = fw.fw_calibrate_random_reads(4 << 30)  # random 8-byte reads/s, 128 B moved each
     random_access = {"ceiling_reads_per_s": ceiling,
                      "achieved_reads_per_s": None if traffic is None else traffic["read_requests"] / (avg_ms / 1e3),
@@ -296,7 +304,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{logic_text} weighted h~U(1,10), R-MAT scale 22 "
+        "config": {"workload": f"{logic_text} weighted h~U(1,10)"
+                               + (" stored as 8-bit codes (h = (10/255)*code)" if args.weights == "q8" else "")
+                               + ", R-MAT scale 22 "
                                f"(a=0.57,b=0.19,c=0.19, edge factor 16, {g['ne']} CSR entries), one walker "
                                f"per vertex ({nv}), L={L}, strategy={args.strategy}",
                    "walker_steps_per_walk_job": steps_per_walk, "preprocess_ms": prep_ms,

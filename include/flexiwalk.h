@@ -63,6 +63,13 @@ typedef struct fw_csr {
     const float *h;         /* ne entries or NULL */
     const uint8_t *label;   /* ne entries or NULL */
     int32_t on_device;
+    /* 8-bit property weights (the low-precision edge weights of Section 7): ne codes or
+     * NULL.  When given, h must be NULL and h(v,u) = h_scale * code, one float32 product
+     * (round to nearest); the walk then reads a 4-byte record {col in bits 0..23, code in
+     * bits 24..31} per edge when nv <= 2^24 (else the usual 8-byte {col, h} record of the
+     * dequantised weight).  Samples depend only on the dequantised weights. */
+    const uint8_t *h8;
+    float h_scale;          /* finite, > 0 when h8 is given; ignored otherwise */
 } fw_csr;
 
 typedef struct fw_graph fw_graph; /* opaque, library-owned device copy of a graph */

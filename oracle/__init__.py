@@ -44,7 +44,7 @@ COUNTER_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials
 class _Graph(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("h", ctypes.c_void_p), ("label", ctypes.c_void_p),
-                ("alias_thr", ctypes.c_void_p), ("alias_idx", ctypes.c_void_p)]
+                ("alias_thr", ctypes.c_void_p), ("alias_idx", ctypes.c_void_p), ("h8", ctypes.c_int32)]
 
 
 class _Logic(ctypes.Structure):
@@ -120,6 +120,8 @@ def _configure(lib):
     lib.og_uniform.argtypes = [ctypes.c_uint32]
     lib.og_uniform.restype = ctypes.c_float
     lib.og_preprocess.argtypes = [ctypes.POINTER(_Graph), P, P]
+    lib.og_dequantize_h8.argtypes = [P, ctypes.c_float, ctypes.c_int64, P]
+    lib.og_dequantize_h8.restype = None
     lib.og_build_alias.argtypes = [ctypes.POINTER(_Graph), P, P]
     lib.og_build_alias.restype = None
     lib.og_preprocess.restype = None
@@ -178,12 +180,16 @@ class Graph:
         self.row_ptr = np.ascontiguousarray(g["row_ptr"], np.int64)
         self.col = np.ascontiguousarray(g["col"], np.int32)
         self.h = None if g.get("h") is None else np.ascontiguousarray(g["h"], np.float32)
+        if g.get("h8") is not None:  # 8-bit property weights: h = h_scale * code
+            assert self.h is None, "give h or h8, not both"
+            self.h = dequantize_h8(g["h8"], g["h_scale"])
         self.label = None if g.get("label") is None else np.ascontiguousarray(g["label"], np.uint8)
         s = _Graph()
         s.nv, s.ne = self.nv, self.ne
         s.row_ptr, s.col = self.row_ptr.ctypes.data, self.col.ctypes.data
         s.h = self.h.ctypes.data if self.h is not None else None
         s.label = self.label.ctypes.data if self.label is not None else None
+        s.h8 = int(g.get("h8") is not None)
         self._s = s
         self._aux = None
         self._alias = None
@@ -207,6 +213,14 @@ class Graph:
             self._alias = (thr, idx)
             self._s.alias_thr, self._s.alias_idx = thr.ctypes.data, idx.ctypes.data
         return self._alias
+
+
+def dequantize_h8(code, h_scale: float) -> np.ndarray:
+    """Weights of 8-bit codes: h = h_scale * code in float32 (og_dequantize_h8)."""
+    c = np.ascontiguousarray(code, np.uint8)
+    out = np.empty(c.shape[0], np.float32)
+    _load().og_dequantize_h8(c.ctypes.data, float(np.float32(h_scale)), c.shape[0], out.ctypes.data)
+    return out
 
 
 def philox(ctr, key) -> np.ndarray:

@@ -114,6 +114,13 @@ static void draw(uint64_t seed, uint32_t walker, uint32_t step, uint32_t idx, ui
     og_philox(ctr, key, out);
 }
 
+/* 8-bit property weights (Section 7, low-precision edge weights): the weight of a code
+ * is h_scale * code, one float32 product rounded to nearest. */
+void og_dequantize_h8(const uint8_t *code, float h_scale, int64_t n, float *h)
+{
+    for (int64_t k = 0; k < n; ++k) h[k] = (float)code[k] * h_scale;
+}
+
 /* Transcendentals: exact value (double libm) rounded once to float32. */
 static float ln_f(float x) { return (float)log((double)x); }
 static float expm1_f(float x) { return (float)expm1((double)x); }
@@ -128,6 +135,8 @@ typedef struct {
     const uint8_t *label; /* NULL unless MetaPath */
     const uint32_t *alias_thr; /* per entry: keep-threshold of its alias slot (og_build_alias), or NULL */
     const int32_t *alias_idx;  /* per entry: row offset of its alias */
+    int32_t h8;                /* 1: h holds dequantised 8-bit codes (og_dequantize_h8); a scanned
+                                  or proposed edge then moves 1 byte of weight instead of 4 */
 } og_graph;
 
 enum { OG_NODE2VEC = 1, OG_METAPATH = 2, OG_SECOND_PR = 3 };
@@ -342,7 +351,7 @@ static float w_avg(const og_logic *lg, int j, int64_t dv, int64_t dvp)
 static double bytes_per_item(const og_ctx *cx)
 {
     double b = 4.0;                                   /* col */
-    if (cx->lg->weighted && cx->g->h) b += 4.0;       /* h */
+    if (cx->lg->weighted && cx->g->h) b += cx->g->h8 ? 1.0 : 4.0; /* h: float or 8-bit code */
     if (cx->lg->kind == OG_METAPATH) b += 1.0;        /* label */
     return b;
 }

@@ -43,7 +43,7 @@ class FlexiWalkError(RuntimeError):
 class fw_csr(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("h", ctypes.c_void_p), ("label", ctypes.c_void_p),
-                ("on_device", ctypes.c_int32)]
+                ("on_device", ctypes.c_int32), ("h8", ctypes.c_void_p), ("h_scale", ctypes.c_float)]
 
 
 class fw_logic(ctypes.Structure):
@@ -143,9 +143,11 @@ def fw_last_error() -> str:
     return _lib.fw_last_error().decode()
 
 
-def fw_graph_create(nv: int, ne: int, row_ptr, col, h=None, label=None, on_device: bool = False) -> int:
-    """Returns an opaque graph handle (int).  Arrays: numpy (host) or torch (device)."""
-    c = fw_csr(nv, ne, _ptr(row_ptr), _ptr(col), _ptr(h), _ptr(label), int(on_device))
+def fw_graph_create(nv: int, ne: int, row_ptr, col, h=None, label=None, on_device: bool = False, h8=None,
+                    h_scale: float = 0.0) -> int:
+    """Returns an opaque graph handle (int).  Arrays: numpy (host) or torch (device).
+    ``h8``/``h_scale``: 8-bit property weights h = h_scale * code instead of ``h``."""
+    c = fw_csr(nv, ne, _ptr(row_ptr), _ptr(col), _ptr(h), _ptr(label), int(on_device), _ptr(h8), float(h_scale))
     out = ctypes.c_void_p()
     _check(_lib.fw_graph_create(ctypes.byref(c), ctypes.byref(out)))
     return out.value

@@ -1,6 +1,7 @@
 // C ABI of the sampler (include/flexiwalk.h): argument checks, device memory
 // ownership, plan construction and kernel launches.  All sampling runs in
 // fw_kernels.hip.
+#include <float.h>
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -57,6 +58,7 @@ static void graph_free(fw_graph *g)
     (void)hipFree(g->h);
     (void)hipFree(g->label);
     (void)hipFree(g->edges);
+    (void)hipFree(g->erec8);
     (void)hipFree(g->vrec);
     (void)hipFree(g->start_hi);
     (void)hipFree(g->scratch);
@@ -78,6 +80,12 @@ static int dev_copy(T **dst, const T *src, int64_t count, int on_device)
     return FW_OK;
 }
 
+// device memory freed at scope exit
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() { (void)hipFree(p); }
+};
+
 extern "C" {
 
 const char *fw_last_error(void) { return fw::host::g_err.c_str(); }
@@ -90,6 +98,9 @@ int fw_graph_create(const fw_csr *in, fw_graph **out)
     if (in->nv >= ((int64_t)1 << 30)) return fail(FW_E_INVALID, "fw_graph_create: nv must be < 2^30");
     if (!in->row_ptr || (in->ne > 0 && !in->col))
         return fail(FW_E_INVALID, "fw_graph_create: row_ptr/col missing");
+    if (in->h8 && in->h) return fail(FW_E_INVALID, "fw_graph_create: give h or h8, not both");
+    if (in->h8 && !(in->h_scale > 0.0f && in->h_scale <= FLT_MAX))
+        return fail(FW_E_INVALID, "fw_graph_create: h_scale must be finite and > 0 with h8");
 
     fw_graph *g = new fw_graph();
     (void)hipGetDevice(&g->device);
@@ -103,8 +114,30 @@ int fw_graph_create(const fw_csr *in, fw_graph **out)
         graph_free(g);
         return rc;
     }
+    // 8-bit weights: the dequantised h serves preprocessing, validation and the index and
+    // proposal builds; the walk reads 4-byte records {col, code} when vertex ids fit 24 bits
+    DevBuf codes;
+    if (in->h8) {
+        g->q8 = true;
+        g->h_scale = in->h_scale;
+        if ((rc = dev_copy((uint8_t **)&codes.p, in->h8, in->ne, in->on_device)) != FW_OK) {
+            graph_free(g);
+            return rc;
+        }
+        if (hipMalloc((void **)&g->h, sizeof(float) * (size_t)(g->ne > 0 ? g->ne : 1)) != hipSuccess) {
+            graph_free(g);
+            return fail(FW_E_NOMEM, "fw_graph_create: hipMalloc failed");
+        }
+        const hipError_t e = fw::launch_dequantize((const uint8_t *)codes.p, g->h_scale, g->ne, g->h, nullptr);
+        if (e != hipSuccess) {
+            graph_free(g);
+            return fail(FW_E_DEVICE, "fw_graph_create: %s", hipGetErrorString(e));
+        }
+    }
+    const bool packed = g->q8 && g->nv <= ((int64_t)1 << 24);
     const bool wide = g->ne >= ((int64_t)1 << 32);
-    if (hipMalloc((void **)&g->edges, sizeof(uint2) * (size_t)(g->ne > 0 ? g->ne : 1)) != hipSuccess ||
+    if ((packed && hipMalloc((void **)&g->erec8, sizeof(uint32_t) * (size_t)(g->ne > 0 ? g->ne : 1)) != hipSuccess) ||
+        (!packed && hipMalloc((void **)&g->edges, sizeof(uint2) * (size_t)(g->ne > 0 ? g->ne : 1)) != hipSuccess) ||
         hipMalloc((void **)&g->vrec, sizeof(uint4) * (size_t)(g->nv > 0 ? g->nv : 1)) != hipSuccess ||
         (wide && hipMalloc((void **)&g->start_hi, sizeof(uint32_t) * (size_t)g->nv) != hipSuccess) ||
         hipMalloc((void **)&g->scratch, 4 * sizeof(unsigned long long)) != hipSuccess) {
@@ -150,6 +183,7 @@ int fw_graph_create(const fw_csr *in, fw_graph **out)
     }
     g->symmetric = (host_chk[0] & 16u) == 0;
     e = fw::launch_layout(g->row_ptr, g->col, g->h, g->nv, g->ne, g->edges, g->vrec, g->start_hi, nullptr);
+    if (e == hipSuccess && packed) e = fw::launch_pack8(g->col, (const uint8_t *)codes.p, g->ne, g->erec8, nullptr);
     if (e == hipSuccess) e = hipMemset(g->scratch, 0, 4 * sizeof(unsigned long long));
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
@@ -327,6 +361,8 @@ void fw::host::fill_args(const fw_graph *g, const fw_logic *lg, fw::WalkArgs &a)
 {
     memset(&a, 0, sizeof(a));
     a.edges = g->edges;
+    a.erec8 = g->erec8;
+    a.h_scale = g->h_scale;
     a.vrec = g->vrec;
     a.start_hi = g->start_hi;
     a.col = g->col;
@@ -337,7 +373,7 @@ void fw::host::fill_args(const fw_graph *g, const fw_logic *lg, fw::WalkArgs &a)
     a.prop = g->prop;
     fill_query(lg, a.q0);
     const bool weighted = lg->weighted && g->h;
-    a.item_bytes = 4 + (weighted ? 4 : 0) + (lg->kind == FW_METAPATH ? 1 : 0);
+    a.item_bytes = 4 + (weighted ? (g->q8 ? 1 : 4) : 0) + (lg->kind == FW_METAPATH ? 1 : 0);
 }
 
 int fw::host::check_plan(const fw_plan *pl)
@@ -433,11 +469,6 @@ int fw_graph_check(fw_graph *g, void *stream)
 }
 
 // Device buffer released on scope exit.
-struct DevBuf {
-    void *p = nullptr;
-    ~DevBuf() { (void)hipFree(p); }
-};
-
 struct Events {
     hipEvent_t a = nullptr, b = nullptr;
     ~Events()

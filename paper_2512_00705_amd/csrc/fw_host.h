@@ -16,7 +16,10 @@ struct fw_graph {
     int32_t *col = nullptr;
     float *h = nullptr;
     uint8_t *label = nullptr;
-    uint2 *edges = nullptr;                 // {col, bits(h)} per entry
+    uint2 *edges = nullptr;                 // {col, bits(h)} per entry, or null when erec8 holds the edges
+    uint32_t *erec8 = nullptr;              // 8-bit weights: {col | code << 24} per entry (nv <= 2^24), or null
+    float h_scale = 0.0f;                   // 8-bit weights: h = h_scale * code
+    bool q8 = false;                        // the weights came as 8-bit codes
     uint4 *vrec = nullptr;                  // {start_lo, degree, bits(h_MAX), bits(h_SUM)} per vertex
     uint32_t *start_hi = nullptr;           // high row-start bits, only when ne >= 2^32
     unsigned long long *scratch = nullptr;  // [0] walker queue, [1] error flag (int)

@@ -71,12 +71,16 @@ constexpr int32_t kDone = INT32_MIN;
 
 // Device layout of a graph.  Besides the caller's CSR the library keeps
 //   edges[k] = {col[k], bits(h[k])}: one 8-byte load per proposed or scanned edge;
+//   erec8[k] = col[k] | code[k] << 24 instead, for 8-bit weights on graphs of at most
+//              2^24 vertices: one 4-byte load, h = h_scale * code;
 //   vrec[v]  = {low 32 bits of row start, degree, bits(h_MAX[v]), bits(h_SUM[v])}:
 //              one 16-byte load per step set-up;
 //   start_hi[v] = high 32 bits of the row start (only when ne >= 2^32, else null);
 //   col (alone) for the membership search and LDS staging of N(prev).
 struct WalkArgs {
-    const uint2 *edges;
+    const uint2 *edges;         // null when erec8 holds the edges
+    const uint32_t *erec8;      // 8-bit weights: {col | code << 24} per entry, or null
+    float h_scale;              // 8-bit weights: h = h_scale * code
     const uint4 *vrec;
     const uint32_t *start_hi;
     const int32_t *col;
@@ -95,7 +99,7 @@ struct WalkArgs {
     int32_t item_bytes;         // col (+ h) (+ label) per scanned or proposed edge
     int32_t tick_steps;         // resumable walks: steps per walker per launch
     int32_t bound;              // 1: Node2Vec split eRJS bound (symmetric graphs only)
-    const uint4 *mtab;          // edge index (4 uint4 per bucket) or null: search the sorted rows
+    const uint4 *mtab;          // edge index (8 uint4 per bucket) or null: search the sorted rows
     const uint4 *prop;          // proposal records (2 uint4 per entry) or null
     int32_t proposal;           // 1: h-proportional eRJS proposals through `prop`
     uint64_t mtab_mask;         // buckets - 1
@@ -108,6 +112,10 @@ struct WalkArgs {
 hipError_t launch_walk(const WalkArgs &a, int kind, bool weighted, bool batch, int grid, hipStream_t s);
 hipError_t launch_zero(unsigned long long *p, int n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+// 8-bit weights: h[k] = h_scale * code[k] (float32 product) for k < ne.
+hipError_t launch_dequantize(const uint8_t *code, float h_scale, int64_t ne, float *h, hipStream_t s);
+// 8-bit weights: erec8[k] = col[k] | code[k] << 24 for k < ne (every col < 2^24).
+hipError_t launch_pack8(const int32_t *col, const uint8_t *code, int64_t ne, uint32_t *erec8, hipStream_t s);
 hipError_t launch_layout(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int64_t ne,
                          uint2 *edges, uint4 *vrec, uint32_t *start_hi, hipStream_t s);
 hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv, uint4 *vrec, hipStream_t s);

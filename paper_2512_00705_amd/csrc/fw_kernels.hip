@@ -107,6 +107,17 @@ __device__ __forceinline__ float edge_weight(const WalkArgs &a, const QueryDev &
     }
 }
 
+// The {col, bits(h)} record of CSR entry k: the 8-byte record, or the 4-byte record of an
+// 8-bit-weight graph decoded (h = h_scale * code, one float32 product).
+__device__ __forceinline__ uint2 edge_rec(const WalkArgs &a, int64_t k)
+{
+    if (a.erec8 != nullptr) {
+        const uint32_t x = a.erec8[k];
+        return make_uint2(x & 0xFFFFFFu, __float_as_uint((float)(x >> 24) * a.h_scale));
+    }
+    return a.edges[k];
+}
+
 __device__ __forceinline__ int64_t row_start(const WalkArgs &a, uint4 r, int32_t v)
 {
     return a.start_hi ? (int64_t)(((uint64_t)a.start_hi[v] << 32) | r.x) : (int64_t)r.x;
@@ -128,7 +139,7 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q
     // round 0: lane l keys neighbour l, k = u^(1/w~) kept as log(u) / w~
     if (lane < deg) {
         const int64_t k = base + lane;
-        const float wt = edge_weight<KIND, W>(a, Q, k, a.edges[k], j, prev, mem, want, sw);
+        const float wt = edge_weight<KIND, W>(a, Q, k, edge_rec(a, k), j, prev, mem, want, sw);
         const U4 x = philox(wid, (uint32_t)j, (uint32_t)lane, 1u, k0, k1);
         key = wt > 0.0f ? ln_f(unit_uniform(x.x0)) / wt : -INFINITY;
         ru = unit_uniform(x.x1);
@@ -145,7 +156,7 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q
         const int64_t i = i0 + lane;
         if (i < deg) {
             const int64_t k = base + i;
-            const float wt = edge_weight<KIND, W>(a, Q, k, a.edges[k], j, prev, mem, want, sw);
+            const float wt = edge_weight<KIND, W>(a, Q, k, edge_rec(a, k), j, prev, mem, want, sw);
             S = S + wt;
             if (S > T) {
                 // key conditioned to beat thr: log u' = log1p(expm1(w~ * thr) * V)
@@ -166,7 +177,7 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q
     wave_argmax(key, bi);
     trig = (uint32_t)wave_sum_u64(nt);
     if (!(key > -INFINITY)) return -1;
-    const uint2 e = a.edges[base + bi];
+    const uint2 e = edge_rec(a, base + bi);
     hsel = W ? __uint_as_float(e.y) : 1.0f;
     return (int32_t)e.x;
 }
@@ -214,7 +225,7 @@ __device__ __forceinline__ bool rvs_group_pass(const WalkArgs &a, int G, uint64_
         const uint8_t want = (KIND == kMetaPath) ? Q.schema[s_j % Q.schema_len] : (uint8_t)0;
         const Mem m = {a.col + s_pbase, s_pdeg, false, false};
         const StepW sw = step_weights<KIND>(Q, s_deg, s_pdeg);
-        const float wt = edge_weight<KIND, W>(a, Q, k, a.edges[k], s_j, s_prev, m, want, sw);
+        const float wt = edge_weight<KIND, W>(a, Q, k, edge_rec(a, k), s_j, s_prev, m, want, sw);
         const U4 x = philox(s_wid, (uint32_t)s_j, (uint32_t)r, 1u, Q.key0, Q.key1);
         key = wt > 0.0f ? ln_f(unit_uniform(x.x0)) / wt : -INFINITY;
         bi = r;
@@ -228,7 +239,7 @@ __device__ __forceinline__ bool rvs_group_pass(const WalkArgs &a, int G, uint64_
         }
     }
     uint2 e = make_uint2(0xffffffffu, 0u);
-    if (key > -INFINITY) e = a.edges[s_base + bi];
+    if (key > -INFINITY) e = edge_rec(a, s_base + bi);
     const int from = my_slot >= 0 ? my_slot * G : lane;
     const int32_t got = __shfl((int32_t)e.x, from, kWave);
     const uint32_t got_h = (uint32_t)__shfl((int32_t)e.y, from, kWave);
@@ -327,7 +338,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                         hlast = 1.0f;
                         if (KIND == kNode2Vec && W && a.bound != 0) {
                             const int64_t pos = sorted_find(a.col + pbase, pdeg, cur);
-                            if (pos >= 0) hlast = __uint_as_float(a.edges[pbase + pos].y);
+                            if (pos >= 0) hlast = __uint_as_float(edge_rec(a, pbase + pos).y);
                         }
                         stop_j = pj + a.tick_steps;
                         st_bytes += 4 + 8 + 16;
@@ -514,7 +525,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                     ee[r] = keep ? make_uint2(r0.x, r0.y) : make_uint2(r0.z, r0.w);
                     ll[r] = (KIND == kMetaPath) ? (uint8_t)(keep ? r1.y : r1.y >> 8) : (uint8_t)0;
                 } else {
-                    ee[r] = a.edges[k];
+                    ee[r] = edge_rec(a, k);
                     ll[r] = (KIND == kMetaPath) ? a.label[k] : (uint8_t)0;
                 }
             }
@@ -569,7 +580,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                         const int64_t rb = mem_trial ? base : pbase;
                         const int32_t pos = sorted_find_interp(a.col + rb, mem_trial ? deg : pdeg, u, (int32_t)a.nv);
                         found = pos >= 0;
-                        if (MB && found && W) hx = __uint_as_float(a.edges[rb + pos].y);
+                        if (MB && found && W) hx = __uint_as_float(edge_rec(a, rb + pos).y);
                     }
                     if (mem_trial) {
                         hsel = W ? hx : 1.0f;
@@ -741,13 +752,30 @@ __global__ void __launch_bounds__(kBlock) preprocess_kernel(const int64_t *row_p
 }
 
 // Device layout: {col, h} edge records and {start, degree, -, -} vertex records.
+// 8-bit property weights: h = h_scale * code, one float32 product.
+__global__ void dequantize_kernel(const uint8_t *code, float h_scale, int64_t ne, float *h)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ne; k += stride)
+        h[k] = (float)code[k] * h_scale;
+}
+
+// 8-bit property weights on graphs of at most 2^24 vertices: a 4-byte edge record.
+__global__ void pack8_kernel(const int32_t *col, const uint8_t *code, int64_t ne, uint32_t *erec8)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ne; k += stride)
+        erec8[k] = (uint32_t)col[k] | ((uint32_t)code[k] << 24);
+}
+
 __global__ void layout_kernel(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int64_t ne,
                               uint2 *edges, uint4 *vrec, uint32_t *start_hi)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int64_t k = t0; k < ne; k += stride)
-        edges[k] = make_uint2((uint32_t)col[k], __float_as_uint(h ? h[k] : 1.0f));
+    if (edges)
+        for (int64_t k = t0; k < ne; k += stride)
+            edges[k] = make_uint2((uint32_t)col[k], __float_as_uint(h ? h[k] : 1.0f));
     for (int64_t v = t0; v < nv; v += stride) {
         const int64_t b = row_ptr[v], e = row_ptr[v + 1];
         vrec[v] = make_uint4((uint32_t)b, (uint32_t)(e - b), 0u, 0u);
@@ -907,7 +935,7 @@ __global__ void __launch_bounds__(kBlock) profile_rvs_kernel(WalkArgs a, const i
         const uint4 rp = a.vrec[prev];
         const int64_t pb = row_start(a, rp, prev), pd = (int64_t)rp.y;
         for (int64_t i = lane; i < m; i += kWave)
-            acc += edge_weight<KIND, W>(a, a.q0, b + i, a.edges[b + i], 1, prev, Mem{a.col + pb, pd, false, false},
+            acc += edge_weight<KIND, W>(a, a.q0, b + i, edge_rec(a, b + i), 1, prev, Mem{a.col + pb, pd, false, false},
                                         a.q0.schema[0], step_weights<KIND>(a.q0, (int32_t)d, (int32_t)pd));
     }
     acc = wave_max(acc);
@@ -930,7 +958,7 @@ __global__ void __launch_bounds__(kBlock) profile_rjs_kernel(WalkArgs a, const i
         for (int t = 0; t < per_node; ++t) {
             const U4 x = philox((uint32_t)s, 0u, (uint32_t)t, 2u, a.q0.key0, a.q0.key1);
             const int64_t k = b + scaled_index(x.x0, x.x1, d);
-            acc += edge_weight<KIND, W>(a, a.q0, k, a.edges[k], 1, prev, Mem{a.col + pb, pd, false, true}, a.q0.schema[0],
+            acc += edge_weight<KIND, W>(a, a.q0, k, edge_rec(a, k), 1, prev, Mem{a.col + pb, pd, false, true}, a.q0.schema[0],
                                         step_weights<KIND>(a.q0, (int32_t)d, (int32_t)pd));
         }
     }
@@ -1088,6 +1116,24 @@ hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const 
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(build_alias_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, label, nv,
                        sc, stk_s, stk_l, alias, prop);
+    return hipGetLastError();
+}
+
+hipError_t launch_dequantize(const uint8_t *code, float h_scale, int64_t ne, float *h, hipStream_t s)
+{
+    if (ne <= 0) return hipSuccess;
+    int64_t blocks = (ne + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(dequantize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, code, h_scale, ne, h);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack8(const int32_t *col, const uint8_t *code, int64_t ne, uint32_t *erec8, hipStream_t s)
+{
+    if (ne <= 0) return hipSuccess;
+    int64_t blocks = (ne + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(pack8_kernel, dim3((unsigned)blocks), dim3(256), 0, s, col, code, ne, erec8);
     return hipGetLastError();
 }
 

@@ -125,6 +125,15 @@ def degree_weights(row_ptr: np.ndarray, col: np.ndarray) -> np.ndarray:
     return deg[np.asarray(col)].astype(np.float32)
 
 
+def quantize_u8(h: np.ndarray, h_top: float = 10.0) -> tuple[np.ndarray, np.float32]:
+    """8-bit codes for float weights in (0, h_top]: scale = h_top / 255 in float32 and
+    code = clip(round(h / scale), 1, 255), so U(1, 10) weights become codes 25..255.
+    Returns (codes uint8, scale); the weights such a graph carries are scale * code."""
+    scale = np.float32(h_top / 255.0)
+    c = np.rint(np.asarray(h, np.float64) / np.float64(scale))
+    return np.clip(c, 1, 255).astype(np.uint8), scale
+
+
 def csr_from_edges(nv: int, edges, h=None, label=None, symmetric: bool = True) -> dict:
     """Small hand-built graphs: CSR from an edge list with optional per-edge values.
 

@@ -17,16 +17,15 @@ class GpuGraph:
         self.g = g
         self.nv, self.ne = int(g["nv"]), int(g["ne"])
         dev = torch.device("cuda:0")
+        keys = ("row_ptr", "col", "h", "label", "h8")  # h8: 8-bit weight codes with g["h_scale"]
         if on_device:
-            self.t = {k: torch.from_numpy(np.ascontiguousarray(g[k])).to(dev)
-                      for k in ("row_ptr", "col", "h", "label") if g.get(k) is not None}
-            arrs = {k: self.t.get(k) for k in ("row_ptr", "col", "h", "label")}
+            self.t = {k: torch.from_numpy(np.ascontiguousarray(g[k])).to(dev) for k in keys if g.get(k) is not None}
+            arrs = {k: self.t.get(k) for k in keys}
         else:
-            arrs = {k: (None if g.get(k) is None else np.ascontiguousarray(g[k]))
-                    for k in ("row_ptr", "col", "h", "label")}
+            arrs = {k: (None if g.get(k) is None else np.ascontiguousarray(g[k])) for k in keys}
             self.host = arrs
         self.handle = fw.fw_graph_create(self.nv, self.ne, arrs["row_ptr"], arrs["col"], arrs["h"], arrs["label"],
-                                         on_device=on_device)
+                                         on_device=on_device, h8=arrs["h8"], h_scale=float(g.get("h_scale", 0.0)))
         if preprocess:
             fw.fw_graph_preprocess(self.handle)
         if index:

@@ -102,6 +102,34 @@ def test_second_pr_scale22(g22, gg22, og22, bound):
     assert_parity(rep)
 
 
+def test_node2vec_scale22_h8(g22):
+    """The scale-22 Node2Vec job with the weights stored as 8-bit codes (4-byte edge
+    records): the autotuned plan and eRVS-only, sampled walkers replayed by the oracle on
+    the same codes, every walk checked to follow edges."""
+    codes, scale = synth.quantize_u8(g22["h"])
+    gq = dict(g22, h=None, h8=codes, h_scale=scale)
+    gg = GpuGraph(gq, index=True, alias=True)
+    try:
+        tuned = fw.fw_plan_autotune(gg.handle, fw.fw_logic_node2vec(0.5, 2.0, True))
+        og = oracle.Graph(gq)
+        og.aux()
+        starts = synth.all_vertices(g22["nv"])
+        for strategy, k in ((oracle.AUTO, 65536), (oracle.RVS_ONLY, 1024)):
+            pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap, bound=tuned.bound,
+                             proposal=tuned.proposal, member_index=True)
+            p, ln, st = gpu_walk(gg, N2V, pl, strategy, starts, 80, 42)
+            ok, pad_ok, _ = edge_check_torch(g22, p, ln)
+            assert ok and pad_ok
+            sub = _sample(g22["nv"], k, 777)
+            ora = oracle.walk(og, N2V, pl, strategy, starts[sub], 80, 42, walker_ids=sub)
+            rep = parity(p[sub], ln[sub], ora)
+            print("h8 scale22", strategy, {k2: (v if not isinstance(v, list) else len(v)) for k2, v in rep.items()},
+                  st)
+            assert_parity(rep)
+    finally:
+        gg.close()
+
+
 def test_metapath_scale22(g22, gg22, og22):
     tuned = fw.fw_plan_autotune(gg22.handle, fw.fw_logic_metapath([0, 1, 2, 3, 4], True))
     pl = oracle.Plan(rho=tuned.rho, rjs_cap=tuned.rjs_cap, member_index=True)

@@ -618,3 +618,72 @@ def test_member_board_chisquare_hub(logic, proposal):
     at_hub = p[:, 1] == 0
     counts = {int(v): int(c) for v, c in zip(*np.unique(p[at_hub, 2], return_counts=True))}
     assert chisq_pvalue(counts, exact.transition(g, lg, 1, 1, 0), int(at_hub.sum())) > 1e-3
+
+
+# ------------------------------------------------------------------ 8-bit property weights
+def _q8(g):
+    codes, scale = synth.quantize_u8(g["h"])
+    gq = dict(g, h=None, h8=codes, h_scale=scale)
+    gf = dict(g, h=(codes.astype(np.float64) * np.float64(scale)).astype(np.float32))
+    return gq, gf
+
+
+Q8_LOGICS = {"n2v": oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=0.5, q=2.0), "2ndpr": PR2, "metapath": MP}
+
+
+@pytest.mark.parametrize("strategy", list(STRATS), ids=list(STRATS))
+@pytest.mark.parametrize("logic", list(Q8_LOGICS), ids=list(Q8_LOGICS))
+@pytest.mark.parametrize("plan", ["paper", "member_h"])
+def test_h8_scale12(g12, strategy, logic, plan):
+    """8-bit weights (4-byte edge records): walks and counters equal the oracle's on the
+    same codes, and walks equal the GPU's own walks on the float graph of the dequantised
+    weights (whose byte counter moves 3 bytes more per scanned or proposed edge)."""
+    gq, gf = _q8(g12)
+    lg = Q8_LOGICS[logic]
+    pl = (oracle.Plan(rho=1.0) if plan == "paper" else
+          oracle.Plan(rho=1.0, bound=2 if lg.kind != oracle.METAPATH else 0, proposal=1, member_index=True))
+    ggq = GpuGraph(gq, index=plan != "paper", alias=plan != "paper")
+    ggf = GpuGraph(gf, index=plan != "paper", alias=plan != "paper")
+    try:
+        starts = synth.all_vertices(g12["nv"])
+        p, ln, st = gpu_walk(ggq, lg, pl, STRATS[strategy], starts, 20, 61)
+        pf, lf, stf = gpu_walk(ggf, lg, pl, STRATS[strategy], starts, 20, 61)
+    finally:
+        ggq.close()
+        ggf.close()
+    np.testing.assert_array_equal(p, pf)
+    np.testing.assert_array_equal(ln, lf)
+    assert st["alg_bytes"] < stf["alg_bytes"]
+    ora = oracle.walk(oracle.Graph(gq), lg, pl, STRATS[strategy], starts, 20, 61)
+    rep = parity(p, ln, ora)
+    assert_parity(rep)
+    if rep["mismatch_walkers"] == 0:
+        _assert_counters(st, ora)
+
+
+def test_h8_wide_graph(g12):
+    """More than 2^24 vertices: the 8-bit weights fall back to 8-byte records of the
+    dequantised weight; walks and counters still equal the oracle's."""
+    gq, _ = _q8(g12)
+    nv = (1 << 24) + 64
+    rp = np.full(nv + 1, g12["ne"], np.int64)
+    rp[: g12["nv"] + 1] = g12["row_ptr"]
+    gw = dict(gq, nv=nv, row_ptr=rp, label=None)
+    gg = GpuGraph(gw)
+    try:
+        starts = synth.all_vertices(g12["nv"])
+        p, ln, st, ora = _run_both(gg, gw, N2V, oracle.Plan(rho=1.0), oracle.AUTO, starts, 12, 67)
+    finally:
+        gg.close()
+    rep = parity(p, ln, ora)
+    assert_parity(rep)
+    if rep["mismatch_walkers"] == 0:
+        _assert_counters(st, ora)
+
+
+def test_h8_argument_errors(g12):
+    gq, _ = _q8(g12)
+    for bad in (dict(gq, h_scale=0.0), dict(gq, h_scale=float("inf")), dict(gq, h=g12["h"])):
+        with pytest.raises(fw.FlexiWalkError) as e:
+            GpuGraph(bad)
+        assert e.value.code == fw.FW_E_INVALID

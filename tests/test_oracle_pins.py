@@ -669,3 +669,75 @@ def test_planted_mistake_is_caught(mut, mutant_libs):
             probs = exact.path_distribution(g, lg, 0, 3)
             caught.append(chisq_pvalue(counts, probs, n) < P_BAD)
     assert any(caught), MUTANTS[mut]
+
+
+# ------------------------------------------------------------------ 8-bit property weights
+def test_dequantize_h8_exact():
+    """h = h_scale * code rounded once to float32: the product of an 8-bit and a 24-bit
+    integer significand is exact in double, so rounding that double to float32 is the
+    correctly rounded product."""
+    codes = np.arange(256, dtype=np.uint8)
+    for scale in (np.float32(10.0 / 255.0), np.float32(1.0), np.float32(3e-5), np.float32(7.0),
+                  np.float32(1e30)):
+        got = oracle.dequantize_h8(codes, scale)
+        want = (codes.astype(np.float64) * np.float64(scale)).astype(np.float32)
+        np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def _q8(g):
+    """The graph with its weights as 8-bit codes, and the float graph of the same weights."""
+    codes, scale = synth.quantize_u8(g["h"])
+    gq = dict(g, h=None, h8=codes, h_scale=scale)
+    gf = dict(g, h=(codes.astype(np.float64) * np.float64(scale)).astype(np.float32))
+    return gq, gf
+
+
+@pytest.mark.parametrize("strategy", [oracle.RVS_ONLY, oracle.RJS_ONLY, oracle.AUTO], ids=["rvs", "rjs", "auto"])
+def test_h8_walks_equal_float_walks(strategy):
+    """A graph given as 8-bit codes walks exactly like the float graph of the dequantised
+    weights; only the algorithmic bytes differ: 3 bytes less per scanned or proposed
+    edge."""
+    g = synth.rmat(8, 8 << 8, seed=3)
+    g["h"], _ = synth.edge_props(g["row_ptr"], g["col"], 5)
+    gq, gf = _q8(g)
+    st = synth.all_vertices(g["nv"])
+    lg = oracle.Logic(**N2V)
+    pl = oracle.Plan(rho=1.0, rjs_cap=1 << 20)
+    a = oracle.walk(oracle.Graph(gq), lg, pl, strategy, st, 12, 21)
+    b = oracle.walk(oracle.Graph(gf), lg, pl, strategy, st, 12, 21)
+    np.testing.assert_array_equal(a.paths, b.paths)
+    for k in a.counters:
+        if k != "alg_bytes":
+            assert a.counters[k] == b.counters[k], k
+    # items moved: every eRVS step scans deg(v) edges, every eRJS trial reads one edge
+    deg = np.diff(g["row_ptr"])
+    items = 0
+    for p, n in zip(a.paths, a.lengths):
+        for j in range(n):
+            items += 0 if strategy == oracle.RJS_ONLY else int(deg[p[j]])
+    if strategy == oracle.RJS_ONLY:
+        items = int(a.counters["rjs_trials"])
+    if strategy != oracle.AUTO:
+        assert b.counters["alg_bytes"] - a.counters["alg_bytes"] == 3 * items
+    else:
+        assert b.counters["alg_bytes"] > a.counters["alg_bytes"]
+
+
+def test_h8_chisquare():
+    """Paths on the triangle graph with 8-bit weights follow the exact distribution of the
+    dequantised weights."""
+    g = triangle_graph()
+    codes = np.array([3, 200, 17, 255, 1, 90, 44, 128, 64], np.uint8)
+    g8 = synth.csr_from_edges(7, [(0, 1), (0, 2), (1, 2), (1, 3), (2, 3), (3, 4), (2, 4), (4, 5), (0, 5)],
+                              h=list(range(9)))
+    # the helper stores h per CSR entry from the edge list: map each entry to its code
+    idx = g8["h"].astype(np.int64)
+    scale = np.float32(0.37)
+    gq = dict(g, h=None, h8=codes[idx], h_scale=scale)
+    gf = dict(g, h=(codes[idx].astype(np.float64) * np.float64(scale)).astype(np.float32))
+    lg = oracle.Logic(**N2V)
+    n = 60000
+    for strategy, plan in ((oracle.RJS_ONLY, oracle.Plan()), (oracle.RVS_ONLY, oracle.Plan(lanes=2)),
+                           (oracle.RJS_ONLY, oracle.Plan(proposal=1, bound=2))):
+        counts, _ = _walk_counts(gq, lg, plan, strategy, 0, 3, n, seed=5)
+        assert chisq_pvalue(counts, exact.path_distribution(gf, lg, 0, 3), n) > P_OK
