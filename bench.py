@@ -200,22 +200,26 @@ def main():
     strat = {"auto": fw.FW_AUTO, "rvs": fw.FW_RVS_ONLY, "rjs": fw.FW_RJS_ONLY}
 
     def run(mode: str, steps: int, warmup: int, plan=plan, paths=paths, lengths=lengths):
+        # one launch with the device counters (steps, trials, algorithmic bytes); the walks
+        # are a fixed function of (seed, walker, step), so every launch below takes the
+        # same steps; the timed launches run without counters, as a caller would
+        stats.zero_()
+        fw.fw_walk(gh, logic, plan, strat[mode], starts, nv, L, seed, paths, lengths, stats)
         for _ in range(warmup):
             fw.fw_walk(gh, logic, plan, strat[mode], starts, nv, L, seed, paths, lengths, None)
         torch.cuda.synchronize()
-        stats.zero_()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         for a, b in evs:
             a.record()
-            fw.fw_walk(gh, logic, plan, strat[mode], starts, nv, L, seed, paths, lengths, stats)
+            fw.fw_walk(gh, logic, plan, strat[mode], starts, nv, L, seed, paths, lengths, None)
             b.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
         fw.fw_graph_check(gh)
         ms = [a.elapsed_time(b) for a, b in evs]
-        st = dict(zip(fw.STAT_NAMES, (stats.cpu().numpy() // max(steps, 1)).tolist()))
+        st = dict(zip(fw.STAT_NAMES, stats.cpu().numpy().tolist()))
         return ms, wall, st
 
     ms, wall, st = run(args.strategy, args.steps, args.warmup)
@@ -371,11 +375,11 @@ def bench_skew(args):
         row = {"weights": name, "h_max": float(h.max()), "h_median": float(np.median(h)), "plan_rho": plan.rho,
                "plan_bound": plan.bound, "plan_proposal": plan.proposal}
         for m, (strat, pl) in modes.items():
-            fw.fw_walk(gh, logic, pl, strat, starts, nv, L, seed, paths, lengths, None)  # warm-up
-            stats.zero_()
+            stats.zero_()  # warm-up launch with the counters; the timed one runs without
+            fw.fw_walk(gh, logic, pl, strat, starts, nv, L, seed, paths, lengths, stats)
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            fw.fw_walk(gh, logic, pl, strat, starts, nv, L, seed, paths, lengths, stats)
+            fw.fw_walk(gh, logic, pl, strat, starts, nv, L, seed, paths, lengths, None)
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1)
@@ -447,9 +451,11 @@ def bench_batched(args):
     b = fw.fw_batch_create(gh, qs, plan, fw.FW_AUTO, starts, paths, lengths)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
+        # one launch with the device counters, then the captured launch without them
+        fw.fw_batch_launch(b, stats, stream)
         for _ in range(args.warmup):
             fw.fw_batch_launch(b, None, stream)
-        fw.fw_batch_capture(b, stats, stream)
+        fw.fw_batch_capture(b, None, stream)
         stream.synchronize()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
         for e_a, e_b in evs:
@@ -459,7 +465,7 @@ def bench_batched(args):
         stream.synchronize()
     fw.fw_graph_check(gh)
     ms = [e_a.elapsed_time(e_b) for e_a, e_b in evs]
-    st = dict(zip(fw.STAT_NAMES, (stats.cpu().numpy() // max(args.steps, 1)).tolist()))
+    st = dict(zip(fw.STAT_NAMES, stats.cpu().numpy().tolist()))
     avg = float(np.mean(ms))
     log(f"batched graph replay ms {['%.2f' % x for x in ms]}, stats {st}")
     per_q = None

@@ -270,7 +270,9 @@ __device__ __forceinline__ void flush_stats(const WalkArgs &a, uint32_t (&cnt)[k
 // seed with counter (i, step, draw, tag), exactly as in a launch of its own.
 // MB: the member board of plan.bound = 2 (Node2Vec, second-order PageRank); a variant of
 // its own so that the lane state it needs costs the other plans no registers.
-template <int KIND, bool W, bool BATCH, bool MB>
+// STATS: the launch accumulates the device counters (a.stats non-null); without them the
+// per-lane counts are dead code and their registers go to the walk.
+template <int KIND, bool W, bool BATCH, bool MB, bool STATS>
 __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
 {
     extern __shared__ int32_t lds_all[];
@@ -304,7 +306,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
     bool exhausted = false;
 
     for (;;) {
-        if (a.stats != nullptr && __ballot((st[kStTrials] | st[kStTriggers] | st[kStSteps]) > 0x40000000u) != 0)
+        if (STATS && __ballot((st[kStTrials] | st[kStTriggers] | st[kStSteps]) > 0x40000000u) != 0)
             flush_stats(a, st, st_bytes);
 
         // 1. hand walkers to idle lanes: one atomic per wave
@@ -713,7 +715,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
         }
     }
 
-    if (a.stats != nullptr) flush_stats(a, st, st_bytes);
+    if (STATS) flush_stats(a, st, st_bytes);
 }
 
 __global__ void zero_kernel(unsigned long long *p, int n)
@@ -990,14 +992,22 @@ hipError_t launch_random_reads(const uint2 *a, uint64_t mask, int blocks, int ro
     return hipGetLastError();
 }
 
+template <int KIND, bool W, bool BATCH, bool STATS>
+static void launch_walk_s(const WalkArgs &a, int grid, size_t lds, hipStream_t s)
+{
+    if (uses_membership(KIND) && a.bound == 2)
+        hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, uses_membership(KIND), STATS>), dim3(grid), dim3(kBlock), lds,
+                           s, a);
+    else
+        hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, false, STATS>), dim3(grid), dim3(kBlock), lds, s, a);
+}
+
 template <int KIND, bool W, bool BATCH>
 static hipError_t launch_walk_t(const WalkArgs &a, int grid, hipStream_t s)
 {
     const size_t lds = (size_t)kWavesPerBlock * (size_t)a.lds_cap * sizeof(int32_t);
-    if (uses_membership(KIND) && a.bound == 2)
-        hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, uses_membership(KIND)>), dim3(grid), dim3(kBlock), lds, s, a);
-    else
-        hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, false>), dim3(grid), dim3(kBlock), lds, s, a);
+    if (a.stats != nullptr) launch_walk_s<KIND, W, BATCH, true>(a, grid, lds, s);
+    else launch_walk_s<KIND, W, BATCH, false>(a, grid, lds, s);
     return hipGetLastError();
 }
 
@@ -1022,7 +1032,7 @@ static int occupancy_blocks(int lds_cap)
 {
     int nb = 0;
     const size_t lds = (size_t)kWavesPerBlock * (size_t)lds_cap * sizeof(int32_t);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<KIND, W, BATCH, false>, kBlock, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<KIND, W, BATCH, false, true>, kBlock, lds) !=
         hipSuccess)
         nb = 1;
     return nb > 0 ? nb : 1;
