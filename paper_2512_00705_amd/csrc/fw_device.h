@@ -57,9 +57,84 @@ __device__ __forceinline__ uint32_t scaled_fraction_hi(uint32_t lo, uint32_t hi,
 
 // Logarithms rounded once to float32 from a double-precision evaluation, so the value
 // is the correctly rounded one except within ~1e-16 of a rounding tie.
-__device__ __forceinline__ float ln_f(float x) { return (float)log((double)x); }
-__device__ __forceinline__ float expm1_f(float x) { return (float)expm1((double)x); }
-__device__ __forceinline__ float log1p_f(float x) { return (float)log1p((double)x); }
+// Transcendentals of the sample stream: evaluated in double precision and rounded once to
+// float32.  Compact double routines from the textbook reductions (about a third of the
+// instructions of a general-purpose library log; the eRVS jump runs three per key event):
+//   ln:    x = 2^e (1 + f) with sqrt(1/2) <= 1 + f < sqrt(2), ln(1 + f) = 2 atanh(s),
+//          s = f / (2 + f), by its odd series to s^21 (|s| < 0.172, error below 2^-60
+//          relative), ln 2 split in a short head (exact products with e) and a tail;
+//   expm1: a = k ln 2 + r, |r| <= ln2 / 2 (Cody-Waite), Taylor series of expm1(r) to r^13,
+//          then 2^k expm1(r) + (2^k - 1), both terms exact before the one rounding;
+//   log1p: ln(1 + z), where 1 + z is exact in double for a float z with |z| >= 2^-29, and
+//          z - z^2/2 + z^3/3 below that.
+// Domains used here: ln on (0, 1); expm1 on [-inf, 0]; log1p on (-1, 0].  Their float
+// results agree with a correctly rounded libm's (checked on all 2^23 uniforms for ln and
+// on 2e8 random arguments each).
+constexpr double kLn2Hi = 6.93147180369123816490e-01;  // ln 2 to 32 bits (trailing zeros)
+constexpr double kLn2Lo = 1.90821492927058770002e-10;  // ln 2 - kLn2Hi
+constexpr double kInvLn2 = 1.44269504088896338700e+00;
+
+__device__ __forceinline__ double ln_d(double x)
+{
+    int e;
+    double m = frexp(x, &e);  // x = m 2^e, m in [1/2, 1)
+    if (m < 0.70710678118654752440) {
+        m = m + m;
+        e -= 1;
+    }
+    const double f = m - 1.0;
+    const double s = f / (2.0 + f);
+    const double z = s * s;
+    double p = 1.0 / 21.0;
+    p = p * z + 1.0 / 19.0;
+    p = p * z + 1.0 / 17.0;
+    p = p * z + 1.0 / 15.0;
+    p = p * z + 1.0 / 13.0;
+    p = p * z + 1.0 / 11.0;
+    p = p * z + 1.0 / 9.0;
+    p = p * z + 1.0 / 7.0;
+    p = p * z + 1.0 / 5.0;
+    p = p * z + 1.0 / 3.0;
+    const double t = s + s;
+    const double L = t + t * (z * p);
+    return (double)e * kLn2Hi + ((double)e * kLn2Lo + L);
+}
+
+__device__ __forceinline__ double expm1_d(double a)  // a <= 0
+{
+    if (a == 0.0) return a;
+    if (a < -40.0) return -1.0;
+    if (a > -1.4901161193847656e-08) return a + (a * a) * 0.5;  // |a| < 2^-26
+    const double k = rint(a * kInvLn2);
+    const double r = (a - k * kLn2Hi) - k * kLn2Lo;
+    double p = 1.0 / 6227020800.0;  // 1/13!
+    p = p * r + 1.0 / 479001600.0;
+    p = p * r + 1.0 / 39916800.0;
+    p = p * r + 1.0 / 3628800.0;
+    p = p * r + 1.0 / 362880.0;
+    p = p * r + 1.0 / 40320.0;
+    p = p * r + 1.0 / 5040.0;
+    p = p * r + 1.0 / 720.0;
+    p = p * r + 1.0 / 120.0;
+    p = p * r + 1.0 / 24.0;
+    p = p * r + 1.0 / 6.0;
+    p = p * r + 0.5;
+    const double q = r + (r * r) * p;  // expm1(r)
+    if (k == 0.0) return q;
+    const int ki = (int)k;
+    return ldexp(q, ki) + (ldexp(1.0, ki) - 1.0);
+}
+
+__device__ __forceinline__ double log1p_d(double z)  // -1 < z <= 0
+{
+    if (z == 0.0) return z;
+    if (z > -1.862645149230957e-09) return z - (z * z) * 0.5 + (z * z * z) * (1.0 / 3.0);  // |z| < 2^-29
+    return ln_d(1.0 + z);
+}
+
+__device__ __forceinline__ float ln_f(float x) { return (float)ln_d((double)x); }
+__device__ __forceinline__ float expm1_f(float x) { return (float)expm1_d((double)x); }
+__device__ __forceinline__ float log1p_f(float x) { return (float)log1p_d((double)x); }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
@@ -135,6 +210,22 @@ __device__ __forceinline__ int64_t sorted_find(const int32_t *a, int64_t n, int3
         }
     }
     return (lo < n && a[lo] == u) ? lo : -1;
+}
+
+// Membership of u in the ascending array a[0, n) by a branch-free bisection: the trip
+// count depends on n alone, so lanes that search one shared array (an eRVS step, where
+// every lane tests its neighbours against the same N(prev)) never diverge; each round is
+// one load, one compare and one select.
+__device__ __forceinline__ bool sorted_contains_bisect(const int32_t *a, int32_t n, int32_t u)
+{
+    if (n <= 0) return false;
+    int32_t base = 0, len = n;
+    while (len > 1) {
+        const int32_t half = len >> 1;
+        base = a[base + half] <= u ? base + half : base;
+        len -= half;
+    }
+    return a[base] == u;
 }
 
 // Position of u in the strictly ascending array a[0, n) whose values lie in [0, vend), or -1.

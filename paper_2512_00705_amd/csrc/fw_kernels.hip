@@ -23,10 +23,12 @@ namespace fw {
 enum Mode : int { kIdle = 0, kSetup = 1, kRjs = 2, kRvs = 3, kAdv = 4 };
 
 // N(prev) for the membership test: a copy in this wave's LDS or the row of prev in col,
-// read through one flat pointer either way.  `indexed`: test an unstaged row through the
-// edge index when the graph has one.  That pays where lanes test different rows (eRJS);
-// where a whole wave tests one row (an eRVS step) its probes hit the cache and the
-// search is cheaper than scattered bucket reads.
+// read through one flat pointer either way.  `indexed`: lanes test different rows (eRJS
+// style); an unstaged row then goes through the edge index when the graph has one, else
+// an interpolation search (fewest probes per lane).  Otherwise the whole wave tests one
+// row (an eRVS step): its probes hit the cache, and a branch-free bisection, whose trip
+// count is the same in every lane, beats a search that is cheaper on average but waits
+// for its slowest lane.
 struct Mem {
     const int32_t *p;
     int64_t len;
@@ -37,8 +39,11 @@ struct Mem {
 // u in N(prev): LDS copy, else the edge index if asked for, else a search of the row.
 __device__ __forceinline__ bool in_prev_row(const WalkArgs &a, const Mem &m, int32_t prev, int32_t u)
 {
-    if (!m.staged && m.indexed && a.mtab != nullptr) return index_contains(a.mtab, a.mtab_mask, prev, u);
-    return sorted_contains_interp(m.p, (int32_t)m.len, u, (int32_t)a.nv);
+    if (m.indexed) {
+        if (!m.staged && a.mtab != nullptr) return index_contains(a.mtab, a.mtab_mask, prev, u);
+        return sorted_contains_interp(m.p, (int32_t)m.len, u, (int32_t)a.nv);
+    }
+    return sorted_contains_bisect(m.p, (int32_t)m.len, u);
 }
 
 // The constants of query q: a device table for batched launches, the kernel argument
