@@ -303,6 +303,9 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
     // h of the edge prev -> cur, and of the edge the current step takes; on a symmetric
     // graph the first is also h(cur, prev), the return edge's property weight
     float hlast = 1.0f, hnext = 1.0f;
+    // path slot j held back so that it goes out with slot j + 1 as one 8-byte store (-1: none);
+    // only an 8-byte-aligned slot below L is held
+    int32_t pend = -1;
     // per-lane counters (32-bit counts, 64-bit bytes), flushed before a count could wrap
     uint32_t st[kStBytes];
 #pragma unroll
@@ -393,6 +396,10 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 mode = kIdle;
                 wid = -1;
             } else if (BATCH && Q.prog && j == stop_j) {
+                if (pend >= 0) {  // the resumed walker reads slots j - 1 and j
+                    Q.paths[(int64_t)wid * ((int64_t)Q.L + 1) + j] = pend;
+                    pend = -1;
+                }
                 Q.prog[wid] = j;  // suspend until the next launch
                 mode = kIdle;
                 wid = -1;
@@ -697,7 +704,15 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
             const QueryDev &Q = query<BATCH>(a, q);
             int32_t *row = Q.paths + (int64_t)wid * ((int64_t)Q.L + 1);
             if (nxt < 0) {
-                for (int r = j + 1; r <= Q.L; ++r) row[r] = -1;
+                if (pend >= 0) {
+                    row[j] = pend;
+                    pend = -1;
+                }
+                // pad with -1: single slots up to a 16-byte boundary, then 16-byte stores
+                int r = j + 1;
+                for (; r <= Q.L && (reinterpret_cast<uintptr_t>(row + r) & 15) != 0; ++r) row[r] = -1;
+                for (; r + 3 <= Q.L; r += 4) *reinterpret_cast<int4 *>(row + r) = make_int4(-1, -1, -1, -1);
+                for (; r <= Q.L; ++r) row[r] = -1;
                 Q.lengths[wid] = j;
                 if (BATCH && Q.prog) {
                     Q.prog[wid] = kDone;
@@ -707,7 +722,14 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 mode = kIdle;
                 wid = -1;
             } else {
-                row[j + 1] = nxt;
+                if (pend >= 0) {
+                    *reinterpret_cast<int2 *>(row + j) = make_int2(pend, nxt);
+                    pend = -1;
+                } else if ((reinterpret_cast<uintptr_t>(row + j + 1) & 7) == 0 && j + 1 < Q.L) {
+                    pend = nxt;
+                } else {
+                    row[j + 1] = nxt;
+                }
                 st[kStSteps] += 1;
                 prev = cur;
                 cur = nxt;
