@@ -123,6 +123,14 @@ __device__ __forceinline__ uint2 edge_rec(const WalkArgs &a, int64_t k)
     return a.edges[k];
 }
 
+// Store the n held path slots p0.. at dst (walk ended or suspended).
+__device__ __forceinline__ void flush_path(int32_t *dst, int32_t n, int32_t p0, int32_t p1, int32_t p2)
+{
+    dst[0] = p0;
+    if (n > 1) dst[1] = p1;
+    if (n > 2) dst[2] = p2;
+}
+
 __device__ __forceinline__ int64_t row_start(const WalkArgs &a, uint4 r, int32_t v)
 {
     return a.start_hi ? (int64_t)(((uint64_t)a.start_hi[v] << 32) | r.x) : (int64_t)r.x;
@@ -303,9 +311,10 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
     // h of the edge prev -> cur, and of the edge the current step takes; on a symmetric
     // graph the first is also h(cur, prev), the return edge's property weight
     float hlast = 1.0f, hnext = 1.0f;
-    // path slot j held back so that it goes out with slot j + 1 as one 8-byte store (-1: none);
-    // only an 8-byte-aligned slot below L is held
-    int32_t pend = -1;
+    // path slots held back so that they go out together: from a 16-byte-aligned slot up to
+    // four (one 16-byte store), from an 8-byte-aligned one two; npend slots ending at slot j
+    // are held in p0, p1, p2
+    int32_t p0 = 0, p1 = 0, p2 = 0, npend = 0;
     // per-lane counters (32-bit counts, 64-bit bytes), flushed before a count could wrap
     uint32_t st[kStBytes];
 #pragma unroll
@@ -396,9 +405,9 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 mode = kIdle;
                 wid = -1;
             } else if (BATCH && Q.prog && j == stop_j) {
-                if (pend >= 0) {  // the resumed walker reads slots j - 1 and j
-                    Q.paths[(int64_t)wid * ((int64_t)Q.L + 1) + j] = pend;
-                    pend = -1;
+                if (npend > 0) {  // the resumed walker reads slots j - 1 and j
+                    flush_path(Q.paths + (int64_t)wid * ((int64_t)Q.L + 1) + (j + 1 - npend), npend, p0, p1, p2);
+                    npend = 0;
                 }
                 Q.prog[wid] = j;  // suspend until the next launch
                 mode = kIdle;
@@ -704,9 +713,9 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
             const QueryDev &Q = query<BATCH>(a, q);
             int32_t *row = Q.paths + (int64_t)wid * ((int64_t)Q.L + 1);
             if (nxt < 0) {
-                if (pend >= 0) {
-                    row[j] = pend;
-                    pend = -1;
+                if (npend > 0) {
+                    flush_path(row + (j + 1 - npend), npend, p0, p1, p2);
+                    npend = 0;
                 }
                 // pad with -1: single slots up to a 16-byte boundary, then 16-byte stores
                 int r = j + 1;
@@ -722,13 +731,29 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 mode = kIdle;
                 wid = -1;
             } else {
-                if (pend >= 0) {
-                    *reinterpret_cast<int2 *>(row + j) = make_int2(pend, nxt);
-                    pend = -1;
-                } else if ((reinterpret_cast<uintptr_t>(row + j + 1) & 7) == 0 && j + 1 < Q.L) {
-                    pend = nxt;
+                const int32_t s = j + 1;
+                if (npend == 0) {
+                    const uintptr_t ad = reinterpret_cast<uintptr_t>(row + s);
+                    if (((ad & 15) == 0 && s + 3 <= Q.L) || ((ad & 7) == 0 && s + 1 <= Q.L)) {
+                        p0 = nxt;
+                        npend = 1;
+                    } else {
+                        row[s] = nxt;
+                    }
                 } else {
-                    row[j + 1] = nxt;
+                    int32_t *first = row + (s - npend);
+                    // the group's size follows from its first slot as when it was started
+                    if ((reinterpret_cast<uintptr_t>(first) & 15) != 0 || s - npend + 3 > Q.L) {
+                        *reinterpret_cast<int2 *>(first) = make_int2(p0, nxt);
+                        npend = 0;
+                    } else if (npend == 3) {
+                        *reinterpret_cast<int4 *>(first) = make_int4(p0, p1, p2, nxt);
+                        npend = 0;
+                    } else {
+                        if (npend == 1) p1 = nxt;
+                        else p2 = nxt;
+                        ++npend;
+                    }
                 }
                 st[kStSteps] += 1;
                 prev = cur;
