@@ -527,8 +527,24 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
             uint8_t ll[kRjsBatch];
             bool ol[kRjsBatch], mr[kRjsBatch];
             const uint32_t k0 = Q.key0, k1 = Q.key1;
+            const StepW sw = step_weights<KIND>(Q, deg, pdeg);
+            // a trial whose acceptance its uniforms already decide (the return column; an
+            // h-proportional proposal whose test value lies below every weight the proposed
+            // edge can have) makes the later proposals of the batch unnecessary: their draws
+            // and loads are skipped (the decision loop stops at that trial)
+            const float wsure = (!uses_membership(KIND) || !hprop)
+                                    ? -1.0f
+                                    : (j == 0 ? 1.0f : fminf(sw.ret, (MB && mb) ? sw.oth : sw.lo));
+            bool sure = false;
 #pragma unroll
             for (int r = 0; r < kRjsBatch; ++r) {
+                if (sure) {
+                    ol[r] = mr[r] = false;
+                    ux[r] = 0u;
+                    ee[r] = make_uint2(0u, 0u);
+                    ll[r] = 0;
+                    continue;
+                }
                 const U4 x = philox((uint32_t)wid, (uint32_t)j, (uint32_t)(trials + r), 0u, k0, k1);
                 const int64_t k = base + scaled_index(x.x0, x.x1, deg);
                 const float z = unit_uniform(x.x3) * area;
@@ -551,8 +567,8 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                     ee[r] = edge_rec(a, k);
                     ll[r] = (KIND == kMetaPath) ? a.label[k] : (uint8_t)0;
                 }
+                sure = ol[r] || (!mr[r] && unit_uniform(x.x2) * B < wsure);
             }
-            const StepW sw = step_weights<KIND>(Q, deg, pdeg);
             // decide proposals in order; the batch shifts down one slot per trial so the
             // decision code appears once
 #pragma unroll 1
