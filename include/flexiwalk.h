@@ -184,14 +184,16 @@ int fw_graph_export_aux(const fw_graph *g, float *hmax, float *hsum);
 int fw_graph_build_index(fw_graph *g, void *stream);
 
 /* Build the proposal records of h-proportional eRJS (plan.proposal = 1): per CSR entry k
- * of row v, 32 bytes {col[k], h[k], col[a], h[a], threshold, labels of k and a, 0, 0} where
- * a and the threshold form Walker's alias table of the row's h (Vose's construction in
- * double precision in index order; threshold = min(floor(p * 2^32), 2^32 - 1) of the slot's
- * keep probability p).  A proposal takes slot floor(R * deg / 2^64) of a 64-bit draw R and
- * keeps it when the high 32 bits of the fraction lie below the threshold, else takes a.
- * One record is one 32-byte read.  Device memory: 32 bytes per entry, plus 20 bytes per
- * entry of scratch while building.  Synchronous; idempotent.  Walks, batches and servers
- * created afterwards can use it. */
+ * of row v, 64 bytes {col[k], h[k], col[a], h[a]}, {threshold, labels of k and a, 0, 0} and
+ * the vertex records (row start, degree, h_MAX, h_SUM) of col[k] and col[a], where a and the
+ * threshold form Walker's alias table of the row's h (Vose's construction in double
+ * precision in index order; threshold = min(floor(p * 2^32), 2^32 - 1) of the slot's keep
+ * probability p).  A proposal takes slot floor(R * deg / 2^64) of a 64-bit draw R and keeps
+ * it when the high 32 bits of the fraction lie below the threshold, else takes a.  A record
+ * sits in one DRAM line: one read gives the proposal and, once it is accepted, the next
+ * step's vertex record.  Runs fw_graph_preprocess first if it has not run.  Device memory:
+ * 64 bytes per entry, plus 20 bytes per entry of scratch while building.  Synchronous;
+ * idempotent.  Walks, batches and servers created afterwards can use it. */
 int fw_graph_build_alias(fw_graph *g, void *stream);
 
 /* Roofline calibration (not part of the method): time random 8-byte reads from a device

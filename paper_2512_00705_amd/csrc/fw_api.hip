@@ -483,10 +483,16 @@ int fw_graph_build_alias(fw_graph *g, void *stream)
     if (!g) return fail(FW_E_INVALID, "fw_graph_build_alias: null graph");
     if (g->prop) return ok();
     HIP_TRY(hipSetDevice(g->device));
+    // the records carry the candidates' vertex records, h_MAX and h_SUM included
+    if (!g->prepped) {
+        const int rc = fw_graph_preprocess(g, stream);
+        if (rc != FW_OK) return rc;
+    }
     const size_t ne = (size_t)(g->ne > 0 ? g->ne : 1);
+    const size_t rec = 16 * (size_t)fw::kPropU4;
     uint4 *prop = nullptr;
-    if (hipMalloc((void **)&prop, 32 * ne) != hipSuccess)
-        return fail(FW_E_NOMEM, "fw_graph_build_alias: hipMalloc of %zu bytes failed", 32 * ne);
+    if (hipMalloc((void **)&prop, rec * ne) != hipSuccess)
+        return fail(FW_E_NOMEM, "fw_graph_build_alias: hipMalloc of %zu bytes failed", rec * ne);
     DevBuf sc, ss, sl, al;
     if (hipMalloc(&sc.p, 8 * ne) != hipSuccess || hipMalloc(&ss.p, 4 * ne) != hipSuccess ||
         hipMalloc(&sl.p, 4 * ne) != hipSuccess || hipMalloc(&al.p, 4 * ne) != hipSuccess) {
@@ -494,7 +500,7 @@ int fw_graph_build_alias(fw_graph *g, void *stream)
         return fail(FW_E_NOMEM, "fw_graph_build_alias: scratch of %zu bytes failed", 20 * ne);
     }
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = fw::launch_build_alias(g->row_ptr, g->col, g->h, g->label, g->nv, (double *)sc.p,
+    hipError_t e = fw::launch_build_alias(g->row_ptr, g->col, g->h, g->label, g->nv, g->vrec, (double *)sc.p,
                                           (int32_t *)ss.p, (int32_t *)sl.p, (int32_t *)al.p, prop, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {

@@ -37,6 +37,10 @@ constexpr int kDefaultLdsCap = 2048; // int32 entries of N(prev) per wavefront
 #define FW_RJS_BATCH 2
 #endif
 constexpr int kRjsBatch = FW_RJS_BATCH; // eRJS proposals whose loads a lane issues together
+// h-proportional proposal record per CSR entry, 64 bytes (one DRAM line holds it whole):
+//   {col_k, bits(h_k), col_a, bits(h_a)}, {threshold, label_k | label_a << 8, 0, 0},
+//   vrec[col_k], vrec[col_a]  (the candidates' vertex records for the next step's set-up)
+constexpr int kPropU4 = 4;
 #ifndef FW_MIN_WAVES
 #define FW_MIN_WAVES 4
 #endif
@@ -100,7 +104,7 @@ struct WalkArgs {
     int32_t tick_steps;         // resumable walks: steps per walker per launch
     int32_t bound;              // 1: Node2Vec split eRJS bound (symmetric graphs only)
     const uint4 *mtab;          // edge index (8 uint4 per bucket) or null: search the sorted rows
-    const uint4 *prop;          // proposal records (2 uint4 per entry) or null
+    const uint4 *prop;          // proposal records (kPropU4 uint4 per entry) or null
     int32_t proposal;           // 1: h-proportional eRJS proposals through `prop`
     uint64_t mtab_mask;         // buckets - 1
 
@@ -124,8 +128,8 @@ hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv,
 // prop[2k] = {col[k], h[k], col[a], h[a]}, prop[2k+1] = {threshold, lab[k] | lab[a] << 8, 0, 0}.
 // sc, stk_s, stk_l and alias are ne-long scratch arrays.
 hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
-                              int64_t nv, double *sc, int32_t *stk_s, int32_t *stk_l, int32_t *alias, uint4 *prop,
-                              hipStream_t s);
+                              int64_t nv, const uint4 *vrec, double *sc, int32_t *stk_s, int32_t *stk_l,
+                              int32_t *alias, uint4 *prop, hipStream_t s);
 // Edge index: inserts every entry (v, col[k]) of the rows with its h (1 when h is null) into
 // `tab` (buckets of 8 keys and 8 h, 128 bytes each, keys all kEmptyKey on entry;
 // buckets = mask + 1, a power of two, at least a quarter of ne).

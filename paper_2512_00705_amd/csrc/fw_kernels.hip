@@ -315,6 +315,9 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
     // four (one 16-byte store), from an 8-byte-aligned one two; npend slots ending at slot j
     // are held in p0, p1, p2
     int32_t p0 = 0, p1 = 0, p2 = 0, npend = 0;
+    // vertex record of the next step's vertex when the accepted proposal's record carried it
+    uint4 nvrec = make_uint4(0u, 0u, 0u, 0u);
+    bool have_nv = false;
     // per-lane counters (32-bit counts, 64-bit bytes), flushed before a count could wrap
     uint32_t st[kStBytes];
 #pragma unroll
@@ -396,6 +399,8 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
         // 2. step set-up: row of cur, bound B, strategy (Section 4.1)
         if (mode == kSetup) {
             const QueryDev &Q = query<BATCH>(a, q);
+            const bool use_nv = have_nv;
+            have_nv = false;
             if (j == Q.L) {
                 Q.lengths[wid] = j;
                 if (BATCH && Q.prog) {
@@ -413,7 +418,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 mode = kIdle;
                 wid = -1;
             } else {
-                const uint4 r = a.vrec[cur];
+                const uint4 r = use_nv ? nvrec : a.vrec[cur];
                 base = row_start(a, r, cur);
                 deg = (int32_t)r.y;
                 st_bytes += 16;
@@ -523,6 +528,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
             const bool split = KIND == kNode2Vec && a.bound != 0 && j > 0;
             const float E = MB ? bE : (split ? fmaxf(0.0f, Q.inv_p * hlast - (hprop ? B * hlast : B)) : 0.0f);
             uint32_t ux[kRjsBatch];
+            uint32_t rsel[kRjsBatch];  // h-proportional: 2 (offset in the row) + (alias taken)
             uint2 ee[kRjsBatch];
             uint8_t ll[kRjsBatch];
             bool ol[kRjsBatch], mr[kRjsBatch];
@@ -541,6 +547,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 if (sure) {
                     ol[r] = mr[r] = false;
                     ux[r] = 0u;
+                    rsel[r] = 0u;
                     ee[r] = make_uint2(0u, 0u);
                     ll[r] = 0;
                     continue;
@@ -551,6 +558,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 ol[r] = E > 0.0f && z < E;
                 mr[r] = MB && uses_membership(KIND) && mb && !ol[r] && z < bZ;
                 ux[r] = x.x2;
+                rsel[r] = 0u;
                 if (ol[r]) {
                     ee[r] = make_uint2((uint32_t)prev, 0u);
                     ll[r] = 0;
@@ -559,8 +567,9 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                     ll[r] = 0;
                 } else if (hprop) {
                     const uint32_t f = scaled_fraction_hi(x.x0, x.x1, deg);
-                    const uint4 r0 = a.prop[2 * k], r1 = a.prop[2 * k + 1];
+                    const uint4 r0 = a.prop[kPropU4 * k], r1 = a.prop[kPropU4 * k + 1];
                     const bool keep = f < r1.x;
+                    rsel[r] = ((uint32_t)(k - base) << 1) | (keep ? 0u : 1u);
                     ee[r] = keep ? make_uint2(r0.x, r0.y) : make_uint2(r0.z, r0.w);
                     ll[r] = (KIND == kMetaPath) ? (uint8_t)(keep ? r1.y : r1.y >> 8) : (uint8_t)0;
                 } else {
@@ -634,6 +643,11 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 if (acc) {
                     nxt = u;
                     hnext = hsel;
+                    if (hprop && !ol[0] && !mr[0]) {
+                        // the record's line holds the accepted candidate's vertex record
+                        nvrec = a.prop[kPropU4 * (base + (int64_t)(rsel[0] >> 1)) + 2 + (rsel[0] & 1u)];
+                        have_nv = true;
+                    }
                     mode = kAdv;
                     st[kStRjs] += 1;
                     break;
@@ -650,6 +664,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                     ll[t] = ll[t + 1];
                     ol[t] = ol[t + 1];
                     mr[t] = mr[t + 1];
+                    rsel[t] = rsel[t + 1];
                 }
             }
         }
@@ -891,11 +906,13 @@ __global__ void __launch_bounds__(kBlock) validate_edges_kernel(const int64_t *r
 }
 
 // Proposal records: one lane per row runs Vose's alias construction in index order, in
-// double precision, with the row's stretch of the scratch arrays as its two stacks.
+// double precision, with the row's stretch of the scratch arrays as its two stacks.  Each
+// 64-byte record also carries the vertex records of its two candidates, so that a step
+// that accepts a proposal finds the next step's row in the line it already fetched.
 __global__ void __launch_bounds__(kBlock) build_alias_kernel(const int64_t *row_ptr, const int32_t *col,
                                                              const float *h, const uint8_t *label, int64_t nv,
-                                                             double *sc, int32_t *stk_s, int32_t *stk_l,
-                                                             int32_t *alias, uint4 *prop)
+                                                             const uint4 *vrec, double *sc, int32_t *stk_s,
+                                                             int32_t *stk_l, int32_t *alias, uint4 *prop)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += stride) {
@@ -928,8 +945,10 @@ __global__ void __launch_bounds__(kBlock) build_alias_kernel(const int64_t *row_
             const uint32_t hk = h ? __float_as_uint(h[b + k]) : __float_as_uint(1.0f);
             const uint32_t ha = h ? __float_as_uint(h[b + al]) : __float_as_uint(1.0f);
             const uint32_t lab = label ? ((uint32_t)label[b + k] | ((uint32_t)label[b + al] << 8)) : 0u;
-            prop[2 * (b + k)] = make_uint4((uint32_t)col[b + k], hk, (uint32_t)col[b + al], ha);
-            prop[2 * (b + k) + 1] = make_uint4(thr, lab, 0u, 0u);
+            prop[kPropU4 * (b + k)] = make_uint4((uint32_t)col[b + k], hk, (uint32_t)col[b + al], ha);
+            prop[kPropU4 * (b + k) + 1] = make_uint4(thr, lab, 0u, 0u);
+            prop[kPropU4 * (b + k) + 2] = vrec[col[b + k]];
+            prop[kPropU4 * (b + k) + 3] = vrec[col[b + al]];
         }
     }
 }
@@ -1186,14 +1205,14 @@ hipError_t launch_validate_edges(const int64_t *row_ptr, const int32_t *col, con
 }
 
 hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
-                              int64_t nv, double *sc, int32_t *stk_s, int32_t *stk_l, int32_t *alias, uint4 *prop,
-                              hipStream_t s)
+                              int64_t nv, const uint4 *vrec, double *sc, int32_t *stk_s, int32_t *stk_l,
+                              int32_t *alias, uint4 *prop, hipStream_t s)
 {
     int64_t blocks = (nv + kBlock - 1) / kBlock;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(build_alias_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, label, nv,
-                       sc, stk_s, stk_l, alias, prop);
+                       vrec, sc, stk_s, stk_l, alias, prop);
     return hipGetLastError();
 }
 
