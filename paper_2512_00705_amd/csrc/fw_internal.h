@@ -34,7 +34,7 @@ constexpr int kBlock = 256;          // 4 wavefronts per block, each independent
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kDefaultLdsCap = 2048; // int32 entries of N(prev) per wavefront
 #ifndef FW_RJS_BATCH
-#define FW_RJS_BATCH 2
+#define FW_RJS_BATCH 3
 #endif
 constexpr int kRjsBatch = FW_RJS_BATCH; // eRJS proposals whose loads a lane issues together
 // h-proportional proposal record per CSR entry, 64 bytes (one DRAM line holds it whole):
