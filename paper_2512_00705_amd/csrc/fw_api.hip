@@ -618,9 +618,9 @@ int fw_plan_autotune_mix(fw_graph *g, const fw_logic *logics, int32_t n_logics, 
 
     // sample walks: seeded walkers spread over all vertices, enough to keep the device busy
     // for milliseconds per candidate (shorter runs time the launch and the tail), long
-    // enough for the walk's degree bias to set in; with several logics each gets an equal
-    // share of the walkers and a candidate's time is the sum over the logics
-    const int64_t n = std::min<int64_t>(g->nv, std::max<int64_t>(1 << 16, (1 << 20) / n_logics));
+    // enough for the walk's degree bias to set in; with several logics each runs at least
+    // 2^18 walkers (shorter runs time noise) and a candidate's time is the sum over the logics
+    const int64_t n = std::min<int64_t>(g->nv, std::max<int64_t>(1 << 18, (1 << 20) / n_logics));
     const int32_t L = 16;
     std::vector<int32_t> starts((size_t)n);
     uint64_t x = 0x9E3779B97F4A7C15ull;
