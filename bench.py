@@ -74,11 +74,12 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--graph", default="rmat22_labels")
-    ap.add_argument("--L", type=int, default=80)
+    ap.add_argument("--L", type=int, default=None, help="walk length (default 80; 40 for metapath)")
     ap.add_argument("--p", type=float, default=0.5)
     ap.add_argument("--q", type=float, default=2.0)
-    ap.add_argument("--logic", default="node2vec", choices=["node2vec", "secondpr"],
-                    help="walk logic of the scale-22 job (node2vec p, q or second-order PageRank gamma)")
+    ap.add_argument("--logic", default="node2vec", choices=["node2vec", "secondpr", "metapath"],
+                    help="walk logic of the scale-22 job (node2vec p, q; second-order PageRank gamma; MetaPath "
+                         "schema 0,1,2,3,4 repeated from 2^20 uniform starts)")
     ap.add_argument("--gamma", type=float, default=0.2)
     ap.add_argument("--weights", default="f32", choices=["f32", "q8"],
                     help="edge property weights as float32, or as 8-bit codes (scale 10/255) of the same weights")
@@ -156,8 +157,9 @@ def main():
         g = dict(g)
         g["h8"], g["h_scale"] = synth.quantize_u8(g["h"])
         g["h"] = None
-    t = {k: torch.from_numpy(g[k]).to(dev) for k in ("row_ptr", "col", "h", "h8") if g.get(k) is not None}
-    gh = fw.fw_graph_create(g["nv"], g["ne"], t["row_ptr"], t["col"], t.get("h"), None, on_device=True,
+    keys = ("row_ptr", "col", "h", "h8") + (("label",) if args.logic == "metapath" else ())
+    t = {k: torch.from_numpy(g[k]).to(dev) for k in keys if g.get(k) is not None}
+    gh = fw.fw_graph_create(g["nv"], g["ne"], t["row_ptr"], t["col"], t.get("h"), t.get("label"), on_device=True,
                             h8=t.get("h8"), h_scale=float(g.get("h_scale", 0.0)))
     del t
     torch.cuda.synchronize()
@@ -178,6 +180,9 @@ def main():
     if args.logic == "secondpr":
         logic = fw.fw_logic_second_pr(args.gamma, True)
         logic_text = f"second-order PageRank gamma={args.gamma}"
+    elif args.logic == "metapath":
+        logic = fw.fw_logic_metapath([0, 1, 2, 3, 4], True)
+        logic_text = "MetaPath schema (0,1,2,3,4) repeated, labels U{0..4}"
     else:
         logic = fw.fw_logic_node2vec(args.p, args.q, True)
         logic_text = f"node2vec p={args.p} q={args.q}"
@@ -192,10 +197,15 @@ def main():
     log(f"preprocess {prep_ms:.2f} ms, autotune {tune_ms:.1f} ms, rho={plan.rho:.3f} d_lo={plan.d_lo} "
         f"lds_cap={plan.lds_cap} bound={plan.bound} proposal={plan.proposal}")
 
-    nv, L, seed = g["nv"], args.L, 42
-    starts = torch.arange(nv, dtype=torch.int32, device=dev)
-    paths = torch.empty((nv, L + 1), dtype=torch.int32, device=dev)
-    lengths = torch.empty(nv, dtype=torch.int32, device=dev)
+    nv, seed = g["nv"], 42
+    L = args.L if args.L is not None else (40 if args.logic == "metapath" else 80)
+    # walkers: one per vertex, or 2^20 uniform starts for MetaPath
+    starts_np = (synth.uniform_starts(nv, 1 << 20, 42) if args.logic == "metapath"
+                 else np.arange(nv, dtype=np.int32))
+    n = len(starts_np)
+    starts = torch.from_numpy(starts_np).to(dev)
+    paths = torch.empty((n, L + 1), dtype=torch.int32, device=dev)
+    lengths = torch.empty(n, dtype=torch.int32, device=dev)
     stats = torch.zeros(fw.FW_NSTATS, dtype=torch.int64, device=dev)
     strat = {"auto": fw.FW_AUTO, "rvs": fw.FW_RVS_ONLY, "rjs": fw.FW_RJS_ONLY}
 
@@ -204,16 +214,16 @@ def main():
         # are a fixed function of (seed, walker, step), so every launch below takes the
         # same steps; the timed launches run without counters, as a caller would
         stats.zero_()
-        fw.fw_walk(gh, logic, plan, strat[mode], starts, nv, L, seed, paths, lengths, stats)
+        fw.fw_walk(gh, logic, plan, strat[mode], starts, n, L, seed, paths, lengths, stats)
         for _ in range(warmup):
-            fw.fw_walk(gh, logic, plan, strat[mode], starts, nv, L, seed, paths, lengths, None)
+            fw.fw_walk(gh, logic, plan, strat[mode], starts, n, L, seed, paths, lengths, None)
         torch.cuda.synchronize()
         evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         for a, b in evs:
             a.record()
-            fw.fw_walk(gh, logic, plan, strat[mode], starts, nv, L, seed, paths, lengths, None)
+            fw.fw_walk(gh, logic, plan, strat[mode], starts, n, L, seed, paths, lengths, None)
             b.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
@@ -238,7 +248,8 @@ def main():
         # and graph allow (Node2Vec's split bound and member board need a symmetric graph)
         sym = fw.fw_graph_info(gh)[3]
         cases = [(m + "_only", m, plan) for m in ("rvs", "rjs") if m != args.strategy]
-        bounds = [0, 1, 2] if (args.logic == "node2vec" and sym) else ([0] if args.logic == "node2vec" else [0, 2])
+        bounds = ([0, 1, 2] if (args.logic == "node2vec" and sym) else [0] if args.logic in ("node2vec", "metapath")
+                  else [0, 2])
         for b in bounds:
             if b != plan.bound:
                 other = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap, bound=b,
@@ -265,6 +276,8 @@ def main():
         og = oracle.Graph(g)
         og.aux()
         lg = (oracle.Logic(kind=oracle.SECOND_PR, weighted=True, gamma=args.gamma) if args.logic == "secondpr"
+              else oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(0, 1, 2, 3, 4))
+              if args.logic == "metapath"
               else oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=args.p, q=args.q))
         pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap, bound=plan.bound, proposal=plan.proposal,
                          member_index=True)
@@ -272,19 +285,19 @@ def main():
         smode = {"auto": 0, "rvs": 1, "rjs": 2}[args.strategy]
         k = args.cpu_sample or 2048
         while True:  # grow a seeded walker sample until the oracle works for ~10-30 s
-            sample = np.sort(rng.choice(nv, size=min(k, nv), replace=False)).astype(np.int64)
+            sample = np.sort(rng.choice(n, size=min(k, n), replace=False)).astype(np.int64)
             c0 = time.perf_counter()
-            r = oracle.walk(og, lg, pl, smode, sample.astype(np.int32), L, seed, walker_ids=sample,
+            r = oracle.walk(og, lg, pl, smode, starts_np[sample], L, seed, walker_ids=sample,
                             diagnostics=False, nthreads=cores)
             cs = time.perf_counter() - c0
-            if args.cpu_sample or cs >= 10.0 or k >= nv:
+            if args.cpu_sample or cs >= 10.0 or k >= n:
                 break
-            k = int(min(nv, k * max(2.0, 15.0 / max(cs, 1e-3))))
+            k = int(min(n, k * max(2.0, 15.0 / max(cs, 1e-3))))
         # the GPU run covered these walkers too: compare the sample
         gp = paths[torch.from_numpy(sample).to(dev)].cpu().numpy()
         same = float((gp == r.paths).all(axis=1).mean())
         cpu = {"value": r.counters["steps"] / cs, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
-               "sample": f"{len(sample)} of {nv} walkers (seeded), full {L}-step walks, {cs:.1f}s; "
+               "sample": f"{len(sample)} of {n} walkers (seeded), full {L}-step walks, {cs:.1f}s; "
                          f"{same * 100:.3f}% identical to the GPU walks"}
         log(f"cpu oracle: {cpu}")
 
@@ -296,7 +309,8 @@ def main():
                      "achieved_reads_per_s": None if traffic is None else traffic["read_requests"] / (avg_ms / 1e3),
                      "frac": None if traffic is None else traffic["read_requests"] / (avg_ms / 1e3) / ceiling}
     out = {
-        "metric": "walker-steps/sec + achieved HBM GB/s, node2vec R-MAT s22; p99 latency served",
+        "metric": ("walker-steps/sec + achieved HBM GB/s, node2vec R-MAT s22; p99 latency served"
+                   if args.logic == "node2vec" else f"walker-steps/sec + achieved HBM GB/s, {args.logic} R-MAT s22"),
         "value": value,
         "unit": "walker-steps/s",
         "n_gpus": 1,
@@ -311,8 +325,10 @@ def main():
         "config": {"workload": f"{logic_text} weighted h~U(1,10)"
                                + (" stored as 8-bit codes (h = (10/255)*code)" if args.weights == "q8" else "")
                                + ", R-MAT scale 22 "
-                               f"(a=0.57,b=0.19,c=0.19, edge factor 16, {g['ne']} CSR entries), one walker "
-                               f"per vertex ({nv}), L={L}, strategy={args.strategy}",
+                               f"(a=0.57,b=0.19,c=0.19, edge factor 16, {g['ne']} CSR entries), "
+                               + (f"{n} uniform start vertices (seed 42)" if args.logic == "metapath"
+                                  else f"one walker per vertex ({nv})")
+                               + f", L={L}, strategy={args.strategy}",
                    "walker_steps_per_walk_job": steps_per_walk, "preprocess_ms": prep_ms,
                    "edge_index_ms": index_ms, "alias_build_ms": alias_ms,
                    "autotune_ms": tune_ms, "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound,

@@ -26,7 +26,7 @@ struct fw_graph {
     bool prepped = false;
     bool symmetric = false;                 // every (v, u) has a reverse (u, v) with equal h
     unsigned long long *mtab = nullptr;     // edge index: 128-byte buckets of 8 keys v << 32 | u and their h, or null
-    uint4 *prop = nullptr;                  // h-proportional proposal records (2 uint4 per entry), or null
+    uint4 *prop = nullptr;                  // h-proportional proposal records (kPropU4 uint4 per entry), or null
     uint64_t mtab_mask = 0;                 // buckets - 1
 };
 
