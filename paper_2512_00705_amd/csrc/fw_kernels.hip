@@ -11,10 +11,15 @@
 //     maximum, then each lane scans its strided neighbours with the jump of Eq. (jump)
 //     and a final wave argmax picks the next vertex;
 //   * walkers are handed out from a global counter, one atomic per wave refill.
-// The membership test u in N(prev) of Node2Vec is an interpolation search over the
-// sorted row of prev, staged in LDS when that row is short enough, else read through L2.
-// Random reads are what this kernel pays for (each costs a DRAM line), so an edge is one
-// 8-byte record {col, h} and a vertex one 16-byte record {start, degree, h_MAX, h_SUM}.
+// The membership test u in N(prev) (Node2Vec, second-order PageRank) is, in eRJS, one
+// bucket of the edge index (or an interpolation search of prev's sorted row) and only
+// when the bounds of w~ leave the test open; in eRVS, where the whole wave tests one row,
+// a bisection of N(prev) staged in LDS when short enough.  Random reads are what this
+// kernel pays for (each costs a DRAM line), so an edge is one 8-byte record {col, h}
+// (4 bytes with 8-bit weights), a vertex one 16-byte record {start, degree, h_MAX, h_SUM},
+// and an h-proportional proposal one 64-byte record that also holds the vertex records
+// of its two candidates.  Optional eRJS boards (split bound, member board; extensions of
+// Section 3.3) cut the expected trials; see walk_kernel.
 #include "fw_device.h"
 #include "fw_internal.h"
 
