@@ -332,7 +332,7 @@ def main():
                    "walker_steps_per_walk_job": steps_per_walk, "preprocess_ms": prep_ms,
                    "edge_index_ms": index_ms, "alias_build_ms": alias_ms,
                    "autotune_ms": tune_ms, "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound,
-                            "proposal": plan.proposal},
+                            "proposal": plan.proposal, "grid": plan.grid},
                    "stats": st, "modes": modes,
                    "hbm_traffic_GBps": None if traffic is None else traffic["bytes"] / (avg_ms / 1e3) / 1e9,
                    "random_access": random_access},
@@ -511,7 +511,7 @@ def bench_batched(args):
                                f"R-MAT scale 24 (0.6,0.175,0.175), {g['ne']} CSR entries",
                    "stats": st, "rho": plan.rho, "d_lo": plan.d_lo,
                    "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound,
-                            "proposal": plan.proposal}, "autotune_ms": tune_ms,
+                            "proposal": plan.proposal, "grid": plan.grid}, "autotune_ms": tune_ms,
                    "per_query_launches_ms": per_q,
                    "per_query_walker_steps_per_s": (st["steps"] / (per_q / 1e3)) if per_q else None},
         "roofline": {"bound": "hbm", "achieved": st["alg_bytes"] / (avg / 1e3) / 1e9, "peak": PEAK_HBM_GBS,
@@ -627,7 +627,7 @@ def bench_served(args):
                    "p50_ms": p50, "p99_ms": p99, "requests": len(reqs), "completed": len(lat),
                    "sustained": sustained, "offered_walker_steps_per_s": offered_steps / T, "server": st,
                    "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound,
-                            "proposal": plan.proposal},
+                            "proposal": plan.proposal, "grid": plan.grid},
                    "busy_retries": busy[0], "rho": plan.rho},
         "roofline": None, "cpu_baseline": None,
     }

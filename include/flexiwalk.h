@@ -233,10 +233,10 @@ int fw_plan_profile(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stre
  * each eRJS bound: the split bound and the member board too for Node2Vec on a symmetric
  * graph, the member board for second-order PageRank; and each
  * proposal: h-proportional too for a weighted logic once fw_graph_build_alias ran), then for the
- * degree gate d_lo in {0, 8, 32, 128} and the LDS budget for N(prev); the fastest plan
- * is returned.  Every candidate samples the same distribution; only the choice of kernel
- * per step, and so the random stream, differs.  Allocates temporary device memory;
- * synchronous on `stream`. */
+ * degree gate d_lo in {0, 8, 32, 128} and the LDS budget for N(prev); the fastest plan is
+ * returned (grid stays 0: the occupancy limit).  Every candidate
+ * samples the same distribution; only the choice of kernel per step, and so the random
+ * stream, differs.  Allocates temporary device memory; synchronous on `stream`. */
 int fw_plan_autotune(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stream);
 
 /* fw_plan_autotune for a mix of logics, such as the queries of a batch or the requests a

@@ -673,7 +673,8 @@ int fw_plan_autotune_mix(fw_graph *g, const fw_logic *logics, int32_t n_logics, 
     if ((any_n2v && g->symmetric) || (any_pr && !any_n2v)) bounds[nbound++] = 2;
     const int nprop = (any_weighted && g->h && g->prop) ? 2 : 1;
     // cost-model constant around the profiled value for each bound and proposal, then the
-    // degree gate, then the LDS budget for N(prev)
+    // degree gate, then the LDS budget for N(prev) (the grid stays at the occupancy limit:
+    // smaller persistent grids timed no faster on the walk and slower on large batches)
     fw_plan bestp = *out;
     float bestt = 1e30f;
     const float rho0 = out->rho;

@@ -221,3 +221,47 @@ def test_batch_second_pr(g12, gg12, bound):
             assert_parity(parity(p, ln, ora))
     finally:
         b.close()
+
+
+def test_autotune_mix(g12, gg12):
+    """One plan for a mix of logics: valid fields, bounds every logic accepts, and a batch
+    run with it equals the oracle."""
+    logics = [fw.fw_logic_node2vec(0.5, 2.0, True), fw.fw_logic_node2vec(2.0, 0.5, True),
+              fw.fw_logic_second_pr(0.2, True)]
+    pl = fw.fw_plan_autotune_mix(gg12.handle, logics)
+    assert pl.rho > 0 and pl.bound in (0, 1, 2) and pl.proposal == 0 and pl.grid >= 0 and pl.lanes == 64
+    with pytest.raises(fw.FlexiWalkError):
+        fw.fw_plan_autotune_mix(gg12.handle, [])
+    # Node2Vec on a graph without equal reverse edges: only the paper's bound is tried
+    # each vertex points to its successor and to the one 3 ahead (no reverse edges, no duplicates)
+    gd = synth.csr_from_edges(64, [(i, (i + 1) % 64) for i in range(64)] + [(i, (i + 3) % 64) for i in range(64)],
+                              h=[1 + (i % 5) for i in range(128)], symmetric=False)
+    gg = GpuGraph(gd)
+    try:
+        assert not fw.fw_graph_info(gg.handle)[3]
+        pd = fw.fw_plan_autotune_mix(gg.handle, [fw.fw_logic_node2vec(0.25, 2.0, True),
+                                                 fw.fw_logic_second_pr(0.3, True)])
+        assert pd.bound == 0
+    finally:
+        gg.close()
+    # the mixed plan drives a batch of its Node2Vec logics (a batch holds one kind) exactly
+    # as the oracle walks them
+    qd = _small_batch(g12["nv"], 9, 23)
+    olg = [oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=0.5, q=2.0),
+           oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=2.0, q=0.5)]
+    opl = oracle.Plan(rho=pl.rho, d_lo=pl.d_lo, rjs_cap=pl.rjs_cap, bound=pl.bound, proposal=pl.proposal)
+    b = Batch(gg12, qd, [logics[i % 2] for i in range(9)], pl, oracle.AUTO)
+    try:
+        fw.fw_batch_launch(b.h)
+        og = oracle.Graph(g12)
+        for i in range(9):
+            n = int(qd["n"][i])
+            if n == 0:
+                continue
+            p, ln = b.query(i)
+            st = qd["starts"][qd["start_off"][i]:qd["start_off"][i] + n]
+            ora = oracle.walk(og, olg[i % 2], opl, oracle.AUTO, st, int(qd["L"][i]), int(qd["seed"][i]))
+            assert_parity(parity(p, ln, ora))
+    finally:
+        b.close()
+
