@@ -41,6 +41,10 @@ constexpr int kRjsBatch = FW_RJS_BATCH; // eRJS proposals whose loads a lane iss
 //   {col_k, bits(h_k), col_a, bits(h_a)}, {threshold, label_k | label_a << 8, 0, 0},
 //   vrec[col_k], vrec[col_a]  (the candidates' vertex records for the next step's set-up)
 constexpr int kPropU4 = 4;
+#ifndef FW_MERGE_RATIO
+#define FW_MERGE_RATIO 8
+#endif
+constexpr int kMergeRatio = FW_MERGE_RATIO;  // eRVS merges N(v) with N(prev) while d(prev) <= this * d(v)
 #ifndef FW_MIN_WAVES
 #define FW_MIN_WAVES 4
 #endif

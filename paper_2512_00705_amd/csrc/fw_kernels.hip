@@ -141,23 +141,74 @@ __device__ __forceinline__ int64_t row_start(const WalkArgs &a, uint4 r, int32_t
     return a.start_hi ? (int64_t)(((uint64_t)a.start_hi[v] << 32) | r.x) : (int64_t)r.x;
 }
 
+// u in N(prev) for the 64 items of one eRVS round, all lanes together: the round's items
+// are consecutive entries of cur's sorted row, so the wave merges them with N(prev)
+// (sorted, m.p[0, m.len)): it loads the next 64 entries of N(prev) from the wave's cursor
+// `lo` (one coalesced load), each lane finds its item among them by a bisection over the
+// lanes (ds_bpermute), and the block advances while some item lies beyond it.  The cursor
+// then moves past everything below the round's largest item.  Over a whole scan this
+// reads N(prev) once, in order, where a search per item costs log d(prev) dependent loads.
+// `valid`: the lane holds an item; every lane must call this.
+__device__ __forceinline__ bool merge_member(const Mem &m, int32_t u, bool valid, int64_t &lo)
+{
+    const int lane = lane_id();
+    bool found = false, done = !valid;
+    int32_t c = 0;
+    for (;;) {
+        const int64_t vi = lo + lane;
+        const int32_t v = vi < m.len ? m.p[vi] : INT32_MAX;
+        c = 0;
+#pragma unroll
+        for (int s = kWave / 2; s > 0; s >>= 1) {
+            const int32_t pv = __shfl(v, c + s - 1, kWave);
+            if (pv < u) c += s;
+        }
+        const int32_t vc = __shfl(v, c & (kWave - 1), kWave);
+        const int32_t vlast = __shfl(v, kWave - 1, kWave);
+        if (!done) {
+            found = c < kWave && vc == u;
+            done = u <= vlast;
+        }
+        if (__ballot(!done) == 0) break;
+        lo += kWave;  // every open item lies beyond this whole block
+    }
+    lo += __shfl(c, kWave - 1, kWave);  // entries below the round's largest item
+    return found;
+}
+
+// Transition weight from the membership of u in N(prev) (the same expression as
+// edge_weight, for Node2Vec and second-order PageRank).
+template <int KIND, bool W>
+__device__ __forceinline__ float weight_of_member(uint2 e, int j, int32_t prev, bool member, const StepW &sw)
+{
+    const float hv = W ? __uint_as_float(e.y) : 1.0f;
+    if (j == 0) return hv;
+    if ((int32_t)e.x == prev) return sw.ret * hv;
+    return member ? sw.mem * hv : sw.oth * hv;
+}
+
 // eRVS for one step, all 64 lanes cooperating.  Returns the next vertex or -1 when no
 // neighbour has positive weight, with the h of the chosen edge in `hsel`.  `trig`
-// receives the number of jump events.
+// receives the number of jump events.  `merge`: find u in N(prev) by merging the rows
+// (merge_member) instead of searching `mem` per item.
 template <int KIND, bool W>
 __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q, const Mem &mem, uint32_t wid,
                                             int j, int32_t prev, int64_t base, int64_t deg, uint8_t want,
-                                            const StepW &sw, uint32_t &trig, float &hsel)
+                                            const StepW &sw, uint32_t &trig, float &hsel, bool merge)
 {
     const int lane = lane_id();
     const uint32_t k0 = Q.key0, k1 = Q.key1;
     float key = -INFINITY;
     int32_t bi = -1;
     float ru = 0.5f;
+    int64_t mlo = 0;  // merge cursor in N(prev)
     // round 0: lane l keys neighbour l, k = u^(1/w~) kept as log(u) / w~
+    const uint2 e0 = lane < deg ? edge_rec(a, base + lane) : make_uint2(0u, 0u);
+    const bool mem0 = merge && merge_member(mem, (int32_t)e0.x, lane < deg, mlo);
     if (lane < deg) {
         const int64_t k = base + lane;
-        const float wt = edge_weight<KIND, W>(a, Q, k, edge_rec(a, k), j, prev, mem, want, sw);
+        const float wt = merge ? weight_of_member<KIND, W>(e0, j, prev, mem0, sw)
+                               : edge_weight<KIND, W>(a, Q, k, e0, j, prev, mem, want, sw);
         const U4 x = philox(wid, (uint32_t)j, (uint32_t)lane, 1u, k0, k1);
         key = wt > 0.0f ? ln_f(unit_uniform(x.x0)) / wt : -INFINITY;
         ru = unit_uniform(x.x1);
@@ -172,9 +223,12 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q
     // running weight passes the skip threshold T = log(r) / log(k_thr)
     for (int64_t i0 = kWave; i0 < deg; i0 += kWave) {
         const int64_t i = i0 + lane;
+        const uint2 ei = i < deg ? edge_rec(a, base + i) : make_uint2(0u, 0u);
+        const bool memi = merge && merge_member(mem, (int32_t)ei.x, i < deg, mlo);
         if (i < deg) {
             const int64_t k = base + i;
-            const float wt = edge_weight<KIND, W>(a, Q, k, edge_rec(a, k), j, prev, mem, want, sw);
+            const float wt = merge ? weight_of_member<KIND, W>(ei, j, prev, memi, sw)
+                                   : edge_weight<KIND, W>(a, Q, k, ei, j, prev, mem, want, sw);
             S = S + wt;
             if (S > T) {
                 // key conditioned to beat thr: log u' = log1p(expm1(w~ * thr) * V)
@@ -730,7 +784,10 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 const uint8_t want = (KIND == kMetaPath) ? Q.schema[s_j % Q.schema_len] : (uint8_t)0;
                 const bool member_test = uses_membership(KIND) && s_j > 0;
                 Mem m = {a.col + s_pbase, s_pdeg, false, false};
-                if (member_test && s_pdeg <= a.lds_cap && (int64_t)s_pdeg <= (int64_t)s_deg * probes(s_pdeg)) {
+                // merge the rows when N(prev) is not much longer than the row scanned
+                const bool merge = member_test && (int64_t)s_pdeg <= (int64_t)kMergeRatio * s_deg;
+                if (member_test && !merge && s_pdeg <= a.lds_cap &&
+                    (int64_t)s_pdeg <= (int64_t)s_deg * probes(s_pdeg)) {
                     wave_lds_sync();
                     for (int32_t i = lane; i < s_pdeg; i += kWave) lds[i] = a.col[s_pbase + i];
                     wave_lds_sync();
@@ -739,7 +796,7 @@ __global__ void __launch_bounds__(kBlock, kMinWaves) walk_kernel(WalkArgs a)
                 }
                 uint32_t trig = 0;
                 const StepW sw = step_weights<KIND>(Q, s_deg, s_pdeg);
-                res = rvs_step<KIND, W>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, sw, trig, hres);
+                res = rvs_step<KIND, W>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, sw, trig, hres, merge);
                 if (lane == src) served(res, hres, trig);
             }
         }
