@@ -687,3 +687,26 @@ def test_h8_argument_errors(g12):
         with pytest.raises(fw.FlexiWalkError) as e:
             GpuGraph(bad)
         assert e.value.code == fw.FW_E_INVALID
+
+
+def test_alias_build_runs_preprocessing(g12):
+    """fw_graph_build_alias on a graph not yet preprocessed preprocesses it first (its
+    records carry the candidates' vertex records, h_MAX and h_SUM included): walks with
+    h-proportional proposals then equal the oracle's."""
+    gg = GpuGraph(g12, preprocess=False)
+    try:
+        fw.fw_graph_build_alias(gg.handle)
+        torch.cuda.synchronize()
+        hmax, hsum = fw.fw_graph_export_aux(gg.handle, gg.nv)
+        ohmax, ohsum = oracle.Graph(g12).aux()
+        np.testing.assert_array_equal(hmax, ohmax)
+        np.testing.assert_array_equal(hsum, ohsum)
+        pl = oracle.Plan(rho=1.0, proposal=1, bound=2)
+        starts = synth.all_vertices(g12["nv"])
+        p, ln, st, ora = _run_both(gg, g12, N2V_RET, pl, oracle.AUTO, starts, 12, 83)
+        rep = parity(p, ln, ora)
+        assert_parity(rep)
+        if rep["mismatch_walkers"] == 0:
+            _assert_counters(st, ora)
+    finally:
+        gg.close()
