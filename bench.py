@@ -93,7 +93,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-scale", type=int, default=25)
-    ap.add_argument("--tick-steps", type=int, default=16)
+    ap.add_argument("--tick-steps", type=int, default=64)
     ap.add_argument("--skew-scale", type=int, default=20, help="skew: R-MAT scale of the topology")
     ap.add_argument("--skew-L", type=int, default=20, help="skew: walk length")
     ap.add_argument("--plan", default="",
