@@ -32,7 +32,7 @@ enum Stat : int {
 
 constexpr int kBlock = 256;          // 4 wavefronts per block, each independent
 constexpr int kWavesPerBlock = kBlock / 64;
-constexpr int kDefaultLdsCap = 2048; // int32 entries of N(prev) per wavefront
+constexpr int kDefaultLdsCap = 1024; // int32 entries of N(prev) per wavefront (5 blocks of 16 KB per CU)
 #ifndef FW_RJS_BATCH
 #define FW_RJS_BATCH 3
 #endif
@@ -46,9 +46,16 @@ constexpr int kPropU4 = 4;
 #endif
 constexpr int kMergeRatio = FW_MERGE_RATIO;  // eRVS merges N(v) with N(prev) while d(prev) <= this * d(v)
 #ifndef FW_MIN_WAVES
-#define FW_MIN_WAVES 4
+#define FW_MIN_WAVES 5
 #endif
-constexpr int kMinWaves = FW_MIN_WAVES;  // resident waves per SIMD the walk kernel is compiled for
+#ifndef FW_MIN_WAVES_BATCH
+#define FW_MIN_WAVES_BATCH 4
+#endif
+// resident waves per SIMD the walk kernel is compiled for: single-query launches at 5 (96
+// VGPRs; the extra wave hides more memory latency than the few spills cost), batched and
+// resumable ones at 4 (their per-query state spills more at 96)
+constexpr int kMinWaves = FW_MIN_WAVES;
+constexpr int kMinWavesBatch = FW_MIN_WAVES_BATCH;
 
 // Per-query constants of a walk job.  Float constants are prepared on the host in float32
 // exactly as the definition states, so every float32 evaluation agrees bit for bit.
