@@ -242,7 +242,10 @@ int fw_plan_autotune(fw_graph *g, const fw_logic *logic, fw_plan *out, void *str
 /* fw_plan_autotune for a mix of logics, such as the queries of a batch or the requests a
  * server takes (Section 5, dynamic query scheduling: one plan serves every query of a
  * launch).  rho is profiled on logics[0]; each candidate plan is timed on every logic
- * (each with an equal share of the sample walkers, at least 2^18) and scored by the sum.
+ * (each with an equal share of the sample walkers, at least 2^18): when the logics share
+ * kind and weighting (one batch can hold them) as one batch of one query per logic, in
+ * the batched kernel that batches and the server run; otherwise as one fw_walk launch per
+ * logic, scored by the sum.
  * Only bounds every logic accepts are tried.  logics: host array of n_logics values,
  * 1 <= n_logics <= 64.  Same allocation and synchronisation as fw_plan_autotune;
  * fw_plan_autotune(g, lg, out, s) equals fw_plan_autotune_mix(g, lg, 1, out, s). */

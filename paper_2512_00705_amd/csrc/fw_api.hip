@@ -622,6 +622,14 @@ int fw_plan_autotune_mix(fw_graph *g, const fw_logic *logics, int32_t n_logics, 
     // 2^18 walkers (shorter runs time noise) and a candidate's time is the sum over the logics
     const int64_t n = std::min<int64_t>(g->nv, std::max<int64_t>(1 << 18, (1 << 20) / n_logics));
     const int32_t L = 16;
+    // a mix that one batch can hold (one kind and weighting) is timed as such a batch, one
+    // query per logic, so that the batched kernel a batch or a server runs is what is
+    // measured; otherwise each logic is timed in fw_walk launches of its own
+    bool batched = n_logics > 1;
+    for (int32_t i = 1; i < n_logics; ++i)
+        batched = batched && logics[i].kind == logics[0].kind &&
+                  (logics[i].weighted != 0) == (logics[0].weighted != 0);
+    const int64_t nq = batched ? n_logics : 1;
     std::vector<int32_t> starts((size_t)n);
     uint64_t x = 0x9E3779B97F4A7C15ull;
     for (int64_t i = 0; i < n; ++i) {
@@ -632,13 +640,45 @@ int fw_plan_autotune_mix(fw_graph *g, const fw_logic *logics, int32_t n_logics, 
     }
     DevBuf d_starts, d_paths, d_len;
     HIP_TRY(hipMalloc(&d_starts.p, sizeof(int32_t) * (size_t)n));
-    HIP_TRY(hipMalloc(&d_paths.p, sizeof(int32_t) * (size_t)n * (L + 1)));
-    HIP_TRY(hipMalloc(&d_len.p, sizeof(int32_t) * (size_t)n));
+    HIP_TRY(hipMalloc(&d_paths.p, sizeof(int32_t) * (size_t)(nq * n * (L + 1))));
+    HIP_TRY(hipMalloc(&d_len.p, sizeof(int32_t) * (size_t)(nq * n)));
     HIP_TRY(hipMemcpy(d_starts.p, starts.data(), sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice));
     Events ev;
     HIP_TRY(hipEventCreate(&ev.a));
     HIP_TRY(hipEventCreate(&ev.b));
+    std::vector<fw_query> qs((size_t)nq);
+    for (int64_t i = 0; i < nq; ++i) {
+        qs[(size_t)i].logic = logics[i];
+        qs[(size_t)i].n = n;
+        qs[(size_t)i].L = L;
+        qs[(size_t)i].seed = 7 + (uint64_t)i;
+        qs[(size_t)i].start_off = 0;  // every query starts from the same sample
+        qs[(size_t)i].out_off = i * n * (L + 1);
+        qs[(size_t)i].len_off = i * n;
+    }
+    auto time_batch = [&](const fw_plan &p, float *ms) -> int {
+        fw_batch *b = nullptr;
+        int r = fw_batch_create(g, qs.data(), nq, &p, FW_AUTO, (const int32_t *)d_starts.p, n, (int32_t *)d_paths.p,
+                                nq * n * (L + 1), (int32_t *)d_len.p, nq * n, &b);
+        if (r != FW_OK) return r;
+        float best = 1e30f;
+        for (int rep = 0; rep < 2 && r == FW_OK; ++rep) {
+            float t = 0;
+            if (hipEventRecord(ev.a, s) != hipSuccess || (r = fw_batch_launch(b, nullptr, stream)) != FW_OK ||
+                hipEventRecord(ev.b, s) != hipSuccess || hipEventSynchronize(ev.b) != hipSuccess ||
+                hipEventElapsedTime(&t, ev.a, ev.b) != hipSuccess) {
+                if (r == FW_OK) r = fail(FW_E_DEVICE, "fw_plan_autotune_mix: timing a batch failed");
+                break;
+            }
+            best = std::min(best, t);
+        }
+        (void)hipStreamSynchronize(s);
+        (void)fw_batch_destroy(b);
+        *ms = best;
+        return r;
+    };
     auto time_plan = [&](const fw_plan &p, float *ms) -> int {
+        if (batched) return time_batch(p, ms);
         float total = 0;
         for (int32_t i = 0; i < n_logics; ++i) {
             float best = 1e30f;
