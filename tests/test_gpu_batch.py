@@ -244,8 +244,10 @@ def test_autotune_mix(g12, gg12):
         assert pd.bound == 0
     finally:
         gg.close()
-    # the mixed plan drives a batch of its Node2Vec logics (a batch holds one kind) exactly
-    # as the oracle walks them
+    # a mix one batch can hold (the two Node2Vec logics) is tuned by timing such a batch;
+    # that plan drives a batch of them exactly as the oracle walks them
+    pl = fw.fw_plan_autotune_mix(gg12.handle, logics[:2])
+    assert pl.rho > 0 and pl.bound in (0, 1, 2) and pl.proposal == 0 and pl.grid >= 0
     qd = _small_batch(g12["nv"], 9, 23)
     olg = [oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=0.5, q=2.0),
            oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=2.0, q=0.5)]
