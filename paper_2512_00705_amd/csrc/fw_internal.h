@@ -53,7 +53,10 @@ constexpr int kMergeRatio = FW_MERGE_RATIO;  // eRVS merges N(v) with N(prev) wh
 #endif
 // resident waves per SIMD the walk kernel is compiled for: single-query launches at 5 (96
 // VGPRs; the extra wave hides more memory latency than the few spills cost), batched and
-// resumable ones at 4 (their per-query state spills more at 96)
+// resumable ones at 4 (their per-query state spills more at 96), and so are launches that
+// keep the device counters, whose extra state would spill heavily at 96 (the persistent
+// grid is sized by the counter-free variant; blocks beyond what is resident start late
+// and find the walker queue drained)
 constexpr int kMinWaves = FW_MIN_WAVES;
 constexpr int kMinWavesBatch = FW_MIN_WAVES_BATCH;
 

@@ -345,7 +345,7 @@ __device__ __forceinline__ void flush_stats(const WalkArgs &a, uint32_t (&cnt)[k
 // STATS: the launch accumulates the device counters (a.stats non-null); without them the
 // per-lane counts are dead code and their registers go to the walk.
 template <int KIND, bool W, bool BATCH, bool MB, bool STATS>
-__global__ void __launch_bounds__(kBlock, BATCH ? kMinWavesBatch : kMinWaves) walk_kernel(WalkArgs a)
+__global__ void __launch_bounds__(kBlock, (BATCH || STATS) ? kMinWavesBatch : kMinWaves) walk_kernel(WalkArgs a)
 {
     extern __shared__ int32_t lds_all[];
     int32_t *lds = lds_all + (threadIdx.x / kWave) * a.lds_cap;
@@ -1181,7 +1181,7 @@ static int occupancy_blocks(int lds_cap)
 {
     int nb = 0;
     const size_t lds = (size_t)kWavesPerBlock * (size_t)lds_cap * sizeof(int32_t);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<KIND, W, BATCH, false, true>, kBlock, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<KIND, W, BATCH, false, false>, kBlock, lds) !=
         hipSuccess)
         nb = 1;
     return nb > 0 ? nb : 1;

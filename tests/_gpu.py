@@ -62,17 +62,19 @@ def fw_plan(pl: oracle.Plan, **speed):
 
 
 def gpu_walk(gg: GpuGraph, lg: oracle.Logic, pl: oracle.Plan, strategy: int, starts: np.ndarray, L: int,
-             seed: int, **speed):
+             seed: int, counters: bool = True, **speed):
+    """counters=False launches without the device counter array, as the benchmark's timed
+    launches run (the library then runs its counter-free kernel variant); stats is {}."""
     dev = torch.device("cuda:0")
     n = int(starts.shape[0])
     st = torch.from_numpy(np.ascontiguousarray(starts, np.int32)).to(dev)
     paths = torch.full((max(n, 1), L + 1), -7, dtype=torch.int32, device=dev)
     lengths = torch.full((max(n, 1),), -7, dtype=torch.int32, device=dev)
-    stats = torch.zeros(fw.FW_NSTATS, dtype=torch.int64, device=dev)
+    stats = torch.zeros(fw.FW_NSTATS, dtype=torch.int64, device=dev) if counters else None
     fw.fw_walk(gg.handle, fw_logic(lg), fw_plan(pl, **speed), strategy, st, n, L, seed, paths, lengths, stats)
     torch.cuda.synchronize()
     return (paths[:n].cpu().numpy(), lengths[:n].cpu().numpy(),
-            dict(zip(fw.STAT_NAMES, stats.cpu().numpy().astype(np.int64).tolist())))
+            dict(zip(fw.STAT_NAMES, stats.cpu().numpy().astype(np.int64).tolist())) if counters else {})
 
 
 def parity(gpu_paths: np.ndarray, gpu_len: np.ndarray, ora: oracle.WalkResult) -> dict:

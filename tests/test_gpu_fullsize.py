@@ -70,6 +70,11 @@ def test_node2vec_scale22(g22, gg22, og22, tuned22, strategy, k, bound, proposal
                      proposal=tuned.proposal if proposal is None else proposal, member_index=True)
     starts = synth.all_vertices(g22["nv"])
     p, ln, st = gpu_walk(gg22, N2V, pl, strategy, starts, 80, 42)
+    # the launch the benchmark times (no counter array, the counter-free kernel variant)
+    # walks exactly as the counted one
+    p2, ln2, _ = gpu_walk(gg22, N2V, pl, strategy, starts, 80, 42, counters=False)
+    assert np.array_equal(p, p2) and np.array_equal(ln, ln2)
+    del p2, ln2
     ok, pad_ok, _ = edge_check_torch(g22, p, ln)
     assert ok and pad_ok
     deg = np.diff(g22["row_ptr"])
@@ -93,6 +98,9 @@ def test_second_pr_scale22(g22, gg22, og22, bound):
                      bound=tuned.bound if bound is None else bound, proposal=tuned.proposal, member_index=True)
     starts = synth.all_vertices(g22["nv"])
     p, ln, st = gpu_walk(gg22, lg, pl, oracle.AUTO, starts, 80, 42)
+    p2, ln2, _ = gpu_walk(gg22, lg, pl, oracle.AUTO, starts, 80, 42, counters=False)
+    assert np.array_equal(p, p2) and np.array_equal(ln, ln2)
+    del p2, ln2
     ok, pad_ok, _ = edge_check_torch(g22, p, ln)
     assert ok and pad_ok
     sub = _sample(g22["nv"], 16384, 4321)
