@@ -131,7 +131,7 @@ def _configure(lib):
     lib.og_walk.restype = ctypes.c_int
     lib.og_step_once.argtypes = [ctypes.POINTER(_Graph), P, P, ctypes.POINTER(_Logic), ctypes.POINTER(_Plan),
                                  ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
-                                 ctypes.c_int32, ctypes.c_int32, P, P, P]
+                                 ctypes.c_int32, ctypes.c_int32, P, P, P, P]
     lib.og_step_once.restype = ctypes.c_int32
     return lib
 
@@ -271,9 +271,11 @@ def walk(graph: Graph, logic: Logic, plan: Plan, strategy: int, starts, L: int, 
     return WalkResult(paths, lengths, margins, kinds, dict(zip(COUNTER_NAMES, ctr.tolist())))
 
 
-def step_once(graph: Graph, logic: Logic, plan: Plan, strategy: int, seed: int, walker: int, j: int,
-              prev: int, cur: int):
-    """One transition from (prev, cur) at step j; returns (next, margin, kind, trials)."""
+def step_info(graph: Graph, logic: Logic, plan: Plan, strategy: int, seed: int, walker: int, j: int,
+              prev: int, cur: int) -> dict:
+    """One transition from (prev, cur) at step j: the next vertex (-1: the walk ends), the
+    smallest relative margin of its float decisions, its kind (0 eRVS, 1 eRJS, 2 eRJS capped
+    then eRVS, 3 ITS, -1 ended), its eRJS trials and its algorithmic bytes."""
     lib = _load()
     hmax, hsum = graph.aux()
     if plan.proposal:
@@ -281,8 +283,17 @@ def step_once(graph: Graph, logic: Logic, plan: Plan, strategy: int, seed: int, 
     m = ctypes.c_float()
     k = ctypes.c_int32()
     t = ctypes.c_int32()
+    b = ctypes.c_double()
     lg, pl = logic._c(), plan._c()
     r = lib.og_step_once(ctypes.byref(graph._s), hmax.ctypes.data, hsum.ctypes.data, ctypes.byref(lg),
                          ctypes.byref(pl), strategy, seed, walker, j, prev, cur, ctypes.byref(m),
-                         ctypes.byref(k), ctypes.byref(t))
-    return int(r), float(m.value), int(k.value), int(t.value)
+                         ctypes.byref(k), ctypes.byref(t), ctypes.byref(b))
+    return {"next": int(r), "margin": float(m.value), "kind": int(k.value), "trials": int(t.value),
+            "bytes": float(b.value)}
+
+
+def step_once(graph: Graph, logic: Logic, plan: Plan, strategy: int, seed: int, walker: int, j: int,
+              prev: int, cur: int):
+    """One transition from (prev, cur) at step j; returns (next, margin, kind, trials)."""
+    r = step_info(graph, logic, plan, strategy, seed, walker, j, prev, cur)
+    return r["next"], r["margin"], r["kind"], r["trials"]

@@ -64,7 +64,9 @@
  * bound's extra column the full return weight instead of its excess over Bn, 7 divides
  * the second-order PageRank term g by d(v) instead of d(v'), 8 never takes an alias
  * table's alias (every slot keeps itself), 9 lets the member region keep a member without
- * its h(v, x) / h_MAX test.
+ * its h(v, x) / h_MAX test, 10 averages the Node2Vec return values over 2 instead of their 3
+ * branches in the sum estimate, 11 inverts the cost model's choice, 12 charges 8 bytes
+ * instead of 16 for the row pointer pair of a step.
  */
 #ifndef OG_MUTANT
 #define OG_MUTANT 0
@@ -343,7 +345,7 @@ static float w_avg(const og_logic *lg, int j, int64_t dv, int64_t dvp)
     }
     if (lg->kind == OG_NODE2VEC) {
         if (j == 0) return 1.0f;
-        return ((1.0f / lg->p + 1.0f) + 1.0f / lg->q) / 3.0f;
+        return ((1.0f / lg->p + 1.0f) + 1.0f / lg->q) / (OG_MUTANT == 10 ? 2.0f : 3.0f);
     }
     return (1.0f + 0.0f) / 2.0f;
 }
@@ -364,16 +366,21 @@ static int64_t rvs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
     uint32_t x[4];
 
     if (!cx->pl->jump) {
-        /* Algorithm 1 as written: one key per item, keep the last maximum */
+        /* Exponential keys without jumps (Section 3.2): every item of positive weight gets
+           the key u_i^(1/w~_i), here its logarithm ln(u_i) / w~_i (the logarithm is
+           increasing, so the largest key is the same item); the sample is the item of the
+           largest key, the larger index among equal keys.  Items of weight 0 are not
+           eligible; with none eligible the walk ends. */
         float best = -INFINITY;
         int64_t best_i = -1;
         for (int64_t i = 0; i < deg; ++i) {
             float wt = transition_weight(cx, base + i, j, prev, deg, dvp);
             if (!(wt > 0.0f)) continue;
             draw(cx->seed, w, (uint32_t)j, (uint32_t)i, 1, x);
-            float k = ln_f(og_uniform(x[0])) / wt;
-            if (best_i >= 0) note_margin(info, k, best);
-            if (k >= best) { best = k; best_i = i; }
+            float key = ln_f(og_uniform(x[0])) / wt;
+            if (best_i >= 0) note_margin(info, key, best);
+            int wins = best_i < 0 || key > best || (key == best && i > best_i);
+            if (wins) { best = key; best_i = i; }
         }
         return best_i;
     }
@@ -579,7 +586,7 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
     info->kind = -1;
     info->trials = 0;
     info->triggers = 0;
-    info->bytes = 16.0; /* row_ptr[cur], row_ptr[cur + 1] */
+    info->bytes = OG_MUTANT == 12 ? 8.0 : 16.0; /* row_ptr[cur], row_ptr[cur + 1]: two 8-byte offsets */
     const int64_t base = g->row_ptr[cur], deg = g->row_ptr[cur + 1] - base;
     if (deg == 0) return -1;
 
@@ -658,7 +665,7 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
             float lhs = board ? cx->pl->rho * area : cx->pl->rho * B;
             float rhs = board ? (float)deg * Shat : Shat;
             note_margin(info, lhs, rhs);
-            use_rjs = lhs < rhs;
+            use_rjs = OG_MUTANT == 11 ? !(lhs < rhs) : lhs < rhs; /* a tie goes to eRVS */
         }
     } else if (cx->strategy == OG_RANDOM_SELECT) {
         if (weighted) info->bytes += 4.0;
@@ -770,10 +777,11 @@ int og_walk(const og_graph *g, const float *hmax, const float *hsum, const og_lo
     return 0;
 }
 
-/* Single transition for a given state (diagnostics and small tests). */
+/* Single transition for a given state (diagnostics and small tests); bytes receives the
+ * step's algorithmic bytes (any output pointer may be NULL). */
 int32_t og_step_once(const og_graph *g, const float *hmax, const float *hsum, const og_logic *lg,
                      const og_plan *pl, int strategy, uint64_t seed, uint32_t walker, int32_t j, int32_t prev,
-                     int32_t cur, float *margin, int32_t *kind, int32_t *trials)
+                     int32_t cur, float *margin, int32_t *kind, int32_t *trials, double *bytes)
 {
     og_ctx cx = {g, hmax, hsum, lg, pl, strategy, seed};
     og_info info;
@@ -781,5 +789,6 @@ int32_t og_step_once(const og_graph *g, const float *hmax, const float *hsum, co
     if (margin) *margin = info.margin;
     if (kind) *kind = info.kind;
     if (trials) *trials = info.trials;
+    if (bytes) *bytes = info.bytes;
     return r;
 }

@@ -18,12 +18,12 @@ import pytest
 import oracle
 import synth
 from oracle import exact
-from tests._helpers import (chisq_pvalue, hub_ring_graph, path_counts, triangle_graph,
+from tests._helpers import (assert_chisq, chisq_pvalue, hub_ring_graph, path_counts, triangle_graph,
                             worked_example_graph)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-P_OK = 1e-3   # a correct sampler passes at this level (fixed seeds: deterministic)
-P_BAD = 1e-8  # a planted mistake must fail far below it
+P_BAD = 1e-8  # a planted mistake must fail far below it (a correct sampler passes at p > 0.01,
+              # assert_chisq; fixed seeds: deterministic)
 
 N2V = dict(kind=oracle.NODE2VEC, weighted=True, p=2.0, q=0.5)
 
@@ -137,9 +137,9 @@ STRATS = [
 def test_worked_example_sampled(name, strategy, plan):
     g = worked_example_graph()
     n = 40000
-    counts, _ = _walk_counts(g, oracle.Logic(**N2V), plan, strategy, 0, 1, n)
     probs = {(0, v): Fraction(p) for v, p in ((1, "0.3"), (2, "0.2"), (3, "0.4"), (4, "0.1"))}
-    assert chisq_pvalue(counts, probs, n) > P_OK
+    assert_chisq(lambda s: chisq_pvalue(_walk_counts(g, oracle.Logic(**N2V), plan, strategy, 0, 1, n, seed=s)[0],
+                                        probs, n), 42, name)
 
 
 @pytest.mark.parametrize("name,strategy,plan", STRATS, ids=[s[0] for s in STRATS])
@@ -148,9 +148,9 @@ def test_node2vec_paths_chisquare(name, strategy, plan):
     lg = oracle.Logic(**N2V)
     n = 60000
     for start in (0, 4):
-        counts, _ = _walk_counts(g, lg, plan, strategy, start, 3, n, seed=7 + start)
         probs = exact.path_distribution(g, lg, start, 3)
-        assert chisq_pvalue(counts, probs, n) > P_OK, (name, start)
+        assert_chisq(lambda s: chisq_pvalue(_walk_counts(g, lg, plan, strategy, start, 3, n, seed=s)[0], probs, n),
+                     7 + start, (name, start))
 
 
 @pytest.mark.parametrize("strategy", [oracle.AUTO, oracle.RVS_ONLY, oracle.RJS_ONLY])
@@ -160,9 +160,9 @@ def test_metapath_paths_chisquare(strategy):
     n = 40000
     plan = oracle.Plan(rho=1.0, lanes=2, rjs_cap=8)
     for start in (0, 2, 6):
-        counts, r = _walk_counts(g, lg, plan, strategy, start, 4, n, seed=11)
         probs = exact.path_distribution(g, lg, start, 4)
-        assert chisq_pvalue(counts, probs, n) > P_OK, start
+        assert_chisq(lambda s: chisq_pvalue(_walk_counts(g, lg, plan, strategy, start, 4, n, seed=s)[0], probs, n),
+                     11, start)
 
 
 def _hub_case(plan, strategy, n=40000, seed=5):
@@ -187,8 +187,8 @@ def _hub_case(plan, strategy, n=40000, seed=5):
     ("rjs", oracle.RJS_ONLY, oracle.Plan()),
 ])
 def test_hub_distribution(name, strategy, plan):
-    p, r = _hub_case(plan, strategy)
-    assert p > P_OK
+    _, r = _hub_case(plan, strategy)
+    assert_chisq(lambda s: _hub_case(plan, strategy, seed=s)[0], 5, name)
     if strategy == oracle.RVS_ONLY and plan.jump:
         # the jump skips most keys: far fewer key draws than items scanned
         assert r.counters["rvs_triggers"] < 0.2 * 600 * r.counters["steps"] / 2
@@ -240,9 +240,9 @@ def test_split_bound_paths_chisquare(name, strategy, plan, logic):
     lg = oracle.Logic(**logic)
     n = 60000
     for start in (0, 4):
-        counts, _ = _walk_counts(g, lg, plan, strategy, start, 3, n, seed=11 + start)
         probs = exact.path_distribution(g, lg, start, 3)
-        assert chisq_pvalue(counts, probs, n) > P_OK, (name, start)
+        assert_chisq(lambda s: chisq_pvalue(_walk_counts(g, lg, plan, strategy, start, 3, n, seed=s)[0], probs, n),
+                     11 + start, (name, start))
 
 
 def test_split_bound_hub_distribution():
@@ -251,12 +251,14 @@ def test_split_bound_hub_distribution():
     lg = oracle.Logic(**N2V_RET)
     og = oracle.Graph(g)
     n = 40000
-    r = oracle.walk(og, lg, oracle.Plan(bound=1), oracle.RJS_ONLY, np.full(n, 1, np.int32), 2, 5, diagnostics=False)
-    went_hub = r.paths[:, 1] == 0
-    counts = {}
-    for v, c in zip(*np.unique(r.paths[went_hub, 2], return_counts=True)):
-        counts[int(v)] = int(c)
-    assert chisq_pvalue(counts, exact.transition(g, lg, 1, 1, 0), int(went_hub.sum())) > P_OK
+
+    def pval(seed):
+        r = oracle.walk(og, lg, oracle.Plan(bound=1), oracle.RJS_ONLY, np.full(n, 1, np.int32), 2, seed,
+                        diagnostics=False)
+        went_hub = r.paths[:, 1] == 0
+        counts = {int(v): int(c) for v, c in zip(*np.unique(r.paths[went_hub, 2], return_counts=True))}
+        return chisq_pvalue(counts, exact.transition(g, lg, 1, 1, 0), int(went_hub.sum()))
+    assert_chisq(pval, 5)
 
 
 def test_split_bound_mean_trials():
@@ -330,9 +332,9 @@ def test_second_pr_paths_chisquare(name, strategy, plan, gamma):
     lg = oracle.Logic(**dict(PR2, gamma=gamma))
     n = 60000
     for start in (0, 4):
-        counts, _ = _walk_counts(g, lg, plan, strategy, start, 3, n, seed=31 + start)
         probs = exact.path_distribution(g, lg, start, 3)
-        assert chisq_pvalue(counts, probs, n) > P_OK, (name, start)
+        assert_chisq(lambda s: chisq_pvalue(_walk_counts(g, lg, plan, strategy, start, 3, n, seed=s)[0], probs, n),
+                     31 + start, (name, start))
 
 
 def test_second_pr_gamma0_is_first_order():
@@ -343,12 +345,14 @@ def test_second_pr_gamma0_is_first_order():
     og = oracle.Graph(g)
     P = exact.first_order_matrix(g)
     n = 80000
+    probs = {u: Fraction(float(P[0, u])) for u in range(g["nv"]) if P[0, u] > 0}
     for strategy in (oracle.RJS_ONLY, oracle.RVS_ONLY):
-        r = oracle.walk(og, lg, oracle.Plan(), strategy, np.full(n, 3, np.int32), 2, 17, diagnostics=False)
-        at_hub = r.paths[:, 1] == 0
-        counts = {int(v): int(c) for v, c in zip(*np.unique(r.paths[at_hub, 2], return_counts=True))}
-        probs = {u: Fraction(float(P[0, u])) for u in range(g["nv"]) if P[0, u] > 0}
-        assert chisq_pvalue(counts, probs, int(at_hub.sum())) > P_OK
+        def pval(seed):
+            r = oracle.walk(og, lg, oracle.Plan(), strategy, np.full(n, 3, np.int32), 2, seed, diagnostics=False)
+            at_hub = r.paths[:, 1] == 0
+            counts = {int(v): int(c) for v, c in zip(*np.unique(r.paths[at_hub, 2], return_counts=True))}
+            return chisq_pvalue(counts, probs, int(at_hub.sum()))
+        assert_chisq(pval, 17, strategy)
 
 
 def test_second_pr_mean_trials():
@@ -419,8 +423,9 @@ def test_h_proposals_paths_chisquare(name, strategy, plan, logic):
     lg = oracle.Logic(**logic)
     n = 60000
     for start in (0, 4):
-        counts, _ = _walk_counts(g, lg, plan, strategy, start, 3, n, seed=61 + start)
-        assert chisq_pvalue(counts, exact.path_distribution(g, lg, start, 3), n) > P_OK, (name, start)
+        probs = exact.path_distribution(g, lg, start, 3)
+        assert_chisq(lambda s: chisq_pvalue(_walk_counts(g, lg, plan, strategy, start, 3, n, seed=s)[0], probs, n),
+                     61 + start, (name, start))
 
 
 def test_h_proposals_hub_and_skew():
@@ -430,11 +435,14 @@ def test_h_proposals_hub_and_skew():
     lg = oracle.Logic(**N2V_RET)
     og = oracle.Graph(g)
     n = 40000
-    r = oracle.walk(og, lg, oracle.Plan(proposal=1, bound=1), oracle.RJS_ONLY, np.full(n, 1, np.int32), 2, 5,
-                    diagnostics=False)
-    at_hub = r.paths[:, 1] == 0
-    counts = {int(v): int(c) for v, c in zip(*np.unique(r.paths[at_hub, 2], return_counts=True))}
-    assert chisq_pvalue(counts, exact.transition(g, lg, 1, 1, 0), int(at_hub.sum())) > P_OK
+
+    def pval(seed):
+        r = oracle.walk(og, lg, oracle.Plan(proposal=1, bound=1), oracle.RJS_ONLY, np.full(n, 1, np.int32), 2, seed,
+                        diagnostics=False)
+        at_hub = r.paths[:, 1] == 0
+        counts = {int(v): int(c) for v, c in zip(*np.unique(r.paths[at_hub, 2], return_counts=True))}
+        return chisq_pvalue(counts, exact.transition(g, lg, 1, 1, 0), int(at_hub.sum()))
+    assert_chisq(pval, 5)
     g = synth.rmat(12, 8 << 12, seed=2)
     g["h"] = synth.pareto_weights(g["row_ptr"], g["col"], 1.0, 3)
     og = oracle.Graph(g)
@@ -484,8 +492,9 @@ def test_member_board_paths_chisquare(name, strategy, plan, logic):
     lg = oracle.Logic(**logic)
     n = 60000
     for start in (0, 4):
-        counts, _ = _walk_counts(g, lg, plan, strategy, start, 3, n, seed=71 + start)
-        assert chisq_pvalue(counts, exact.path_distribution(g, lg, start, 3), n) > P_OK, (name, start)
+        probs = exact.path_distribution(g, lg, start, 3)
+        assert_chisq(lambda s: chisq_pvalue(_walk_counts(g, lg, plan, strategy, start, 3, n, seed=s)[0], probs, n),
+                     71 + start, (name, start))
 
 
 def test_member_board_hub():
@@ -495,11 +504,13 @@ def test_member_board_hub():
     for logic in (N2V_RET, PR2):
         lg = oracle.Logic(**logic)
         for prop in (0, 1):
-            r = oracle.walk(og, lg, oracle.Plan(bound=2, proposal=prop), oracle.RJS_ONLY, np.full(n, 1, np.int32), 2,
-                            5, diagnostics=False)
-            at_hub = r.paths[:, 1] == 0
-            counts = {int(v): int(c) for v, c in zip(*np.unique(r.paths[at_hub, 2], return_counts=True))}
-            assert chisq_pvalue(counts, exact.transition(g, lg, 1, 1, 0), int(at_hub.sum())) > P_OK, (logic, prop)
+            def pval(seed):
+                r = oracle.walk(og, lg, oracle.Plan(bound=2, proposal=prop), oracle.RJS_ONLY, np.full(n, 1, np.int32),
+                                2, seed, diagnostics=False)
+                at_hub = r.paths[:, 1] == 0
+                counts = {int(v): int(c) for v, c in zip(*np.unique(r.paths[at_hub, 2], return_counts=True))}
+                return chisq_pvalue(counts, exact.transition(g, lg, 1, 1, 0), int(at_hub.sum()))
+            assert_chisq(pval, 5, (logic, prop))
 
 
 def test_member_board_mean_trials():
@@ -545,8 +556,9 @@ def test_selection_policies_exact(strategy, logic):
     lg = oracle.Logic(**logic)
     n = 60000
     for start in (0, 4):
-        counts, _ = _walk_counts(g, lg, oracle.Plan(d_lo=3, lanes=2), strategy, start, 3, n, seed=51 + start)
-        assert chisq_pvalue(counts, exact.path_distribution(g, lg, start, 3), n) > P_OK
+        probs = exact.path_distribution(g, lg, start, 3)
+        assert_chisq(lambda s: chisq_pvalue(_walk_counts(g, lg, oracle.Plan(d_lo=3, lanes=2), strategy, start, 3, n,
+                                                         seed=s)[0], probs, n), 51 + start, start)
 
 
 def test_selection_policy_ratios():
@@ -630,6 +642,136 @@ def test_determinism_and_walker_ids():
     np.testing.assert_array_equal(full.paths, again.paths)
 
 
+# ------------------------------------------------------------------ cost model, sum estimate, bytes
+def _kind(g, lg, plan, j, prev, cur, strategy=oracle.AUTO):
+    """eRJS (1, or 2 when capped) or eRVS (0) at one hand-computed state."""
+    k = oracle.step_info(oracle.Graph(g), lg, plan, strategy, 3, 0, j, prev, cur)["kind"]
+    return {0: "rvs", 1: "rjs", 2: "rjs"}[k]
+
+
+# (state, logic, B, S^) by hand from Section 4.1 Eq. (runtime) and Section 4.2 Eq.
+# (sum_estimation): B = max(w) * h_MAX[v], S^ = mean over the logic's return values of w,
+# times h_SUM[v].  The paper's plan (uniform proposals, bound max(w) * h_MAX) compares rho * B
+# with S^ and takes eRJS only when rho * B < S^ (a tie goes to eRVS).
+def _selector_cases():
+    tri, tri_l = triangle_graph(), triangle_graph(labels=True)
+    return [
+        # Node2Vec a = 2, b = 1/2 at prev = 0, cur = 1: N(1) = {0, 2, 3}, h = 1, 3, 4, so
+        # h_MAX = 4, h_SUM = 8; w in {1/2, 1, 2}: B = 2 * 4 = 8, mean (1/2 + 1 + 2) / 3 = 7/6,
+        # S^ = fl(fl(7/6) * 8)
+        ("node2vec", tri, oracle.Logic(**N2V), 1, 0, 1, 8.0,
+         float(np.float32(np.float32(np.float32(np.float32(0.5) + np.float32(1)) + np.float32(2)) / np.float32(3))
+               * np.float32(8))),
+        # MetaPath: w in {1, 0}, B = 1 * h_MAX, S^ = (1 + 0) / 2 * h_SUM; N(2) has h = 2, 3, 1, 3
+        ("metapath", tri_l, oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(0, 1, 2)), 1, 0, 2, 3.0, 4.5),
+        # second-order PageRank gamma = 1/4 at prev = 2 (d 4), cur = 1 (d 3): max_d = 4,
+        # w in {5/4, 1}: B = 5/4 * 4 = 5, S^ = (5/4 + 1) / 2 * 8 = 9
+        ("2ndpr", tri, oracle.Logic(**PR2), 1, 2, 1, 5.0, 9.0),
+        # unweighted Node2Vec a = b = 1: every w = 1, h = 1: B = 1, S^ = d(1) = 3
+        ("unweighted", tri, oracle.Logic(kind=oracle.NODE2VEC, weighted=False, p=1.0, q=1.0), 1, 0, 1, 1.0, 3.0),
+        # first step (no previous vertex): w = 1 for every logic with one: B = h_MAX = 4, S^ = h_SUM = 8
+        ("first_step", tri, oracle.Logic(**N2V), 0, -1, 1, 4.0, 8.0),
+    ]
+
+
+def _pin_selector():
+    for name, g, lg, j, prev, cur, B, S in _selector_cases():
+        B32, S32 = np.float32(B), np.float32(S)
+        rho_tie = np.float32(S32 / B32)
+        assert np.float32(rho_tie * B32) == S32, name  # an exact float32 tie
+        for rho, want in ((rho_tie * np.float32(0.98), "rjs"), (rho_tie, "rvs"), (rho_tie * np.float32(1.02), "rvs")):
+            got = _kind(g, lg, oracle.Plan(rho=float(rho)), j, prev, cur)
+            assert got == want, (name, float(rho), float(rho * B32), S, got)
+        # the degree gate: below d_lo every step is eRVS, whatever the cost model says
+        deg = int(g["row_ptr"][cur + 1] - g["row_ptr"][cur])
+        assert _kind(g, lg, oracle.Plan(rho=float(rho_tie) * 0.5, d_lo=deg + 1), j, prev, cur) == "rvs", name
+        assert _kind(g, lg, oracle.Plan(rho=float(rho_tie) * 0.5, d_lo=deg), j, prev, cur) == "rjs", name
+
+
+def test_cost_model_selector_and_sum_estimate():
+    """Which kernel AUTO picks at hand-computed states on both sides of rho * B = S^ (and at
+    the exact tie, which goes to eRVS): pins the bound B, the sum estimate S^ (its mean over
+    the logic's return values: Node2Vec's three, MetaPath's two, second-order PageRank's two)
+    and the direction of Eq. (runtime)."""
+    _pin_selector()
+
+
+def _directed(nv, rows, h=None):
+    """CSR from {v: [sorted neighbours]} (directed: the byte pins need states whose
+    membership outcomes are fixed)."""
+    rp = np.zeros(nv + 1, np.int64)
+    col = []
+    for v in range(nv):
+        col += rows.get(v, [])
+        rp[v + 1] = len(col)
+    g = {"nv": nv, "ne": len(col), "row_ptr": rp, "col": np.array(col, np.int32), "h": None, "label": None}
+    if h is not None:
+        g["h"] = np.full(len(col), h, np.float32)
+    return g
+
+
+def _pin_bytes():
+    """Hand-counted algorithmic bytes of single steps (the byte model of the measurement
+    section: 16 B for the row pointer pair, 4 B of h_MAX and 4 B of h_SUM where the step
+    reads them, 4 B col + 4 B h (+1 B label) per scanned or proposed edge, a membership test
+    of u in N(v') as a binary search of 4 B probes or one 8-B key of the edge index, the
+    h-proportional proposal's alias col, alias h and threshold (12 B), a member-region trial's
+    neighbour of v' (4 B) and its lookup of (v, x) with h (12 B, or a search of v's row), and
+    4 B start + 4 B per path slot + 4 B length per walk)."""
+    # v = 0 with N(0) = {2}; v' = 1 with N(1) = {2, 3, 4, 5, 6} (5 entries: ceil(log2 6) = 3
+    # probes); Node2Vec a = 1, b = 2^30: w = 1 on N(v'), ~1e-9 elsewhere, so every proposal's
+    # accept test is left open by the bounds of w and needs the membership test.
+    g = _directed(8, {0: [2], 1: [2, 3, 4, 5, 6], 7: [3]})
+    n2v = oracle.Logic(kind=oracle.NODE2VEC, weighted=False, p=1.0, q=float(2 ** 30))
+    og = oracle.Graph(g)
+
+    def b(lg, plan, strategy, j, prev, cur, graph=og):
+        return oracle.step_info(graph, lg, plan, strategy, 3, 0, j, prev, cur)["bytes"]
+
+    # one eRJS trial (proposes 2, a member): 16 + 4 (col) + 3 probes * 4 B, or one 8-B index key
+    assert b(n2v, oracle.Plan(), oracle.RJS_ONLY, 1, 1, 0) == 16 + 4 + 12
+    assert b(n2v, oracle.Plan(member_index=True), oracle.RJS_ONLY, 1, 1, 0) == 16 + 4 + 8
+    # v = 7 with N(7) = {3}, v' = 1: 3 is a member, but now test a non-member: v' = 0 with N(0) = {2}
+    # (one probe): every trial rejects, so rjs_cap = 3 trials, then eRVS scans 1 entry and
+    # tests it (min(4 * d(v'), 4 * deg * probes) = min(4, 4) bytes)
+    assert b(n2v, oracle.Plan(rjs_cap=3), oracle.RJS_ONLY, 1, 0, 7) == 16 + 3 * (4 + 4 * 1) + (4 + 4)
+    assert b(n2v, oracle.Plan(rjs_cap=3, member_index=True), oracle.RJS_ONLY, 1, 0, 7) == 16 + 3 * (4 + 8) + (4 + 4)
+    # a trial whose accept test the bounds already decide reads no membership: a = b = 1
+    flat = oracle.Logic(kind=oracle.NODE2VEC, weighted=False, p=1.0, q=1.0)
+    assert b(flat, oracle.Plan(), oracle.RJS_ONLY, 1, 1, 0) == 16 + 4
+    # the first step has no membership at all
+    assert b(n2v, oracle.Plan(), oracle.RJS_ONLY, 0, -1, 0) == 16 + 4
+    # eRVS: d(v) = 5 entries of 4 B; N(v') staged (4 * d(v') = 4) against 5 searches of 1 probe
+    assert b(n2v, oracle.Plan(), oracle.RVS_ONLY, 1, 0, 1) == 16 + 5 * 4 + min(4 * 1, 4 * 5 * 1)
+    # ... and with N(v') = 5 entries against a 1-entry row: one search of 3 probes (12) < staging (20)
+    assert b(n2v, oracle.Plan(), oracle.RVS_ONLY, 1, 1, 0) == 16 + 1 * 4 + min(4 * 5, 4 * 1 * 3)
+    # weighted: 4 B of h per edge, and h_MAX (eRJS only) or h_MAX + h_SUM (the cost model)
+    gw = _directed(8, {0: [2], 1: [2, 3, 4, 5, 6], 7: [3]}, h=2.0)
+    ogw = oracle.Graph(gw)
+    n2vw = oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=1.0, q=float(2 ** 30))
+    assert b(n2vw, oracle.Plan(), oracle.RJS_ONLY, 1, 1, 0, ogw) == 16 + 4 + (4 + 4) + 12
+    assert b(n2vw, oracle.Plan(rho=1e-6), oracle.AUTO, 1, 1, 0, ogw) == 16 + 8 + (4 + 4) + 12
+    # h-proportional proposal: its record adds the alias col, alias h and threshold (12 B)
+    assert b(n2vw, oracle.Plan(proposal=1), oracle.RJS_ONLY, 1, 1, 0, ogw) == 16 + 4 + (4 + 4 + 12) + 12
+    # member board (second-order PageRank, gamma = 1: only members of N(v') weigh anything,
+    # so every trial is a member-region trial): v = 0 with N(0) = {1, 2}, v' = 1 with
+    # N(1) = {2}: the trial reads x = 2 (4 B) and looks (0, 2) up: a search of the 2-entry row
+    # (ceil(log2 3) = 2 probes) or 12 B of the index (key and h); it is kept, h = 1 = h_MAX
+    gm = _directed(3, {0: [1, 2], 1: [2]})
+    ogm = oracle.Graph(gm)
+    pr1 = oracle.Logic(kind=oracle.SECOND_PR, weighted=False, gamma=1.0)
+    assert b(pr1, oracle.Plan(bound=2), oracle.RJS_ONLY, 1, 1, 0, ogm) == 16 + 4 + 4 * 2
+    assert b(pr1, oracle.Plan(bound=2, member_index=True), oracle.RJS_ONLY, 1, 1, 0, ogm) == 16 + 4 + 12
+    # a walk's own I/O: a start at an isolated vertex reads its row pointers and ends:
+    # 4 (start) + 4 * (L + 1) (path row) + 4 (length) + 16
+    r = oracle.walk(og, n2v, oracle.Plan(), oracle.AUTO, np.array([5], np.int32), 7, 1)
+    assert r.lengths[0] == 0 and r.counters["alg_bytes"] == 4 + 4 * 8 + 4 + 16
+
+
+def test_algorithmic_bytes_hand_counted():
+    _pin_bytes()
+
+
 # ------------------------------------------------------------------ planted mistakes
 MUTANTS = {
     1: "Node2Vec return weight uses 1/q",
@@ -641,7 +783,12 @@ MUTANTS = {
     7: "second-order PageRank divides gamma by d(v) instead of d(v')",
     8: "alias tables never take the alias",
     9: "member region keeps a member without its h test",
+    10: "sum estimate averages Node2Vec over 2 branches instead of 3",
+    11: "cost model's choice inverted",
+    12: "row pointer pair charged 8 bytes instead of 16",
 }
+# planted mistakes caught by deterministic pins (hand-computed states), not by chi-square
+DETERMINISTIC_PINS = {10: "_pin_selector", 11: "_pin_selector", 12: "_pin_bytes"}
 
 
 @pytest.fixture(scope="module")
@@ -652,6 +799,11 @@ def mutant_libs(tmp_path_factory):
 
 @pytest.mark.parametrize("mut", sorted(MUTANTS), ids=[MUTANTS[k] for k in sorted(MUTANTS)])
 def test_planted_mistake_is_caught(mut, mutant_libs):
+    if mut in DETERMINISTIC_PINS:
+        with oracle.use_library(mutant_libs[mut]):
+            with pytest.raises(AssertionError):
+                globals()[DETERMINISTIC_PINS[mut]]()
+        return
     g = triangle_graph()
     caught = []
     with oracle.use_library(mutant_libs[mut]):
@@ -737,7 +889,8 @@ def test_h8_chisquare():
     gf = dict(g, h=(codes[idx].astype(np.float64) * np.float64(scale)).astype(np.float32))
     lg = oracle.Logic(**N2V)
     n = 60000
+    probs = exact.path_distribution(gf, lg, 0, 3)
     for strategy, plan in ((oracle.RJS_ONLY, oracle.Plan()), (oracle.RVS_ONLY, oracle.Plan(lanes=2)),
                            (oracle.RJS_ONLY, oracle.Plan(proposal=1, bound=2))):
-        counts, _ = _walk_counts(gq, lg, plan, strategy, 0, 3, n, seed=5)
-        assert chisq_pvalue(counts, exact.path_distribution(gf, lg, 0, 3), n) > P_OK
+        assert_chisq(lambda s: chisq_pvalue(_walk_counts(gq, lg, plan, strategy, 0, 3, n, seed=s)[0], probs, n), 5,
+                     (strategy, plan.bound))
