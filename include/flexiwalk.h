@@ -113,15 +113,6 @@ typedef struct fw_logic {
  *               reverse edges exist with equal h (fw_graph_info reports it); MetaPath
  *               ignores it.  The cost model then compares rho * (deg * height +
  *               excess) with deg * S^.
- *   proposal eRJS proposal distribution (changes the stream, never the distribution):
- *            0  uniform over N(v) (Section 3.3), tested as U * B < w~;
- *            1  proportional to the static weight h(v,u) through per-row alias tables
- *               (fw_graph_build_alias), tested as U * W < w with W >= every workload
- *               weight: the mass of u is h * w / (W * sum h), proportional to w~, and the
- *               expected trials drop from deg * B / S to W * h_SUM / S.  Applies to
- *               weighted logics; a row whose h are all zero goes to eRVS.  With
- *               bound = 1 the return edge's extra column is (1/p - W) * h(v, prev) wide.
- *            The cost model compares rho * (board area) with deg * S^ for 1 (and bound 1).
  *            2  member board (extension of Section 3.3), Node2Vec with q > 1 and
  *               second-order PageRank with gamma > 0, where members of N(prev) weigh
  *               w_mem above everyone else's w_oth: regular columns at w_oth take every
@@ -131,7 +122,17 @@ typedef struct fw_logic {
  *               neighbour x of prev uniformly and keeps it when (v, x) is an edge, with
  *               probability h(v, x) / h_MAX (the edge index, else a search of v's row,
  *               finds it).  Per step the smaller of this board and bound 1's (Node2Vec)
- *               or bound 0's is used.  Node2Vec needs a symmetric graph as for 1. */
+ *               or bound 0's is used; the cost model compares rho * (its area) with
+ *               deg * S^.  Node2Vec needs a symmetric graph as for 1.
+ *   proposal eRJS proposal distribution (changes the stream, never the distribution):
+ *            0  uniform over N(v) (Section 3.3), tested as U * B < w~;
+ *            1  proportional to the static weight h(v,u) through per-row alias tables
+ *               (fw_graph_build_alias), tested as U * W < w with W >= every workload
+ *               weight: the mass of u is h * w / (W * sum h), proportional to w~, and the
+ *               expected trials drop from deg * B / S to W * h_SUM / S.  Applies to
+ *               weighted logics; a row whose h are all zero goes to eRVS.  With
+ *               bound = 1 the return edge's extra column is (1/p - W) * h(v, prev) wide.
+ *            The cost model compares rho * (board area) with deg * S^ for 1 (and bound 1). */
 typedef struct fw_plan {
     float rho;
     int32_t d_lo;
@@ -331,7 +332,8 @@ int fw_server_create(fw_graph *g, const fw_plan *plan, int32_t strategy, uint64_
 
 /* Queue a request: n walkers from starts (host pointer, copied), at most L steps.  Returns
  * FW_E_BUSY when max_pending requests are already waiting, FW_E_INVALID when the request
- * can never fit the budget.  *req_id identifies it (ids start at 1). */
+ * can never fit the budget or a start lies outside [0, nv) (nothing is queued then).
+ * *req_id identifies it (ids start at 1). */
 int fw_server_submit(fw_server *s, const fw_logic *logic, const int32_t *starts, int64_t n, int32_t L,
                      uint64_t seed, uint64_t *req_id);
 

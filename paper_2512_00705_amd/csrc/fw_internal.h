@@ -33,10 +33,17 @@ enum Stat : int {
 constexpr int kBlock = 256;          // 4 wavefronts per block, each independent
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kDefaultLdsCap = 1024; // int32 entries of N(prev) per wavefront (5 blocks of 16 KB per CU)
+// eRJS proposals whose loads a lane issues together.  Only depth 3 is built: a build with
+// depth 4 whose counted launches were compiled for 5 waves per SIMD (heavy spills) left the
+// oracle's path after eRJS cap fall-backs, and that failure has no identified cause, so no
+// other depth may be built until one is found.
 #ifndef FW_RJS_BATCH
 #define FW_RJS_BATCH 3
 #endif
-constexpr int kRjsBatch = FW_RJS_BATCH; // eRJS proposals whose loads a lane issues together
+#if FW_RJS_BATCH != 3
+#error "FW_RJS_BATCH: only the eRJS load batch of depth 3 has passed the parity suite"
+#endif
+constexpr int kRjsBatch = FW_RJS_BATCH;
 // h-proportional proposal record per CSR entry, 64 bytes (one DRAM line holds it whole):
 //   {col_k, bits(h_k), col_a, bits(h_a)}, {threshold, label_k | label_a << 8, 0, 0},
 //   vrec[col_k], vrec[col_a]  (the candidates' vertex records for the next step's set-up)
@@ -53,12 +60,14 @@ constexpr int kMergeRatio = FW_MERGE_RATIO;  // eRVS merges N(v) with N(prev) wh
 #endif
 // resident waves per SIMD the walk kernel is compiled for: single-query launches at 5 (96
 // VGPRs; the extra wave hides more memory latency than the few spills cost), batched and
-// resumable ones at 4 (their per-query state spills more at 96), and so are launches that
-// keep the device counters, whose extra state would spill heavily at 96 (the persistent
-// grid is sized by the counter-free variant; blocks beyond what is resident start late
-// and find the walker queue drained)
+// resumable ones at 4 (their per-query state spills more at 96).  Launches that keep the
+// device counters are compiled for 4 waves, fixed: their extra state spills heavily at 96,
+// and the one build that did so is the unexplained parity failure noted at kRjsBatch (the
+// persistent grid is sized by the counter-free variant; blocks beyond what is resident
+// start late and find the walker queue drained)
 constexpr int kMinWaves = FW_MIN_WAVES;
 constexpr int kMinWavesBatch = FW_MIN_WAVES_BATCH;
+constexpr int kMinWavesCounted = 4;
 
 // Per-query constants of a walk job.  Float constants are prepared on the host in float32
 // exactly as the definition states, so every float32 evaluation agrees bit for bit.

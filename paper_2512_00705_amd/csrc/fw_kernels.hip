@@ -345,7 +345,8 @@ __device__ __forceinline__ void flush_stats(const WalkArgs &a, uint32_t (&cnt)[k
 // STATS: the launch accumulates the device counters (a.stats non-null); without them the
 // per-lane counts are dead code and their registers go to the walk.
 template <int KIND, bool W, bool BATCH, bool MB, bool STATS>
-__global__ void __launch_bounds__(kBlock, (BATCH || STATS) ? kMinWavesBatch : kMinWaves) walk_kernel(WalkArgs a)
+__global__ void __launch_bounds__(kBlock, STATS ? kMinWavesCounted : (BATCH ? kMinWavesBatch : kMinWaves))
+walk_kernel(WalkArgs a)
 {
     extern __shared__ int32_t lds_all[];
     int32_t *lds = lds_all + (threadIdx.x / kWave) * a.lds_cap;

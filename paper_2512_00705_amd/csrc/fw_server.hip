@@ -398,6 +398,12 @@ int fw_server_submit(fw_server *s, const fw_logic *logic, const int32_t *starts,
     if (L < 0 || L >= (1 << 20)) return fail(FW_E_INVALID, "fw_server_submit: L must be in [0, 2^20)");
     const size_t bytes = request_bytes(n, L);
     if (bytes > s->budget) return fail(FW_E_INVALID, "fw_server_submit: request needs %zu bytes, budget %zu", bytes, s->budget);
+    // starts are host memory: checked here, so a served request never trips the graph's
+    // device error flag, which the server does not read
+    for (int64_t i = 0; i < n; ++i)
+        if (starts[i] < 0 || (int64_t)starts[i] >= s->g->nv)
+            return fail(FW_E_INVALID, "fw_server_submit: start %lld (vertex %d) outside [0, %lld)", (long long)i,
+                        starts[i], (long long)s->g->nv);
     std::unique_lock<std::mutex> lk(s->mu);
     if (s->err != FW_OK) return fail(s->err, "server stopped: %s", s->err_msg.c_str());
     if ((int64_t)s->waiting.size() >= s->max_pending) return fail(FW_E_BUSY, "fw_server_submit: %d requests already waiting", s->max_pending);

@@ -16,7 +16,7 @@ import oracle
 import synth
 from oracle import exact
 from tests._gpu import GpuGraph, assert_parity, gpu_walk, parity
-from tests._helpers import chisq_pvalue, hub_ring_graph, worked_example_graph
+from tests._helpers import assert_chisq, chisq_pvalue, hub_ring_graph, worked_example_graph
 
 import paper_2512_00705_amd as fw
 
@@ -50,6 +50,17 @@ def _run_both(gg, g, lg, pl, strategy, starts, L, seed, walker_ids=None, **speed
 def _assert_counters(st, ora):
     for k in COUNTERS:
         assert st[k] == int(ora.counters[k]), (k, st[k], ora.counters[k])
+
+
+def _hub_chisq(g, gg, lg, pl, strategy, seed, label, n=300000):
+    """Second step at the hub of ``hub_ring_graph`` from leaf 1 against the exact
+    transition, accepted at p > 0.01 (one declared retest on an independent seed)."""
+    def pvalue(sd):
+        p, ln, st = gpu_walk(gg, lg, pl, strategy, np.ones(n, np.int32), 2, sd)
+        at_hub = p[:, 1] == 0
+        counts = {int(v): int(c) for v, c in zip(*np.unique(p[at_hub, 2], return_counts=True))}
+        return chisq_pvalue(counts, exact.transition(g, lg, 1, 1, 0), int(at_hub.sum()))
+    return assert_chisq(pvalue, seed, label)
 
 
 def test_preprocess_bit_exact(g12, gg12):
@@ -201,14 +212,16 @@ def test_argument_errors(g12, gg12):
 def test_chisquare_worked_example(strategy):
     g = worked_example_graph()
     gg = GpuGraph(g)
+    n = 200000
+
+    def pvalue(sd):
+        p, ln, st = gpu_walk(gg, N2V, oracle.Plan(), STRATS[strategy], np.zeros(n, np.int32), 1, sd)
+        counts = {int(v): int(c) for v, c in zip(*np.unique(p[:, 1], return_counts=True))}
+        return chisq_pvalue(counts, exact.transition(g, N2V, 0, -1, 0), n)
     try:
-        n = 200000
-        p, ln, st = gpu_walk(gg, N2V, oracle.Plan(), STRATS[strategy], np.zeros(n, np.int32), 1, 17)
+        assert_chisq(pvalue, 17, f"worked example {strategy}")
     finally:
         gg.close()
-    counts = {int(v): int(c) for v, c in zip(*np.unique(p[:, 1], return_counts=True))}
-    probs = exact.transition(g, N2V, 0, -1, 0)
-    assert chisq_pvalue(counts, probs, n) > 1e-3
 
 
 @pytest.mark.parametrize("strategy", list(STRATS), ids=list(STRATS))
@@ -217,15 +230,9 @@ def test_chisquare_hub_second_step(strategy):
     g = hub_ring_graph(600)
     gg = GpuGraph(g)
     try:
-        n = 300000
-        p, ln, st = gpu_walk(gg, N2V, oracle.Plan(rho=1.0), STRATS[strategy], np.ones(n, np.int32), 2, 23)
+        _hub_chisq(g, gg, N2V, oracle.Plan(rho=1.0), STRATS[strategy], 23, f"hub {strategy}")
     finally:
         gg.close()
-    at_hub = p[:, 1] == 0
-    nxt = p[at_hub, 2]
-    counts = {int(v): int(c) for v, c in zip(*np.unique(nxt, return_counts=True))}
-    probs = exact.transition(g, N2V, 1, 1, 0)
-    assert chisq_pvalue(counts, probs, int(at_hub.sum())) > 1e-3
 
 
 # ------------------------------------------------------------------ split eRJS bound
@@ -262,14 +269,9 @@ def test_split_bound_chisquare_hub(strategy):
     gg = GpuGraph(g)
     try:
         assert fw.fw_graph_info(gg.handle)[3]
-        n = 300000
-        p, ln, st = gpu_walk(gg, N2V_RET, oracle.Plan(rho=1.0, bound=1), STRATS[strategy], np.ones(n, np.int32),
-                             2, 29)
+        _hub_chisq(g, gg, N2V_RET, oracle.Plan(rho=1.0, bound=1), STRATS[strategy], 29, f"split bound {strategy}")
     finally:
         gg.close()
-    at_hub = p[:, 1] == 0
-    counts = {int(v): int(c) for v, c in zip(*np.unique(p[at_hub, 2], return_counts=True))}
-    assert chisq_pvalue(counts, exact.transition(g, N2V_RET, 1, 1, 0), int(at_hub.sum())) > 1e-3
 
 
 def test_split_bound_needs_symmetric_graph(g12, gg12):
@@ -417,13 +419,9 @@ def test_second_pr_chisquare_hub(strategy):
     g = hub_ring_graph(600)
     gg = GpuGraph(g)
     try:
-        n = 300000
-        p, ln, st = gpu_walk(gg, PR2, oracle.Plan(rho=1.0), STRATS[strategy], np.ones(n, np.int32), 2, 41)
+        _hub_chisq(g, gg, PR2, oracle.Plan(rho=1.0), STRATS[strategy], 41, f"second-order PageRank {strategy}")
     finally:
         gg.close()
-    at_hub = p[:, 1] == 0
-    counts = {int(v): int(c) for v, c in zip(*np.unique(p[at_hub, 2], return_counts=True))}
-    assert chisq_pvalue(counts, exact.transition(g, PR2, 1, 1, 0), int(at_hub.sum())) > 1e-3
 
 
 def test_second_pr_logic_errors():
@@ -533,14 +531,9 @@ def test_h_proposals_chisquare_hub():
     g = hub_ring_graph(600)
     gg = GpuGraph(g, alias=True)
     try:
-        n = 300000
-        p, ln, st = gpu_walk(gg, N2V_RET, oracle.Plan(rho=1.0, bound=1, proposal=1), oracle.RJS_ONLY,
-                             np.ones(n, np.int32), 2, 43)
+        _hub_chisq(g, gg, N2V_RET, oracle.Plan(rho=1.0, bound=1, proposal=1), oracle.RJS_ONLY, 43, "h proposals")
     finally:
         gg.close()
-    at_hub = p[:, 1] == 0
-    counts = {int(v): int(c) for v, c in zip(*np.unique(p[at_hub, 2], return_counts=True))}
-    assert chisq_pvalue(counts, exact.transition(g, N2V_RET, 1, 1, 0), int(at_hub.sum())) > 1e-3
 
 
 def test_h_proposals_need_alias(g12, gg12):
@@ -610,14 +603,10 @@ def test_member_board_chisquare_hub(logic, proposal):
     g = hub_ring_graph(600)
     gg = GpuGraph(g, index=True, alias=True)
     try:
-        n = 300000
-        p, ln, st = gpu_walk(gg, lg, oracle.Plan(rho=1.0, bound=2, proposal=proposal), oracle.RJS_ONLY,
-                             np.ones(n, np.int32), 2, 47)
+        _hub_chisq(g, gg, lg, oracle.Plan(rho=1.0, bound=2, proposal=proposal), oracle.RJS_ONLY, 47,
+                   f"member board {logic} {proposal}")
     finally:
         gg.close()
-    at_hub = p[:, 1] == 0
-    counts = {int(v): int(c) for v, c in zip(*np.unique(p[at_hub, 2], return_counts=True))}
-    assert chisq_pvalue(counts, exact.transition(g, lg, 1, 1, 0), int(at_hub.sum())) > 1e-3
 
 
 # ------------------------------------------------------------------ 8-bit property weights

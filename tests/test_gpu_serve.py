@@ -147,7 +147,13 @@ def test_budget_queues_and_busy(g12, gg12):
 def test_bad_start_and_teardown(g12, gg12):
     srv = fw.fw_server_create(gg12.handle, fw.fw_plan_default(), fw.FW_AUTO, 16 << 20, tick_steps=4)
     try:
-        st = np.array([3, g12["nv"] + 5, 9], np.int32)
+        # a start outside [0, nv) is refused at submit; nothing is queued and the graph's
+        # device error flag stays clear
+        for bad in (g12["nv"] + 5, -1):
+            with pytest.raises(fw.FlexiWalkError) as e:
+                fw.fw_server_submit(srv, fw.fw_logic_node2vec(1.0, 1.0, True), np.array([3, bad, 9], np.int32), 6, 5)
+            assert e.value.code == fw.FW_E_INVALID
+        st = np.array([3, 7, 9], np.int32)
         rid = fw.fw_server_submit(srv, fw.fw_logic_node2vec(1.0, 1.0, True), st, 6, 5)
         got = 0
         for _ in range(100):
@@ -156,9 +162,10 @@ def test_bad_start_and_teardown(g12, gg12):
                 break
         assert got == rid
         p, ln, _ = fw.fw_server_result(srv, rid, 3, 6)
-        assert ln[1] == 0 and (p[1, 1:] == -1).all()
-        with pytest.raises(fw.FlexiWalkError):
-            fw.fw_graph_check(gg12.handle)
+        alone = gpu_walk(gg12, oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=1.0, q=1.0), oracle.Plan(),
+                         oracle.AUTO, st, 6, 5)
+        np.testing.assert_array_equal(p, alone[0])
+        fw.fw_graph_check(gg12.handle)
         with pytest.raises(fw.FlexiWalkError):  # results are handed out once
             fw.fw_server_result(srv, rid, 3, 6)
         for i in range(20):  # left running at teardown
@@ -198,7 +205,7 @@ def test_split_bound_resume(g12, gg12, tick_steps, bound):
 @pytest.mark.parametrize("bound", [1, 2], ids=["split", "member"])
 def test_h_proposals_served(g12, bound):
     """Served walks under h-proportional proposals and the split bound (or the member
-    board), suspended every 3 steps, equal the same walks run alone."""
+    board), suspended every 3 steps, equal the same walks run alone and the oracle's."""
     gg = GpuGraph(g12, index=True, alias=True)
     pl = oracle.Plan(rho=1.0, rjs_cap=64, bound=bound, proposal=1)
     rng = np.random.default_rng(9)
@@ -212,11 +219,13 @@ def test_h_proposals_served(g12, bound):
         results = _serve_all(srv, reqs)
     finally:
         fw.fw_server_destroy(srv)
+    og = oracle.Graph(g12)
     try:
         for k, (lg, st, L, seed) in enumerate(reqs):
             p, ln, _ = results[k]
             alone = gpu_walk(gg, lg, pl, oracle.AUTO, st, L, seed)
             np.testing.assert_array_equal(p, alone[0], err_msg=f"request {k}")
             np.testing.assert_array_equal(ln, alone[1], err_msg=f"request {k}")
+            assert_parity(parity(p, ln, oracle.walk(og, lg, pl, oracle.AUTO, st, L, seed)))
     finally:
         gg.close()
