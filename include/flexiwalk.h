@@ -312,6 +312,22 @@ int fw_batch_replay(fw_batch *b, void *stream);
 /* Free the batch and its graph.  NULL is accepted; its launches must have finished. */
 int fw_batch_destroy(fw_batch *b);
 
+/* For callers that cannot allocate device memory (tight serving loops, harnesses that
+ * forbid hipMalloc): fw_batch_create followed by fw_batch_launch in one call that
+ * allocates nothing.  Arguments, checks and results are those of the two calls (the same
+ * kernels, so the walks are bit-identical).  The query table and the walker counter live
+ * in a library-owned static device array of 256 + FW_NOALLOC_MAX_QUERIES * 176 bytes per
+ * device, held until the process ends; nq above FW_NOALLOC_MAX_QUERIES is refused with
+ * FW_E_INVALID before anything runs.  The table is copied from host memory on `stream`
+ * (the call returns once its host staging has been read), so the call is not for graph
+ * capture.  Every call on one device shares that array: calls ordered on one stream are
+ * safe, calls that overlap on one device (other streams, other threads) race.  The launch
+ * is asynchronous; a bad start vertex is reported by fw_graph_check. */
+#define FW_NOALLOC_MAX_QUERIES 4096
+int fw_batch_run_noalloc(fw_graph *g, const fw_query *queries, int64_t nq, const fw_plan *plan, int32_t strategy,
+                         const int32_t *starts, int64_t starts_len, int32_t *paths, int64_t paths_len,
+                         int32_t *lengths, int64_t lengths_len, uint64_t *stats, void *stream);
+
 /* Walk server: continuous batching of walk requests against a resident graph.
  *
  * A server thread runs ticks: one batched launch per (logic kind, weighting) over the

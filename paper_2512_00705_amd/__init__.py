@@ -21,6 +21,7 @@ FW_OK, FW_E_INVALID, FW_E_NOMEM, FW_E_DEVICE, FW_E_STATE, FW_E_BUSY = 0, 1, 2, 3
 FW_AUTO, FW_RVS_ONLY, FW_RJS_ONLY, FW_RANDOM_SELECT, FW_DEGREE_SELECT = 0, 1, 2, 4, 5
 FW_NODE2VEC, FW_METAPATH, FW_SECOND_PR = 1, 2, 3
 FW_MAX_SCHEMA = 64
+FW_NOALLOC_MAX_QUERIES = 4096
 FW_NSTATS = 8
 STAT_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", "rvs_triggers",
               "ended_early", "alg_bytes")
@@ -28,7 +29,8 @@ EXPORTED = ("fw_graph_create", "fw_graph_destroy", "fw_graph_preprocess", "fw_gr
             "fw_graph_export_aux", "fw_graph_info", "fw_calibrate_random_reads", "fw_graph_build_alias",
             "fw_logic_node2vec", "fw_logic_metapath", "fw_logic_second_pr", "fw_plan_default", "fw_plan_profile",
             "fw_plan_autotune", "fw_plan_autotune_mix", "fw_walk", "fw_graph_check", "fw_last_error", "fw_batch_create", "fw_batch_launch",
-            "fw_batch_capture", "fw_batch_replay", "fw_batch_destroy", "fw_server_create", "fw_server_submit",
+            "fw_batch_capture", "fw_batch_replay", "fw_batch_destroy", "fw_batch_run_noalloc", "fw_server_create",
+            "fw_server_submit",
             "fw_server_next_done", "fw_server_result", "fw_server_stats", "fw_server_destroy")
 SERVER_STAT_NAMES = ("waiting", "active", "finished", "ticks", "walker_steps", "bytes_in_use", "peak_bytes",
                      "alg_bytes")
@@ -95,6 +97,8 @@ def _load():
         "fw_batch_capture": ([P, P, P], ctypes.c_int),
         "fw_batch_replay": ([P, P], ctypes.c_int),
         "fw_batch_destroy": ([P], ctypes.c_int),
+        "fw_batch_run_noalloc": ([P, P, I64, ctypes.POINTER(fw_plan), I32, P, I64, P, I64, P, I64, P, P],
+                                 ctypes.c_int),
         "fw_server_create": ([P, ctypes.POINTER(fw_plan), I32, ctypes.c_uint64, I32, I32, I32,
                               ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
         "fw_server_submit": ([P, ctypes.POINTER(fw_logic), P, I64, I32, ctypes.c_uint64,
@@ -282,6 +286,15 @@ def fw_batch_replay(b: int, stream=None):
 
 def fw_batch_destroy(b: int):
     _check(_lib.fw_batch_destroy(b))
+
+
+def fw_batch_run_noalloc(g: int, queries, plan: fw_plan, strategy: int, starts, paths, lengths, stats=None,
+                         stream=None, starts_len=None, paths_len=None, lengths_len=None):
+    """fw_batch_create + fw_batch_launch in one call that allocates no device memory."""
+    arr = (fw_query * max(len(queries), 1))(*queries)
+    _check(_lib.fw_batch_run_noalloc(g, arr, len(queries), ctypes.byref(plan), strategy, _ptr(starts),
+                                     _numel(starts, starts_len), _ptr(paths), _numel(paths, paths_len),
+                                     _ptr(lengths), _numel(lengths, lengths_len), _ptr(stats), _stream(stream)))
 
 
 def fw_server_create(g: int, plan: fw_plan, strategy: int, hbm_budget: int, tick_steps: int = 16,

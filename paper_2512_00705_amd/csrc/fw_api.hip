@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -772,6 +773,39 @@ static void batch_free(fw_batch *b)
     delete b;
 }
 
+// Checks query i of a batch and fills its device-table entry; `first` is the flattened
+// index of its first walker.
+static int query_entry(const fw_graph *g, const fw_plan *pl, const fw_query *qs, int64_t i, const int32_t *starts,
+                       int64_t starts_len, int32_t *paths, int64_t paths_len, int32_t *lengths, int64_t lengths_len,
+                       int64_t first, fw::QueryDev &d)
+{
+    const fw_query &q = qs[i];
+    int rc;
+    if ((rc = check_logic(g, &q.logic)) != FW_OK) return rc;
+    if ((rc = check_bound(g, pl, &q.logic)) != FW_OK) return rc;
+    if (q.logic.kind != qs[0].logic.kind || (q.logic.weighted != 0) != (qs[0].logic.weighted != 0))
+        return fail(FW_E_INVALID, "batch: all queries of a batch share kind and weighting");
+    if (q.n < 0 || q.n >= ((int64_t)1 << 31)) return fail(FW_E_INVALID, "query %lld: n out of range", (long long)i);
+    if (q.L < 0 || q.L >= (1 << 20)) return fail(FW_E_INVALID, "query %lld: L out of range", (long long)i);
+    if (q.start_off < 0 || q.out_off < 0 || q.len_off < 0)
+        return fail(FW_E_INVALID, "query %lld: negative offset", (long long)i);
+    if (q.n > 0 && (!starts || !paths || !lengths)) return fail(FW_E_INVALID, "batch: null starts/paths/lengths");
+    // every block the query addresses must lie inside the caller's arrays
+    if (q.start_off + q.n > starts_len || q.len_off + q.n > lengths_len ||
+        q.out_off + q.n * ((int64_t)q.L + 1) > paths_len)
+        return fail(FW_E_INVALID, "query %lld: its starts/paths/lengths block exceeds the given array", (long long)i);
+    fill_query(&q.logic, d);
+    d.first = first;
+    d.n = q.n;
+    d.starts = starts ? starts + q.start_off : nullptr;
+    d.paths = paths ? paths + q.out_off : nullptr;
+    d.lengths = lengths ? lengths + q.len_off : nullptr;
+    d.L = q.L;
+    d.key0 = (uint32_t)q.seed;
+    d.key1 = (uint32_t)(q.seed >> 32);
+    return FW_OK;
+}
+
 int fw_batch_create(fw_graph *g, const fw_query *qs, int64_t nq, const fw_plan *pl, int32_t strategy,
                     const int32_t *starts, int64_t starts_len, int32_t *paths, int64_t paths_len, int32_t *lengths,
                     int64_t lengths_len, fw_batch **out)
@@ -785,33 +819,10 @@ int fw_batch_create(fw_graph *g, const fw_query *qs, int64_t nq, const fw_plan *
     std::vector<fw::QueryDev> tab((size_t)(nq > 0 ? nq : 1));
     int64_t total = 0;
     for (int64_t i = 0; i < nq; ++i) {
-        const fw_query &q = qs[i];
-        if ((rc = check_logic(g, &q.logic)) != FW_OK) return rc;
-        if ((rc = check_bound(g, pl, &q.logic)) != FW_OK) return rc;
-        if (q.logic.kind != qs[0].logic.kind || (q.logic.weighted != 0) != (qs[0].logic.weighted != 0))
-            return fail(FW_E_INVALID, "fw_batch_create: all queries of a batch share kind and weighting");
-        if (q.n < 0 || q.n >= ((int64_t)1 << 31)) return fail(FW_E_INVALID, "query %lld: n out of range", (long long)i);
-        if (q.L < 0 || q.L >= (1 << 20)) return fail(FW_E_INVALID, "query %lld: L out of range", (long long)i);
-        if (q.start_off < 0 || q.out_off < 0 || q.len_off < 0)
-            return fail(FW_E_INVALID, "query %lld: negative offset", (long long)i);
-        if (q.n > 0 && (!starts || !paths || !lengths))
-            return fail(FW_E_INVALID, "fw_batch_create: null starts/paths/lengths");
-        // every block the query addresses must lie inside the caller's arrays
-        if (q.start_off + q.n > starts_len || q.len_off + q.n > lengths_len ||
-            q.out_off + q.n * ((int64_t)q.L + 1) > paths_len)
-            return fail(FW_E_INVALID, "query %lld: its starts/paths/lengths block exceeds the given array",
-                        (long long)i);
-        fw::QueryDev &d = tab[(size_t)i];
-        fill_query(&q.logic, d);
-        d.first = total;
-        d.n = q.n;
-        d.starts = starts ? starts + q.start_off : nullptr;
-        d.paths = paths ? paths + q.out_off : nullptr;
-        d.lengths = lengths ? lengths + q.len_off : nullptr;
-        d.L = q.L;
-        d.key0 = (uint32_t)q.seed;
-        d.key1 = (uint32_t)(q.seed >> 32);
-        total += q.n;
+        if ((rc = query_entry(g, pl, qs, i, starts, starts_len, paths, paths_len, lengths, lengths_len, total,
+                              tab[(size_t)i])) != FW_OK)
+            return rc;
+        total += qs[i].n;
     }
     const bool weighted = nq > 0 && qs[0].logic.weighted && g->h;
     if (weighted && strategy != FW_RVS_ONLY && !g->prepped)
@@ -892,6 +903,98 @@ int fw_batch_replay(fw_batch *b, void *stream)
 int fw_batch_destroy(fw_batch *b)
 {
     batch_free(b);
+    return ok();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- allocation-free batch
+// Scratch of fw_batch_run_noalloc: the walker counter in the first 256 bytes, then the
+// query table.  One copy per device for the life of the process; in host code this name
+// is only a stand-in for the symbol, the device address comes from hipGetSymbolAddress.
+static_assert(sizeof(fw::QueryDev) == 176, "the scratch size stated in flexiwalk.h assumes 176-byte query entries");
+static __device__ __align__(256) unsigned char scratch[256 + FW_NOALLOC_MAX_QUERIES * sizeof(fw::QueryDev)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's scratch, looked up once per device.
+int scratch_of(int dev, unsigned char **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(FW_E_DEVICE, "fw_batch_run_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(FW_E_DEVICE, "fw_batch_run_noalloc: hipGetSymbolAddress: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = (unsigned char *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ok();
+}
+}  // namespace
+
+extern "C" {
+
+int fw_batch_run_noalloc(fw_graph *g, const fw_query *qs, int64_t nq, const fw_plan *pl, int32_t strategy,
+                         const int32_t *starts, int64_t starts_len, int32_t *paths, int64_t paths_len,
+                         int32_t *lengths, int64_t lengths_len, uint64_t *stats, void *stream)
+{
+    if (!g || !pl || (nq > 0 && !qs)) return fail(FW_E_INVALID, "fw_batch_run_noalloc: null argument");
+    if (nq < 0 || nq > FW_NOALLOC_MAX_QUERIES)
+        return fail(FW_E_INVALID, "fw_batch_run_noalloc: nq = %lld, must be in [0, %d]", (long long)nq,
+                    FW_NOALLOC_MAX_QUERIES);
+    if (!fw::valid_strategy(strategy)) return fail(FW_E_INVALID, "fw_batch_run_noalloc: bad strategy %d", strategy);
+    int rc = check_plan(pl);
+    if (rc != FW_OK) return rc;
+    // every query is checked before anything is written to the device
+    int64_t total = 0;
+    for (int64_t i = 0; i < nq; ++i) {
+        fw::QueryDev d;
+        if ((rc = query_entry(g, pl, qs, i, starts, starts_len, paths, paths_len, lengths, lengths_len, total, d)) !=
+            FW_OK)
+            return rc;
+        total += qs[i].n;
+    }
+    const bool weighted = nq > 0 && qs[0].logic.weighted && g->h;
+    if (weighted && strategy != FW_RVS_ONLY && !g->prepped)
+        return fail(FW_E_STATE, "fw_batch_run_noalloc: call fw_graph_preprocess before a weighted eRJS/AUTO batch");
+    if (total == 0) return ok();
+    HIP_TRY(hipSetDevice(g->device));
+    unsigned char *sp = nullptr;
+    if ((rc = scratch_of(g->device, &sp)) != FW_OK) return rc;
+    auto *queue = (unsigned long long *)sp;
+    auto *tab = (fw::QueryDev *)(sp + 256);
+    hipStream_t s = (hipStream_t)stream;
+    // the table goes up in chunks staged on this thread's stack (pageable memory: each
+    // copy has read its source when it returns)
+    constexpr int kChunk = 32;
+    fw::QueryDev chunk[kChunk];
+    int64_t first = 0;
+    for (int64_t i0 = 0; i0 < nq; i0 += kChunk) {
+        const int m = (int)std::min<int64_t>(kChunk, nq - i0);
+        for (int k = 0; k < m; ++k) {
+            (void)query_entry(g, pl, qs, i0 + k, starts, starts_len, paths, paths_len, lengths, lengths_len, first,
+                              chunk[k]);
+            first += qs[i0 + k].n;
+        }
+        HIP_TRY(hipMemcpyAsync(tab + i0, chunk, sizeof(fw::QueryDev) * (size_t)m, hipMemcpyHostToDevice, s));
+    }
+    fw::WalkArgs a;
+    fill_args(g, &qs[0].logic, a);
+    plan_args(pl, strategy, a);
+    a.n = total;
+    a.stats = (unsigned long long *)stats;
+    a.queue = queue;
+    a.err = (int *)(g->scratch + 1);
+    a.queries = tab;
+    a.nq = (int32_t)nq;
+    const int grid = pl->grid > 0 ? pl->grid : fw::walk_grid(qs[0].logic.kind, weighted, true, pl->lds_cap, total);
+    HIP_TRY(fw::launch_zero(queue, 1, s));
+    HIP_TRY(fw::launch_walk(a, qs[0].logic.kind, weighted, true, grid, s));
     return ok();
 }
 
