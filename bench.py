@@ -25,6 +25,19 @@ KERNEL_SOURCES = ("paper_2512_00705_amd/csrc/fw_kernels.hip", "paper_2512_00705_
 TRAFFIC_FILE = "profiles/traffic_walk_kernel_node2vec_rmat22.txt"
 
 
+def host_cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -279,8 +292,7 @@ def main():
               else oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(0, 1, 2, 3, 4))
               if args.logic == "metapath"
               else oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=args.p, q=args.q))
-        pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap, bound=plan.bound, proposal=plan.proposal,
-                         member_index=True)
+        pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap, bound=plan.bound, proposal=plan.proposal)
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
         smode = {"auto": 0, "rvs": 1, "rjs": 2}[args.strategy]
         k = args.cpu_sample or 2048
@@ -296,9 +308,26 @@ def main():
         # the GPU run covered these walkers too: compare the sample
         gp = paths[torch.from_numpy(sample).to(dev)].cpu().numpy()
         same = float((gp == r.paths).all(axis=1).mean())
+        # a plain CPU sampler beside it: inverse transform sampling over every step's exact
+        # weights (cumulative sum, binary search) on the same walkers, same cores
+        # (every step reads the whole row: a smaller sample, grown until ~5-15 s of work)
+        ki = 64
+        while True:
+            isub = sample[:ki]
+            i0 = time.perf_counter()
+            ri = oracle.walk(og, lg, pl, oracle.ITS, starts_np[isub], L, seed, walker_ids=isub,
+                             diagnostics=False, nthreads=cores)
+            its_s = time.perf_counter() - i0
+            if its_s >= 5.0 or ki >= len(sample):
+                break
+            ki = int(min(len(sample), ki * max(2.0, 8.0 / max(its_s, 1e-3))))
         cpu = {"value": r.counters["steps"] / cs, "unit": "walker-steps/s", "cores": cores, "kind": "oracle",
                "sample": f"{len(sample)} of {n} walkers (seeded), full {L}-step walks, {cs:.1f}s; "
-                         f"{same * 100:.3f}% identical to the GPU walks"}
+                         f"{same * 100:.3f}% identical to the GPU walks",
+               "cpu": host_cpu_model(), "nproc": os.cpu_count(),
+               "its": {"value": ri.counters["steps"] / its_s, "unit": "walker-steps/s", "cores": cores,
+                       "sample": f"the first {len(isub)} walkers of that sample, full {L}-step walks, "
+                                 f"{its_s:.1f}s"}}
         log(f"cpu oracle: {cpu}")
 
     fw.fw_graph_destroy(gh)

@@ -185,17 +185,28 @@ int fw_graph_export_aux(const fw_graph *g, float *hmax, float *hsum);
 int fw_graph_build_index(fw_graph *g, void *stream);
 
 /* Build the proposal records of h-proportional eRJS (plan.proposal = 1): per CSR entry k
- * of row v, 64 bytes {col[k], h[k], col[a], h[a]}, {threshold, labels of k and a, 0, 0} and
- * the vertex records (row start, degree, h_MAX, h_SUM) of col[k] and col[a], where a and the
- * threshold form Walker's alias table of the row's h (Vose's construction in double
- * precision in index order; threshold = min(floor(p * 2^32), 2^32 - 1) of the slot's keep
- * probability p).  A proposal takes slot floor(R * deg / 2^64) of a 64-bit draw R and keeps
- * it when the high 32 bits of the fraction lie below the threshold, else takes a.  A record
- * sits in one DRAM line: one read gives the proposal and, once it is accepted, the next
- * step's vertex record.  Runs fw_graph_preprocess first if it has not run.  Device memory:
- * 64 bytes per entry, plus 20 bytes per entry of scratch while building.  Synchronous;
+ * of row v, 64 bytes {col[k], h[k], col[a], h[a]}, {threshold, labels of k and a, a, 0} and
+ * the vertex records (row start, degree, h_MAX, h_SUM) of col[k] and col[a], where a (an
+ * offset in the row) and the threshold form Walker's alias table of the row's h.  The
+ * table is built with the sweeping construction (Huebschle-Schneider and Sanders,
+ * "Parallel Weighted Random Sampling") in exact integer arithmetic: q_k = floor(h_k /
+ * h_MAX * 2^32) (2^32 for every entry when the graph is unweighted or the row has no
+ * positive h), buckets of Q = sum q_k units, entry k bringing q_k * deg units; a bucket
+ * keeping K units has threshold min(floor(K * 2^32 / Q), 2^32 - 1), so entry k is proposed
+ * with probability q_k / Q.  The result does not depend on how the construction is
+ * scheduled (one wave per row here, a sequential sweep in a reference).  A proposal takes
+ * slot floor(R * deg / 2^64) of a 64-bit draw R and keeps it when the high 32 bits of the
+ * fraction lie below the threshold, else takes a.  A record sits in one DRAM line.  Runs
+ * fw_graph_preprocess first if it has not run.  Device memory: 64 bytes per entry, plus
+ * 20 bytes per entry and 16 per vertex of scratch while building.  Synchronous;
  * idempotent.  Walks, batches and servers created afterwards can use it. */
 int fw_graph_build_alias(fw_graph *g, void *stream);
+
+/* Copy the alias tables behind the proposal records to the host (ne entries each, host
+ * pointers): thr[k] = the keep threshold of slot k, alias[k] = the row offset of its alias.
+ * For replaying the sample stream outside the library.  Synchronous; FW_E_STATE before
+ * fw_graph_build_alias. */
+int fw_graph_export_alias(const fw_graph *g, uint32_t *thr, int32_t *alias);
 
 /* Roofline calibration (not part of the method): time random 8-byte reads from a device
  * array of `bytes` (a power of two >= 1 MiB), 2^20 lanes each issuing four independent

@@ -56,7 +56,7 @@ class _Logic(ctypes.Structure):
 class _Plan(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_float), ("d_lo", ctypes.c_int32), ("rjs_cap", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("jump", ctypes.c_int32), ("bound_scale", ctypes.c_float),
-                ("bound", ctypes.c_int32), ("proposal", ctypes.c_int32), ("member_index", ctypes.c_int32)]
+                ("bound", ctypes.c_int32), ("proposal", ctypes.c_int32)]
 
 
 @dataclass
@@ -91,13 +91,11 @@ class Plan:
     bound_scale: float = 1.0
     bound: int = 0  # 0: max(w) * h_MAX (Section 3.3); 1: Node2Vec split bound (return edge apart)
     proposal: int = 0  # 0: uniform eRJS proposals (Section 3.3); 1: proportional to h (alias tables)
-    member_index: bool = False  # byte accounting only: membership tests read an edge index
 
     def _c(self):
         s = _Plan()
         s.rho, s.d_lo, s.rjs_cap, s.lanes = self.rho, self.d_lo, self.rjs_cap, self.lanes
         s.jump, s.bound_scale, s.bound = int(self.jump), self.bound_scale, self.bound
-        s.member_index = int(self.member_index)
         s.proposal = self.proposal
         return s
 

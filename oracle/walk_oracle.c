@@ -161,10 +161,6 @@ typedef struct {
     int32_t bound;       /* 0: max(w) * h_MAX (Section 3.3); 1: Node2Vec split bound; 2: split and
                             member board, the smaller per step */
     int32_t proposal;    /* 0: uniform eRJS proposals (Section 3.3); 1: proportional to h */
-    int32_t member_index; /* byte accounting only: an eRJS membership test reads one 8-byte key
-                             of an edge index (1), a member-region test its key and its 4-byte h,
-                             or each binary-searches the sorted row (0);
-                             eRVS always searches the row (all its tests share N(prev)) */
 } og_plan;
 
 /* OG_RANDOM_SELECT and OG_DEGREE_SELECT are the two selection policies the paper compares
@@ -192,47 +188,82 @@ void og_preprocess(const og_graph *g, float *hmax, float *hsum)
 }
 
 /* Alias tables of the static weights h (Walker, "An efficient method for generating
- * discrete random variables with general distributions", ACM TOMS 1977; construction of
- * Vose, IEEE TSE 1991).  Row v with n entries: scaled_k = h_k * n / H (double, H the sum
- * of h in index order); slots below 1 ("small") and at or above 1 ("large") are stacked in
- * index order and paired last in, first out: the small slot keeps probability scaled_s
- * with the large one as its alias, and the large one gives up 1 - scaled_s.  Leftover
- * slots keep themselves.  A slot's probability is stored as the threshold
- * min(floor(p * 2^32), 2^32 - 1): a proposal draws a 64-bit R, takes slot
- * floor(R * n / 2^64) and keeps it when the high 32 bits of the fraction (R * n mod 2^64)
- * lie below the threshold, else takes its alias; index k then has probability h_k / H.
- * A row whose h are all zero keeps every slot (eRJS never proposes there, see og_step). */
+ * discrete random variables with general distributions", ACM TOMS 1977), built with the
+ * sweeping construction of Huebschle-Schneider and Sanders ("Parallel Weighted Random
+ * Sampling", ESA 2019) in exact integer arithmetic, so that any correct execution of it,
+ * sequential or parallel, yields the same table.
+ *
+ * Row v with n entries and row maximum h_MAX:
+ *   q_k = floor(h_k / h_MAX * 2^32)   (the quotient in double, one rounding; 2^32 for
+ *                                      every entry of an unweighted or all-zero row)
+ *   Q   = sum q_k;  a bucket holds Q units, entry k brings a_k = q_k * n units;
+ *   light entries have a_k < Q, heavy ones a_k >= Q.
+ * The sweep walks the light entries in index order with a current heavy entry j (the
+ * heavy entries in index order) holding a residual r, starting at r = a_j:
+ *   - while r < Q, heavy j is spent: its bucket keeps r, its alias is the next heavy
+ *     entry j', which first tops that bucket up: r = a_j' - (Q - r);
+ *   - the light entry i keeps a_i with alias j, and r -= Q - a_i.
+ * After the last light entry the remaining heavy entries are closed the same way (a
+ * bucket that keeps a full Q is its own alias).  Every value stays below 2^63.
+ * A bucket that keeps K units stores the threshold min(floor(K * 2^32 / Q), 2^32 - 1): a
+ * proposal draws a 64-bit R, takes slot floor(R * n / 2^64) and keeps it when the high
+ * 32 bits of the fraction (R * n mod 2^64) lie below the threshold, else takes its alias;
+ * entry k then has probability q_k / Q, which is h_k / sum h up to the 2^-32 rounding of
+ * q_k and of the thresholds. */
+static uint32_t alias_threshold(uint64_t keep, uint64_t Q)
+{
+    const unsigned __int128 t = ((unsigned __int128)keep << 32) / Q;
+    return t >= 0xFFFFFFFFu ? 0xFFFFFFFFu : (uint32_t)t;
+}
+
 void og_build_alias(const og_graph *g, uint32_t *thr, int32_t *alias)
 {
     #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t v = 0; v < g->nv; ++v) {
         const int64_t b = g->row_ptr[v], n = g->row_ptr[v + 1] - b;
         if (n == 0) continue;
-        double H = 0.0;
-        for (int64_t k = 0; k < n; ++k) H += g->h ? (double)g->h[b + k] : 1.0;
-        double *sc = (double *)malloc(sizeof(double) * (size_t)n);
-        int64_t *small = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-        int64_t *large = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
-        double *p = (double *)malloc(sizeof(double) * (size_t)n);
-        int64_t ns = 0, nl = 0;
+        float hmax = 0.0f;
+        for (int64_t k = 0; k < n; ++k)
+            if (g->h && g->h[b + k] > hmax) hmax = g->h[b + k];
+        uint64_t *a = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+        uint64_t Q = 0;
         for (int64_t k = 0; k < n; ++k) {
-            alias[b + k] = (int32_t)k;
-            p[k] = 1.0;
-            sc[k] = H > 0.0 ? ((g->h ? (double)g->h[b + k] : 1.0) * (double)n) / H : 1.0;
-            if (sc[k] < 1.0) small[ns++] = k; else large[nl++] = k;
+            const uint64_t q = (g->h && hmax > 0.0f) ? (uint64_t)floor(((double)g->h[b + k] / (double)hmax) * 4294967296.0)
+                                                      : (uint64_t)1 << 32;
+            a[k] = q;
+            Q += q;
         }
-        while (ns > 0 && nl > 0) {
-            const int64_t s = small[--ns], l = large[--nl];
-            p[s] = sc[s];
-            alias[b + s] = (int32_t)l;
-            sc[l] = (sc[l] + sc[s]) - 1.0;
-            if (sc[l] < 1.0) small[ns++] = l; else large[nl++] = l;
+        for (int64_t k = 0; k < n; ++k) a[k] *= (uint64_t)n;
+        int64_t j = 0;
+        while (a[j] < Q) ++j; /* the first heavy entry (one exists: the a_k sum to n * Q) */
+        uint64_t r = a[j];
+        for (int64_t i = 0; i < n; ++i) {
+            if (a[i] >= Q) continue; /* light entries only */
+            while (r < Q) { /* a later heavy entry exists: the residuals of the heavy
+                               entries cover every light entry's deficit exactly */
+                int64_t jn = j + 1;
+                while (jn < n - 1 && a[jn] < Q) ++jn;
+                thr[b + j] = alias_threshold(r, Q);
+                alias[b + j] = (int32_t)jn;
+                r = a[jn] - (Q - r);
+                j = jn;
+            }
+            thr[b + i] = alias_threshold(a[i], Q);
+            alias[b + i] = (int32_t)j;
+            r -= Q - a[i];
         }
-        for (int64_t k = 0; k < n; ++k) {
-            const double t = floor(p[k] * 4294967296.0);
-            thr[b + k] = (OG_MUTANT == 8 || t >= 4294967295.0) ? 0xFFFFFFFFu : (uint32_t)t;
+        for (;;) { /* close the remaining heavy entries */
+            int64_t jn = j + 1;
+            while (jn < n && a[jn] < Q) ++jn;
+            thr[b + j] = alias_threshold(r, Q);
+            alias[b + j] = (int32_t)((r < Q && jn < n) ? jn : j);
+            if (jn >= n) break;
+            r = a[jn] - (Q - r);
+            j = jn;
         }
-        free(sc); free(small); free(large); free(p);
+        if (OG_MUTANT == 8)
+            for (int64_t k = 0; k < n; ++k) thr[b + k] = 0xFFFFFFFFu;
+        free(a);
     }
 }
 
@@ -472,19 +503,12 @@ static int64_t rjs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
         float wt = hprop ? workload_weight(cx, base + idx, j, prev, deg, dvp)
                          : transition_weight(cx, base + idx, j, prev, deg, dvp);
         float y = og_uniform(x[2]) * B;
+        /* bytes: the proposed edge, the alias slot's threshold and second candidate
+           (h-proportional), and the binary search of N(v') that decides u in N(v')
+           (Node2Vec, second-order PageRank after the first step), charged on every trial */
         info->bytes += bytes_per_item(cx) + (hprop ? 12.0 : 0.0);
-        /* a membership search is needed only when the accept test is not already
-           decided by the smallest and largest weight u could have */
-        if ((lg->kind == OG_NODE2VEC || lg->kind == OG_SECOND_PR) && j > 0 && cx->g->col[base + idx] != prev) {
-            float hv = (!hprop && lg->weighted && cx->g->h) ? cx->g->h[base + idx] : 1.0f;
-            float wa = 1.0f, wb = 1.0f / lg->q;
-            if (lg->kind == OG_SECOND_PR) second_pr_weights(lg, deg, dvp, &wa, &wb);
-            float lo = fminf(wa, wb) * hv, hi = fmaxf(wa, wb) * hv;
-            if (!(y < lo) && y < hi) {
-                int64_t pdeg = cx->g->row_ptr[prev + 1] - cx->g->row_ptr[prev];
-                info->bytes += cx->pl->member_index ? 8.0 : 4.0 * ceil_log2_plus1(pdeg);
-            }
-        }
+        if ((lg->kind == OG_NODE2VEC || lg->kind == OG_SECOND_PR) && j > 0)
+            info->bytes += 4.0 * ceil_log2_plus1(dvp);
         if (y < wt) return idx;
     }
     return -2;
@@ -523,7 +547,8 @@ static int64_t rjs_sample_member(const og_ctx *cx, uint32_t w, int j, int32_t pr
         note_margin(info, z, zm);
         if (z < zm) {
             const int32_t xv = g->col[pbase + (int64_t)(((unsigned __int128)R64 * (unsigned __int128)(uint64_t)dvp) >> 64)];
-            info->bytes += 4.0 + (cx->pl->member_index ? 12.0 : 4.0 * ceil_log2_plus1(deg));
+            /* bytes: x, a binary search of N(v) for it, and h(v, x) */
+            info->bytes += 4.0 + 4.0 * ceil_log2_plus1(deg) + (cx->lg->weighted && g->h ? 4.0 : 0.0);
             if (xv == prev) continue;
             const int64_t pos = row_find(g, cur, xv);
             if (pos < 0) continue;

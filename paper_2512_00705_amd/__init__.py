@@ -26,7 +26,7 @@ FW_NSTATS = 8
 STAT_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", "rvs_triggers",
               "ended_early", "alg_bytes")
 EXPORTED = ("fw_graph_create", "fw_graph_destroy", "fw_graph_preprocess", "fw_graph_build_index",
-            "fw_graph_export_aux", "fw_graph_info", "fw_calibrate_random_reads", "fw_graph_build_alias",
+            "fw_graph_export_aux", "fw_graph_export_alias", "fw_graph_info", "fw_calibrate_random_reads", "fw_graph_build_alias",
             "fw_logic_node2vec", "fw_logic_metapath", "fw_logic_second_pr", "fw_plan_default", "fw_plan_profile",
             "fw_plan_autotune", "fw_plan_autotune_mix", "fw_walk", "fw_graph_check", "fw_last_error", "fw_batch_create", "fw_batch_launch",
             "fw_batch_capture", "fw_batch_replay", "fw_batch_destroy", "fw_batch_run_noalloc", "fw_server_create",
@@ -79,6 +79,7 @@ def _load():
         "fw_graph_build_alias": ([P, P], ctypes.c_int),
         "fw_calibrate_random_reads": ([ctypes.c_int64, ctypes.POINTER(ctypes.c_double), P], ctypes.c_int),
         "fw_graph_export_aux": ([P, P, P], ctypes.c_int),
+        "fw_graph_export_alias": ([P, P, P], ctypes.c_int),
         "fw_graph_info": ([P, P, P, P, P], ctypes.c_int),
         "fw_logic_node2vec": ([ctypes.c_float, ctypes.c_float, I32, ctypes.POINTER(fw_logic)], ctypes.c_int),
         "fw_logic_metapath": ([P, I32, I32, ctypes.POINTER(fw_logic)], ctypes.c_int),
@@ -178,6 +179,14 @@ def fw_calibrate_random_reads(nbytes: int = 4 << 30, stream=None) -> float:
     out = ctypes.c_double()
     _check(_lib.fw_calibrate_random_reads(int(nbytes), ctypes.byref(out), _stream(stream)))
     return out.value
+
+
+def fw_graph_export_alias(g: int, ne: int):
+    """(thr uint32[ne], alias int32[ne]) of the proposal records' alias tables."""
+    thr = np.empty(ne, np.uint32)
+    alias = np.empty(ne, np.int32)
+    _check(_lib.fw_graph_export_alias(g, thr.ctypes.data, alias.ctypes.data))
+    return thr, alias
 
 
 def fw_graph_export_aux(g: int, nv: int):

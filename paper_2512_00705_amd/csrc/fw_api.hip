@@ -250,6 +250,23 @@ int fw_graph_export_aux(const fw_graph *g, float *hmax, float *hsum)
     return ok();
 }
 
+int fw_graph_export_alias(const fw_graph *g, uint32_t *thr, int32_t *alias)
+{
+    if (!g || (g->ne > 0 && (!thr || !alias))) return fail(FW_E_INVALID, "fw_graph_export_alias: null argument");
+    if (!g->prop) return fail(FW_E_STATE, "fw_graph_export_alias: no proposal records (fw_graph_build_alias)");
+    if (g->ne == 0) return ok();
+    HIP_TRY(hipSetDevice(g->device));
+    HIP_TRY(hipDeviceSynchronize());
+    // gathered on the device from the second uint4 of each record, then copied whole
+    DevBuf dt, da;
+    HIP_TRY(hipMalloc(&dt.p, sizeof(uint32_t) * (size_t)g->ne));
+    HIP_TRY(hipMalloc(&da.p, sizeof(int32_t) * (size_t)g->ne));
+    HIP_TRY(fw::launch_export_alias(g->prop, g->ne, (uint32_t *)dt.p, (int32_t *)da.p, nullptr));
+    HIP_TRY(hipMemcpy(thr, dt.p, sizeof(uint32_t) * (size_t)g->ne, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(alias, da.p, sizeof(int32_t) * (size_t)g->ne, hipMemcpyDeviceToHost));
+    return ok();
+}
+
 int fw_graph_info(const fw_graph *g, int64_t *nv, int64_t *ne, int64_t *max_deg, int32_t *symmetric)
 {
     if (!g) return fail(FW_E_INVALID, "fw_graph_info: null graph");
@@ -494,15 +511,20 @@ int fw_graph_build_alias(fw_graph *g, void *stream)
     uint4 *prop = nullptr;
     if (hipMalloc((void **)&prop, rec * ne) != hipSuccess)
         return fail(FW_E_NOMEM, "fw_graph_build_alias: hipMalloc of %zu bytes failed", rec * ne);
-    DevBuf sc, ss, sl, al;
-    if (hipMalloc(&sc.p, 8 * ne) != hipSuccess || hipMalloc(&ss.p, 4 * ne) != hipSuccess ||
-        hipMalloc(&sl.p, 4 * ne) != hipSuccess || hipMalloc(&al.p, 4 * ne) != hipSuccess) {
+    DevBuf val, idx, rowinfo;
+    const size_t nv = (size_t)(g->nv > 0 ? g->nv : 1);
+    if (hipMalloc(&val.p, 16 * ne) != hipSuccess || hipMalloc(&idx.p, 4 * ne) != hipSuccess ||
+        hipMalloc(&rowinfo.p, 16 * nv) != hipSuccess) {
         (void)hipFree(prop);
-        return fail(FW_E_NOMEM, "fw_graph_build_alias: scratch of %zu bytes failed", 20 * ne);
+        return fail(FW_E_NOMEM, "fw_graph_build_alias: scratch of %zu bytes failed", 20 * ne + 16 * nv);
     }
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = fw::launch_build_alias(g->row_ptr, g->col, g->h, g->label, g->nv, g->vrec, (double *)sc.p,
-                                          (int32_t *)ss.p, (int32_t *)sl.p, (int32_t *)al.p, prop, s);
+    // every record is written by the build; zeroed first so that none can ever hold an
+    // out-of-range vertex
+    hipError_t e = hipMemsetAsync(prop, 0, rec * ne, s);
+    if (e == hipSuccess)
+        e = fw::launch_build_alias(g->row_ptr, g->col, g->h, g->label, g->nv, g->vrec, (uint4 *)val.p,
+                                          (int32_t *)idx.p, (ulonglong2 *)rowinfo.p, prop, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(prop);

@@ -146,13 +146,16 @@ hipError_t launch_pack8(const int32_t *col, const uint8_t *code, int64_t ne, uin
 hipError_t launch_layout(const int64_t *row_ptr, const int32_t *col, const float *h, int64_t nv, int64_t ne,
                          uint2 *edges, uint4 *vrec, uint32_t *start_hi, hipStream_t s);
 hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv, uint4 *vrec, hipStream_t s);
-// Proposal records of h-proportional eRJS: Walker's alias table per row (Vose's
-// construction, one lane per row, in double precision in index order) written as
-// prop[2k] = {col[k], h[k], col[a], h[a]}, prop[2k+1] = {threshold, lab[k] | lab[a] << 8, 0, 0}.
-// sc, stk_s, stk_l and alias are ne-long scratch arrays.
+// Proposal records of h-proportional eRJS: Walker's alias table per row (the sweeping
+// construction in exact integer arithmetic, in parallel form: a scan pass and a merge
+// pass, one wave per row) written as prop[4k] = {col[k], h[k], col[a], h[a]},
+// prop[4k+1] = {threshold, lab[k] | lab[a] << 8, a, 0}, prop[4k+2..3] = vrec of col[k],
+// col[a].  Scratch: val (16 bytes) and idx (4 bytes) per entry, rowinfo (16 bytes) per row.
 hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
-                              int64_t nv, const uint4 *vrec, double *sc, int32_t *stk_s, int32_t *stk_l,
-                              int32_t *alias, uint4 *prop, hipStream_t s);
+                              int64_t nv, const uint4 *vrec, uint4 *val, int32_t *idx, ulonglong2 *rowinfo,
+                              uint4 *prop, hipStream_t s);
+// thr[k] = threshold and alias[k] = alias offset of proposal record k, for k < ne.
+hipError_t launch_export_alias(const uint4 *prop, int64_t ne, uint32_t *thr, int32_t *alias, hipStream_t s);
 // Edge index: inserts every entry (v, col[k]) of the rows with its h (1 when h is null) into
 // `tab` (buckets of 8 keys and 8 h, 128 bytes each, keys all kEmptyKey on entry;
 // buckets = mask + 1, a power of two, at least a quarter of ne).

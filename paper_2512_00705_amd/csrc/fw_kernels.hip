@@ -27,6 +27,19 @@ namespace fw {
 
 enum Mode : int { kIdle = 0, kSetup = 1, kRjs = 2, kRvs = 3, kAdv = 4 };
 
+// Dynamic LDS of a walk block: each wave's two slots of 64 vertex records filled by LDS DMA
+// from proposal records, then each wave's N(prev) staging area (lds_cap int32).
+static size_t walk_lds_bytes(int lds_cap)
+{
+    return (size_t)kWavesPerBlock * (size_t)lds_cap * sizeof(int32_t) + (size_t)kWavesPerBlock * 2 * kWave * 16;
+}
+
+// An LDS address for the LDS-DMA load builtin (the pointer must lie in this block's LDS).
+__device__ __forceinline__ __attribute__((address_space(3))) void *lds_ptr(uint4 *p)
+{
+    return (__attribute__((address_space(3))) void *)p;
+}
+
 // N(prev) for the membership test: a copy in this wave's LDS or the row of prev in col,
 // read through one flat pointer either way.  `indexed`: lanes test different rows (eRJS
 // style); an unstaged row then goes through the edge index when the graph has one, else
@@ -349,7 +362,12 @@ __global__ void __launch_bounds__(kBlock, STATS ? kMinWavesCounted : (BATCH ? kM
 walk_kernel(WalkArgs a)
 {
     extern __shared__ int32_t lds_all[];
-    int32_t *lds = lds_all + (threadIdx.x / kWave) * a.lds_cap;
+    // this wave's two slots of 64 vertex records (candidate kept, alias taken), then its
+    // N(prev) staging area
+    // (its offset is uniform over the wave; readfirstlane keeps it in a scalar register)
+    uint4 *nvstage = reinterpret_cast<uint4 *>(lds_all) +
+                     __builtin_amdgcn_readfirstlane((uint32_t)(threadIdx.x / kWave) * 2 * kWave);
+    int32_t *lds = lds_all + kWavesPerBlock * 2 * kWave * 4 + (threadIdx.x / kWave) * a.lds_cap;
     const int lane = lane_id();
     const uint64_t below = lanes_below(lane);
 
@@ -602,6 +620,13 @@ walk_kernel(WalkArgs a)
                                     ? -1.0f
                                     : (j == 0 ? 1.0f : fminf(sw.ret, (MB && mb) ? sw.oth : sw.lo));
             bool sure = false;
+            // the batch's first proposal (the one most often accepted) also copies its
+            // two candidates' vertex records into this wave's LDS slots, in the same
+            // request as the rest of the record (LDS DMA: no registers): an accepted
+            // candidate's record is then read from LDS.  A line read again after its
+            // first read has returned is mostly gone from L2 already (random reads turn
+            // it over faster than one round trip), so a later read costs a DRAM request.
+            bool nv0_ok = false;
 #pragma unroll
             for (int r = 0; r < kRjsBatch; ++r) {
                 if (sure) {
@@ -627,7 +652,13 @@ walk_kernel(WalkArgs a)
                     ll[r] = 0;
                 } else if (hprop) {
                     const uint32_t f = scaled_fraction_hi(x.x0, x.x1, deg);
-                    const uint4 r0 = a.prop[kPropU4 * k], r1 = a.prop[kPropU4 * k + 1];
+                    const uint4 *rec = a.prop + kPropU4 * k;
+                    if (r == 0) {
+                        __builtin_amdgcn_global_load_lds(rec + 2, lds_ptr(nvstage), 16, 0, 0);
+                        __builtin_amdgcn_global_load_lds(rec + 3, lds_ptr(nvstage + kWave), 16, 0, 0);
+                        nv0_ok = true;
+                    }
+                    const uint4 r0 = rec[0], r1 = rec[1];
                     const bool keep = f < r1.x;
                     rsel[r] = ((uint32_t)(k - base) << 1) | (keep ? 0u : 1u);
                     ee[r] = keep ? make_uint2(r0.x, r0.y) : make_uint2(r0.z, r0.w);
@@ -655,8 +686,9 @@ walk_kernel(WalkArgs a)
                     acc = true;  // the extra column belongs to the return edge
                 } else if (MB && uses_membership(KIND) && mr[0]) {
                     // member region: keep x = u when it is a neighbour of cur (not prev),
-                    // with probability h(cur, x) / h_MAX
-                    st_bytes += 4 + (a.mtab ? 12 : 4 * (uint64_t)probes(deg));
+                    // with probability h(cur, x) / h_MAX.  Bytes: x, a search of cur's row
+                    // and h(cur, x)
+                    st_bytes += 4 + 4 * (uint64_t)probes(deg) + (W ? 4 : 0);
                     look = u != prev;
                 } else if (MB && uses_membership(KIND) && mb) {
                     // regular columns of the member board: every proposal at w_oth, the
@@ -671,7 +703,6 @@ walk_kernel(WalkArgs a)
                         const float lo = sw.lo * hw, hi = sw.hi * hw;
                         acc = y < lo;
                         look = !acc && y < hi;
-                        if (look) st_bytes += a.mtab ? 8 : 4 * (uint64_t)probes(pdeg);
                     }
                 } else {
                     acc = y < (ll[0] == want ? hw : 0.0f);
@@ -699,13 +730,21 @@ walk_kernel(WalkArgs a)
                 }
                 ++trials;
                 st[kStTrials] += 1;
-                if (!ol[0] && !mr[0]) st_bytes += (uint64_t)a.item_bytes + (hprop ? 12 : 0);
+                // algorithmic bytes of a proposal: the proposed edge (col, h, label), the
+                // alias slot's threshold and second candidate (h-proportional), and, on a
+                // board whose acceptance depends on u in N(prev), a binary search of N(prev)
+                // on every trial, whether or not this lane needed it
+                if (STATS && !ol[0] && !mr[0])
+                    st_bytes += (uint64_t)a.item_bytes + (hprop ? 12 : 0) +
+                                ((uses_membership(KIND) && j > 0 && !(MB && mb)) ? 4 * (uint64_t)probes(pdeg) : 0);
                 if (acc) {
                     nxt = u;
                     hnext = hsel;
                     if (hprop && !ol[0] && !mr[0]) {
                         // the record's line holds the accepted candidate's vertex record
-                        nvrec = a.prop[kPropU4 * (base + (int64_t)(rsel[0] >> 1)) + 2 + (rsel[0] & 1u)];
+                        nvrec = (r == 0 && nv0_ok)
+                                    ? nvstage[(rsel[0] & 1u) * kWave + lane]
+                                    : a.prop[kPropU4 * (base + (int64_t)(rsel[0] >> 1)) + 2 + (rsel[0] & 1u)];
                         have_nv = true;
                     }
                     mode = kAdv;
@@ -968,50 +1007,228 @@ __global__ void __launch_bounds__(kBlock) validate_edges_kernel(const int64_t *r
     if (lane == 0 && dmax > 0) atomicMax(max_deg, dmax);
 }
 
-// Proposal records: one lane per row runs Vose's alias construction in index order, in
-// double precision, with the row's stretch of the scratch arrays as its two stacks.  Each
-// 64-byte record also carries the vertex records of its two candidates, so that a step
-// that accepts a proposal finds the next step's row in the line it already fetched.
-__global__ void __launch_bounds__(kBlock) build_alias_kernel(const int64_t *row_ptr, const int32_t *col,
-                                                             const float *h, const uint8_t *label, int64_t nv,
-                                                             const uint4 *vrec, double *sc, int32_t *stk_s,
-                                                             int32_t *stk_l, int32_t *alias, uint4 *prop)
+// Proposal records of h-proportional eRJS: Walker's alias table of each row's h, built
+// with the sweeping construction of Huebschle-Schneider and Sanders (Parallel Weighted
+// Random Sampling) in exact integer arithmetic, here in its parallel form.  Row v with n
+// entries: q_k = floor(h_k / h_MAX * 2^32) (double quotient, one rounding; 2^32 when the
+// row has no positive h or the graph is unweighted), Q = sum q_k, entry k brings
+// a_k = q_k * n units to buckets of Q units; light entries (a_k < Q) have the deficit
+// Q - a_k, heavy ones the surplus a_k - Q.  With D the deficits of the light entries
+// before a given one and E the surplus of the heavy entries up to a given one (both in
+// index order), the sequential sweep is equivalent to:
+//   * light entry i keeps a_i and takes as alias the first heavy entry j with E_j >= D_i;
+//   * heavy entry j keeps Q + E_j - D(n_j), where n_j counts the light entries with
+//     D_i <= E_j and D(n_j) is their total deficit (the total of all deficits, which
+//     equals the last E, when n_j covers them all); unless it keeps a full Q its alias is
+//     the next heavy entry.
+// Sums of up to 2^31 values below 2^63 need 128 bits; everything is an integer, so the
+// result does not depend on the order of any sum.  A bucket keeping K units stores the
+// threshold min(floor(K * 2^32 / Q), 2^32 - 1).
+//
+// Pass 1 (one wave per row): Q, then each light entry's D and each heavy entry's E, the
+// light entries compacted at the row's front in index order and the heavy ones at its
+// back in reverse order (val: the 128-bit sum, idx: the entry's offset), and {Q, light
+// count} per row.  Pass 2 (one wave per row): both merges of the two sorted sequences,
+// 64 entries of each at a time, and the 64-byte record of every entry:
+//   {col_k, bits(h_k), col_a, bits(h_a)}, {threshold, label_k | label_a << 8, a, 0},
+//   vrec[col_k], vrec[col_a]   (a: the alias's offset in the row).
+using u128 = unsigned __int128;
+constexpr u128 kU128Max = ~(u128)0;
+
+__device__ __forceinline__ u128 shfl_u128(u128 x, int src)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += stride) {
+    const uint64_t lo = (uint64_t)__shfl((long long)(uint64_t)x, src, kWave);
+    const uint64_t hi = (uint64_t)__shfl((long long)(uint64_t)(x >> 64), src, kWave);
+    return ((u128)hi << 64) | lo;
+}
+
+__device__ __forceinline__ u128 shfl_up_u128(u128 x, int d)
+{
+    const uint64_t lo = (uint64_t)__shfl_up((long long)(uint64_t)x, d, kWave);
+    const uint64_t hi = (uint64_t)__shfl_up((long long)(uint64_t)(x >> 64), d, kWave);
+    return ((u128)hi << 64) | lo;
+}
+
+__device__ __forceinline__ u128 wave_incl_scan_u128(u128 x)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const u128 y = shfl_up_u128(x, d);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// q_k of the construction: h_k relative to the row maximum in 32 fractional bits.
+__device__ __forceinline__ uint64_t alias_q(const float *h, int64_t k, float hmax)
+{
+    if (h == nullptr || !(hmax > 0.0f)) return (uint64_t)1 << 32;
+    return (uint64_t)floor(((double)h[k] / (double)hmax) * 4294967296.0);
+}
+
+__device__ __forceinline__ uint32_t alias_thr(u128 keep, uint64_t Q)
+{
+    const u128 t = (keep << 32) / (u128)Q;
+    return t >= (u128)0xFFFFFFFFu ? 0xFFFFFFFFu : (uint32_t)t;
+}
+
+__global__ void __launch_bounds__(kBlock) alias_scan_kernel(const int64_t *row_ptr, const float *h, int64_t nv,
+                                                            const uint4 *vrec, uint4 *val, int32_t *idx,
+                                                            ulonglong2 *rowinfo)
+{
+    const int lane = lane_id();
+    const uint64_t below = lanes_below(lane);
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; v < nv; v += nw) {
         const int64_t b = row_ptr[v];
-        const int32_t n = (int32_t)(row_ptr[v + 1] - b);
+        const int64_t n = row_ptr[v + 1] - b;
         if (n == 0) continue;
-        double H = 0.0;
-        for (int32_t k = 0; k < n; ++k) H += h ? (double)h[b + k] : 1.0;
-        int32_t ns = 0, nl = 0;
-        for (int32_t k = 0; k < n; ++k) {
-            alias[b + k] = k;
-            const double x = H > 0.0 ? ((h ? (double)h[b + k] : 1.0) * (double)n) / H : 1.0;
-            sc[b + k] = x;
-            if (x < 1.0) stk_s[b + ns++] = k;
-            else stk_l[b + nl++] = k;
+        const float hmax = __uint_as_float(vrec[v].z);
+        uint64_t qs = 0;
+        for (int64_t k = lane; k < n; k += kWave) qs += alias_q(h, b + k, hmax);
+        const uint64_t Q = wave_sum_u64(qs);
+        u128 dcarry = 0, ecarry = 0;
+        int64_t nl = 0, nh = 0;
+        for (int64_t k0 = 0; k0 < n; k0 += kWave) {
+            const int64_t k = k0 + lane;
+            const bool valid = k < n;
+            const uint64_t a = valid ? alias_q(h, b + k, hmax) * (uint64_t)n : 0;
+            const bool light = valid && a < Q, heavy = valid && a >= Q;
+            const uint64_t lm = __ballot(light), hm = __ballot(heavy);
+            const u128 d = light ? (u128)(Q - a) : 0, e = heavy ? (u128)(a - Q) : 0;
+            const u128 dinc = wave_incl_scan_u128(d), einc = wave_incl_scan_u128(e);
+            if (light) {
+                const int64_t pos = b + nl + __popcll(lm & below);
+                const u128 x = dcarry + dinc - d;  // deficits before this entry
+                val[pos] = make_uint4((uint32_t)x, (uint32_t)(x >> 32), (uint32_t)(x >> 64), (uint32_t)(x >> 96));
+                idx[pos] = (int32_t)k;
+            }
+            if (heavy) {
+                const int64_t pos = b + n - 1 - (nh + __popcll(hm & below));
+                const u128 x = ecarry + einc;  // surplus up to and including this entry
+                val[pos] = make_uint4((uint32_t)x, (uint32_t)(x >> 32), (uint32_t)(x >> 64), (uint32_t)(x >> 96));
+                idx[pos] = (int32_t)k;
+            }
+            dcarry += shfl_u128(dinc, kWave - 1);
+            ecarry += shfl_u128(einc, kWave - 1);
+            nl += __popcll(lm);
+            nh += __popcll(hm);
         }
-        while (ns > 0 && nl > 0) {
-            const int32_t s = stk_s[b + --ns], l = stk_l[b + --nl];
-            alias[b + s] = l;
-            const double x = (sc[b + l] + sc[b + s]) - 1.0;
-            sc[b + l] = x;
-            if (x < 1.0) stk_s[b + ns++] = l;
-            else stk_l[b + nl++] = l;
+        if (lane == 0) rowinfo[v] = make_ulonglong2((unsigned long long)Q, (unsigned long long)nl);
+    }
+}
+
+__device__ __forceinline__ u128 load_u128(const uint4 *p)
+{
+    const uint4 x = *p;
+    return ((u128)x.w << 96) | ((u128)x.z << 64) | ((u128)x.y << 32) | (u128)x.x;
+}
+
+// Index of the first of the 64 wave lanes whose x (ascending over the lanes) is >= key
+// (ge) or > key (!ge); 64 when there is none.
+__device__ __forceinline__ int wave_bound_u128(u128 x, u128 key, bool ge)
+{
+    int c = 0;
+#pragma unroll
+    for (int s = kWave / 2; s > 0; s >>= 1) {
+        const u128 y = shfl_u128(x, c + s - 1);
+        if (ge ? (y < key) : (y <= key)) c += s;
+    }
+    // c in [0, 63]: one more test decides between c and 64
+    const u128 y = shfl_u128(x, c);
+    return (ge ? (y < key) : (y <= key)) ? c + 1 : c;
+}
+
+__device__ __forceinline__ void write_record(const int32_t *col, const float *h, const uint8_t *label,
+                                             const uint4 *vrec, int64_t b, int32_t k, int32_t al, uint32_t thr,
+                                             uint4 *prop)
+{
+    const uint32_t hk = h ? __float_as_uint(h[b + k]) : __float_as_uint(1.0f);
+    const uint32_t ha = h ? __float_as_uint(h[b + al]) : __float_as_uint(1.0f);
+    const uint32_t lab = label ? ((uint32_t)label[b + k] | ((uint32_t)label[b + al] << 8)) : 0u;
+    const int32_t ck = col[b + k], ca = col[b + al];
+    uint4 *r = prop + (int64_t)kPropU4 * (b + k);
+    r[0] = make_uint4((uint32_t)ck, hk, (uint32_t)ca, ha);
+    r[1] = make_uint4(thr, lab, (uint32_t)al, 0u);
+    r[2] = vrec[ck];
+    r[3] = vrec[ca];
+}
+
+__global__ void __launch_bounds__(kBlock) alias_merge_kernel(const int64_t *row_ptr, const int32_t *col,
+                                                             const float *h, const uint8_t *label, int64_t nv,
+                                                             const uint4 *vrec, const uint4 *val, const int32_t *idx,
+                                                             const ulonglong2 *rowinfo, uint4 *prop)
+{
+    const int lane = lane_id();
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; v < nv; v += nw) {
+        const int64_t b = row_ptr[v];
+        const int64_t n = row_ptr[v + 1] - b;
+        if (n == 0) continue;
+        const ulonglong2 ri = rowinfo[v];
+        const uint64_t Q = (uint64_t)ri.x;
+        const int64_t nl = (int64_t)ri.y, nh = n - nl;  // nh >= 1: the a_k sum to n * Q
+        if (nh <= 0) {  // unreachable (see above); every record stays a valid self-alias
+            for (int64_t k = lane; k < n; k += kWave)
+                write_record(col, h, label, vrec, b, (int32_t)k, (int32_t)k, 0xFFFFFFFFu, prop);
+            continue;
         }
-        for (int32_t k = 0; k < n; ++k) {
-            const int32_t al = alias[b + k];
-            const double p = al != k ? sc[b + k] : 1.0;  // paired slots keep their scaled weight
-            const double t = floor(p * 4294967296.0);
-            const uint32_t thr = t >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)t;
-            const uint32_t hk = h ? __float_as_uint(h[b + k]) : __float_as_uint(1.0f);
-            const uint32_t ha = h ? __float_as_uint(h[b + al]) : __float_as_uint(1.0f);
-            const uint32_t lab = label ? ((uint32_t)label[b + k] | ((uint32_t)label[b + al] << 8)) : 0u;
-            prop[kPropU4 * (b + k)] = make_uint4((uint32_t)col[b + k], hk, (uint32_t)col[b + al], ha);
-            prop[kPropU4 * (b + k) + 1] = make_uint4(thr, lab, 0u, 0u);
-            prop[kPropU4 * (b + k) + 2] = vrec[col[b + k]];
-            prop[kPropU4 * (b + k) + 3] = vrec[col[b + al]];
+        const float hmax = __uint_as_float(vrec[v].z);
+        // heavy entry j (in index order) sits at b + n - 1 - j
+        const u128 e_last = load_u128(val + b + n - nh);
+        // light entries: alias = the first heavy entry whose E reaches the entry's D
+        for (int64_t li = 0, hj = 0; li < nl;) {
+            if (hj >= nh) {
+                // unreachable in exact arithmetic (the last E equals the total deficit, so
+                // every light entry finds its heavy one); kept so that the loop always ends
+                // and every record stays a valid self-alias
+                for (int64_t i = li + lane; i < nl; i += kWave) {
+                    const int32_t k = idx[b + i];
+                    write_record(col, h, label, vrec, b, k, k, 0xFFFFFFFFu, prop);
+                }
+                break;
+            }
+            const int64_t i = li + lane, j = hj + lane;
+            const u128 D = i < nl ? load_u128(val + b + i) : kU128Max;
+            const u128 E = j < nh ? load_u128(val + b + n - 1 - j) : kU128Max;
+            const int32_t hix = j < nh ? idx[b + n - 1 - j] : -1;
+            const int c = wave_bound_u128(E, D, true);
+            const bool found = i < nl && c < kWave && hj + c < nh;
+            const int32_t al = __shfl(hix, c & (kWave - 1), kWave);
+            const int cnt = __popcll(__ballot(found));  // a prefix of the lanes (D ascends)
+            if (cnt == 0) {
+                hj += kWave;
+                continue;
+            }
+            if (found) {
+                const int32_t k = idx[b + i];
+                const uint64_t a = alias_q(h, b + k, hmax) * (uint64_t)n;
+                write_record(col, h, label, vrec, b, k, al, alias_thr((u128)a, Q), prop);
+            }
+            li += cnt;
+        }
+        // heavy entries: keep Q + E_j - D(n_j), alias the next heavy entry unless full
+        for (int64_t hj = 0, li = 0; hj < nh;) {
+            const int64_t i = li + lane, j = hj + lane;
+            const u128 D = i < nl ? load_u128(val + b + i) : kU128Max;
+            const u128 E = j < nh ? load_u128(val + b + n - 1 - j) : kU128Max;
+            const int c = wave_bound_u128(D, E, false);  // light entries with D <= E_j in this block
+            const bool found = j < nh && c < kWave;
+            const u128 dn = shfl_u128(D, c & (kWave - 1));
+            const int cnt = __popcll(__ballot(found));  // a prefix of the lanes (E ascends)
+            if (cnt == 0) {
+                li += kWave;
+                continue;
+            }
+            if (found) {
+                const u128 spent = li + c < nl ? dn : e_last;
+                const u128 keep = (u128)Q + E - spent;
+                const int32_t k = idx[b + n - 1 - j];
+                const int32_t al = (keep < (u128)Q && j + 1 < nh) ? idx[b + n - 2 - j] : k;
+                write_record(col, h, label, vrec, b, k, al, alias_thr(keep, Q), prop);
+            }
+            hj += cnt;
         }
     }
 }
@@ -1155,7 +1372,7 @@ static void launch_walk_s(const WalkArgs &a, int grid, size_t lds, hipStream_t s
 template <int KIND, bool W, bool BATCH>
 static hipError_t launch_walk_t(const WalkArgs &a, int grid, hipStream_t s)
 {
-    const size_t lds = (size_t)kWavesPerBlock * (size_t)a.lds_cap * sizeof(int32_t);
+    const size_t lds = walk_lds_bytes(a.lds_cap);
     if (a.stats != nullptr) launch_walk_s<KIND, W, BATCH, true>(a, grid, lds, s);
     else launch_walk_s<KIND, W, BATCH, false>(a, grid, lds, s);
     return hipGetLastError();
@@ -1181,7 +1398,7 @@ template <int KIND, bool W, bool BATCH>
 static int occupancy_blocks(int lds_cap)
 {
     int nb = 0;
-    const size_t lds = (size_t)kWavesPerBlock * (size_t)lds_cap * sizeof(int32_t);
+    const size_t lds = walk_lds_bytes(lds_cap);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<KIND, W, BATCH, false, false>, kBlock, lds) !=
         hipSuccess)
         nb = 1;
@@ -1267,15 +1484,38 @@ hipError_t launch_validate_edges(const int64_t *row_ptr, const int32_t *col, con
     return hipGetLastError();
 }
 
-hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
-                              int64_t nv, const uint4 *vrec, double *sc, int32_t *stk_s, int32_t *stk_l,
-                              int32_t *alias, uint4 *prop, hipStream_t s)
+__global__ void export_alias_kernel(const uint4 *prop, int64_t ne, uint32_t *thr, int32_t *alias)
 {
-    int64_t blocks = (nv + kBlock - 1) / kBlock;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < ne; k += stride) {
+        const uint4 r1 = prop[(int64_t)kPropU4 * k + 1];
+        thr[k] = r1.x;
+        alias[k] = (int32_t)r1.z;
+    }
+}
+
+hipError_t launch_export_alias(const uint4 *prop, int64_t ne, uint32_t *thr, int32_t *alias, hipStream_t s)
+{
+    if (ne <= 0) return hipSuccess;
+    int64_t blocks = (ne + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(export_alias_kernel, dim3((unsigned)blocks), dim3(256), 0, s, prop, ne, thr, alias);
+    return hipGetLastError();
+}
+
+hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
+                              int64_t nv, const uint4 *vrec, uint4 *val, int32_t *idx, ulonglong2 *rowinfo,
+                              uint4 *prop, hipStream_t s)
+{
+    int64_t blocks = (nv + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(build_alias_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, label, nv,
-                       vrec, sc, stk_s, stk_l, alias, prop);
+    hipLaunchKernelGGL(alias_scan_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, h, nv, vrec, val, idx,
+                       rowinfo);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(alias_merge_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, label, nv,
+                       vrec, val, idx, rowinfo, prop);
     return hipGetLastError();
 }
 

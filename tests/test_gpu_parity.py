@@ -331,7 +331,7 @@ def test_edge_index_same_walks(g12, gg12, gi12, strategy, bound):
     np.testing.assert_array_equal(a[1], b[1])
     for k in COUNTERS[:-1]:
         assert a[2][k] == b[2][k], k
-    ora = oracle.walk(oracle.Graph(g12), lg, oracle.Plan(rho=1.0, bound=bound, member_index=True),
+    ora = oracle.walk(oracle.Graph(g12), lg, oracle.Plan(rho=1.0, bound=bound),
                       STRATS[strategy], starts, 20, 3)
     rep = parity(b[0], b[1], ora)
     assert_parity(rep)
@@ -347,7 +347,7 @@ def test_edge_index_hub_rows(strategy):
     gg = GpuGraph(g, index=True)
     try:
         starts = np.arange(1, 3001, dtype=np.int32)
-        pl = oracle.Plan(rho=1.0, member_index=True)
+        pl = oracle.Plan(rho=1.0)
         p, ln, st, ora = _run_both(gg, g, N2V, pl, STRATS[strategy], starts, 6, 11, lds_cap=0)
         rep = parity(p, ln, ora)
         assert_parity(rep)
@@ -363,7 +363,7 @@ def test_edge_index_idempotent_and_tiny_graphs():
         try:
             fw.fw_graph_build_index(gg.handle)  # second call is a no-op
             p, ln, st = gpu_walk(gg, N2V, oracle.Plan(), oracle.AUTO, np.zeros(3, np.int32), 4, 1)
-            ora = oracle.walk(oracle.Graph(g), N2V, oracle.Plan(member_index=True), oracle.AUTO,
+            ora = oracle.walk(oracle.Graph(g), N2V, oracle.Plan(), oracle.AUTO,
                               np.zeros(3, np.int32), 4, 1)
             np.testing.assert_array_equal(p, ora.paths)
         finally:
@@ -381,7 +381,7 @@ def test_second_pr_scale12(g12, gg12, gi12, strategy, weighted, indexed):
     """Eq. (2ndpr) with gamma = 0.2, one walker per vertex, L = 20: walks and counters
     equal the oracle's, with the sorted-row search and with the edge index."""
     lg = oracle.Logic(kind=oracle.SECOND_PR, weighted=weighted, gamma=0.2)
-    pl = oracle.Plan(rho=1.0, member_index=indexed)
+    pl = oracle.Plan(rho=1.0)
     starts = synth.all_vertices(g12["nv"])
     gg = gi12 if indexed else gg12
     p, ln, st = gpu_walk(gg, lg, pl, STRATS[strategy], starts, 20, 42)
@@ -494,8 +494,7 @@ def test_h_proposals_scale12(g12, ga12, strategy, bound, logic):
     """plan.proposal = 1: alias-table proposals, the test on w; walks and counters equal
     the oracle's (which builds its alias tables independently)."""
     lg = HP_LOGICS[logic]
-    pl = oracle.Plan(rho=1.0, bound=bound if lg.kind != oracle.METAPATH else 0, proposal=1, rjs_cap=256,
-                     member_index=True)
+    pl = oracle.Plan(rho=1.0, bound=bound if lg.kind != oracle.METAPATH else 0, proposal=1, rjs_cap=256)
     starts = synth.all_vertices(g12["nv"])
     p, ln, st, ora = _run_both(ga12, g12, lg, pl, STRATS[strategy], starts, 20, 31)
     rep = parity(p, ln, ora)
@@ -574,7 +573,7 @@ def test_member_board_scale12(g12, gn12, ga12, strategy, proposal, indexed, logi
     or plain board; a member-region trial finds (cur, x) and its h through the edge index
     or a search of cur's row.  Walks and counters equal the oracle's."""
     lg = MB_LOGICS[logic]
-    pl = oracle.Plan(rho=1.0, bound=2, proposal=proposal, rjs_cap=256, member_index=indexed)
+    pl = oracle.Plan(rho=1.0, bound=2, proposal=proposal, rjs_cap=256)
     starts = synth.all_vertices(g12["nv"])
     p, ln, st, ora = _run_both(ga12 if indexed else gn12, g12, lg, pl, STRATS[strategy], starts, 20, 53)
     rep = parity(p, ln, ora)
@@ -630,7 +629,7 @@ def test_h8_scale12(g12, strategy, logic, plan):
     gq, gf = _q8(g12)
     lg = Q8_LOGICS[logic]
     pl = (oracle.Plan(rho=1.0) if plan == "paper" else
-          oracle.Plan(rho=1.0, bound=2 if lg.kind != oracle.METAPATH else 0, proposal=1, member_index=True))
+          oracle.Plan(rho=1.0, bound=2 if lg.kind != oracle.METAPATH else 0, proposal=1))
     ggq = GpuGraph(gq, index=plan != "paper", alias=plan != "paper")
     ggf = GpuGraph(gf, index=plan != "paper", alias=plan != "paper")
     try:
@@ -676,6 +675,43 @@ def test_h8_argument_errors(g12):
         with pytest.raises(fw.FlexiWalkError) as e:
             GpuGraph(bad)
         assert e.value.code == fw.FW_E_INVALID
+
+
+def _alias_graphs():
+    out = {}
+    g = synth.rmat(12, 8 << 12, seed=1, nlabels=5)
+    out["rmat12"] = g
+    out["unweighted"] = dict(g, h=None)
+    gz = synth.rmat(11, 8 << 11, seed=4)
+    hz = gz["h"].copy()
+    hz[::3] = 0.0  # zero weights, and rows whose weights are all zero
+    gz["h"] = hz
+    out["zeros"] = gz
+    gp = synth.rmat(12, 8 << 12, seed=3)
+    gp["h"] = synth.pareto_weights(gp["row_ptr"], gp["col"], 1.0, 5)
+    out["pareto1"] = gp
+    out["hub600"] = hub_ring_graph(600)
+    # one row of 200,000 entries (many 64-entry tiles of the scan and of both merges)
+    n = 200000
+    star = synth.csr_from_edges(n + 1, [(0, i) for i in range(1, n + 1)])
+    star["h"] = synth.pareto_weights(star["row_ptr"], star["col"], 1.5, 9)
+    out["star200k"] = star
+    return out
+
+
+@pytest.mark.parametrize("name", ["rmat12", "unweighted", "zeros", "pareto1", "hub600", "star200k"])
+def test_alias_tables_equal_oracle(name):
+    """The proposal records' alias tables (built on the GPU, one wave per row, by prefix
+    sums and merges) equal the oracle's sequential sweep entry for entry."""
+    g = _alias_graphs()[name]
+    gg = GpuGraph(g, alias=True)
+    try:
+        thr, al = fw.fw_graph_export_alias(gg.handle, gg.ne)
+    finally:
+        gg.close()
+    othr, oal = oracle.Graph(g).alias()
+    np.testing.assert_array_equal(al, oal)
+    np.testing.assert_array_equal(thr, othr)
 
 
 def test_alias_build_runs_preprocessing(g12):

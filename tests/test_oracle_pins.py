@@ -712,12 +712,13 @@ def _directed(nv, rows, h=None):
 
 def _pin_bytes():
     """Hand-counted algorithmic bytes of single steps (the byte model of the measurement
-    section: 16 B for the row pointer pair, 4 B of h_MAX and 4 B of h_SUM where the step
-    reads them, 4 B col + 4 B h (+1 B label) per scanned or proposed edge, a membership test
-    of u in N(v') as a binary search of 4 B probes or one 8-B key of the edge index, the
-    h-proportional proposal's alias col, alias h and threshold (12 B), a member-region trial's
-    neighbour of v' (4 B) and its lookup of (v, x) with h (12 B, or a search of v's row), and
-    4 B start + 4 B per path slot + 4 B length per walk)."""
+    plan: 16 B for the row pointer pair, 4 B of h_MAX and 4 B of h_SUM where the step reads
+    them, 4 B col + 4 B h (+1 B label) per scanned or proposed edge, on every eRJS trial of a
+    board whose acceptance depends on u in N(v') a binary search of N(v') in 4 B probes
+    (ceil(log2(d(v') + 1)) of them), for an eRVS step the cheaper of staging N(v') and one such
+    search per scanned edge, the h-proportional proposal's alias col, alias h and threshold
+    (12 B), a member-region trial's neighbour of v' (4 B), a binary search of v's row and
+    h(v, x) (4 B when weighted), and 4 B start + 4 B per path slot + 4 B length per walk)."""
     # v = 0 with N(0) = {2}; v' = 1 with N(1) = {2, 3, 4, 5, 6} (5 entries: ceil(log2 6) = 3
     # probes); Node2Vec a = 1, b = 2^30: w = 1 on N(v'), ~1e-9 elsewhere, so every proposal's
     # accept test is left open by the bounds of w and needs the membership test.
@@ -728,17 +729,16 @@ def _pin_bytes():
     def b(lg, plan, strategy, j, prev, cur, graph=og):
         return oracle.step_info(graph, lg, plan, strategy, 3, 0, j, prev, cur)["bytes"]
 
-    # one eRJS trial (proposes 2, a member): 16 + 4 (col) + 3 probes * 4 B, or one 8-B index key
+    # one eRJS trial (proposes 2, a member): 16 + 4 (col) + 3 probes * 4 B
     assert b(n2v, oracle.Plan(), oracle.RJS_ONLY, 1, 1, 0) == 16 + 4 + 12
-    assert b(n2v, oracle.Plan(member_index=True), oracle.RJS_ONLY, 1, 1, 0) == 16 + 4 + 8
     # v = 7 with N(7) = {3}, v' = 1: 3 is a member, but now test a non-member: v' = 0 with N(0) = {2}
     # (one probe): every trial rejects, so rjs_cap = 3 trials, then eRVS scans 1 entry and
     # tests it (min(4 * d(v'), 4 * deg * probes) = min(4, 4) bytes)
     assert b(n2v, oracle.Plan(rjs_cap=3), oracle.RJS_ONLY, 1, 0, 7) == 16 + 3 * (4 + 4 * 1) + (4 + 4)
-    assert b(n2v, oracle.Plan(rjs_cap=3, member_index=True), oracle.RJS_ONLY, 1, 0, 7) == 16 + 3 * (4 + 8) + (4 + 4)
-    # a trial whose accept test the bounds already decide reads no membership: a = b = 1
+    # the search is charged on every trial, also one whose accept test the weight bounds
+    # already decide (a = b = 1: every neighbour weighs 1)
     flat = oracle.Logic(kind=oracle.NODE2VEC, weighted=False, p=1.0, q=1.0)
-    assert b(flat, oracle.Plan(), oracle.RJS_ONLY, 1, 1, 0) == 16 + 4
+    assert b(flat, oracle.Plan(), oracle.RJS_ONLY, 1, 1, 0) == 16 + 4 + 12
     # the first step has no membership at all
     assert b(n2v, oracle.Plan(), oracle.RJS_ONLY, 0, -1, 0) == 16 + 4
     # eRVS: d(v) = 5 entries of 4 B; N(v') staged (4 * d(v') = 4) against 5 searches of 1 probe
@@ -756,12 +756,15 @@ def _pin_bytes():
     # member board (second-order PageRank, gamma = 1: only members of N(v') weigh anything,
     # so every trial is a member-region trial): v = 0 with N(0) = {1, 2}, v' = 1 with
     # N(1) = {2}: the trial reads x = 2 (4 B) and looks (0, 2) up: a search of the 2-entry row
-    # (ceil(log2 3) = 2 probes) or 12 B of the index (key and h); it is kept, h = 1 = h_MAX
+    # (ceil(log2 3) = 2 probes); it is kept, h = 1 = h_MAX
     gm = _directed(3, {0: [1, 2], 1: [2]})
     ogm = oracle.Graph(gm)
     pr1 = oracle.Logic(kind=oracle.SECOND_PR, weighted=False, gamma=1.0)
     assert b(pr1, oracle.Plan(bound=2), oracle.RJS_ONLY, 1, 1, 0, ogm) == 16 + 4 + 4 * 2
-    assert b(pr1, oracle.Plan(bound=2, member_index=True), oracle.RJS_ONLY, 1, 1, 0, ogm) == 16 + 4 + 12
+    # ... weighted (h = 2 everywhere): h_MAX (4 B), and h(0, 2) with the member trial
+    gmw = _directed(3, {0: [1, 2], 1: [2]}, h=2.0)
+    pr1w = oracle.Logic(kind=oracle.SECOND_PR, weighted=True, gamma=1.0)
+    assert b(pr1w, oracle.Plan(bound=2), oracle.RJS_ONLY, 1, 1, 0, oracle.Graph(gmw)) == 16 + 4 + (4 + 4 * 2 + 4)
     # a walk's own I/O: a start at an isolated vertex reads its row pointers and ends:
     # 4 (start) + 4 * (L + 1) (path row) + 4 (length) + 16
     r = oracle.walk(og, n2v, oracle.Plan(), oracle.AUTO, np.array([5], np.int32), 7, 1)
