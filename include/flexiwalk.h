@@ -245,8 +245,9 @@ int fw_plan_profile(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stre
  * each eRJS bound: the split bound and the member board too for Node2Vec on a symmetric
  * graph, the member board for second-order PageRank; and each
  * proposal: h-proportional too for a weighted logic once fw_graph_build_alias ran), then for the
- * degree gate d_lo in {0, 8, 32, 128} and the LDS budget for N(prev); the fastest plan is
- * returned (grid stays 0: the occupancy limit).  Every candidate
+ * degree gate d_lo in {0, 8, 32, 128}, the LDS budget for N(prev), the eRJS trial cap
+ * rjs_cap in {16, 64, 256, 1024, 4096} and the persistent grid (the occupancy limit, half
+ * of it, twice it); the fastest plan is returned.  Every candidate
  * samples the same distribution; only the choice of kernel per step, and so the random
  * stream, differs.  Allocates temporary device memory; synchronous on `stream`. */
 int fw_plan_autotune(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stream);

@@ -736,8 +736,7 @@ int fw_plan_autotune_mix(fw_graph *g, const fw_logic *logics, int32_t n_logics, 
     if ((any_n2v && g->symmetric) || (any_pr && !any_n2v)) bounds[nbound++] = 2;
     const int nprop = (any_weighted && g->h && g->prop) ? 2 : 1;
     // cost-model constant around the profiled value for each bound and proposal, then the
-    // degree gate, then the LDS budget for N(prev) (the grid stays at the occupancy limit:
-    // smaller persistent grids timed no faster on the walk and slower on large batches)
+    // degree gate, the LDS budget for N(prev), the eRJS trial cap and the persistent grid
     fw_plan bestp = *out;
     float bestt = 1e30f;
     const float rho0 = out->rho;
@@ -768,6 +767,30 @@ int fw_plan_autotune_mix(fw_graph *g, const fw_logic *logics, int32_t n_logics, 
         float t;
         if ((rc = time_plan(p, &t)) != FW_OK) return rc;
         if (t < bestt) bestt = t, bestp = p;
+    }
+    // the trial cap K: a step past it falls back to eRVS (an exact sample either way), so a
+    // small cap bounds the time a lane spends where the bound is loose
+    for (int32_t k : {16, 64, 256, 4096}) {
+        fw_plan p = bestp;
+        p.rjs_cap = k;
+        float t;
+        if ((rc = time_plan(p, &t)) != FW_OK) return rc;
+        if (t < bestt) bestt = t, bestp = p;
+    }
+    // the persistent grid: the occupancy limit (0), half of it, and twice it (blocks past
+    // the resident ones start as others finish)
+    {
+        int64_t nw = 0;
+        for (int32_t i = 0; i < n_logics; ++i) nw += n;
+        const int full = fw::walk_grid(logics[0].kind, logics[0].weighted && g->h, batched, bestp.lds_cap, nw);
+        for (int gr : {full / 2, full * 2}) {
+            if (gr < 1) continue;
+            fw_plan p = bestp;
+            p.grid = gr;
+            float t;
+            if ((rc = time_plan(p, &t)) != FW_OK) return rc;
+            if (t < bestt) bestt = t, bestp = p;
+        }
     }
     *out = bestp;
     return ok();

@@ -69,3 +69,14 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=300)
     assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
+
+
+def test_one_off_share():
+    """Shares of the one-off costs beside one job, and the jobs on a resident graph after
+    which all of them fall below the paper's largest reported share (3.98 %)."""
+    r = bench.one_off_share(prep_ms=1.0, profile_ms=9.0, index_ms=40.0, alias_ms=30.0, tune_ms=120.0, job_ms=10.0)
+    assert r["paper_like_ms"] == 10.0 and r["all_ms"] == 191.0
+    assert abs(r["paper_like_share_one_job"] - 0.5) < 1e-12
+    assert abs(r["all_share_one_job"] - 191.0 / 201.0) < 1e-12
+    k = r["jobs_for_all_below_3.98pct"]
+    assert 191.0 / (191.0 + k * 10.0) < 0.0398 <= 191.0 / (191.0 + (k - 1) * 10.0)
