@@ -100,7 +100,13 @@ typedef struct fw_logic {
  *   rho      EdgeCost_RJS / EdgeCost_RVS of Eq. (runtime), > 0
  *   d_lo     steps at vertices of degree < d_lo always use eRVS (0 disables)
  *   rjs_cap  eRJS trials before an exact fall-back to eRVS, >= 1
- *   lanes    eRVS lanes per step; must be 64 (one wavefront)
+ *   lanes    eRVS lanes P per step below hub_deg; must be 64 (one wavefront)
+ *   hub_deg  rows of at least this degree are scanned by eRVS with hub_lanes lanes (0: never)
+ *   hub_lanes eRVS lanes P for those rows: 64, 128 or 256 (the wave runs P / 64 virtual lanes
+ *            per lane, so a round reads P / 64 blocks of 64 edges at once); P changes which
+ *            items share a skip threshold and so the random stream, never the distribution;
+ *            fw_walk only: fw_batch_create, fw_batch_run_noalloc and fw_server_create
+ *            return FW_E_INVALID for hub_deg > 0 with hub_lanes != 64
  *   lds_cap  int32 entries of N(prev) staged in LDS per wavefront, 0..8192 (0: never stage)
  *   grid     persistent blocks (0 = fill the device)
  *   bound    eRJS bound (changes the stream, never the distribution):
@@ -142,6 +148,8 @@ typedef struct fw_plan {
     int32_t grid;
     int32_t bound;
     int32_t proposal;
+    int32_t hub_deg;
+    int32_t hub_lanes;
 } fw_plan;
 
 /* Counters accumulated by fw_walk into a device array of FW_NSTATS uint64 values:
@@ -229,8 +237,8 @@ int fw_logic_metapath(const uint8_t *schema, int32_t m, int32_t weighted, fw_log
 /* Build a second-order PageRank logic; 0 <= gamma <= 1. */
 int fw_logic_second_pr(float gamma, int32_t weighted, fw_logic *out);
 
-/* Default plan: rho = 8, d_lo = 0, rjs_cap = 1024, lanes = 64, lds_cap and grid chosen
- * by the library. */
+/* Default plan: rho = 8, d_lo = 0, rjs_cap = 1024, lanes = 64, hub_deg = 0 (every row at
+ * 64 lanes), hub_lanes = 64, lds_cap and grid chosen by the library. */
 int fw_plan_default(fw_plan *out);
 
 /* Profiling kernels of Section 5: time weight evaluation of a fixed fraction of the nodes
@@ -246,8 +254,10 @@ int fw_plan_profile(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stre
  * graph, the member board for second-order PageRank; and each
  * proposal: h-proportional too for a weighted logic once fw_graph_build_alias ran), then for the
  * degree gate d_lo in {0, 8, 32, 128}, the LDS budget for N(prev), the eRJS trial cap
- * rjs_cap in {16, 64, 256, 1024, 4096} and the persistent grid (the occupancy limit, half
- * of it, twice it); the fastest plan is returned.  Every candidate
+ * rjs_cap in {16, 64, 256, 1024, 4096}, the eRVS lanes on long rows (hub_lanes 128 or
+ * 256 from hub_deg 1024 or 8192; fw_plan_autotune only, never for a mix) and the
+ * persistent grid (the occupancy limit, half of it, twice it); the fastest plan is
+ * returned.  Every candidate
  * samples the same distribution; only the choice of kernel per step, and so the random
  * stream, differs.  Allocates temporary device memory; synchronous on `stream`. */
 int fw_plan_autotune(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stream);

@@ -56,7 +56,8 @@ class _Logic(ctypes.Structure):
 class _Plan(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_float), ("d_lo", ctypes.c_int32), ("rjs_cap", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("jump", ctypes.c_int32), ("bound_scale", ctypes.c_float),
-                ("bound", ctypes.c_int32), ("proposal", ctypes.c_int32)]
+                ("bound", ctypes.c_int32), ("proposal", ctypes.c_int32), ("hub_deg", ctypes.c_int32),
+                ("hub_lanes", ctypes.c_int32)]
 
 
 @dataclass
@@ -91,12 +92,15 @@ class Plan:
     bound_scale: float = 1.0
     bound: int = 0  # 0: max(w) * h_MAX (Section 3.3); 1: Node2Vec split bound (return edge apart)
     proposal: int = 0  # 0: uniform eRJS proposals (Section 3.3); 1: proportional to h (alias tables)
+    hub_deg: int = 0  # eRVS rows of at least this degree use hub_lanes lanes (0: never)
+    hub_lanes: int = 64
 
     def _c(self):
         s = _Plan()
         s.rho, s.d_lo, s.rjs_cap, s.lanes = self.rho, self.d_lo, self.rjs_cap, self.lanes
         s.jump, s.bound_scale, s.bound = int(self.jump), self.bound_scale, self.bound
         s.proposal = self.proposal
+        s.hub_deg, s.hub_lanes = self.hub_deg, self.hub_lanes
         return s
 
 

@@ -161,6 +161,8 @@ typedef struct {
     int32_t bound;       /* 0: max(w) * h_MAX (Section 3.3); 1: Node2Vec split bound; 2: split and
                             member board, the smaller per step */
     int32_t proposal;    /* 0: uniform eRJS proposals (Section 3.3); 1: proportional to h */
+    int32_t hub_deg;     /* rows of at least this degree run eRVS with hub_lanes lanes (0: never) */
+    int32_t hub_lanes;   /* P for those rows */
 } og_plan;
 
 /* OG_RANDOM_SELECT and OG_DEGREE_SELECT are the two selection policies the paper compares
@@ -393,7 +395,8 @@ static double bytes_per_item(const og_ctx *cx)
 static int64_t rvs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int64_t base, int64_t deg,
                           int64_t dvp, og_info *info)
 {
-    const int64_t P = cx->pl->lanes;
+    /* P: the plan's lanes, or hub_lanes on a row of degree >= hub_deg */
+    const int64_t P = (cx->pl->hub_deg > 0 && deg >= cx->pl->hub_deg) ? cx->pl->hub_lanes : cx->pl->lanes;
     uint32_t x[4];
 
     if (!cx->pl->jump) {

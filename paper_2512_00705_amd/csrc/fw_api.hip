@@ -324,6 +324,8 @@ int fw_plan_default(fw_plan *out)
     out->lds_cap = fw::kDefaultLdsCap;
     out->grid = 0;
     out->bound = 0;
+    out->hub_deg = 0;
+    out->hub_lanes = 64;
     return ok();
 }
 
@@ -405,6 +407,9 @@ int fw::host::check_plan(const fw_plan *pl)
     if (pl->grid < 0) return fail(FW_E_INVALID, "plan.grid must be >= 0");
     if (pl->bound < 0 || pl->bound > 2) return fail(FW_E_INVALID, "plan.bound must be 0, 1 or 2");
     if (pl->proposal < 0 || pl->proposal > 1) return fail(FW_E_INVALID, "plan.proposal must be 0 or 1");
+    if (pl->hub_deg < 0) return fail(FW_E_INVALID, "plan.hub_deg must be >= 0");
+    if (pl->hub_lanes != 64 && pl->hub_lanes != 128 && pl->hub_lanes != 256)
+        return fail(FW_E_INVALID, "plan.hub_lanes must be 64, 128 or 256");
     return FW_OK;
 }
 
@@ -427,6 +432,8 @@ void fw::host::plan_args(const fw_plan *pl, int32_t strategy, fw::WalkArgs &a)
     a.lds_cap = pl->lds_cap;
     a.bound = pl->bound;
     a.proposal = pl->proposal;
+    a.hub_deg = pl->hub_deg;
+    a.hub_v = pl->hub_lanes / 64;
 }
 
 extern "C" {
@@ -777,6 +784,20 @@ int fw_plan_autotune_mix(fw_graph *g, const fw_logic *logics, int32_t n_logics, 
         if ((rc = time_plan(p, &t)) != FW_OK) return rc;
         if (t < bestt) bestt = t, bestp = p;
     }
+    // eRVS lanes on long rows, for one logic only (hub lanes run in fw_walk launches; a mix
+    // is tuned for the batches and servers that take it): P = 128 or 256 on rows of at
+    // least 1024 or 8192 entries
+    if (n_logics == 1) {
+        for (int32_t hl : {128, 256})
+            for (int32_t hd : {1024, 8192}) {
+                fw_plan p = bestp;
+                p.hub_deg = hd;
+                p.hub_lanes = hl;
+                float t;
+                if ((rc = time_plan(p, &t)) != FW_OK) return rc;
+                if (t < bestt) bestt = t, bestp = p;
+            }
+    }
     // the persistent grid: the occupancy limit (0), half of it, and twice it (blocks past
     // the resident ones start as others finish)
     {
@@ -861,6 +882,8 @@ int fw_batch_create(fw_graph *g, const fw_query *qs, int64_t nq, const fw_plan *
         return fail(FW_E_INVALID, "fw_batch_create: bad strategy %d", strategy);
     int rc = check_plan(pl);
     if (rc != FW_OK) return rc;
+    if (pl->hub_deg > 0 && pl->hub_lanes != 64)
+        return fail(FW_E_INVALID, "fw_batch_create: hub lanes (hub_lanes > 64) apply to fw_walk launches only");
     std::vector<fw::QueryDev> tab((size_t)(nq > 0 ? nq : 1));
     int64_t total = 0;
     for (int64_t i = 0; i < nq; ++i) {
@@ -995,6 +1018,8 @@ int fw_batch_run_noalloc(fw_graph *g, const fw_query *qs, int64_t nq, const fw_p
     if (!fw::valid_strategy(strategy)) return fail(FW_E_INVALID, "fw_batch_run_noalloc: bad strategy %d", strategy);
     int rc = check_plan(pl);
     if (rc != FW_OK) return rc;
+    if (pl->hub_deg > 0 && pl->hub_lanes != 64)
+        return fail(FW_E_INVALID, "fw_batch_run_noalloc: hub lanes (hub_lanes > 64) apply to fw_walk launches only");
     // every query is checked before anything is written to the device
     int64_t total = 0;
     for (int64_t i = 0; i < nq; ++i) {

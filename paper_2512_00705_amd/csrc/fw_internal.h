@@ -129,6 +129,8 @@ struct WalkArgs {
     const uint4 *mtab;          // edge index (8 uint4 per bucket) or null: search the sorted rows
     const uint4 *prop;          // proposal records (kPropU4 uint4 per entry) or null
     int32_t proposal;           // 1: h-proportional eRJS proposals through `prop`
+    int32_t hub_deg;            // eRVS rows of at least this degree use hub_v * 64 lanes (0: never)
+    int32_t hub_v;              // virtual lanes per lane there: 1, 2 or 4
     uint64_t mtab_mask;         // buckets - 1
 
     QueryDev q0;                // the query of a single-query launch

@@ -161,15 +161,23 @@ __device__ __forceinline__ int64_t row_start(const WalkArgs &a, uint4 r, int32_t
 // lanes (ds_bpermute), and the block advances while some item lies beyond it.  The cursor
 // then moves past everything below the round's largest item.  Over a whole scan this
 // reads N(prev) once, in order, where a search per item costs log d(prev) dependent loads.
+// A round whose largest item lies below the entry at the cursor holds no member and
+// leaves the cursor where it is: it needs no bisection (the usual round of a hub row
+// scanned from a short N(prev)).
 // `valid`: the lane holds an item; every lane must call this.
 __device__ __forceinline__ bool merge_member(const Mem &m, int32_t u, bool valid, int64_t &lo)
 {
     const int lane = lane_id();
+    const uint64_t vm = __ballot(valid);
+    if (vm == 0) return false;
+    // items are consecutive entries of a sorted row: the largest sits in the last valid lane
+    const int32_t umax = __builtin_amdgcn_readlane(u, 63 - __builtin_clzll((unsigned long long)vm));
     bool found = false, done = !valid;
     int32_t c = 0;
-    for (;;) {
+    for (bool first = true;; first = false) {
         const int64_t vi = lo + lane;
         const int32_t v = vi < m.len ? m.p[vi] : INT32_MAX;
+        if (first && umax < __builtin_amdgcn_readfirstlane(v)) return false;
         c = 0;
 #pragma unroll
         for (int s = kWave / 2; s > 0; s >>= 1) {
@@ -267,6 +275,108 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q
     return (int32_t)e.x;
 }
 
+// rvs_step with P = 64 * V reservoir lanes (V > 1, hub rows): lane l of the wave runs the
+// virtual lanes l, l + 64, ..., l + 64 (V - 1), and virtual lane vl owns items vl, vl + P,
+// vl + 2P, ... (Section 3.2, parallel form).  A round reads V blocks of 64 edges at once,
+// so a long row is scanned with V times the reads in flight.  Results, `trig` and `hsel`
+// as for rvs_step; the lane's best virtual lane (larger index wins ties) then enters the
+// wave's argmax.
+template <int KIND, bool W, int V>
+__device__ __forceinline__ int32_t rvs_step_hub(const WalkArgs &a, const QueryDev &Q, const Mem &mem, uint32_t wid,
+                                            int j, int32_t prev, int64_t base, int64_t deg, uint8_t want,
+                                            const StepW &sw, uint32_t &trig, float &hsel, bool merge)
+{
+    constexpr int P = kWave * V;
+    const int lane = lane_id();
+    const uint32_t k0 = Q.key0, k1 = Q.key1;
+    float key[V], thr[V], T[V], S[V];
+    int32_t bi[V];
+    int64_t mlo = 0;  // merge cursor in N(prev)
+    // round 0: virtual lane vl keys neighbour vl, k = u^(1/w~) kept as log(u) / w~
+    uint2 e0[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int64_t l = lane + kWave * v;
+        e0[v] = l < deg ? edge_rec(a, base + l) : make_uint2(0u, 0u);
+    }
+    float kmax = -INFINITY;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const int64_t l = lane + kWave * v;
+        const bool memv = merge && merge_member(mem, (int32_t)e0[v].x, l < deg, mlo);
+        key[v] = -INFINITY;
+        bi[v] = -1;
+        T[v] = 0.5f;  // holds the threshold draw until lkg is known
+        if (l < deg) {
+            const float wt = merge ? weight_of_member<KIND, W>(e0[v], j, prev, memv, sw)
+                                   : edge_weight<KIND, W>(a, Q, base + l, e0[v], j, prev, mem, want, sw);
+            const U4 x = philox(wid, (uint32_t)j, (uint32_t)l, 1u, k0, k1);
+            key[v] = wt > 0.0f ? ln_f(unit_uniform(x.x0)) / wt : -INFINITY;
+            T[v] = unit_uniform(x.x1);
+            bi[v] = (int32_t)l;
+        }
+        kmax = fmaxf(kmax, key[v]);
+    }
+    const float lkg = wave_max(kmax);
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        thr[v] = lkg;
+        T[v] = (lkg == -INFINITY) ? 0.0f : (lkg >= 0.0f ? INFINITY : ln_f(T[v]) / lkg);
+        S[v] = 0.0f;
+    }
+    uint32_t nt = 0;
+    // scan: a key is drawn only where a virtual lane's running weight passes its skip
+    // threshold T = log(r) / log(k_thr)
+    for (int64_t i0 = P; i0 < deg; i0 += P) {
+        uint2 ei[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int64_t i = i0 + lane + kWave * v;
+            ei[v] = i < deg ? edge_rec(a, base + i) : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const int64_t i = i0 + lane + kWave * v;
+            const bool memi = merge && merge_member(mem, (int32_t)ei[v].x, i < deg, mlo);
+            if (i < deg) {
+                const float wt = merge ? weight_of_member<KIND, W>(ei[v], j, prev, memi, sw)
+                                       : edge_weight<KIND, W>(a, Q, base + i, ei[v], j, prev, mem, want, sw);
+                S[v] = S[v] + wt;
+                if (S[v] > T[v]) {
+                    // key conditioned to beat thr: log u' = log1p(expm1(w~ * thr) * V)
+                    const U4 x = philox(wid, (uint32_t)j, (uint32_t)i, 1u, k0, k1);
+                    const float av = wt * thr[v];
+                    const float m1 = expm1_f(av);
+                    const float z = m1 * unit_uniform(x.x0);
+                    const float lg = log1p_f(z);
+                    key[v] = lg / wt;
+                    bi[v] = (int32_t)i;
+                    thr[v] = key[v];
+                    S[v] = 0.0f;
+                    T[v] = thr[v] >= 0.0f ? INFINITY : ln_f(unit_uniform(x.x1)) / thr[v];
+                    ++nt;
+                }
+            }
+        }
+    }
+    float key0 = key[0];
+    int32_t bi0 = bi[0];
+#pragma unroll
+    for (int v = 1; v < V; ++v)
+        if (key[v] > key0 || (key[v] == key0 && bi[v] > bi0)) {
+            key0 = key[v];
+            bi0 = bi[v];
+        }
+    float &keyb = key0;
+    int32_t &bib = bi0;
+    wave_argmax(keyb, bib);
+    trig = (uint32_t)wave_sum_u64(nt);
+    if (!(keyb > -INFINITY)) return -1;
+    const uint2 e = edge_rec(a, base + bib);
+    hsel = W ? __uint_as_float(e.y) : 1.0f;
+    return (int32_t)e.x;
+}
+
 // eRVS for up to 64/G steps at once, one G-lane group per step, for rows of at most G
 // neighbours.  Such a step is decided by round 0 alone (every neighbour gets its key,
 // there is nothing to scan), so the result equals the one-wave eRVS bit for bit.
@@ -357,8 +467,10 @@ __device__ __forceinline__ void flush_stats(const WalkArgs &a, uint32_t (&cnt)[k
 // its own so that the lane state it needs costs the other plans no registers.
 // STATS: the launch accumulates the device counters (a.stats non-null); without them the
 // per-lane counts are dead code and their registers go to the walk.
-template <int KIND, bool W, bool BATCH, bool MB, bool STATS>
-__global__ void __launch_bounds__(kBlock, STATS ? kMinWavesCounted : (BATCH ? kMinWavesBatch : kMinWaves))
+// HV: virtual lanes per lane of eRVS on rows of degree >= hub_deg (P = 64 * HV there); a
+// variant of its own so that the extra lane state costs the other plans no registers.
+template <int KIND, bool W, bool BATCH, bool MB, bool STATS, int HV = 1>
+__global__ void __launch_bounds__(kBlock, (STATS || HV > 1) ? kMinWavesCounted : (BATCH ? kMinWavesBatch : kMinWaves))
 walk_kernel(WalkArgs a)
 {
     extern __shared__ int32_t lds_all[];
@@ -826,8 +938,10 @@ walk_kernel(WalkArgs a)
                 Mem m = {a.col + s_pbase, s_pdeg, false, false};
                 // merge the rows when N(prev) is not much longer than the row scanned
                 const bool merge = member_test && (int64_t)s_pdeg <= (int64_t)kMergeRatio * s_deg;
-                if (member_test && !merge && s_pdeg <= a.lds_cap &&
-                    (int64_t)s_pdeg <= (int64_t)s_deg * probes(s_pdeg)) {
+                // stage N(prev) in LDS for the merge (its reads become LDS reads), or for the
+                // per-item searches when they would read more than the staging
+                if (member_test && s_pdeg <= a.lds_cap &&
+                    (merge || (int64_t)s_pdeg <= (int64_t)s_deg * probes(s_pdeg))) {
                     wave_lds_sync();
                     for (int32_t i = lane; i < s_pdeg; i += kWave) lds[i] = a.col[s_pbase + i];
                     wave_lds_sync();
@@ -836,7 +950,12 @@ walk_kernel(WalkArgs a)
                 }
                 uint32_t trig = 0;
                 const StepW sw = step_weights<KIND>(Q, s_deg, s_pdeg);
-                res = rvs_step<KIND, W>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, sw, trig, hres, merge);
+                // P = 64 lanes, or 64 * HV on a row of degree >= hub_deg
+                if (HV > 1 && a.hub_deg > 0 && s_deg >= a.hub_deg)
+                    res = rvs_step_hub<KIND, W, HV>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, sw, trig, hres,
+                                                    merge);
+                else
+                    res = rvs_step<KIND, W>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, sw, trig, hres, merge);
                 if (lane == src) served(res, hres, trig);
             }
         }
@@ -1359,14 +1478,24 @@ hipError_t launch_random_reads(const uint2 *a, uint64_t mask, int blocks, int ro
     return hipGetLastError();
 }
 
+template <int KIND, bool W, bool BATCH, bool STATS, int HV>
+static void launch_walk_h(const WalkArgs &a, int grid, size_t lds, hipStream_t s)
+{
+    if (uses_membership(KIND) && a.bound == 2)
+        hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, uses_membership(KIND), STATS, HV>), dim3(grid), dim3(kBlock),
+                           lds, s, a);
+    else
+        hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, false, STATS, HV>), dim3(grid), dim3(kBlock), lds, s, a);
+}
+
+// hub lanes (P > 64 on long rows) are built for single-query launches only
 template <int KIND, bool W, bool BATCH, bool STATS>
 static void launch_walk_s(const WalkArgs &a, int grid, size_t lds, hipStream_t s)
 {
-    if (uses_membership(KIND) && a.bound == 2)
-        hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, uses_membership(KIND), STATS>), dim3(grid), dim3(kBlock), lds,
-                           s, a);
-    else
-        hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, false, STATS>), dim3(grid), dim3(kBlock), lds, s, a);
+    const int hv = (BATCH || a.hub_deg <= 0) ? 1 : a.hub_v;
+    if (!BATCH && hv == 4) launch_walk_h<KIND, W, BATCH, STATS, (BATCH ? 1 : 4)>(a, grid, lds, s);
+    else if (!BATCH && hv == 2) launch_walk_h<KIND, W, BATCH, STATS, (BATCH ? 1 : 2)>(a, grid, lds, s);
+    else launch_walk_h<KIND, W, BATCH, STATS, 1>(a, grid, lds, s);
 }
 
 template <int KIND, bool W, bool BATCH>

@@ -345,6 +345,8 @@ int fw_server_create(fw_graph *g, const fw_plan *plan, int32_t strategy, uint64_
     if (!g || !plan || !out) return fail(FW_E_INVALID, "fw_server_create: null argument");
     int rc = fw::host::check_plan(plan);
     if (rc != FW_OK) return rc;
+    if (plan->hub_deg > 0 && plan->hub_lanes != 64)
+        return fail(FW_E_INVALID, "fw_server_create: hub lanes (hub_lanes > 64) apply to fw_walk launches only");
     if (!fw::valid_strategy(strategy))
         return fail(FW_E_INVALID, "fw_server_create: bad strategy %d", strategy);
     if (tick_steps < 1) return fail(FW_E_INVALID, "fw_server_create: tick_steps must be >= 1");

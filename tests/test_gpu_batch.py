@@ -230,6 +230,7 @@ def test_autotune_mix(g12, gg12):
               fw.fw_logic_second_pr(0.2, True)]
     pl = fw.fw_plan_autotune_mix(gg12.handle, logics)
     assert pl.rho > 0 and pl.bound in (0, 1, 2) and pl.proposal == 0 and pl.grid >= 0 and pl.lanes == 64
+    assert pl.hub_deg == 0 and pl.hub_lanes == 64  # a mix keeps P = 64 (batches and servers run no hub lanes)
     with pytest.raises(fw.FlexiWalkError):
         fw.fw_plan_autotune_mix(gg12.handle, [])
     # Node2Vec on a graph without equal reverse edges: only the paper's bound is tried

@@ -81,7 +81,8 @@ def test_node2vec_scale22(g22, gg22, og22, tuned22, strategy, k, bound, proposal
     tuned = tuned22
     pl = oracle.Plan(rho=tuned.rho if rho is None else rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap,
                      bound=tuned.bound if bound is None else bound,
-                     proposal=tuned.proposal if proposal is None else proposal)
+                     proposal=tuned.proposal if proposal is None else proposal, hub_deg=tuned.hub_deg,
+                     hub_lanes=tuned.hub_lanes)
     starts = synth.all_vertices(g22["nv"])
     p, ln, st = gpu_walk(gg22, N2V, pl, strategy, starts, 80, 42)
     # the launch the benchmark times (no counter array, the counter-free kernel variant)
@@ -104,6 +105,26 @@ def test_node2vec_scale22(g22, gg22, og22, tuned22, strategy, k, bound, proposal
         assert (ora.kinds == 0).any() and (ora.kinds == 1).any()
 
 
+@pytest.mark.parametrize("hub_deg,hub_lanes", [(1024, 256), (4096, 128)])
+def test_node2vec_scale22_hub_lanes(g22, gg22, og22, tuned22, hub_deg, hub_lanes):
+    """eRVS-only at scale 22 with P = hub_lanes on rows of degree >= hub_deg (a third of the
+    steps, most of the scanned entries): 16,384 sampled walkers against the oracle with
+    the same degree bucket."""
+    pl = oracle.Plan(rho=tuned22.rho, d_lo=tuned22.d_lo, rjs_cap=tuned22.rjs_cap, bound=tuned22.bound,
+                     proposal=tuned22.proposal, hub_deg=hub_deg, hub_lanes=hub_lanes)
+    starts = synth.all_vertices(g22["nv"])
+    p, ln, st = gpu_walk(gg22, N2V, pl, oracle.RVS_ONLY, starts, 80, 42, counters=False)
+    ok, pad_ok, _ = edge_check_torch(g22, p, ln)
+    assert ok and pad_ok
+    sub = _sample(g22["nv"], 16384, 1234)
+    ora = oracle.walk(og22, N2V, pl, oracle.RVS_ONLY, starts[sub], 80, 42, walker_ids=sub)
+    rep = parity(p[sub], ln[sub], ora)
+    print("scale22 hub lanes", hub_deg, hub_lanes, {k2: (v if not isinstance(v, list) else len(v))
+                                                    for k2, v in rep.items()})
+    assert_parity(rep)
+    assert rep["steps"] >= 16384 * 40
+
+
 @pytest.mark.parametrize("bound", [None, 0], ids=["tuned", "paper"])
 def test_second_pr_scale22(g22, gg22, og22, bound):
     """Second-order PageRank (gamma = 0.2), one walker per vertex, L = 80, the autotuned
@@ -112,7 +133,8 @@ def test_second_pr_scale22(g22, gg22, og22, bound):
     lg = oracle.Logic(kind=oracle.SECOND_PR, weighted=True, gamma=0.2)
     tuned = fw.fw_plan_autotune(gg22.handle, fw.fw_logic_second_pr(0.2, True))
     pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap,
-                     bound=tuned.bound if bound is None else bound, proposal=tuned.proposal)
+                     bound=tuned.bound if bound is None else bound, proposal=tuned.proposal,
+                     hub_deg=tuned.hub_deg, hub_lanes=tuned.hub_lanes)
     starts = synth.all_vertices(g22["nv"])
     p, ln, st = gpu_walk(gg22, lg, pl, oracle.AUTO, starts, 80, 42)
     p2, ln2, _ = gpu_walk(gg22, lg, pl, oracle.AUTO, starts, 80, 42, counters=False)
@@ -141,7 +163,7 @@ def test_node2vec_scale22_h8(g22):
         starts = synth.all_vertices(g22["nv"])
         for strategy, k in ((oracle.AUTO, 65536), (oracle.RVS_ONLY, 16384)):
             pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap, bound=tuned.bound,
-                             proposal=tuned.proposal)
+                             proposal=tuned.proposal, hub_deg=tuned.hub_deg, hub_lanes=tuned.hub_lanes)
             p, ln, st = gpu_walk(gg, N2V, pl, strategy, starts, 80, 42)
             ok, pad_ok, _ = edge_check_torch(g22, p, ln)
             assert ok and pad_ok
@@ -157,7 +179,7 @@ def test_node2vec_scale22_h8(g22):
 
 def test_metapath_scale22(g22, gg22, og22):
     tuned = fw.fw_plan_autotune(gg22.handle, fw.fw_logic_metapath([0, 1, 2, 3, 4], True))
-    pl = oracle.Plan(rho=tuned.rho, rjs_cap=tuned.rjs_cap)
+    pl = oracle.Plan(rho=tuned.rho, rjs_cap=tuned.rjs_cap, hub_deg=tuned.hub_deg, hub_lanes=tuned.hub_lanes)
     starts = synth.uniform_starts(g22["nv"], 1 << 20, 42)
     p, ln, st = gpu_walk(gg22, MP, pl, oracle.AUTO, starts, 40, 42)
     ok, pad_ok, (pos, taken) = edge_check_torch(g22, p, ln)

@@ -183,6 +183,9 @@ def _hub_case(plan, strategy, n=40000, seed=5):
 @pytest.mark.parametrize("name,strategy,plan", [
     ("rvs_jump_P64", oracle.RVS_ONLY, oracle.Plan(lanes=64)),
     ("rvs_jump_P7", oracle.RVS_ONLY, oracle.Plan(lanes=7)),
+    ("rvs_jump_P256", oracle.RVS_ONLY, oracle.Plan(lanes=256)),
+    ("rvs_jump_P1024", oracle.RVS_ONLY, oracle.Plan(lanes=1024)),
+    ("rvs_hub_bucket_P256", oracle.RVS_ONLY, oracle.Plan(hub_deg=600, hub_lanes=256)),
     ("rvs_nojump", oracle.RVS_ONLY, oracle.Plan(jump=False)),
     ("rjs", oracle.RJS_ONLY, oracle.Plan()),
 ])
@@ -192,6 +195,24 @@ def test_hub_distribution(name, strategy, plan):
     if strategy == oracle.RVS_ONLY and plan.jump:
         # the jump skips most keys: far fewer key draws than items scanned
         assert r.counters["rvs_triggers"] < 0.2 * 600 * r.counters["steps"] / 2
+
+
+def test_hub_lane_bucket_dispatch():
+    """The degree bucket picks P per step: with hub_deg = 600 the hub's eRVS steps run with
+    hub_lanes lanes and every other row with 64, so the walks equal those of a plan with
+    P = 256 everywhere (rows of at most 64 entries are keyed in round 0 alone, which does not
+    depend on P); one more than the hub's degree leaves every step at P = 64.  P itself
+    changes the stream: the P = 256 and P = 64 walks differ."""
+    g = hub_ring_graph()
+    og = oracle.Graph(g)
+    lg = oracle.Logic(**N2V)
+    starts = np.arange(1, 601, dtype=np.int32)
+    walk = lambda pl: oracle.walk(og, lg, pl, oracle.RVS_ONLY, starts, 6, 17, diagnostics=False).paths
+    p64, p256 = walk(oracle.Plan(lanes=64)), walk(oracle.Plan(lanes=256))
+    assert not np.array_equal(p64, p256)
+    assert np.array_equal(walk(oracle.Plan(hub_deg=600, hub_lanes=256)), p256)
+    assert np.array_equal(walk(oracle.Plan(hub_deg=601, hub_lanes=256)), p64)
+    assert np.array_equal(walk(oracle.Plan(hub_deg=0, hub_lanes=256)), p64)
 
 
 def test_rjs_mean_trials_and_known_bound():
