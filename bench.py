@@ -25,6 +25,29 @@ KERNEL_SOURCES = ("paper_2512_00705_amd/csrc/fw_kernels.hip", "paper_2512_00705_
 TRAFFIC_FILE = "profiles/traffic_walk_kernel_node2vec_rmat22.txt"
 
 
+def parse_plan(text: str):
+    """A plan from ``rho,d_lo,lds_cap[,bound[,proposal[,rjs_cap[,grid[,hub_deg,hub_lanes]]]]]``;
+    omitted fields take fw_plan_default's values."""
+    import paper_2512_00705_amd as fw
+    f = text.split(",")
+    names = ("rho", "d_lo", "lds_cap", "bound", "proposal", "rjs_cap", "grid", "hub_deg", "hub_lanes")
+    if not 3 <= len(f) <= len(names):
+        raise SystemExit(f"--plan: expected 3..{len(names)} comma-separated fields, got {len(f)}")
+    kw = {n: (float(v) if n == "rho" else int(v)) for n, v in zip(names, f)}
+    return fw.fw_plan_default(**kw)
+
+
+def plan_arg(plan) -> str:
+    """The --plan text that reproduces ``plan`` (float rho in full precision)."""
+    return ",".join([repr(float(plan.rho))] + [str(int(getattr(plan, n))) for n in
+                     ("d_lo", "lds_cap", "bound", "proposal", "rjs_cap", "grid", "hub_deg", "hub_lanes")])
+
+
+def plan_dict(plan) -> dict:
+    return {n: (float(getattr(plan, n)) if n == "rho" else int(getattr(plan, n))) for n in
+            ("rho", "d_lo", "lds_cap", "bound", "proposal", "rjs_cap", "grid", "hub_deg", "hub_lanes")}
+
+
 def one_off_share(prep_ms, profile_ms, index_ms, alias_ms, tune_ms, job_ms) -> dict:
     """One-off costs beside one walk job.  The paper reports profiling plus preprocessing at
     0.46-3.98 % of total runtime; here the same two (profiling kernels, h_MAX/h_SUM pass)
@@ -125,7 +148,8 @@ def main():
     ap.add_argument("--skew-scale", type=int, default=20, help="skew: R-MAT scale of the topology")
     ap.add_argument("--skew-L", type=int, default=20, help="skew: walk length")
     ap.add_argument("--plan", default="",
-                    help="rho,d_lo,lds_cap[,bound[,proposal]]: use this plan instead of autotuning")
+                    help="rho,d_lo,lds_cap[,bound[,proposal[,rjs_cap[,grid[,hub_deg,hub_lanes]]]]]: use this plan "
+                         "instead of autotuning (the plan_arg of a bench line)")
     ap.add_argument("--per-query", type=int, default=1, help="batched: also time one launch per query")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB: only run a plain device-to-device copy of this size 3 times (counter calibration)")
@@ -222,14 +246,11 @@ def main():
     profile_ms = (time.perf_counter() - p0) * 1e3
     t1 = time.time()
     if args.plan:
-        f = args.plan.split(",")
-        plan = fw.fw_plan_default(rho=float(f[0]), d_lo=int(f[1]), lds_cap=int(f[2]),
-                                  bound=int(f[3]) if len(f) > 3 else 0, proposal=int(f[4]) if len(f) > 4 else 0)
+        plan = parse_plan(args.plan)
     else:
         plan = fw.fw_plan_autotune(gh, logic)
     tune_ms = (time.time() - t1) * 1e3
-    log(f"preprocess {prep_ms:.2f} ms, autotune {tune_ms:.1f} ms, rho={plan.rho:.3f} d_lo={plan.d_lo} "
-        f"lds_cap={plan.lds_cap} bound={plan.bound} proposal={plan.proposal}")
+    log(f"preprocess {prep_ms:.2f} ms, autotune {tune_ms:.1f} ms, plan {plan_arg(plan)}")
 
     nv, seed = g["nv"], 42
     L = args.L if args.L is not None else (40 if args.logic == "metapath" else 80)
@@ -383,8 +404,7 @@ def main():
                    "edge_index_ms": index_ms, "alias_build_ms": alias_ms,
                    "autotune_ms": tune_ms, "profile_ms": profile_ms,
                    "one_off_share": one_off_share(prep_ms, profile_ms, index_ms, alias_ms, tune_ms, avg_ms),
-                   "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound,
-                            "proposal": plan.proposal, "grid": plan.grid},
+                   "plan": plan_dict(plan), "plan_arg": plan_arg(plan),
                    "stats": st, "modes": modes,
                    "hbm_traffic_GBps": None if traffic is None else traffic["bytes"] / (avg_ms / 1e3) / 1e9,
                    "random_access": random_access},
@@ -562,8 +582,7 @@ def bench_batched(args):
                                f"({int(qd['n'].sum())} walkers), L in 5..200, one captured HIP-graph launch, "
                                f"R-MAT scale 24 (0.6,0.175,0.175), {g['ne']} CSR entries",
                    "stats": st, "rho": plan.rho, "d_lo": plan.d_lo,
-                   "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound,
-                            "proposal": plan.proposal, "grid": plan.grid}, "autotune_ms": tune_ms,
+                   "plan": plan_dict(plan), "autotune_ms": tune_ms,
                    "per_query_launches_ms": per_q,
                    "per_query_walker_steps_per_s": (st["steps"] / (per_q / 1e3)) if per_q else None},
         "roofline": {"bound": "hbm", "achieved": st["alg_bytes"] / (avg / 1e3) / 1e9, "peak": PEAK_HBM_GBS,
@@ -678,8 +697,7 @@ def bench_served(args):
                                f"batching (tick {args.tick_steps} steps), budget {budget >> 30} GiB",
                    "p50_ms": p50, "p99_ms": p99, "requests": len(reqs), "completed": len(lat),
                    "sustained": sustained, "offered_walker_steps_per_s": offered_steps / T, "server": st,
-                   "plan": {"rho": plan.rho, "d_lo": plan.d_lo, "lds_cap": plan.lds_cap, "bound": plan.bound,
-                            "proposal": plan.proposal, "grid": plan.grid},
+                   "plan": plan_dict(plan),
                    "busy_retries": busy[0], "rho": plan.rho},
         "roofline": None, "cpu_baseline": None,
     }

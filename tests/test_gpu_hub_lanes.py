@@ -77,9 +77,11 @@ def test_hub_lanes_scale12(g12, gg12, logic, strategy, hub_lanes):
     assert_parity(rep)
     if rep["mismatch_walkers"] == 0:
         _assert_counters(st, ora)
-    # the bucket changes the stream: the walks differ from the P = 64 plan's
-    p64, _, _ = gpu_walk(gg12, lg, oracle.Plan(rho=2.0, rjs_cap=64), STRATS[strategy], starts, 20, 42)
-    assert not np.array_equal(p, p64)
+    # the bucket changes the stream: eRVS-only walks differ from the P = 64 plan's (under
+    # AUTO the long rows mostly go to eRJS, and the walks may coincide)
+    if strategy == "rvs":
+        p64, _, _ = gpu_walk(gg12, lg, oracle.Plan(rho=2.0, rjs_cap=64), STRATS[strategy], starts, 20, 42)
+        assert not np.array_equal(p, p64)
 
 
 @pytest.mark.parametrize("hub_lanes", [128, 256])
