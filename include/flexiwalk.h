@@ -241,8 +241,9 @@ int fw_logic_second_pr(float gamma, int32_t weighted, fw_logic *out);
  * 64 lanes), hub_lanes = 64, lds_cap and grid chosen by the library. */
 int fw_plan_default(fw_plan *out);
 
-/* Profiling kernels of Section 5: time weight evaluation of a fixed fraction of the nodes
- * with eRJS-style random proposals and with eRVS-style coalesced scans on this graph and
+/* Profiling kernels of Section 5: time weight evaluation of a sample of the nodes (the
+ * non-isolated ones among up to 32768 evenly spaced vertex ids, at most 16384) with
+ * eRJS-style random proposals and with eRVS-style coalesced scans on this graph and
  * logic, and set out->rho to the per-edge cost ratio EdgeCost_RJS / EdgeCost_RVS of
  * Eq. (runtime); the other fields come from fw_plan_default.  Synchronous on `stream`;
  * the graph must be preprocessed for a weighted logic. */

@@ -581,24 +581,30 @@ int fw_plan_profile(fw_graph *g, const fw_logic *lg, fw_plan *out, void *stream)
     HIP_TRY(hipSetDevice(g->device));
     hipStream_t s = (hipStream_t)stream;
 
-    // a fixed fraction of the non-isolated nodes, spread over the id range
-    std::vector<int64_t> rp((size_t)g->nv + 1);
-    HIP_TRY(hipMemcpy(rp.data(), g->row_ptr, sizeof(int64_t) * rp.size(), hipMemcpyDeviceToHost));
+    // up to 16384 non-isolated nodes spread over the id range: 32768 evenly spaced
+    // candidates (every vertex of a smaller graph), read on the device, keeping the
+    // non-isolated ones in id order
+    const int64_t ncand = std::min<int64_t>(g->nv, 32768);
+    if (ncand == 0) return ok();
+    const int64_t stride = std::max<int64_t>(1, g->nv / std::max<int64_t>(1, ncand));
+    std::vector<int2> cand((size_t)ncand);
+    {
+        DevBuf d_cand;
+        HIP_TRY(hipMalloc(&d_cand.p, sizeof(int2) * cand.size()));
+        HIP_TRY(fw::launch_profile_pick(g->row_ptr, stride, (int)ncand, (int2 *)d_cand.p, s));
+        HIP_TRY(hipMemcpyAsync(cand.data(), d_cand.p, sizeof(int2) * cand.size(), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     std::vector<int32_t> nodes;
-    int64_t nonempty = 0;
-    for (int64_t v = 0; v < g->nv; ++v) nonempty += rp[v + 1] > rp[v];
-    const int64_t want = std::min<int64_t>(nonempty, 16384);
-    const int64_t stride = want > 0 ? std::max<int64_t>(1, nonempty / want) : 1;
-    int64_t seen = 0;
-    for (int64_t v = 0; v < g->nv && (int64_t)nodes.size() < want; ++v)
-        if (rp[v + 1] > rp[v] && (seen++ % stride) == 0) nodes.push_back((int32_t)v);
-    if (nodes.empty()) return ok();
     const int per_rvs = 256, per_rjs = 64;
     double e_rvs = 0, e_rjs = 0;
-    for (int32_t v : nodes) {
-        e_rvs += (double)std::min<int64_t>(rp[v + 1] - rp[v], per_rvs);
+    for (const int2 &c : cand) {
+        if (c.y <= 0 || nodes.size() >= 16384) continue;
+        nodes.push_back(c.x);
+        e_rvs += (double)std::min<int32_t>(c.y, per_rvs);
         e_rjs += per_rjs;
     }
+    if (nodes.empty()) return ok();
 
     fw::WalkArgs a;
     fill_args(g, lg, a);

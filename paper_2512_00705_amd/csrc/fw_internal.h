@@ -175,6 +175,8 @@ hipError_t launch_validate_edges(const int64_t *row_ptr, const int32_t *col, con
                                  int *err, unsigned long long *max_deg, hipStream_t s);
 hipError_t launch_profile(const WalkArgs &a, int kind, bool weighted, bool rjs_style, const int32_t *nodes,
                           int nsample, int per_node, float *sink, hipStream_t s);
+// {vertex k * stride, its degree} for k < n (stride * (n - 1) < nv).
+hipError_t launch_profile_pick(const int64_t *row_ptr, int64_t stride, int n, int2 *out, hipStream_t s);
 int walk_grid(int kind, bool weighted, bool batch, int lds_cap, int64_t n);
 
 }  // namespace fw

@@ -1403,6 +1403,25 @@ __global__ void __launch_bounds__(kBlock) check_symmetry_kernel(const int64_t *r
     if (__ballot(bad) != 0 && lane == 0) atomicOr(err, 16);
 }
 
+// Candidate nodes for the profiling kernels: candidate k is vertex k * stride (k < n), reported
+// as {vertex, degree}.
+__global__ void __launch_bounds__(kBlock) profile_pick_kernel(const int64_t *row_ptr, int64_t stride, int n,
+                                                             int2 *out)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const int64_t v = (int64_t)k * stride;
+    out[k] = make_int2((int32_t)v, (int32_t)(row_ptr[v + 1] - row_ptr[v]));
+}
+
+hipError_t launch_profile_pick(const int64_t *row_ptr, int64_t stride, int n, int2 *out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(profile_pick_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                       row_ptr, stride, n, out);
+    return hipGetLastError();
+}
+
 // Profiling kernels (Section 5, "Flexi-Runtime Profiling Kernels"): evaluate workload
 // weights of sampled nodes either as eRVS does (a wave scanning a row, coalesced) or
 // as eRJS does (a lane proposing random neighbours).  Their time ratio per edge is the

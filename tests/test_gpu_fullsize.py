@@ -6,7 +6,8 @@ Scale-22 R-MAT (4.19M vertices, ~128M CSR entries, weights U(1,10), labels 0..4)
 * MetaPath schema (0,1,2,3,4) repeated, 1M uniform starts (seed 42), L=40.
 The oracle replays a seeded sample of walkers (same walker ids, so the same random
 streams; every walker for MetaPath) and every walk of the launch is checked to step along
-edges, to match the schema, and to pad with -1.
+edges, to match the schema, and to pad with -1.  Also at full size: 4096 batched queries
+on the skewed scale-24 graph, and the walk server on the labelled scale-25 graph.
 """
 from __future__ import annotations
 
@@ -252,5 +253,61 @@ def test_batched_scale24():
             ln = lengths[int(qd["len_off"][i]):int(qd["len_off"][i]) + n].cpu().numpy()
             ok, pad_ok, _ = edge_check_torch(g, p, ln)
             assert ok and pad_ok, i
+    finally:
+        gg.close()
+
+
+def test_served_scale25():
+    """The served configuration at full size: R-MAT scale 25 with labels (1.05 B entries,
+    rows up to 639,407), edge index and proposal records built, one plan tuned over the
+    served logic mix (Node2Vec p, q in {0.25, 0.5, 1, 2, 4}, MetaPath (0,1,2,3,4)), continuous
+    batching with 64-step ticks and a 32 GiB budget.  48 requests (start sets log-uniform in
+    1..4096, L in 10..100) arrive together; up to 64 walkers of every request are replayed
+    by the oracle."""
+    from tests._gpu import fw_plan
+    from tests.test_gpu_serve import _serve_all
+
+    print("generating R-MAT scale 25", flush=True)
+    g = synth.workload_graph("rmat25_labels")
+    print("uploading and building the edge index and proposal records", flush=True)
+    gg = GpuGraph(g, index=True, alias=True)
+    try:
+        pq = [0.25, 0.5, 1.0, 2.0, 4.0]
+        mix = [fw.fw_logic_node2vec(p, q, True) for p in pq for q in pq]
+        mix.append(fw.fw_logic_metapath([0, 1, 2, 3, 4], True))
+        tuned = fw.fw_plan_autotune_mix(gg.handle, mix)
+        pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap, bound=tuned.bound,
+                         proposal=tuned.proposal)
+        print("plan", tuned.rho, tuned.d_lo, tuned.lds_cap, tuned.bound, tuned.proposal, tuned.rjs_cap, flush=True)
+        rng = np.random.default_rng(25)
+        reqs = []
+        for i in range(48):
+            if i % 2 == 0:
+                lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=float(rng.choice(pq)), q=float(rng.choice(pq)))
+            else:
+                lg = oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(0, 1, 2, 3, 4))
+            n = int(np.clip(np.floor(np.exp(rng.uniform(0, np.log(4096)))), 1, 4096))
+            reqs.append((lg, rng.integers(0, g["nv"], n).astype(np.int32), int(rng.integers(10, 101)), 5000 + i))
+        srv = fw.fw_server_create(gg.handle, fw_plan(pl, lds_cap=tuned.lds_cap, grid=tuned.grid), fw.FW_AUTO,
+                                  32 << 30, tick_steps=64, max_active=8192, max_pending=1 << 16)
+        try:
+            print("serving", flush=True)
+            results = _serve_all(srv, reqs)
+            stats = fw.fw_server_stats(srv)
+        finally:
+            fw.fw_server_destroy(srv)
+        assert len(results) == len(reqs) and stats["finished"] == len(reqs) and stats["bytes_in_use"] == 0
+        print("oracle replay", flush=True)
+        og = oracle.Graph(g)
+        og.aux()
+        steps = 0
+        for k, (lg, st, L, seed) in enumerate(reqs):
+            p, ln, _ = results[k]
+            sub = np.arange(min(64, len(st)), dtype=np.int64)
+            ora = oracle.walk(og, lg, pl, oracle.AUTO, st[sub], L, seed, walker_ids=sub)
+            rep = parity(p[sub], ln[sub], ora)
+            assert_parity(rep)
+            steps += rep["steps"]
+        print("served scale 25: requests", len(reqs), "oracle steps", steps, stats, flush=True)
     finally:
         gg.close()
