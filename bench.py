@@ -229,6 +229,11 @@ def main():
     a0 = time.perf_counter()
     fw.fw_graph_build_alias(gh)
     alias_ms = (time.perf_counter() - a0) * 1e3
+    label_ms = 0.0
+    if args.logic == "metapath":  # label groups for label-conditioned proposals
+        a0 = time.perf_counter()
+        fw.fw_graph_build_label_alias(gh)
+        label_ms = (time.perf_counter() - a0) * 1e3
     if args.logic == "secondpr":
         logic = fw.fw_logic_second_pr(args.gamma, True)
         logic_text = f"second-order PageRank gamma={args.gamma}"
@@ -310,9 +315,12 @@ def main():
                 other = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap, bound=b,
                                            proposal=plan.proposal)
                 cases.append((("paper_bound", "split_bound", "member_board")[b], args.strategy, other))
-        flip = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap, bound=plan.bound,
-                                  proposal=1 - plan.proposal)
-        cases.append((("h" if flip.proposal else "uniform") + "_proposals", args.strategy, flip))
+        names = {0: "uniform_proposals", 1: "h_proposals", 2: "label_proposals"}
+        for pr in ([0, 1, 2] if args.logic == "metapath" else [0, 1]):
+            if pr != plan.proposal:
+                other = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap, bound=plan.bound,
+                                           proposal=pr)
+                cases.append((names[pr], args.strategy, other))
         paper = fw.fw_plan_default(rho=plan.rho, d_lo=plan.d_lo, lds_cap=plan.lds_cap)
         cases.append(("paper_eRJS", args.strategy, paper))  # uniform proposals, bound max(w) * h_MAX
         for name, m, pl in cases:
@@ -401,9 +409,9 @@ def main():
                                   else f"one walker per vertex ({nv})")
                                + f", L={L}, strategy={args.strategy}",
                    "walker_steps_per_walk_job": steps_per_walk, "preprocess_ms": prep_ms,
-                   "edge_index_ms": index_ms, "alias_build_ms": alias_ms,
+                   "edge_index_ms": index_ms, "alias_build_ms": alias_ms, "label_groups_build_ms": label_ms,
                    "autotune_ms": tune_ms, "profile_ms": profile_ms,
-                   "one_off_share": one_off_share(prep_ms, profile_ms, index_ms, alias_ms, tune_ms, avg_ms),
+                   "one_off_share": one_off_share(prep_ms, profile_ms, index_ms, alias_ms + label_ms, tune_ms, avg_ms),
                    "plan": plan_dict(plan), "plan_arg": plan_arg(plan),
                    "stats": st, "modes": modes,
                    "hbm_traffic_GBps": None if traffic is None else traffic["bytes"] / (avg_ms / 1e3) / 1e9,
@@ -614,6 +622,7 @@ def bench_served(args):
     fw.fw_graph_preprocess(gh)
     fw.fw_graph_build_index(gh)
     fw.fw_graph_build_alias(gh)
+    fw.fw_graph_build_label_alias(gh)
     # one plan for the server: tuned over every logic the requests may carry
     pq = np.array([0.25, 0.5, 1.0, 2.0, 4.0], np.float32)
     mix = [fw.fw_logic_node2vec(float(p), float(q), True) for p in pq for q in pq]

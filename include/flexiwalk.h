@@ -138,6 +138,13 @@ typedef struct fw_logic {
  *               expected trials drop from deg * B / S to W * h_SUM / S.  Applies to
  *               weighted logics; a row whose h are all zero goes to eRVS.  With
  *               bound = 1 the return edge's extra column is (1/p - W) * h(v, prev) wide.
+ *            2  as 1 for Node2Vec and second-order PageRank; MetaPath proposes from the
+ *               wanted label's group of the row through its own alias table
+ *               (fw_graph_build_label_alias; an extension of Section 3.3, not in the
+ *               paper): the MetaPath weight is h on the schema's label and 0 elsewhere,
+ *               so that proposal is the sample (one trial).  An empty group, or one whose
+ *               h are all 0, ends the walk.  The cost model weighs that one trial against
+ *               the eRVS scan: eRJS iff deg >= d_lo and rho < deg.
  *            The cost model compares rho * (board area) with deg * S^ for 1 (and bound 1). */
 typedef struct fw_plan {
     float rho;
@@ -210,6 +217,18 @@ int fw_graph_build_index(fw_graph *g, void *stream);
  * idempotent.  Walks, batches and servers created afterwards can use it. */
 int fw_graph_build_alias(fw_graph *g, void *stream);
 
+/* Label groups for label-conditioned MetaPath proposals (plan.proposal = 2): the entries
+ * of each row taken in (label, row position) order, so that the entries of label l form
+ * group (v, l), and one alias table per group over its h (the construction of
+ * fw_graph_build_alias, with the group's h maximum; 1 per entry on an unweighted graph).
+ * Device memory: a 64-byte record per entry in grouped order, as fw_graph_build_alias
+ * writes them (the alias field holds the slot within the group), and 8 bytes per (vertex,
+ * label) for the group starts; while building, 45 bytes per entry and 20 per (vertex,
+ * label) of scratch.  Needs edge labels, all below 16 (FW_E_INVALID otherwise; FW_E_STATE
+ * without labels).  Runs fw_graph_preprocess first if it has not run.  Synchronous;
+ * idempotent. */
+int fw_graph_build_label_alias(fw_graph *g, void *stream);
+
 /* Copy the alias tables behind the proposal records to the host (ne entries each, host
  * pointers): thr[k] = the keep threshold of slot k, alias[k] = the row offset of its alias.
  * For replaying the sample stream outside the library.  Synchronous; FW_E_STATE before
@@ -253,7 +272,8 @@ int fw_plan_profile(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stre
  * 16 steps, AUTO) are timed for rho scaled by 1/16 .. 4 around the profiled value (with
  * each eRJS bound: the split bound and the member board too for Node2Vec on a symmetric
  * graph, the member board for second-order PageRank; and each
- * proposal: h-proportional too for a weighted logic once fw_graph_build_alias ran), then for the
+ * proposal: h-proportional too for a weighted logic once fw_graph_build_alias ran, and
+ * label-conditioned for MetaPath once fw_graph_build_label_alias ran), then for the
  * degree gate d_lo in {0, 8, 32, 128}, the LDS budget for N(prev), the eRJS trial cap
  * rjs_cap in {16, 64, 256, 1024, 4096}, the eRVS lanes on long rows (hub_lanes 128 or
  * 256 from hub_deg 1024 or 8192; fw_plan_autotune only, never for a mix) and the

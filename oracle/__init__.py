@@ -44,7 +44,9 @@ COUNTER_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials
 class _Graph(ctypes.Structure):
     _fields_ = [("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("h", ctypes.c_void_p), ("label", ctypes.c_void_p),
-                ("alias_thr", ctypes.c_void_p), ("alias_idx", ctypes.c_void_p), ("h8", ctypes.c_int32)]
+                ("alias_thr", ctypes.c_void_p), ("alias_idx", ctypes.c_void_p), ("h8", ctypes.c_int32),
+                ("nlab", ctypes.c_int32), ("lrow", ctypes.c_void_p), ("lperm", ctypes.c_void_p),
+                ("lthr", ctypes.c_void_p), ("lalias", ctypes.c_void_p)]
 
 
 class _Logic(ctypes.Structure):
@@ -91,7 +93,8 @@ class Plan:
     jump: bool = True
     bound_scale: float = 1.0
     bound: int = 0  # 0: max(w) * h_MAX (Section 3.3); 1: Node2Vec split bound (return edge apart)
-    proposal: int = 0  # 0: uniform eRJS proposals (Section 3.3); 1: proportional to h (alias tables)
+    proposal: int = 0  # 0: uniform eRJS proposals (Section 3.3); 1: proportional to h (alias tables);
+    # 2: as 1, and MetaPath proposes within the wanted label's group (label_alias)
     hub_deg: int = 0  # eRVS rows of at least this degree use hub_lanes lanes (0: never)
     hub_lanes: int = 64
 
@@ -126,6 +129,8 @@ def _configure(lib):
     lib.og_dequantize_h8.restype = None
     lib.og_build_alias.argtypes = [ctypes.POINTER(_Graph), P, P]
     lib.og_build_alias.restype = None
+    lib.og_build_label_alias.argtypes = [ctypes.POINTER(_Graph), ctypes.c_int32, P, P, P, P]
+    lib.og_build_label_alias.restype = ctypes.c_int
     lib.og_preprocess.restype = None
     lib.og_walk.argtypes = [ctypes.POINTER(_Graph), P, P, ctypes.POINTER(_Logic), ctypes.POINTER(_Plan),
                             ctypes.c_int, P, P, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
@@ -195,6 +200,7 @@ class Graph:
         self._s = s
         self._aux = None
         self._alias = None
+        self._label_alias = None
 
     def aux(self):
         """(h_MAX, h_SUM) per node, computed by the oracle."""
@@ -215,6 +221,26 @@ class Graph:
             self._alias = (thr, idx)
             self._s.alias_thr, self._s.alias_idx = thr.ctypes.data, idx.ctypes.data
         return self._alias
+
+    def label_alias(self):
+        """(nlab, lrow, lperm, lthr, lalias): the label groups of each row and their alias
+        tables, used by label-conditioned MetaPath proposals (og_build_label_alias); nlab is
+        the largest label + 1."""
+        if self._label_alias is None:
+            assert self.label is not None, "label-conditioned proposals need edge labels"
+            nlab = int(self.label.max()) + 1 if self.ne > 0 else 1
+            lrow = np.empty(self.nv * nlab + 1, np.int64)
+            lperm = np.empty(max(self.ne, 1), np.int32)
+            lthr = np.empty(max(self.ne, 1), np.uint32)
+            lalias = np.empty(max(self.ne, 1), np.int32)
+            rc = _load().og_build_label_alias(ctypes.byref(self._s), nlab, lrow.ctypes.data, lperm.ctypes.data,
+                                              lthr.ctypes.data, lalias.ctypes.data)
+            assert rc == 0
+            self._label_alias = (nlab, lrow, lperm, lthr, lalias)
+            self._s.nlab = nlab
+            self._s.lrow, self._s.lperm = lrow.ctypes.data, lperm.ctypes.data
+            self._s.lthr, self._s.lalias = lthr.ctypes.data, lalias.ctypes.data
+        return self._label_alias
 
 
 def dequantize_h8(code, h_scale: float) -> np.ndarray:
@@ -247,6 +273,15 @@ class WalkResult:
     counters: dict = field(default_factory=dict)
 
 
+def _tables(graph: Graph, logic: Logic, plan: Plan):
+    """Build the proposal tables a plan reads: the alias tables for h-proportional
+    proposals, and the label groups for label-conditioned MetaPath proposals."""
+    if plan.proposal == 2 and logic.kind == METAPATH:
+        graph.label_alias()
+    elif plan.proposal:
+        graph.alias()
+
+
 def walk(graph: Graph, logic: Logic, plan: Plan, strategy: int, starts, L: int, seed: int,
          walker_ids=None, diagnostics: bool = True, nthreads: int = 0) -> WalkResult:
     """Free-running walks from ``starts`` (see ``og_walk`` in walk_oracle.c)."""
@@ -255,8 +290,7 @@ def walk(graph: Graph, logic: Logic, plan: Plan, strategy: int, starts, L: int, 
     n = starts.shape[0]
     wid = None if walker_ids is None else np.ascontiguousarray(walker_ids, np.int64)
     hmax, hsum = graph.aux()
-    if plan.proposal:
-        graph.alias()
+    _tables(graph, logic, plan)
     paths = np.empty((n, L + 1), np.int32)
     lengths = np.empty(n, np.int32)
     margins = np.empty((n, L), np.float32) if diagnostics else None
@@ -280,8 +314,7 @@ def step_info(graph: Graph, logic: Logic, plan: Plan, strategy: int, seed: int, 
     then eRVS, 3 ITS, -1 ended), its eRJS trials and its algorithmic bytes."""
     lib = _load()
     hmax, hsum = graph.aux()
-    if plan.proposal:
-        graph.alias()
+    _tables(graph, logic, plan)
     m = ctypes.c_float()
     k = ctypes.c_int32()
     t = ctypes.c_int32()

@@ -30,6 +30,11 @@
  *     w(u) / W for W >= every workload weight; the mass of u is then h * w / (W * sum h),
  *     proportional to w~, so the distribution is unchanged and the expected trials drop
  *     from deg * max(w) * h_MAX / S to W * sum h / S;
+ *   - optional label-conditioned proposals for MetaPath (plan.proposal = 2, not in the
+ *     paper; other logics take the h-proportional proposals above): a MetaPath weight is
+ *     h when the edge label is the schema's, else 0, so with an alias table per (vertex,
+ *     label) group of the static h one proposal from the wanted label's group is already
+ *     a sample of the step: eRJS with a bound that equals every weight, one trial;
  *   - optional member board (plan.bound = 2, not in the paper) for logics whose weight is
  *     larger on N(v') than off it (Node2Vec with q > 1, second-order PageRank with g > 0):
  *     regular columns at the lower weight w_oth take every proposal (members included),
@@ -66,7 +71,8 @@
  * table's alias (every slot keeps itself), 9 lets the member region keep a member without
  * its h(v, x) / h_MAX test, 10 averages the Node2Vec return values over 2 instead of their 3
  * branches in the sum estimate, 11 inverts the cost model's choice, 12 charges 8 bytes
- * instead of 16 for the row pointer pair of a step.
+ * instead of 16 for the row pointer pair of a step, 13 builds a label group's alias table
+ * from the whole row's h maximum and ignores the group's weights (uniform within the group).
  */
 #ifndef OG_MUTANT
 #define OG_MUTANT 0
@@ -139,6 +145,15 @@ typedef struct {
     const int32_t *alias_idx;  /* per entry: row offset of its alias */
     int32_t h8;                /* 1: h holds dequantised 8-bit codes (og_dequantize_h8); a scanned
                                   or proposed edge then moves 1 byte of weight instead of 4 */
+    /* label groups (og_build_label_alias), or NULL: nlab labels 0..nlab-1; lrow[v * nlab + l]
+       is the first position of group (v, l) in grouped order, lrow[nv * nlab] = ne; per
+       grouped position its row offset (lperm), keep-threshold (lthr) and alias slot within
+       the group (lalias) */
+    int32_t nlab;
+    const int64_t *lrow;
+    const int32_t *lperm;
+    const uint32_t *lthr;
+    const int32_t *lalias;
 } og_graph;
 
 enum { OG_NODE2VEC = 1, OG_METAPATH = 2, OG_SECOND_PR = 3 };
@@ -160,7 +175,8 @@ typedef struct {
     float bound_scale;   /* multiplies the eRJS bound (>= 1 keeps it a bound) */
     int32_t bound;       /* 0: max(w) * h_MAX (Section 3.3); 1: Node2Vec split bound; 2: split and
                             member board, the smaller per step */
-    int32_t proposal;    /* 0: uniform eRJS proposals (Section 3.3); 1: proportional to h */
+    int32_t proposal;    /* 0: uniform eRJS proposals (Section 3.3); 1: proportional to h; 2: as 1,
+                            and MetaPath proposes within the wanted label's group (og_build_label_alias) */
     int32_t hub_deg;     /* rows of at least this degree run eRVS with hub_lanes lanes (0: never) */
     int32_t hub_lanes;   /* P for those rows */
 } og_plan;
@@ -218,6 +234,51 @@ static uint32_t alias_threshold(uint64_t keep, uint64_t Q)
     return t >= 0xFFFFFFFFu ? 0xFFFFFFFFu : (uint32_t)t;
 }
 
+/* The sweep over one sequence of n >= 1 values h[0..n) (NULL: all 1) with maximum hmax:
+ * thr[k] and alias[k] (an index into the sequence) for each k. */
+static void alias_sweep(const float *h, int64_t n, float hmax, uint32_t *thr, int32_t *alias)
+{
+    uint64_t *a = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    uint64_t Q = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        const uint64_t q = (h && hmax > 0.0f) ? (uint64_t)floor(((double)h[k] / (double)hmax) * 4294967296.0)
+                                              : (uint64_t)1 << 32;
+        a[k] = q;
+        Q += q;
+    }
+    for (int64_t k = 0; k < n; ++k) a[k] *= (uint64_t)n;
+    int64_t j = 0;
+    while (a[j] < Q) ++j; /* the first heavy entry (one exists: the a_k sum to n * Q) */
+    uint64_t r = a[j];
+    for (int64_t i = 0; i < n; ++i) {
+        if (a[i] >= Q) continue; /* light entries only */
+        while (r < Q) { /* a later heavy entry exists: the residuals of the heavy
+                           entries cover every light entry's deficit exactly */
+            int64_t jn = j + 1;
+            while (jn < n - 1 && a[jn] < Q) ++jn;
+            thr[j] = alias_threshold(r, Q);
+            alias[j] = (int32_t)jn;
+            r = a[jn] - (Q - r);
+            j = jn;
+        }
+        thr[i] = alias_threshold(a[i], Q);
+        alias[i] = (int32_t)j;
+        r -= Q - a[i];
+    }
+    for (;;) { /* close the remaining heavy entries */
+        int64_t jn = j + 1;
+        while (jn < n && a[jn] < Q) ++jn;
+        thr[j] = alias_threshold(r, Q);
+        alias[j] = (int32_t)((r < Q && jn < n) ? jn : j);
+        if (jn >= n) break;
+        r = a[jn] - (Q - r);
+        j = jn;
+    }
+    if (OG_MUTANT == 8)
+        for (int64_t k = 0; k < n; ++k) thr[k] = 0xFFFFFFFFu;
+    free(a);
+}
+
 void og_build_alias(const og_graph *g, uint32_t *thr, int32_t *alias)
 {
     #pragma omp parallel for schedule(dynamic, 256)
@@ -227,48 +288,49 @@ void og_build_alias(const og_graph *g, uint32_t *thr, int32_t *alias)
         float hmax = 0.0f;
         for (int64_t k = 0; k < n; ++k)
             if (g->h && g->h[b + k] > hmax) hmax = g->h[b + k];
-        uint64_t *a = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
-        uint64_t Q = 0;
-        for (int64_t k = 0; k < n; ++k) {
-            const uint64_t q = (g->h && hmax > 0.0f) ? (uint64_t)floor(((double)g->h[b + k] / (double)hmax) * 4294967296.0)
-                                                      : (uint64_t)1 << 32;
-            a[k] = q;
-            Q += q;
-        }
-        for (int64_t k = 0; k < n; ++k) a[k] *= (uint64_t)n;
-        int64_t j = 0;
-        while (a[j] < Q) ++j; /* the first heavy entry (one exists: the a_k sum to n * Q) */
-        uint64_t r = a[j];
-        for (int64_t i = 0; i < n; ++i) {
-            if (a[i] >= Q) continue; /* light entries only */
-            while (r < Q) { /* a later heavy entry exists: the residuals of the heavy
-                               entries cover every light entry's deficit exactly */
-                int64_t jn = j + 1;
-                while (jn < n - 1 && a[jn] < Q) ++jn;
-                thr[b + j] = alias_threshold(r, Q);
-                alias[b + j] = (int32_t)jn;
-                r = a[jn] - (Q - r);
-                j = jn;
-            }
-            thr[b + i] = alias_threshold(a[i], Q);
-            alias[b + i] = (int32_t)j;
-            r -= Q - a[i];
-        }
-        for (;;) { /* close the remaining heavy entries */
-            int64_t jn = j + 1;
-            while (jn < n && a[jn] < Q) ++jn;
-            thr[b + j] = alias_threshold(r, Q);
-            alias[b + j] = (int32_t)((r < Q && jn < n) ? jn : j);
-            if (jn >= n) break;
-            r = a[jn] - (Q - r);
-            j = jn;
-        }
-        if (OG_MUTANT == 8)
-            for (int64_t k = 0; k < n; ++k) thr[b + k] = 0xFFFFFFFFu;
-        free(a);
+        alias_sweep(g->h ? g->h + b : NULL, n, hmax, thr + b, alias + b);
     }
 }
 
+/* Label groups for label-conditioned proposals (plan.proposal = 2, MetaPath; an extension,
+ * not in the paper).  Row v's entries are taken in (label, row position) order; the entries
+ * of label l form group (v, l), whose first grouped position is lrow[v * nlab + l] (so that
+ * lrow[v * nlab] = row_ptr[v] and lrow[nv * nlab] = ne).  lperm gives each grouped
+ * position's row offset, and each group gets the alias table of its own h values by the
+ * sweep above (its maximum as h_MAX; lalias indexes the group).  A MetaPath step that
+ * wants label l then proposes from group (v, l) alone: every proposal has the wanted label
+ * and probability h / (sum of h over the group), so one trial samples the step.  Returns
+ * -1 if a label is >= nlab. */
+int og_build_label_alias(const og_graph *g, int32_t nlab, int64_t *lrow, int32_t *lperm, uint32_t *lthr,
+                         int32_t *lalias)
+{
+    for (int64_t k = 0; k < g->ne; ++k)
+        if (g->label[k] >= nlab) return -1;
+    int bad = 0;
+    #pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t v = 0; v < g->nv; ++v) {
+        const int64_t b = g->row_ptr[v], n = g->row_ptr[v + 1] - b;
+        int64_t pos = b;
+        float *hg = (float *)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1));
+        for (int32_t l = 0; l < nlab; ++l) {
+            lrow[v * nlab + l] = pos;
+            const int64_t g0 = pos;
+            float hmax = 0.0f;
+            for (int64_t k = 0; k < n; ++k) {
+                if (g->label[b + k] != l) continue;
+                lperm[pos] = (int32_t)k;
+                hg[pos - g0] = g->h ? g->h[b + k] : 1.0f;
+                if (hg[pos - g0] > hmax) hmax = hg[pos - g0];
+                ++pos;
+            }
+            if (pos > g0) alias_sweep((g->h && OG_MUTANT != 13) ? hg : NULL, pos - g0, hmax, lthr + g0, lalias + g0);
+        }
+        if (pos != b + n) bad = 1;
+        free(hg);
+    }
+    lrow[g->nv * nlab] = g->ne;
+    return bad ? -1 : 0;
+}
 /* ------------------------------------------------------------------ one step */
 typedef struct {
     const og_graph *g;
@@ -620,11 +682,62 @@ int32_t og_step(const og_ctx *cx, uint32_t w, int j, int32_t prev, int32_t cur, 
 
     const int64_t dvp = j > 0 ? g->row_ptr[prev + 1] - g->row_ptr[prev] : 0; /* d(v') */
     const int weighted = lg->weighted && g->h;
+
+    /* label-conditioned proposals (plan.proposal = 2, MetaPath): the step's eRJS draws one
+       proposal from the group of the wanted label, which it always keeps; its eRJS cost is
+       one trial against deg for eRVS in Eq. (runtime).  A step whose group is empty, or
+       whose group has only zero weights, ends the walk (no neighbour has positive weight). */
+    if (lg->kind == OG_METAPATH && cx->pl->proposal == 2 && cx->strategy != OG_ITS) {
+        const int want = lg->schema[j % lg->schema_len];
+        info->bytes += 8.0; /* the group's first and last position */
+        const int64_t g0 = want < g->nlab ? g->lrow[cur * g->nlab + want] : 0;
+        const int64_t n = want < g->nlab ? g->lrow[cur * g->nlab + want + 1] - g0 : 0;
+        if (n == 0) return -1;
+        int use_rjs = 0;
+        if (cx->strategy == OG_RJS_ONLY) {
+            use_rjs = 1;
+        } else if (cx->strategy == OG_AUTO) {
+            if (deg >= cx->pl->d_lo) {
+                note_margin(info, cx->pl->rho, (float)deg);
+                use_rjs = cx->pl->rho < (float)deg; /* a tie goes to eRVS */
+            }
+        } else if (cx->strategy == OG_RANDOM_SELECT) {
+            uint32_t x[4];
+            draw(cx->seed, w, (uint32_t)j, 0, 4, x);
+            use_rjs = og_uniform(x[0]) < 0.5f;
+        } else if (cx->strategy == OG_DEGREE_SELECT) {
+            use_rjs = deg >= cx->pl->d_lo;
+        }
+        int64_t off;
+        if (use_rjs) {
+            uint32_t x[4];
+            draw(cx->seed, w, (uint32_t)j, 0, 0, x);
+            info->trials = 1;
+            const uint64_t R = ((uint64_t)x[1] << 32) | x[0];
+            const unsigned __int128 P = (unsigned __int128)R * (unsigned __int128)(uint64_t)n;
+            int64_t t = (int64_t)(P >> 64);
+            const uint32_t f = (uint32_t)((uint64_t)P >> 32);
+            if (!(f < g->lthr[g0 + t])) t = g->lalias[g0 + t];
+            off = g->lperm[g0 + t];
+            info->bytes += bytes_per_item(cx) + 12.0;
+            if (weighted && !(g->h[base + off] > 0.0f)) return -1; /* the group's weights are all 0 */
+            info->kind = 1;
+        } else {
+            info->kind = 0;
+            info->bytes += (double)deg * bytes_per_item(cx);
+            off = rvs_sample(cx, w, j, prev, base, deg, dvp, info);
+            if (off < 0) {
+                info->kind = -1;
+                return -1;
+            }
+        }
+        return g->col[base + off];
+    }
     const float hm = (weighted && OG_MUTANT != 5) ? cx->hmax[cur] : 1.0f;
     const float hs = weighted ? cx->hsum[cur] : (float)deg;
     /* h-proportional proposals: the eRJS test compares U * B with w (not w~), so B bounds
        the workload weights alone */
-    const int hprop = cx->pl->proposal == 1 && weighted;
+    const int hprop = cx->pl->proposal >= 1 && weighted;
     const float hB = hprop ? 1.0f : hm;
     float B = (w_max(lg, j, deg, dvp) * hB) * cx->pl->bound_scale; /* upper bound of max w~ (or w) */
     const float Shat = w_avg(lg, j, deg, dvp) * hs;                /* estimate of sum w~ */

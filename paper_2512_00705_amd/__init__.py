@@ -26,7 +26,7 @@ FW_NSTATS = 8
 STAT_NAMES = ("steps", "rjs_steps", "rvs_steps", "rjs_fallbacks", "rjs_trials", "rvs_triggers",
               "ended_early", "alg_bytes")
 EXPORTED = ("fw_graph_create", "fw_graph_destroy", "fw_graph_preprocess", "fw_graph_build_index",
-            "fw_graph_export_aux", "fw_graph_export_alias", "fw_graph_info", "fw_calibrate_random_reads", "fw_graph_build_alias",
+            "fw_graph_export_aux", "fw_graph_export_alias", "fw_graph_info", "fw_calibrate_random_reads", "fw_graph_build_alias", "fw_graph_build_label_alias",
             "fw_logic_node2vec", "fw_logic_metapath", "fw_logic_second_pr", "fw_plan_default", "fw_plan_profile",
             "fw_plan_autotune", "fw_plan_autotune_mix", "fw_walk", "fw_graph_check", "fw_last_error", "fw_batch_create", "fw_batch_launch",
             "fw_batch_capture", "fw_batch_replay", "fw_batch_destroy", "fw_batch_run_noalloc", "fw_server_create",
@@ -78,6 +78,7 @@ def _load():
         "fw_graph_preprocess": ([P, P], ctypes.c_int),
         "fw_graph_build_index": ([P, P], ctypes.c_int),
         "fw_graph_build_alias": ([P, P], ctypes.c_int),
+        "fw_graph_build_label_alias": ([P, P], ctypes.c_int),
         "fw_calibrate_random_reads": ([ctypes.c_int64, ctypes.POINTER(ctypes.c_double), P], ctypes.c_int),
         "fw_graph_export_aux": ([P, P, P], ctypes.c_int),
         "fw_graph_export_alias": ([P, P, P], ctypes.c_int),
@@ -173,6 +174,10 @@ def fw_graph_build_index(g: int, stream=None):
 
 def fw_graph_build_alias(g: int, stream=None):
     _check(_lib.fw_graph_build_alias(g, _stream(stream)))
+
+
+def fw_graph_build_label_alias(g: int, stream=None):
+    _check(_lib.fw_graph_build_label_alias(g, _stream(stream)))
 
 
 def fw_calibrate_random_reads(nbytes: int = 4 << 30, stream=None) -> float:

@@ -65,6 +65,8 @@ static void graph_free(fw_graph *g)
     (void)hipFree(g->scratch);
     (void)hipFree(g->mtab);
     (void)hipFree(g->prop);
+    (void)hipFree(g->lrow);
+    (void)hipFree(g->lprop);
     delete g;
 }
 
@@ -391,6 +393,9 @@ void fw::host::fill_args(const fw_graph *g, const fw_logic *lg, fw::WalkArgs &a)
     a.mtab = (const uint4 *)g->mtab;
     a.mtab_mask = g->mtab_mask;
     a.prop = g->prop;
+    a.lrow = g->lrow;
+    a.lprop = g->lprop;
+    a.nlab = g->nlab;
     fill_query(lg, a.q0);
     const bool weighted = lg->weighted && g->h;
     a.item_bytes = 4 + (weighted ? (g->q8 ? 1 : 4) : 0) + (lg->kind == FW_METAPATH ? 1 : 0);
@@ -406,7 +411,7 @@ int fw::host::check_plan(const fw_plan *pl)
         return fail(FW_E_INVALID, "plan.lds_cap in [0, %d]", fw::kMaxLdsCap);
     if (pl->grid < 0) return fail(FW_E_INVALID, "plan.grid must be >= 0");
     if (pl->bound < 0 || pl->bound > 2) return fail(FW_E_INVALID, "plan.bound must be 0, 1 or 2");
-    if (pl->proposal < 0 || pl->proposal > 1) return fail(FW_E_INVALID, "plan.proposal must be 0 or 1");
+    if (pl->proposal < 0 || pl->proposal > 2) return fail(FW_E_INVALID, "plan.proposal must be 0, 1 or 2");
     if (pl->hub_deg < 0) return fail(FW_E_INVALID, "plan.hub_deg must be >= 0");
     if (pl->hub_lanes != 64 && pl->hub_lanes != 128 && pl->hub_lanes != 256)
         return fail(FW_E_INVALID, "plan.hub_lanes must be 64, 128 or 256");
@@ -415,8 +420,11 @@ int fw::host::check_plan(const fw_plan *pl)
 
 int fw::host::check_bound(const fw_graph *g, const fw_plan *pl, const fw_logic *lg)
 {
-    if (pl->proposal == 1 && lg->weighted && g->h && !g->prop)
-        return fail(FW_E_STATE, "plan.proposal = 1 needs fw_graph_build_alias first");
+    const bool lab = pl->proposal == 2 && lg->kind == FW_METAPATH;
+    if (pl->proposal >= 1 && !lab && lg->weighted && g->h && !g->prop)
+        return fail(FW_E_STATE, "plan.proposal = %d needs fw_graph_build_alias first", (int)pl->proposal);
+    if (lab && !g->lprop)
+        return fail(FW_E_STATE, "plan.proposal = 2 with a MetaPath logic needs fw_graph_build_label_alias first");
     if (pl->bound >= 1 && lg->kind == FW_NODE2VEC && !g->symmetric)
         return fail(FW_E_INVALID, "plan.bound = %d needs every edge's reverse with the same h (fw_graph_info)",
                     (int)pl->bound);
@@ -530,7 +538,7 @@ int fw_graph_build_alias(fw_graph *g, void *stream)
     // out-of-range vertex
     hipError_t e = hipMemsetAsync(prop, 0, rec * ne, s);
     if (e == hipSuccess)
-        e = fw::launch_build_alias(g->row_ptr, g->col, g->h, g->label, g->nv, g->vrec, (uint4 *)val.p,
+        e = fw::launch_build_alias(g->row_ptr, g->col, g->h, g->label, g->nv, g->vrec, nullptr, (uint4 *)val.p,
                                           (int32_t *)idx.p, (ulonglong2 *)rowinfo.p, prop, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -538,6 +546,77 @@ int fw_graph_build_alias(fw_graph *g, void *stream)
         return fail(FW_E_DEVICE, "fw_graph_build_alias: %s", hipGetErrorString(e));
     }
     g->prop = prop;
+    return ok();
+}
+
+int fw_graph_build_label_alias(fw_graph *g, void *stream)
+{
+    if (!g) return fail(FW_E_INVALID, "fw_graph_build_label_alias: null graph");
+    if (!g->label) return fail(FW_E_STATE, "fw_graph_build_label_alias: the graph has no edge labels");
+    if (g->lprop) return ok();
+    HIP_TRY(hipSetDevice(g->device));
+    // the records carry the candidates' vertex records, h_MAX and h_SUM included
+    if (!g->prepped) {
+        const int rc = fw_graph_preprocess(g, stream);
+        if (rc != FW_OK) return rc;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    int mx = 0;
+    {
+        DevBuf d;
+        HIP_TRY(hipMalloc(&d.p, sizeof(int)));
+        HIP_TRY(hipMemsetAsync(d.p, 0, sizeof(int), s));
+        HIP_TRY(fw::launch_label_max(g->label, g->ne, (int *)d.p, s));
+        HIP_TRY(hipMemcpyAsync(&mx, d.p, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    const int nlab = mx + 1;
+    if (nlab > fw::kMaxLabels)
+        return fail(FW_E_INVALID, "fw_graph_build_label_alias: label %d; label groups take labels below %d", mx,
+                    fw::kMaxLabels);
+    const size_t ne = (size_t)(g->ne > 0 ? g->ne : 1);
+    const size_t ng = (size_t)g->nv * (size_t)nlab;  // groups
+    const size_t rec = 16 * (size_t)fw::kPropU4;
+    int64_t *lrow = nullptr;
+    uint4 *lprop = nullptr;
+    if (hipMalloc((void **)&lrow, sizeof(int64_t) * (ng + 1)) != hipSuccess) {
+        return fail(FW_E_NOMEM, "fw_graph_build_label_alias: hipMalloc of %zu bytes failed", 8 * (ng + 1));
+    }
+    if (hipMalloc((void **)&lprop, rec * ne) != hipSuccess) {
+        (void)hipFree(lrow);
+        return fail(FW_E_NOMEM, "fw_graph_build_label_alias: hipMalloc of %zu bytes failed", rec * ne);
+    }
+    DevBuf gmax, vcol, vh, vlab, val, idx, rowinfo;
+    const size_t ngr = ng > 0 ? ng : 1;
+    if (hipMalloc(&gmax.p, 4 * ngr) != hipSuccess || hipMalloc(&vcol.p, 4 * ne) != hipSuccess ||
+        (g->h && hipMalloc(&vh.p, 4 * ne) != hipSuccess) || hipMalloc(&vlab.p, ne) != hipSuccess ||
+        hipMalloc(&val.p, 16 * ne) != hipSuccess || hipMalloc(&idx.p, 4 * ne) != hipSuccess ||
+        hipMalloc(&rowinfo.p, 16 * ngr) != hipSuccess) {
+        (void)hipFree(lrow);
+        (void)hipFree(lprop);
+        return fail(FW_E_NOMEM, "fw_graph_build_label_alias: scratch of %zu bytes failed", 29 * ne + 20 * ngr);
+    }
+    const int64_t total = g->ne;
+    // every record is written by the build; zeroed first so that none can ever hold an
+    // out-of-range vertex
+    hipError_t e = hipMemsetAsync(lprop, 0, rec * ne, s);
+    if (e == hipSuccess)
+        e = fw::launch_label_groups(g->row_ptr, g->col, g->h, g->label, g->nv, nlab, lrow, (float *)gmax.p,
+                                    (int32_t *)vcol.p, (float *)vh.p, (uint8_t *)vlab.p, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(lrow + ng, &total, sizeof(int64_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = fw::launch_build_alias(lrow, (const int32_t *)vcol.p, (const float *)vh.p, (const uint8_t *)vlab.p,
+                                   (int64_t)ng, g->vrec, (const float *)gmax.p, (uint4 *)val.p, (int32_t *)idx.p,
+                                   (ulonglong2 *)rowinfo.p, lprop, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(lrow);
+        (void)hipFree(lprop);
+        return fail(FW_E_DEVICE, "fw_graph_build_label_alias: %s", hipGetErrorString(e));
+    }
+    g->lrow = lrow;
+    g->lprop = lprop;
+    g->nlab = nlab;
     return ok();
 }
 
@@ -747,20 +826,31 @@ int fw_plan_autotune_mix(fw_graph *g, const fw_logic *logics, int32_t n_logics, 
     int nbound = 1;
     if (any_n2v && g->symmetric) bounds[nbound++] = 1;
     if ((any_n2v && g->symmetric) || (any_pr && !any_n2v)) bounds[nbound++] = 2;
-    const int nprop = (any_weighted && g->h && g->prop) ? 2 : 1;
+    // proposals: uniform; h-proportional for a weighted logic once the records exist;
+    // label-conditioned for MetaPath once the label groups exist (the mix's other logics
+    // then take h-proportional proposals, whose records a weighted one needs)
+    bool any_mp = false, any_w_other = false;
+    for (int32_t i = 0; i < n_logics; ++i) {
+        any_mp = any_mp || logics[i].kind == FW_METAPATH;
+        any_w_other = any_w_other || (logics[i].kind != FW_METAPATH && logics[i].weighted);
+    }
+    int32_t props[3] = {0, 0, 0};
+    int nprop = 1;
+    if (any_weighted && g->h && g->prop) props[nprop++] = 1;
+    if (any_mp && g->lprop && (!any_w_other || !g->h || g->prop)) props[nprop++] = 2;
     // cost-model constant around the profiled value for each bound and proposal, then the
     // degree gate, the LDS budget for N(prev), the eRJS trial cap and the persistent grid
     fw_plan bestp = *out;
     float bestt = 1e30f;
     const float rho0 = out->rho;
     const float scales[] = {0.0625f, 0.25f, 0.5f, 1.0f, 2.0f, 4.0f};
-    for (int32_t prop = 0; prop < nprop; ++prop) {
+    for (int ip = 0; ip < nprop; ++ip) {
         for (int ib = 0; ib < nbound; ++ib) {
             for (float sc : scales) {
                 fw_plan p = *out;
                 p.rho = std::max(1e-3f, rho0 * sc);
                 p.bound = bounds[ib];
-                p.proposal = prop;
+                p.proposal = props[ip];
                 float t;
                 if ((rc = time_plan(p, &t)) != FW_OK) return rc;
                 if (t < bestt) bestt = t, bestp = p;

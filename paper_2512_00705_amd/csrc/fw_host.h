@@ -27,6 +27,9 @@ struct fw_graph {
     bool symmetric = false;                 // every (v, u) has a reverse (u, v) with equal h
     unsigned long long *mtab = nullptr;     // edge index: 128-byte buckets of 8 keys v << 32 | u and their h, or null
     uint4 *prop = nullptr;                  // h-proportional proposal records (kPropU4 uint4 per entry), or null
+    int64_t *lrow = nullptr;                // label groups: first grouped position of (v, l) at v * nlab + l, or null
+    uint4 *lprop = nullptr;                 // proposal records of the label groups (grouped order), or null
+    int32_t nlab = 0;                       // label groups exist for labels 0 .. nlab - 1
     uint64_t mtab_mask = 0;                 // buckets - 1
 };
 

@@ -128,7 +128,11 @@ struct WalkArgs {
     int32_t bound;              // 1: Node2Vec split eRJS bound (symmetric graphs only)
     const uint4 *mtab;          // edge index (8 uint4 per bucket) or null: search the sorted rows
     const uint4 *prop;          // proposal records (kPropU4 uint4 per entry) or null
-    int32_t proposal;           // 1: h-proportional eRJS proposals through `prop`
+    int32_t proposal;           // 1: h-proportional eRJS proposals through `prop`; 2: as 1, and
+                                // MetaPath proposes within the wanted label's group (`lprop`)
+    const int64_t *lrow;        // label groups: first grouped position of (v, l) at v * nlab + l
+    const uint4 *lprop;         // proposal records of the label groups (kPropU4 uint4 per entry)
+    int32_t nlab;               // labels 0 .. nlab - 1 have groups
     int32_t hub_deg;            // eRVS rows of at least this degree use hub_v * 64 lanes (0: never)
     int32_t hub_v;              // virtual lanes per lane there: 1, 2 or 4
     uint64_t mtab_mask;         // buckets - 1
@@ -153,9 +157,22 @@ hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv,
 // pass, one wave per row) written as prop[4k] = {col[k], h[k], col[a], h[a]},
 // prop[4k+1] = {threshold, lab[k] | lab[a] << 8, a, 0}, prop[4k+2..3] = vrec of col[k],
 // col[a].  Scratch: val (16 bytes) and idx (4 bytes) per entry, rowinfo (16 bytes) per row.
+// rmax: each row's h maximum, or null to take it from vrec[row] (rows are vertices).
 hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
-                              int64_t nv, const uint4 *vrec, uint4 *val, int32_t *idx, ulonglong2 *rowinfo,
-                              uint4 *prop, hipStream_t s);
+                              int64_t nv, const uint4 *vrec, const float *rmax, uint4 *val, int32_t *idx,
+                              ulonglong2 *rowinfo, uint4 *prop, hipStream_t s);
+// Labels of a graph with label groups: at most this many (0 .. kMaxLabels - 1).
+constexpr int kMaxLabels = 16;
+// *out = the largest of label[0 .. ne) (atomicMax into *out, which starts at 0).
+hipError_t launch_label_max(const uint8_t *label, int64_t ne, int *out, hipStream_t s);
+// Label groups of every row (nlab <= kMaxLabels labels, each below nlab): lrow[v * nlab + l]
+// = row_ptr[v] + the entries of row v with a smaller label, gmax[v * nlab + l] = the largest
+// h of group (v, l) (0 when empty; 1 when h is null), and the entries in grouped order:
+// vcol, vh (when h is non-null) and vlab at position lrow[v * nlab + l] + (rank among the
+// row's label-l entries).  lrow[nv * nlab] is not written.
+hipError_t launch_label_groups(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
+                               int64_t nv, int nlab, int64_t *lrow, float *gmax, int32_t *vcol, float *vh,
+                               uint8_t *vlab, hipStream_t s);
 // thr[k] = threshold and alias[k] = alias offset of proposal record k, for k < ne.
 hipError_t launch_export_alias(const uint4 *prop, int64_t ne, uint32_t *thr, int32_t *alias, hipStream_t s);
 // Edge index: inserts every entry (v, col[k]) of the rows with its h (1 when h is null) into

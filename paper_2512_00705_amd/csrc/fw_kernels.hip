@@ -615,6 +615,46 @@ walk_kernel(WalkArgs a)
                 if (deg == 0) {
                     nxt = -1;
                     mode = kAdv;
+                } else if (KIND == kMetaPath && a.proposal == 2) {
+                    // label-conditioned proposals: the wanted label's group of the row, whose
+                    // one proposal is the sample (an eRJS cost of one trial against deg for
+                    // eRVS in Eq. (runtime)); an empty group ends the walk
+                    const int32_t wl = (int32_t)Q.schema[j % Q.schema_len];
+                    int64_t g0 = 0, g1 = 0;
+                    if (wl < a.nlab) {
+                        g0 = a.lrow[(int64_t)cur * a.nlab + wl];
+                        g1 = a.lrow[(int64_t)cur * a.nlab + wl + 1];
+                    }
+                    st_bytes += 8;
+                    if (g1 == g0) {
+                        nxt = -1;
+                        mode = kAdv;
+                    } else {
+                        pbase = g0;  // MetaPath has no N(prev): these hold the group
+                        pdeg = (int32_t)(g1 - g0);
+                        bool rjs;
+                        if (a.strategy == kRjsOnly) {
+                            rjs = true;
+                        } else if (a.strategy == kRandomSelect) {
+                            const U4 x = philox((uint32_t)wid, (uint32_t)j, 0u, 4u, Q.key0, Q.key1);
+                            rjs = unit_uniform(x.x0) < 0.5f;
+                        } else if (a.strategy == kDegreeSelect) {
+                            rjs = deg >= a.d_lo;
+                        } else if (a.strategy == kRvsOnly) {
+                            rjs = false;
+                        } else {
+                            rjs = deg >= a.d_lo && a.rho < (float)deg;  // a tie goes to eRVS
+                        }
+                        fell_back = false;
+                        B = 1.0f;
+                        area = 1.0f;
+                        bE = 0.0f;
+                        bZ = 0.0f;
+                        mb = false;
+                        hmx = 1.0f;
+                        mode = rjs ? kRjs : kRvs;
+                        trials = 0;
+                    }
                 } else {
                     bool rjs = false;
                     fell_back = false;
@@ -714,7 +754,13 @@ walk_kernel(WalkArgs a)
             // member board: a trial in the member region proposes a neighbour x of prev
             // (the index draw over d(v')); the entry (cur, x) and its h come from the edge
             // index or a search of cur's row
-            const bool hprop = W && a.proposal != 0;
+            // label-conditioned proposals (MetaPath): pbase and pdeg hold the wanted label's
+            // group of the row; its records sit in lprop at their grouped positions
+            const bool lab = KIND == kMetaPath && a.proposal == 2;
+            const bool hprop = (W && a.proposal != 0) || lab;
+            const int64_t pb = lab ? pbase : base;
+            const int32_t pn = lab ? pdeg : deg;
+            const uint4 *precs = lab ? a.lprop : a.prop;
             const bool split = KIND == kNode2Vec && a.bound != 0 && j > 0;
             const float E = MB ? bE : (split ? fmaxf(0.0f, Q.inv_p * hlast - (hprop ? B * hlast : B)) : 0.0f);
             uint32_t ux[kRjsBatch];
@@ -728,9 +774,10 @@ walk_kernel(WalkArgs a)
             // h-proportional proposal whose test value lies below every weight the proposed
             // edge can have) makes the later proposals of the batch unnecessary: their draws
             // and loads are skipped (the decision loop stops at that trial)
-            const float wsure = (!uses_membership(KIND) || !hprop)
-                                    ? -1.0f
-                                    : (j == 0 ? 1.0f : fminf(sw.ret, (MB && mb) ? sw.oth : sw.lo));
+            const float wsure = lab ? INFINITY
+                                    : (!uses_membership(KIND) || !hprop)
+                                          ? -1.0f
+                                          : (j == 0 ? 1.0f : fminf(sw.ret, (MB && mb) ? sw.oth : sw.lo));
             bool sure = false;
             // the batch's first proposal (the one most often accepted) also copies its
             // two candidates' vertex records into this wave's LDS slots, in the same
@@ -750,7 +797,7 @@ walk_kernel(WalkArgs a)
                     continue;
                 }
                 const U4 x = philox((uint32_t)wid, (uint32_t)j, (uint32_t)(trials + r), 0u, k0, k1);
-                const int64_t k = base + scaled_index(x.x0, x.x1, deg);
+                const int64_t k = pb + scaled_index(x.x0, x.x1, pn);
                 const float z = unit_uniform(x.x3) * area;
                 ol[r] = E > 0.0f && z < E;
                 mr[r] = MB && uses_membership(KIND) && mb && !ol[r] && z < bZ;
@@ -763,8 +810,8 @@ walk_kernel(WalkArgs a)
                     ee[r] = make_uint2((uint32_t)a.col[pbase + scaled_index(x.x0, x.x1, pdeg)], 0u);
                     ll[r] = 0;
                 } else if (hprop) {
-                    const uint32_t f = scaled_fraction_hi(x.x0, x.x1, deg);
-                    const uint4 *rec = a.prop + kPropU4 * k;
+                    const uint32_t f = scaled_fraction_hi(x.x0, x.x1, pn);
+                    const uint4 *rec = precs + kPropU4 * k;
                     if (r == 0) {
                         __builtin_amdgcn_global_load_lds(rec + 2, lds_ptr(nvstage), 16, 0, 0);
                         __builtin_amdgcn_global_load_lds(rec + 3, lds_ptr(nvstage + kWave), 16, 0, 0);
@@ -772,7 +819,7 @@ walk_kernel(WalkArgs a)
                     }
                     const uint4 r0 = rec[0], r1 = rec[1];
                     const bool keep = f < r1.x;
-                    rsel[r] = ((uint32_t)(k - base) << 1) | (keep ? 0u : 1u);
+                    rsel[r] = ((uint32_t)(k - pb) << 1) | (keep ? 0u : 1u);
                     ee[r] = keep ? make_uint2(r0.x, r0.y) : make_uint2(r0.z, r0.w);
                     ll[r] = (KIND == kMetaPath) ? (uint8_t)(keep ? r1.y : r1.y >> 8) : (uint8_t)0;
                 } else {
@@ -849,6 +896,13 @@ walk_kernel(WalkArgs a)
                 if (STATS && !ol[0] && !mr[0])
                     st_bytes += (uint64_t)a.item_bytes + (hprop ? 12 : 0) +
                                 ((uses_membership(KIND) && j > 0 && !(MB && mb)) ? 4 * (uint64_t)probes(pdeg) : 0);
+                if (lab && !(hv > 0.0f)) {
+                    // a proposal of weight 0 from a label group: the group's weights are all
+                    // 0, so no neighbour has positive weight and the walk ends
+                    nxt = -1;
+                    mode = kAdv;
+                    break;
+                }
                 if (acc) {
                     nxt = u;
                     hnext = hsel;
@@ -856,7 +910,7 @@ walk_kernel(WalkArgs a)
                         // the record's line holds the accepted candidate's vertex record
                         nvrec = (r == 0 && nv0_ok)
                                     ? nvstage[(rsel[0] & 1u) * kWave + lane]
-                                    : a.prop[kPropU4 * (base + (int64_t)(rsel[0] >> 1)) + 2 + (rsel[0] & 1u)];
+                                    : precs[kPropU4 * (pb + (int64_t)(rsel[0] >> 1)) + 2 + (rsel[0] & 1u)];
                         have_nv = true;
                     }
                     mode = kAdv;
@@ -1193,8 +1247,8 @@ __device__ __forceinline__ uint32_t alias_thr(u128 keep, uint64_t Q)
 }
 
 __global__ void __launch_bounds__(kBlock) alias_scan_kernel(const int64_t *row_ptr, const float *h, int64_t nv,
-                                                            const uint4 *vrec, uint4 *val, int32_t *idx,
-                                                            ulonglong2 *rowinfo)
+                                                            const uint4 *vrec, const float *rmax, uint4 *val,
+                                                            int32_t *idx, ulonglong2 *rowinfo)
 {
     const int lane = lane_id();
     const uint64_t below = lanes_below(lane);
@@ -1203,7 +1257,7 @@ __global__ void __launch_bounds__(kBlock) alias_scan_kernel(const int64_t *row_p
         const int64_t b = row_ptr[v];
         const int64_t n = row_ptr[v + 1] - b;
         if (n == 0) continue;
-        const float hmax = __uint_as_float(vrec[v].z);
+        const float hmax = rmax ? rmax[v] : __uint_as_float(vrec[v].z);
         uint64_t qs = 0;
         for (int64_t k = lane; k < n; k += kWave) qs += alias_q(h, b + k, hmax);
         const uint64_t Q = wave_sum_u64(qs);
@@ -1276,8 +1330,9 @@ __device__ __forceinline__ void write_record(const int32_t *col, const float *h,
 
 __global__ void __launch_bounds__(kBlock) alias_merge_kernel(const int64_t *row_ptr, const int32_t *col,
                                                              const float *h, const uint8_t *label, int64_t nv,
-                                                             const uint4 *vrec, const uint4 *val, const int32_t *idx,
-                                                             const ulonglong2 *rowinfo, uint4 *prop)
+                                                             const uint4 *vrec, const float *rmax, const uint4 *val,
+                                                             const int32_t *idx, const ulonglong2 *rowinfo,
+                                                             uint4 *prop)
 {
     const int lane = lane_id();
     const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
@@ -1293,7 +1348,7 @@ __global__ void __launch_bounds__(kBlock) alias_merge_kernel(const int64_t *row_
                 write_record(col, h, label, vrec, b, (int32_t)k, (int32_t)k, 0xFFFFFFFFu, prop);
             continue;
         }
-        const float hmax = __uint_as_float(vrec[v].z);
+        const float hmax = rmax ? rmax[v] : __uint_as_float(vrec[v].z);
         // heavy entry j (in index order) sits at b + n - 1 - j
         const u128 e_last = load_u128(val + b + n - nh);
         // light entries: alias = the first heavy entry whose E reaches the entry's D
@@ -1652,18 +1707,115 @@ hipError_t launch_export_alias(const uint4 *prop, int64_t ne, uint32_t *thr, int
 }
 
 hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
-                              int64_t nv, const uint4 *vrec, uint4 *val, int32_t *idx, ulonglong2 *rowinfo,
-                              uint4 *prop, hipStream_t s)
+                              int64_t nv, const uint4 *vrec, const float *rmax, uint4 *val, int32_t *idx,
+                              ulonglong2 *rowinfo, uint4 *prop, hipStream_t s)
 {
     int64_t blocks = (nv + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(alias_scan_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, h, nv, vrec, val, idx,
-                       rowinfo);
+    hipLaunchKernelGGL(alias_scan_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, h, nv, vrec, rmax, val,
+                       idx, rowinfo);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(alias_merge_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, label, nv,
-                       vrec, val, idx, rowinfo, prop);
+                       vrec, rmax, val, idx, rowinfo, prop);
+    return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) label_max_kernel(const uint8_t *label, int64_t ne, int *out)
+{
+    int m = 0;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < ne; k += (int64_t)gridDim.x * 256)
+        m = max(m, (int)label[k]);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
+    if (lane_id() == 0 && m > 0) atomicMax(out, m);
+}
+
+hipError_t launch_label_max(const uint8_t *label, int64_t ne, int *out, hipStream_t s)
+{
+    if (ne <= 0) return hipSuccess;
+    int64_t blocks = (ne + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(label_max_kernel, dim3((unsigned)blocks), dim3(256), 0, s, label, ne, out);
+    return hipGetLastError();
+}
+
+// Label groups, one wave per row: pass 1 counts each label's entries and takes its h maximum
+// (a ballot and a wave maximum per label and 64-entry chunk), pass 2 scatters the entries in
+// row order to their group's next positions (rank = earlier entries of the same label).
+__global__ void __launch_bounds__(kBlock) label_group_kernel(const int64_t *row_ptr, const int32_t *col,
+                                                             const float *h, const uint8_t *label, int64_t nv,
+                                                             int nlab, int64_t *lrow, float *gmax, int32_t *vcol,
+                                                             float *vh, uint8_t *vlab)
+{
+    const int lane = lane_id();
+    const uint64_t below = lanes_below(lane);
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+    for (int64_t v = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; v < nv; v += nw) {
+        const int64_t b = row_ptr[v], n = row_ptr[v + 1] - b;
+        int64_t pos[kMaxLabels];
+        float mx[kMaxLabels];
+#pragma unroll
+        for (int l = 0; l < kMaxLabels; ++l) {
+            pos[l] = 0;
+            mx[l] = 0.0f;
+        }
+        for (int64_t k0 = 0; k0 < n; k0 += kWave) {
+            const int64_t k = k0 + lane;
+            const int lab = k < n ? (int)label[b + k] : -1;
+            const float hv = k < n ? (h ? h[b + k] : 1.0f) : 0.0f;
+#pragma unroll
+            for (int l = 0; l < kMaxLabels; ++l) {
+                if (l < nlab) {
+                    const uint64_t m = __ballot(lab == l);
+                    pos[l] += __popcll(m);
+                    if (m != 0) mx[l] = fmaxf(mx[l], wave_max(lab == l ? hv : 0.0f));
+                }
+            }
+        }
+        int64_t start = b;
+#pragma unroll
+        for (int l = 0; l < kMaxLabels; ++l) {
+            if (l < nlab) {
+                if (lane == 0) {
+                    lrow[v * nlab + l] = start;
+                    gmax[v * nlab + l] = mx[l];
+                }
+                const int64_t c = pos[l];
+                pos[l] = start;
+                start += c;
+            }
+        }
+        for (int64_t k0 = 0; k0 < n; k0 += kWave) {
+            const int64_t k = k0 + lane;
+            const int lab = k < n ? (int)label[b + k] : -1;
+#pragma unroll
+            for (int l = 0; l < kMaxLabels; ++l) {
+                if (l < nlab) {
+                    const uint64_t m = __ballot(lab == l);
+                    if (lab == l) {
+                        const int64_t p = pos[l] + __popcll(m & below);
+                        vcol[p] = col[b + k];
+                        if (vh) vh[p] = h[b + k];
+                        vlab[p] = (uint8_t)l;
+                    }
+                    pos[l] += __popcll(m);
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_label_groups(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
+                               int64_t nv, int nlab, int64_t *lrow, float *gmax, int32_t *vcol, float *vh,
+                               uint8_t *vlab, hipStream_t s)
+{
+    if (nv <= 0) return hipSuccess;
+    int64_t blocks = (nv + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(label_group_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, label, nv,
+                       nlab, lrow, gmax, vcol, vh, vlab);
     return hipGetLastError();
 }
 

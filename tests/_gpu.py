@@ -13,7 +13,7 @@ MARGIN = 1e-6  # a float decision within this relative gap is a flagged boundary
 
 class GpuGraph:
     def __init__(self, g: dict, on_device: bool = True, preprocess: bool = True, index: bool = False,
-                 alias: bool = False):
+                 alias: bool = False, label_alias: bool = False):
         self.g = g
         self.nv, self.ne = int(g["nv"]), int(g["ne"])
         dev = torch.device("cuda:0")
@@ -32,6 +32,8 @@ class GpuGraph:
             fw.fw_graph_build_index(self.handle)
         if alias:
             fw.fw_graph_build_alias(self.handle)
+        if label_alias:
+            fw.fw_graph_build_label_alias(self.handle)
         torch.cuda.synchronize()
 
     def close(self):

@@ -34,7 +34,7 @@ def g22():
 
 @pytest.fixture(scope="module")
 def gg22(g22):
-    gg = GpuGraph(g22, index=True, alias=True)  # as the benchmark runs it
+    gg = GpuGraph(g22, index=True, alias=True, label_alias=True)  # as the benchmark runs it
     yield gg
     gg.close()
 
@@ -178,9 +178,13 @@ def test_node2vec_scale22_h8(g22):
         gg.close()
 
 
-def test_metapath_scale22(g22, gg22, og22):
+@pytest.mark.parametrize("proposal", [None, 2], ids=["tuned", "label_groups"])
+def test_metapath_scale22(g22, gg22, og22, proposal):
+    """The MetaPath job at full size with the tuned plan, and with label-conditioned
+    proposals forced; every walker replayed by the oracle."""
     tuned = fw.fw_plan_autotune(gg22.handle, fw.fw_logic_metapath([0, 1, 2, 3, 4], True))
-    pl = oracle.Plan(rho=tuned.rho, rjs_cap=tuned.rjs_cap, hub_deg=tuned.hub_deg, hub_lanes=tuned.hub_lanes)
+    pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap, hub_deg=tuned.hub_deg,
+                     hub_lanes=tuned.hub_lanes, proposal=tuned.proposal if proposal is None else proposal)
     starts = synth.uniform_starts(g22["nv"], 1 << 20, 42)
     p, ln, st = gpu_walk(gg22, MP, pl, oracle.AUTO, starts, 40, 42)
     ok, pad_ok, (pos, taken) = edge_check_torch(g22, p, ln)
@@ -193,8 +197,10 @@ def test_metapath_scale22(g22, gg22, og22):
     # every walker of the job replayed by the oracle
     ora = oracle.walk(og22, MP, pl, oracle.AUTO, starts, 40, 42)
     rep = parity(p, ln, ora)
-    print("metapath22", {k2: (v if not isinstance(v, list) else len(v)) for k2, v in rep.items()}, st)
+    print("metapath22", pl, {k2: (v if not isinstance(v, list) else len(v)) for k2, v in rep.items()}, st)
     assert_parity(rep)
+    if pl.proposal == 2:
+        assert st["rjs_trials"] == st["rjs_steps"] > 0
 
 
 def test_batched_scale24():

@@ -430,6 +430,105 @@ def test_alias_tables_realise_h(weights):
             assert abs(got[k] - h[k] / H) <= Fraction(e - b + 2, 1 << 31), (v, k)
 
 
+def _labelled_rmat(scale, seed, weights="uniform"):
+    g = synth.rmat(scale, 8 << scale, seed=seed, nlabels=5)
+    if weights != "uniform":
+        g["h"] = synth.pareto_weights(g["row_ptr"], g["col"], float(weights[6:]), seed)
+    return g
+
+
+@pytest.mark.parametrize("weights", ["triangle", "uniform", "pareto1"])
+def test_label_groups_realise_h(weights):
+    """Label-conditioned proposals: group (v, l) holds exactly the entries of row v with
+    label l, in row order, starting where the groups of the smaller labels end; its alias
+    table draws each of them with probability h / (sum of h over the group), to within the
+    2^-32 granularity of the thresholds."""
+    g = triangle_graph(labels=True) if weights == "triangle" else _labelled_rmat(9, 3, weights)
+    og = oracle.Graph(g)
+    nlab, lrow, lperm, lthr, lalias = og.label_alias()
+    assert nlab == int(g["label"].max()) + 1 and lrow[g["nv"] * nlab] == g["ne"]
+    rows = range(g["nv"]) if g["nv"] <= 700 else np.random.default_rng(1).choice(g["nv"], 150, replace=False)
+    for v in rows:
+        b, e = int(g["row_ptr"][v]), int(g["row_ptr"][v + 1])
+        assert lrow[v * nlab] == b and lrow[(v + 1) * nlab] == e if v + 1 < g["nv"] else lrow[v * nlab] == b
+        for lab in range(nlab):
+            g0, g1 = int(lrow[v * nlab + lab]), int(lrow[v * nlab + lab + 1])
+            want = [k for k in range(e - b) if g["label"][b + k] == lab]
+            assert list(lperm[g0:g1]) == want, (v, lab)
+            if g1 == g0:
+                continue
+            n = g1 - g0
+            P = [Fraction(0)] * n
+            for t in range(n):
+                keep = Fraction(int(lthr[g0 + t]), 1 << 32)
+                P[t] += keep / n
+                P[int(lalias[g0 + t])] += (1 - keep) / n
+            assert sum(P) == 1
+            h = [Fraction(float(g["h"][b + k])) for k in want]
+            H = sum(h)
+            for t in range(n):
+                assert abs(P[t] - h[t] / H) <= Fraction(n + 2, 1 << 31), (v, lab, t)
+
+
+MP_L = dict(kind=oracle.METAPATH, weighted=True, schema=(0, 1, 2))
+MP_LAB = [("rjs", oracle.RJS_ONLY, oracle.Plan(proposal=2)),
+          ("auto", oracle.AUTO, oracle.Plan(proposal=2, rho=2.5, lanes=2)),
+          ("auto_dlo", oracle.AUTO, oracle.Plan(proposal=2, rho=0.5, d_lo=3, lanes=2)),
+          ("random", oracle.RANDOM_SELECT, oracle.Plan(proposal=2, lanes=2))]
+
+
+@pytest.mark.parametrize("name,strategy,plan", MP_LAB, ids=[s[0] for s in MP_LAB])
+def test_label_proposals_paths_chisquare(name, strategy, plan):
+    """MetaPath paths with label-conditioned proposals against the exact path
+    probabilities (triangle graph with labels, two starts, three steps)."""
+    g = triangle_graph(labels=True)
+    lg = oracle.Logic(**MP_L)
+    n = 60000
+    for start in (0, 4):
+        probs = exact.path_distribution(g, lg, start, 3)
+        assert_chisq(lambda s: chisq_pvalue(_walk_counts(g, lg, plan, strategy, start, 3, n, seed=s)[0], probs, n),
+                     13 + start, (name, start))
+
+
+def test_label_proposals_one_trial_and_valid_walks():
+    """Every eRJS step of a label-conditioned plan takes one trial; every step follows an
+    edge with the schema's label; a walk ends exactly where the current vertex has no
+    neighbour with the wanted label (all weights here are positive)."""
+    g = _labelled_rmat(10, 7)
+    og = oracle.Graph(g)
+    lg = oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(0, 1, 2, 3, 4))
+    starts = synth.uniform_starts(g["nv"], 3000, 5)
+    r = oracle.walk(og, lg, oracle.Plan(proposal=2, rho=4.0), oracle.AUTO, starts, 12, 9)
+    c = r.counters
+    assert c["rjs_steps"] > 0 and c["rvs_steps"] > 0  # rows below rho go to eRVS
+    assert c["rjs_trials"] == c["rjs_steps"] and c["rjs_fallbacks"] == 0
+    rp, col, lab = g["row_ptr"], g["col"], g["label"]
+    for p, n in zip(r.paths, r.lengths):
+        for j in range(n):
+            row = range(int(rp[p[j]]), int(rp[p[j] + 1]))
+            assert any(col[k] == p[j + 1] and lab[k] == j % 5 for k in row)
+        if n < 12:
+            assert not any(lab[k] == n % 5 for k in range(int(rp[p[n]]), int(rp[p[n] + 1])))
+
+
+def test_label_proposals_zero_weight_group_ends_walk():
+    """A group whose weights are all 0 holds no neighbour of positive weight: the walk ends
+    there, under the label-conditioned proposal as under eRVS and uniform eRJS."""
+    # vertex 0: label-0 neighbours 1, 2 with h = 0, a label-1 neighbour 3 with h = 5
+    g = synth.csr_from_edges(4, [(0, 1), (0, 2), (0, 3)], h=[0.0, 0.0, 5.0], label=[0, 0, 1])
+    og = oracle.Graph(g)
+    lg = oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(0, 1))
+    st = np.zeros(50, np.int32)
+    for strategy, plan in ((oracle.RJS_ONLY, oracle.Plan(proposal=2)), (oracle.RVS_ONLY, oracle.Plan(proposal=2)),
+                           (oracle.RJS_ONLY, oracle.Plan())):
+        r = oracle.walk(og, lg, plan, strategy, st, 3, 4)
+        assert (r.lengths == 0).all(), (strategy, plan.proposal)
+    lg1 = oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(1, 0))
+    r = oracle.walk(og, lg1, oracle.Plan(proposal=2), oracle.RJS_ONLY, st, 3, 4)
+    # the label-1 step goes to 3; 3's only edge (back to 0) has label 1, so the label-0 step ends
+    assert (r.paths[:, 1] == 3).all() and (r.lengths == 1).all()
+
+
 N2V_H = [("rjs", oracle.RJS_ONLY, oracle.Plan(proposal=1)),
          ("rjs_split", oracle.RJS_ONLY, oracle.Plan(proposal=1, bound=1)),
          ("auto_split", oracle.AUTO, oracle.Plan(proposal=1, bound=1, rho=1.0, lanes=2)),
@@ -786,6 +885,11 @@ def _pin_bytes():
     gmw = _directed(3, {0: [1, 2], 1: [2]}, h=2.0)
     pr1w = oracle.Logic(kind=oracle.SECOND_PR, weighted=True, gamma=1.0)
     assert b(pr1w, oracle.Plan(bound=2), oracle.RJS_ONLY, 1, 1, 0, oracle.Graph(gmw)) == 16 + 4 + (4 + 4 * 2 + 4)
+    # label-conditioned MetaPath proposal: the group's two positions (8 B), then one trial:
+    # col, h and label (9 B) and the alias slot's col, h and threshold (12 B)
+    gl = synth.csr_from_edges(3, [(0, 1), (0, 2)], h=[2.0, 3.0], label=[0, 1])
+    mpl = oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(1,))
+    assert b(mpl, oracle.Plan(proposal=2), oracle.RJS_ONLY, 0, -1, 0, oracle.Graph(gl)) == 16 + 8 + 9 + 12
     # a walk's own I/O: a start at an isolated vertex reads its row pointers and ends:
     # 4 (start) + 4 * (L + 1) (path row) + 4 (length) + 16
     r = oracle.walk(og, n2v, oracle.Plan(), oracle.AUTO, np.array([5], np.int32), 7, 1)
@@ -810,9 +914,14 @@ MUTANTS = {
     10: "sum estimate averages Node2Vec over 2 branches instead of 3",
     11: "cost model's choice inverted",
     12: "row pointer pair charged 8 bytes instead of 16",
+    13: "label groups proposed uniformly, ignoring h",
 }
 # planted mistakes caught by deterministic pins (hand-computed states), not by chi-square
-DETERMINISTIC_PINS = {10: "_pin_selector", 11: "_pin_selector", 12: "_pin_bytes"}
+DETERMINISTIC_PINS = {10: "_pin_selector", 11: "_pin_selector", 12: "_pin_bytes", 13: "_pin_label_groups"}
+
+
+def _pin_label_groups():
+    test_label_groups_realise_h("pareto1")
 
 
 @pytest.fixture(scope="module")
@@ -828,7 +937,7 @@ def test_planted_mistake_is_caught(mut, mutant_libs):
             with pytest.raises(AssertionError):
                 globals()[DETERMINISTIC_PINS[mut]]()
         return
-    g = triangle_graph()
+    g = triangle_graph(labels=True)
     caught = []
     with oracle.use_library(mutant_libs[mut]):
         for name, logic, strategy, plan in (("rvs_P2", N2V, oracle.RVS_ONLY, oracle.Plan(lanes=2)),
@@ -838,7 +947,8 @@ def test_planted_mistake_is_caught(mut, mutant_libs):
                                             ("rjs_2ndpr", PR2, oracle.RJS_ONLY, oracle.Plan()),
                                             ("rvs_2ndpr", PR2, oracle.RVS_ONLY, oracle.Plan(lanes=2)),
                                             ("rjs_hprop", N2V, oracle.RJS_ONLY, oracle.Plan(proposal=1)),
-                                            ("rjs_member", PR2, oracle.RJS_ONLY, oracle.Plan(bound=2))):
+                                            ("rjs_member", PR2, oracle.RJS_ONLY, oracle.Plan(bound=2)),
+                                            ("rjs_label", MP_L, oracle.RJS_ONLY, oracle.Plan(proposal=2))):
             lg = oracle.Logic(**logic)
             n = 60000
             counts, _ = _walk_counts(g, lg, plan, strategy, 0, 3, n, seed=7)
