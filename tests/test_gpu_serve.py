@@ -229,3 +229,37 @@ def test_h_proposals_served(g12, bound):
             assert_parity(parity(p, ln, oracle.walk(og, lg, pl, oracle.AUTO, st, L, seed)))
     finally:
         gg.close()
+
+
+@pytest.mark.parametrize("tick_steps", [3, 64])
+def test_label_proposals_served(g12, tick_steps):
+    """The served configuration's plan kind: label-conditioned proposals for MetaPath and
+    h-proportional ones for Node2Vec under the member board, requests suspended every few
+    steps; each result equals the same request run alone and the oracle's walks."""
+    gg = GpuGraph(g12, alias=True, label_alias=True)
+    pl = oracle.Plan(rho=1.0, rjs_cap=64, bound=2, proposal=2)
+    rng = np.random.default_rng(40 + tick_steps)
+    reqs = []
+    for i in range(16):
+        if i % 2:
+            lg = oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(0, 1, 2, 3, 4))
+        else:
+            lg = oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=float(rng.choice([0.25, 2.0])), q=2.0)
+        reqs.append((lg, rng.integers(0, g12["nv"], int(rng.integers(1, 300))).astype(np.int32),
+                     int(rng.integers(1, 40)), 900 + i))
+    try:
+        srv = fw.fw_server_create(gg.handle, fw.fw_plan_default(rho=pl.rho, rjs_cap=pl.rjs_cap, bound=2, proposal=2),
+                                  fw.FW_AUTO, 64 << 20, tick_steps=tick_steps, max_active=8)
+        try:
+            results = _serve_all(srv, reqs)
+        finally:
+            fw.fw_server_destroy(srv)
+        og = oracle.Graph(g12)
+        for k, (lg, st, L, seed) in enumerate(reqs):
+            p, ln, _ = results[k]
+            alone = gpu_walk(gg, lg, pl, oracle.AUTO, st, L, seed)
+            np.testing.assert_array_equal(p, alone[0], err_msg=f"request {k}")
+            np.testing.assert_array_equal(ln, alone[1], err_msg=f"request {k}")
+            assert_parity(parity(p, ln, oracle.walk(og, lg, pl, oracle.AUTO, st, L, seed)))
+    finally:
+        gg.close()
