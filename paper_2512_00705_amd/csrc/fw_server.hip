@@ -7,7 +7,10 @@
 // requests (results copied to host memory, device block freed) and admits waiting ones in
 // arrival order while their device block fits the HBM budget.  A request that arrives
 // while others run therefore joins at the next tick and shares every later launch with
-// them.  Walker i of a request draws from the request's seed with Philox counter
+// them.  The results of the requests that finished in a tick are copied out while the
+// next tick runs (a copy stream beside the launch stream; the finished requests' blocks
+// are no longer touched by later launches and are freed once copied).  Walker i of a
+// request draws from the request's seed with Philox counter
 // (i, step, draw, tag), so its result is the same alone, in any mix and for any tick
 // length.
 #include <stdarg.h>
@@ -127,19 +130,22 @@ struct fw_server {
     size_t budget = 0;
     char *arena_base = nullptr;
     Arena arena;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;              // launches, uploads, the done counters
+    hipStream_t cstream = nullptr;             // result copies, beside the next tick
+    hipEvent_t ev_tick = nullptr;              // a tick's launches and done-counter copy are complete
     int32_t *d_done = nullptr;                 // finished walkers per slot
     fw::QueryDev *d_table = nullptr;           // kGroups groups x max_active entries
     fw::QueryDev *h_table = nullptr;           // pinned staging of the same
     unsigned long long *d_queue = nullptr;     // one walker counter per group
     unsigned long long *d_stats = nullptr;     // FW_NSTATS counters
-    std::vector<int32_t> h_done;
+    int32_t *h_done = nullptr;                 // pinned copy of d_done after each tick
     std::vector<int32_t> free_slots;
 
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Request *> waiting;
     std::vector<Request *> active;             // touched by the server thread only
+    std::vector<Request *> done_tick;          // finished in the last tick, results not yet copied (server thread)
     std::deque<uint64_t> finished;
     std::unordered_map<uint64_t, Request *> reqs;
     uint64_t next_id = 1;
@@ -212,7 +218,8 @@ int admit(fw_server *s, std::vector<Request *> &picked)
     return FW_OK;
 }
 
-// One tick: a batched launch per group of admitted requests.
+// One tick: a batched launch per group of admitted requests, then the done counters' copy
+// and an event (nothing waits here; tick_wait does).
 int tick(fw_server *s)
 {
     for (int grp = 0; grp < kGroups; ++grp) {
@@ -257,43 +264,56 @@ int tick(fw_server *s)
         SRV_TRY(fw::launch_zero(s->d_queue + grp, 1, s->stream));
         SRV_TRY(fw::launch_walk(a, kind, weighted, true, grid, s->stream));
     }
-    SRV_TRY(hipMemcpyAsync(s->h_done.data(), s->d_done, sizeof(int32_t) * s->h_done.size(), hipMemcpyDeviceToHost,
+    SRV_TRY(hipMemcpyAsync(s->h_done, s->d_done, sizeof(int32_t) * (size_t)s->max_active, hipMemcpyDeviceToHost,
                            s->stream));
-    SRV_TRY(hipStreamSynchronize(s->stream));
-    s->ticks++;
+    SRV_TRY(hipEventRecord(s->ev_tick, s->stream));
     return FW_OK;
 }
 
-// Copy out and release requests whose walkers all finished.
-int retire(fw_server *s)
+// Wait for the tick, then move the requests whose walkers all finished from `active` to
+// `done_tick` (their results are copied out by retire, beside the next tick).
+int tick_wait(fw_server *s)
 {
+    SRV_TRY(hipEventSynchronize(s->ev_tick));
+    s->ticks++;
     std::vector<Request *> still;
     for (Request *r : s->active) {
-        if (s->h_done[(size_t)r->slot] < r->n) {
-            still.push_back(r);
-            continue;
-        }
+        if (s->h_done[(size_t)r->slot] < r->n) still.push_back(r);
+        else s->done_tick.push_back(r);
+    }
+    s->active.swap(still);
+    return FW_OK;
+}
+
+// Copy out and release the requests of `done_tick`.
+int retire(fw_server *s)
+{
+    if (s->done_tick.empty()) return FW_OK;
+    for (Request *r : s->done_tick) {
         r->paths.resize((size_t)r->n * ((size_t)r->L + 1));
         r->lengths.resize((size_t)r->n);
         if (r->n > 0) {
             SRV_TRY(hipMemcpyAsync(r->paths.data(), s->arena_base + r->o_paths, sizeof(int32_t) * r->paths.size(),
-                                   hipMemcpyDeviceToHost, s->stream));
+                                   hipMemcpyDeviceToHost, s->cstream));
             SRV_TRY(hipMemcpyAsync(r->lengths.data(), s->arena_base + r->o_len, sizeof(int32_t) * r->lengths.size(),
-                                   hipMemcpyDeviceToHost, s->stream));
+                                   hipMemcpyDeviceToHost, s->cstream));
         }
-        SRV_TRY(hipStreamSynchronize(s->stream));
-        std::lock_guard<std::mutex> lk(s->mu);
+    }
+    SRV_TRY(hipStreamSynchronize(s->cstream));
+    std::lock_guard<std::mutex> lk(s->mu);
+    const auto now = Clock::now();
+    for (Request *r : s->done_tick) {
         s->arena.release(r->off, r->bytes);
         s->free_slots.push_back(r->slot);
         r->slot = -1;
         r->state = 2;
-        r->t_done = Clock::now();
+        r->t_done = now;
         std::vector<int32_t>().swap(r->starts);
         s->finished.push_back(r->id);
         s->n_finished++;
-        s->cv_done.notify_all();
     }
-    s->active.swap(still);
+    s->done_tick.clear();
+    s->cv_done.notify_all();
     return FW_OK;
 }
 
@@ -309,14 +329,17 @@ void serve(fw_server *s)
             std::unique_lock<std::mutex> lk(s->mu);
             if (s->stop || s->err != FW_OK) break;
             pick(s, picked);
-            if (s->active.empty() && picked.empty()) {
+            if (s->active.empty() && picked.empty() && s->done_tick.empty()) {
                 s->cv_work.wait(lk, [s] { return s->stop || !s->waiting.empty(); });
                 continue;
             }
         }
         if (admit(s, picked) != FW_OK) break;
-        if (tick(s) != FW_OK) break;
+        const bool launched = !s->active.empty();
+        if (launched && tick(s) != FW_OK) break;
+        // the last tick's finished requests are copied out while this one runs
         if (retire(s) != FW_OK) break;
+        if (launched && tick_wait(s) != FW_OK) break;
     }
 }
 
@@ -325,6 +348,9 @@ void server_free(fw_server *s)
     if (!s) return;
     for (auto &kv : s->reqs) delete kv.second;
     if (s->stream) (void)hipStreamDestroy(s->stream);
+    if (s->cstream) (void)hipStreamDestroy(s->cstream);
+    if (s->ev_tick) (void)hipEventDestroy(s->ev_tick);
+    if (s->h_done) (void)hipHostFree(s->h_done);
     (void)hipFree(s->arena_base);
     (void)hipFree(s->d_done);
     (void)hipFree(s->d_table);
@@ -364,7 +390,6 @@ int fw_server_create(fw_graph *g, const fw_plan *plan, int32_t strategy, uint64_
     s->max_active = max_active;
     s->max_pending = max_pending;
     s->budget = (size_t)hbm_budget;
-    s->h_done.assign((size_t)max_active, 0);
     for (int32_t i = max_active - 1; i >= 0; --i) s->free_slots.push_back(i);
     if (hipMalloc((void **)&s->arena_base, s->budget) != hipSuccess ||
         hipMalloc((void **)&s->d_done, sizeof(int32_t) * (size_t)max_active) != hipSuccess ||
@@ -372,12 +397,15 @@ int fw_server_create(fw_graph *g, const fw_plan *plan, int32_t strategy, uint64_
         hipMalloc((void **)&s->d_queue, kGroups * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void **)&s->d_stats, FW_NSTATS * sizeof(unsigned long long)) != hipSuccess ||
         hipHostMalloc((void **)&s->h_table, sizeof(fw::QueryDev) * kGroups * (size_t)max_active, hipHostMallocDefault) !=
-            hipSuccess) {
+            hipSuccess ||
+        hipHostMalloc((void **)&s->h_done, sizeof(int32_t) * (size_t)max_active, hipHostMallocDefault) != hipSuccess) {
         server_free(s);
         return fail(FW_E_NOMEM, "fw_server_create: allocation failed");
     }
     s->arena.reset(s->budget);
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&s->cstream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&s->ev_tick, hipEventDisableTiming) != hipSuccess ||
         hipMemset(s->d_stats, 0, FW_NSTATS * sizeof(unsigned long long)) != hipSuccess ||
         hipMemset(s->d_done, 0, sizeof(int32_t) * (size_t)max_active) != hipSuccess) {
         server_free(s);
@@ -486,6 +514,7 @@ int fw_server_destroy(fw_server *s)
     }
     if (s->th.joinable()) s->th.join();
     (void)hipStreamSynchronize(s->stream);
+    (void)hipStreamSynchronize(s->cstream);
     server_free(s);
     return fw::host::ok();
 }
