@@ -526,12 +526,13 @@ int fw_graph_build_alias(fw_graph *g, void *stream)
     uint4 *prop = nullptr;
     if (hipMalloc((void **)&prop, rec * ne) != hipSuccess)
         return fail(FW_E_NOMEM, "fw_graph_build_alias: hipMalloc of %zu bytes failed", rec * ne);
-    DevBuf val, idx, rowinfo;
+    DevBuf val, idx, rowinfo, hubs, nhub;
     const size_t nv = (size_t)(g->nv > 0 ? g->nv : 1);
     if (hipMalloc(&val.p, 16 * ne) != hipSuccess || hipMalloc(&idx.p, 4 * ne) != hipSuccess ||
-        hipMalloc(&rowinfo.p, 16 * nv) != hipSuccess) {
+        hipMalloc(&rowinfo.p, 16 * nv) != hipSuccess || hipMalloc(&hubs.p, 4 * nv) != hipSuccess ||
+        hipMalloc(&nhub.p, sizeof(int)) != hipSuccess) {
         (void)hipFree(prop);
-        return fail(FW_E_NOMEM, "fw_graph_build_alias: scratch of %zu bytes failed", 20 * ne + 16 * nv);
+        return fail(FW_E_NOMEM, "fw_graph_build_alias: scratch of %zu bytes failed", 20 * ne + 20 * nv);
     }
     hipStream_t s = (hipStream_t)stream;
     // every record is written by the build; zeroed first so that none can ever hold an
@@ -539,7 +540,8 @@ int fw_graph_build_alias(fw_graph *g, void *stream)
     hipError_t e = hipMemsetAsync(prop, 0, rec * ne, s);
     if (e == hipSuccess)
         e = fw::launch_build_alias(g->row_ptr, g->col, g->h, g->label, g->nv, g->vrec, nullptr, (uint4 *)val.p,
-                                          (int32_t *)idx.p, (ulonglong2 *)rowinfo.p, prop, s);
+                                   (int32_t *)idx.p, (ulonglong2 *)rowinfo.p, (int32_t *)hubs.p, (int *)nhub.p, prop,
+                                   s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(prop);
@@ -586,15 +588,16 @@ int fw_graph_build_label_alias(fw_graph *g, void *stream)
         (void)hipFree(lrow);
         return fail(FW_E_NOMEM, "fw_graph_build_label_alias: hipMalloc of %zu bytes failed", rec * ne);
     }
-    DevBuf gmax, vcol, vh, vlab, val, idx, rowinfo;
+    DevBuf gmax, vcol, vh, vlab, val, idx, rowinfo, hubs, nhub;
     const size_t ngr = ng > 0 ? ng : 1;
     if (hipMalloc(&gmax.p, 4 * ngr) != hipSuccess || hipMalloc(&vcol.p, 4 * ne) != hipSuccess ||
         (g->h && hipMalloc(&vh.p, 4 * ne) != hipSuccess) || hipMalloc(&vlab.p, ne) != hipSuccess ||
         hipMalloc(&val.p, 16 * ne) != hipSuccess || hipMalloc(&idx.p, 4 * ne) != hipSuccess ||
-        hipMalloc(&rowinfo.p, 16 * ngr) != hipSuccess) {
+        hipMalloc(&rowinfo.p, 16 * ngr) != hipSuccess || hipMalloc(&hubs.p, 4 * ngr) != hipSuccess ||
+        hipMalloc(&nhub.p, sizeof(int)) != hipSuccess) {
         (void)hipFree(lrow);
         (void)hipFree(lprop);
-        return fail(FW_E_NOMEM, "fw_graph_build_label_alias: scratch of %zu bytes failed", 29 * ne + 20 * ngr);
+        return fail(FW_E_NOMEM, "fw_graph_build_label_alias: scratch of %zu bytes failed", 29 * ne + 24 * ngr);
     }
     const int64_t total = g->ne;
     // every record is written by the build; zeroed first so that none can ever hold an
@@ -607,7 +610,7 @@ int fw_graph_build_label_alias(fw_graph *g, void *stream)
     if (e == hipSuccess)
         e = fw::launch_build_alias(lrow, (const int32_t *)vcol.p, (const float *)vh.p, (const uint8_t *)vlab.p,
                                    (int64_t)ng, g->vrec, (const float *)gmax.p, (uint4 *)val.p, (int32_t *)idx.p,
-                                   (ulonglong2 *)rowinfo.p, lprop, s);
+                                   (ulonglong2 *)rowinfo.p, (int32_t *)hubs.p, (int *)nhub.p, lprop, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         (void)hipFree(lrow);

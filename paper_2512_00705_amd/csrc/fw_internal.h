@@ -158,9 +158,11 @@ hipError_t launch_preprocess(const int64_t *row_ptr, const float *h, int64_t nv,
 // prop[4k+1] = {threshold, lab[k] | lab[a] << 8, a, 0}, prop[4k+2..3] = vrec of col[k],
 // col[a].  Scratch: val (16 bytes) and idx (4 bytes) per entry, rowinfo (16 bytes) per row.
 // rmax: each row's h maximum, or null to take it from vrec[row] (rows are vertices).
+// Rows longer than 8192 entries are merged one thread per entry (hubs: nv int32 of
+// scratch, nhub: one int).
 hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
                               int64_t nv, const uint4 *vrec, const float *rmax, uint4 *val, int32_t *idx,
-                              ulonglong2 *rowinfo, uint4 *prop, hipStream_t s);
+                              ulonglong2 *rowinfo, int32_t *hubs, int *nhub, uint4 *prop, hipStream_t s);
 // Labels of a graph with label groups: at most this many (0 .. kMaxLabels - 1).
 constexpr int kMaxLabels = 16;
 // *out = the largest of label[0 .. ne) (atomicMax into *out, which starts at 0).

@@ -1206,31 +1206,63 @@ __global__ void __launch_bounds__(kBlock) validate_edges_kernel(const int64_t *r
 //   {col_k, bits(h_k), col_a, bits(h_a)}, {threshold, label_k | label_a << 8, a, 0},
 //   vrec[col_k], vrec[col_a]   (a: the alias's offset in the row).
 using u128 = unsigned __int128;
-constexpr u128 kU128Max = ~(u128)0;
 
-__device__ __forceinline__ u128 shfl_u128(u128 x, int src)
+// The sums of a row of n entries stay below n * Q <= n^2 * 2^32 (every q_k <= 2^32): 64 bits
+// hold them for rows of at most 2^15 entries, which take the 64-bit path (half the lane
+// exchanges of the 128-bit one).
+constexpr int64_t kAlias64Max = (int64_t)1 << 15;
+// Rows longer than this are merged by alias_hub_kernel, many waves per row.
+constexpr int64_t kAliasHubRow = 8192;
+
+template <typename T>
+__device__ __forceinline__ T shfl_t(T x, int src)
 {
-    const uint64_t lo = (uint64_t)__shfl((long long)(uint64_t)x, src, kWave);
-    const uint64_t hi = (uint64_t)__shfl((long long)(uint64_t)(x >> 64), src, kWave);
-    return ((u128)hi << 64) | lo;
+    if constexpr (sizeof(T) == 8) {
+        return (T)__shfl((long long)x, src, kWave);
+    } else {
+        const uint64_t lo = (uint64_t)__shfl((long long)(uint64_t)x, src, kWave);
+        const uint64_t hi = (uint64_t)__shfl((long long)(uint64_t)(x >> 64), src, kWave);
+        return ((u128)hi << 64) | lo;
+    }
 }
 
-__device__ __forceinline__ u128 shfl_up_u128(u128 x, int d)
+template <typename T>
+__device__ __forceinline__ T shfl_up_t(T x, int d)
 {
-    const uint64_t lo = (uint64_t)__shfl_up((long long)(uint64_t)x, d, kWave);
-    const uint64_t hi = (uint64_t)__shfl_up((long long)(uint64_t)(x >> 64), d, kWave);
-    return ((u128)hi << 64) | lo;
+    if constexpr (sizeof(T) == 8) {
+        return (T)__shfl_up((long long)x, d, kWave);
+    } else {
+        const uint64_t lo = (uint64_t)__shfl_up((long long)(uint64_t)x, d, kWave);
+        const uint64_t hi = (uint64_t)__shfl_up((long long)(uint64_t)(x >> 64), d, kWave);
+        return ((u128)hi << 64) | lo;
+    }
 }
 
-__device__ __forceinline__ u128 wave_incl_scan_u128(u128 x)
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan_t(T x)
 {
     const int lane = lane_id();
 #pragma unroll
     for (int d = 1; d < kWave; d <<= 1) {
-        const u128 y = shfl_up_u128(x, d);
+        const T y = shfl_up_t(x, d);
         if (lane >= d) x += y;
     }
     return x;
+}
+
+// A sum as stored in `val` (16 bytes, zero-extended from 64 bits).
+template <typename T>
+__device__ __forceinline__ T load_t(const uint4 *p)
+{
+    const uint4 x = *p;
+    if constexpr (sizeof(T) == 8) return ((uint64_t)x.y << 32) | (uint64_t)x.x;
+    else return ((u128)x.w << 96) | ((u128)x.z << 64) | ((u128)x.y << 32) | (u128)x.x;
+}
+
+template <typename T>
+__device__ __forceinline__ uint4 pack_t(T x)
+{
+    return make_uint4((uint32_t)x, (uint32_t)((uint64_t)x >> 32), (uint32_t)((u128)x >> 64), (uint32_t)((u128)x >> 96));
 }
 
 // q_k of the construction: h_k relative to the row maximum in 32 fractional bits.
@@ -1246,70 +1278,72 @@ __device__ __forceinline__ uint32_t alias_thr(u128 keep, uint64_t Q)
     return t >= (u128)0xFFFFFFFFu ? 0xFFFFFFFFu : (uint32_t)t;
 }
 
+// Pass 1 on row [b, b + n) with maximum hmax, sums of type T.
+template <typename T>
+__device__ __forceinline__ void alias_scan_row(const float *h, int64_t b, int64_t n, float hmax, uint4 *val,
+                                               int32_t *idx, ulonglong2 *rowinfo_v)
+{
+    const int lane = lane_id();
+    const uint64_t below = lanes_below(lane);
+    uint64_t qs = 0;
+    for (int64_t k = lane; k < n; k += kWave) qs += alias_q(h, b + k, hmax);
+    const uint64_t Q = wave_sum_u64(qs);
+    T dcarry = 0, ecarry = 0;
+    int64_t nl = 0, nh = 0;
+    for (int64_t k0 = 0; k0 < n; k0 += kWave) {
+        const int64_t k = k0 + lane;
+        const bool valid = k < n;
+        const uint64_t a = valid ? alias_q(h, b + k, hmax) * (uint64_t)n : 0;
+        const bool light = valid && a < Q, heavy = valid && a >= Q;
+        const uint64_t lm = __ballot(light), hm = __ballot(heavy);
+        const T d = light ? (T)(Q - a) : (T)0, e = heavy ? (T)(a - Q) : (T)0;
+        const T dinc = wave_incl_scan_t(d), einc = wave_incl_scan_t(e);
+        if (light) {
+            const int64_t pos = b + nl + __popcll(lm & below);
+            val[pos] = pack_t<T>(dcarry + dinc - d);  // deficits before this entry
+            idx[pos] = (int32_t)k;
+        }
+        if (heavy) {
+            const int64_t pos = b + n - 1 - (nh + __popcll(hm & below));
+            val[pos] = pack_t<T>(ecarry + einc);  // surplus up to and including this entry
+            idx[pos] = (int32_t)k;
+        }
+        dcarry += shfl_t(dinc, kWave - 1);
+        ecarry += shfl_t(einc, kWave - 1);
+        nl += __popcll(lm);
+        nh += __popcll(hm);
+    }
+    if (lane == 0) *rowinfo_v = make_ulonglong2((unsigned long long)Q, (unsigned long long)nl);
+}
+
 __global__ void __launch_bounds__(kBlock) alias_scan_kernel(const int64_t *row_ptr, const float *h, int64_t nv,
                                                             const uint4 *vrec, const float *rmax, uint4 *val,
                                                             int32_t *idx, ulonglong2 *rowinfo)
 {
-    const int lane = lane_id();
-    const uint64_t below = lanes_below(lane);
     const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
     for (int64_t v = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; v < nv; v += nw) {
         const int64_t b = row_ptr[v];
         const int64_t n = row_ptr[v + 1] - b;
         if (n == 0) continue;
         const float hmax = rmax ? rmax[v] : __uint_as_float(vrec[v].z);
-        uint64_t qs = 0;
-        for (int64_t k = lane; k < n; k += kWave) qs += alias_q(h, b + k, hmax);
-        const uint64_t Q = wave_sum_u64(qs);
-        u128 dcarry = 0, ecarry = 0;
-        int64_t nl = 0, nh = 0;
-        for (int64_t k0 = 0; k0 < n; k0 += kWave) {
-            const int64_t k = k0 + lane;
-            const bool valid = k < n;
-            const uint64_t a = valid ? alias_q(h, b + k, hmax) * (uint64_t)n : 0;
-            const bool light = valid && a < Q, heavy = valid && a >= Q;
-            const uint64_t lm = __ballot(light), hm = __ballot(heavy);
-            const u128 d = light ? (u128)(Q - a) : 0, e = heavy ? (u128)(a - Q) : 0;
-            const u128 dinc = wave_incl_scan_u128(d), einc = wave_incl_scan_u128(e);
-            if (light) {
-                const int64_t pos = b + nl + __popcll(lm & below);
-                const u128 x = dcarry + dinc - d;  // deficits before this entry
-                val[pos] = make_uint4((uint32_t)x, (uint32_t)(x >> 32), (uint32_t)(x >> 64), (uint32_t)(x >> 96));
-                idx[pos] = (int32_t)k;
-            }
-            if (heavy) {
-                const int64_t pos = b + n - 1 - (nh + __popcll(hm & below));
-                const u128 x = ecarry + einc;  // surplus up to and including this entry
-                val[pos] = make_uint4((uint32_t)x, (uint32_t)(x >> 32), (uint32_t)(x >> 64), (uint32_t)(x >> 96));
-                idx[pos] = (int32_t)k;
-            }
-            dcarry += shfl_u128(dinc, kWave - 1);
-            ecarry += shfl_u128(einc, kWave - 1);
-            nl += __popcll(lm);
-            nh += __popcll(hm);
-        }
-        if (lane == 0) rowinfo[v] = make_ulonglong2((unsigned long long)Q, (unsigned long long)nl);
+        if (n <= kAlias64Max) alias_scan_row<uint64_t>(h, b, n, hmax, val, idx, rowinfo + v);
+        else alias_scan_row<u128>(h, b, n, hmax, val, idx, rowinfo + v);
     }
-}
-
-__device__ __forceinline__ u128 load_u128(const uint4 *p)
-{
-    const uint4 x = *p;
-    return ((u128)x.w << 96) | ((u128)x.z << 64) | ((u128)x.y << 32) | (u128)x.x;
 }
 
 // Index of the first of the 64 wave lanes whose x (ascending over the lanes) is >= key
 // (ge) or > key (!ge); 64 when there is none.
-__device__ __forceinline__ int wave_bound_u128(u128 x, u128 key, bool ge)
+template <typename T>
+__device__ __forceinline__ int wave_bound_t(T x, T key, bool ge)
 {
     int c = 0;
 #pragma unroll
     for (int s = kWave / 2; s > 0; s >>= 1) {
-        const u128 y = shfl_u128(x, c + s - 1);
+        const T y = shfl_t(x, c + s - 1);
         if (ge ? (y < key) : (y <= key)) c += s;
     }
     // c in [0, 63]: one more test decides between c and 64
-    const u128 y = shfl_u128(x, c);
+    const T y = shfl_t(x, c);
     return (ge ? (y < key) : (y <= key)) ? c + 1 : c;
 }
 
@@ -1328,6 +1362,72 @@ __device__ __forceinline__ void write_record(const int32_t *col, const float *h,
     r[3] = vrec[ca];
 }
 
+// Pass 2 on row [b, b + n) with Q and nl from pass 1, sums of type T.
+template <typename T>
+__device__ __forceinline__ void alias_merge_row(const int32_t *col, const float *h, const uint8_t *label,
+                                                const uint4 *vrec, const uint4 *val, const int32_t *idx, int64_t b,
+                                                int64_t n, uint64_t Q, int64_t nl, float hmax, uint4 *prop)
+{
+    const int lane = lane_id();
+    constexpr T kMax = ~(T)0;
+    const int64_t nh = n - nl;  // >= 1 (the caller checked)
+    // heavy entry j (in index order) sits at b + n - 1 - j
+    const T e_last = load_t<T>(val + b + n - nh);
+    // light entries: alias = the first heavy entry whose E reaches the entry's D
+    for (int64_t li = 0, hj = 0; li < nl;) {
+        if (hj >= nh) {
+            // unreachable in exact arithmetic (the last E equals the total deficit, so
+            // every light entry finds its heavy one); kept so that the loop always ends
+            // and every record stays a valid self-alias
+            for (int64_t i = li + lane; i < nl; i += kWave) {
+                const int32_t k = idx[b + i];
+                write_record(col, h, label, vrec, b, k, k, 0xFFFFFFFFu, prop);
+            }
+            break;
+        }
+        const int64_t i = li + lane, j = hj + lane;
+        const T D = i < nl ? load_t<T>(val + b + i) : kMax;
+        const T E = j < nh ? load_t<T>(val + b + n - 1 - j) : kMax;
+        const int32_t hix = j < nh ? idx[b + n - 1 - j] : -1;
+        const int c = wave_bound_t(E, D, true);
+        const bool found = i < nl && c < kWave && hj + c < nh;
+        const int32_t al = __shfl(hix, c & (kWave - 1), kWave);
+        const int cnt = __popcll(__ballot(found));  // a prefix of the lanes (D ascends)
+        if (cnt == 0) {
+            hj += kWave;
+            continue;
+        }
+        if (found) {
+            const int32_t k = idx[b + i];
+            const uint64_t a = alias_q(h, b + k, hmax) * (uint64_t)n;
+            write_record(col, h, label, vrec, b, k, al, alias_thr((u128)a, Q), prop);
+        }
+        li += cnt;
+    }
+    // heavy entries: keep Q + E_j - D(n_j), alias the next heavy entry unless full
+    for (int64_t hj = 0, li = 0; hj < nh;) {
+        const int64_t i = li + lane, j = hj + lane;
+        const T D = i < nl ? load_t<T>(val + b + i) : kMax;
+        const T E = j < nh ? load_t<T>(val + b + n - 1 - j) : kMax;
+        const int c = wave_bound_t(D, E, false);  // light entries with D <= E_j in this block
+        const bool found = j < nh && c < kWave;
+        const T dn = shfl_t(D, c & (kWave - 1));
+        const int cnt = __popcll(__ballot(found));  // a prefix of the lanes (E ascends)
+        if (cnt == 0) {
+            li += kWave;
+            continue;
+        }
+        if (found) {
+            const T spent = li + c < nl ? dn : e_last;
+            const T keep = (T)Q + E - spent;
+            const int32_t k = idx[b + n - 1 - j];
+            const int32_t al = (keep < (T)Q && j + 1 < nh) ? idx[b + n - 2 - j] : k;
+            write_record(col, h, label, vrec, b, k, al, alias_thr((u128)keep, Q), prop);
+        }
+        hj += cnt;
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) alias_merge_kernel(const int64_t *row_ptr, const int32_t *col,
                                                              const float *h, const uint8_t *label, int64_t nv,
                                                              const uint4 *vrec, const float *rmax, const uint4 *val,
@@ -1342,67 +1442,83 @@ __global__ void __launch_bounds__(kBlock) alias_merge_kernel(const int64_t *row_
         if (n == 0) continue;
         const ulonglong2 ri = rowinfo[v];
         const uint64_t Q = (uint64_t)ri.x;
-        const int64_t nl = (int64_t)ri.y, nh = n - nl;  // nh >= 1: the a_k sum to n * Q
-        if (nh <= 0) {  // unreachable (see above); every record stays a valid self-alias
+        const int64_t nl = (int64_t)ri.y;
+        if (n - nl <= 0) {  // unreachable (the a_k sum to n * Q); every record stays a valid self-alias
             for (int64_t k = lane; k < n; k += kWave)
                 write_record(col, h, label, vrec, b, (int32_t)k, (int32_t)k, 0xFFFFFFFFu, prop);
             continue;
         }
+        if (n > kAliasHubRow) continue;  // alias_hub_kernel
         const float hmax = rmax ? rmax[v] : __uint_as_float(vrec[v].z);
-        // heavy entry j (in index order) sits at b + n - 1 - j
-        const u128 e_last = load_u128(val + b + n - nh);
-        // light entries: alias = the first heavy entry whose E reaches the entry's D
-        for (int64_t li = 0, hj = 0; li < nl;) {
-            if (hj >= nh) {
-                // unreachable in exact arithmetic (the last E equals the total deficit, so
-                // every light entry finds its heavy one); kept so that the loop always ends
-                // and every record stays a valid self-alias
-                for (int64_t i = li + lane; i < nl; i += kWave) {
-                    const int32_t k = idx[b + i];
-                    write_record(col, h, label, vrec, b, k, k, 0xFFFFFFFFu, prop);
+        if (n <= kAlias64Max) alias_merge_row<uint64_t>(col, h, label, vrec, val, idx, b, n, Q, nl, hmax, prop);
+        else alias_merge_row<u128>(col, h, label, vrec, val, idx, b, n, Q, nl, hmax, prop);
+    }
+}
+
+// The rows longer than kAliasHubRow, appended to `hubs` in any order (*nhub counts them).
+__global__ void __launch_bounds__(256) alias_hub_list_kernel(const int64_t *row_ptr, int64_t nv, int32_t *hubs,
+                                                             int *nhub)
+{
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nv; v += (int64_t)gridDim.x * 256)
+        if (row_ptr[v + 1] - row_ptr[v] > kAliasHubRow) hubs[atomicAdd(nhub, 1)] = (int32_t)v;
+}
+
+// Pass 2 for the long rows, one thread per entry (blockIdx.y picks the row, the blocks of a
+// row stride over its entries): the same two merges, each entry finding its partner by a
+// binary search of the other sorted sequence instead of a wave walking the row, so that a
+// hub row is spread over many waves.  Light entry i: alias = the first heavy entry with
+// E >= D_i.  Heavy entry j: keep Q + E_j - D(first light entry with D > E_j, or the last
+// E), alias the next heavy entry unless it keeps a full bucket.
+__global__ void __launch_bounds__(256) alias_hub_kernel(const int64_t *row_ptr, const int32_t *col, const float *h,
+                                                        const uint8_t *label, const uint4 *vrec, const float *rmax,
+                                                        const uint4 *val, const int32_t *idx,
+                                                        const ulonglong2 *rowinfo, const int32_t *hubs,
+                                                        const int *nhub, uint4 *prop)
+{
+    const int nh_rows = *nhub;
+    for (int hr = blockIdx.y; hr < nh_rows; hr += gridDim.y) {
+        const int64_t v = hubs[hr];
+        const int64_t b = row_ptr[v];
+        const int64_t n = row_ptr[v + 1] - b;
+        const ulonglong2 ri = rowinfo[v];
+        const uint64_t Q = (uint64_t)ri.x;
+        const int64_t nl = (int64_t)ri.y, nh = n - nl;
+        const float hmax = rmax ? rmax[v] : __uint_as_float(vrec[v].z);
+        for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) {
+            if (nh <= 0) {  // unreachable (the a_k sum to n * Q); a valid self-alias
+                write_record(col, h, label, vrec, b, (int32_t)t, (int32_t)t, 0xFFFFFFFFu, prop);
+                continue;
+            }
+            if (t < nl) {
+                const u128 D = load_t<u128>(val + b + t);
+                int64_t lo = 0, hi = nh;  // first heavy j with E_j >= D (E_j at b + n - 1 - j, ascending in j)
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (load_t<u128>(val + b + n - 1 - mid) < D) lo = mid + 1;
+                    else hi = mid;
                 }
-                break;
-            }
-            const int64_t i = li + lane, j = hj + lane;
-            const u128 D = i < nl ? load_u128(val + b + i) : kU128Max;
-            const u128 E = j < nh ? load_u128(val + b + n - 1 - j) : kU128Max;
-            const int32_t hix = j < nh ? idx[b + n - 1 - j] : -1;
-            const int c = wave_bound_u128(E, D, true);
-            const bool found = i < nl && c < kWave && hj + c < nh;
-            const int32_t al = __shfl(hix, c & (kWave - 1), kWave);
-            const int cnt = __popcll(__ballot(found));  // a prefix of the lanes (D ascends)
-            if (cnt == 0) {
-                hj += kWave;
-                continue;
-            }
-            if (found) {
-                const int32_t k = idx[b + i];
+                const int32_t k = idx[b + t];
+                if (lo >= nh) {  // unreachable in exact arithmetic; a valid self-alias
+                    write_record(col, h, label, vrec, b, k, k, 0xFFFFFFFFu, prop);
+                    continue;
+                }
                 const uint64_t a = alias_q(h, b + k, hmax) * (uint64_t)n;
-                write_record(col, h, label, vrec, b, k, al, alias_thr((u128)a, Q), prop);
-            }
-            li += cnt;
-        }
-        // heavy entries: keep Q + E_j - D(n_j), alias the next heavy entry unless full
-        for (int64_t hj = 0, li = 0; hj < nh;) {
-            const int64_t i = li + lane, j = hj + lane;
-            const u128 D = i < nl ? load_u128(val + b + i) : kU128Max;
-            const u128 E = j < nh ? load_u128(val + b + n - 1 - j) : kU128Max;
-            const int c = wave_bound_u128(D, E, false);  // light entries with D <= E_j in this block
-            const bool found = j < nh && c < kWave;
-            const u128 dn = shfl_u128(D, c & (kWave - 1));
-            const int cnt = __popcll(__ballot(found));  // a prefix of the lanes (E ascends)
-            if (cnt == 0) {
-                li += kWave;
-                continue;
-            }
-            if (found) {
-                const u128 spent = li + c < nl ? dn : e_last;
+                write_record(col, h, label, vrec, b, k, idx[b + n - 1 - lo], alias_thr((u128)a, Q), prop);
+            } else {
+                const int64_t j = t - nl;
+                const u128 E = load_t<u128>(val + b + n - 1 - j);
+                int64_t lo = 0, hi = nl;  // first light i with D_i > E (D ascending in i)
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (load_t<u128>(val + b + mid) <= E) lo = mid + 1;
+                    else hi = mid;
+                }
+                const u128 spent = lo < nl ? load_t<u128>(val + b + lo) : load_t<u128>(val + b + n - nh);
                 const u128 keep = (u128)Q + E - spent;
                 const int32_t k = idx[b + n - 1 - j];
                 const int32_t al = (keep < (u128)Q && j + 1 < nh) ? idx[b + n - 2 - j] : k;
                 write_record(col, h, label, vrec, b, k, al, alias_thr(keep, Q), prop);
             }
-            hj += cnt;
         }
     }
 }
@@ -1708,7 +1824,7 @@ hipError_t launch_export_alias(const uint4 *prop, int64_t ne, uint32_t *thr, int
 
 hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const float *h, const uint8_t *label,
                               int64_t nv, const uint4 *vrec, const float *rmax, uint4 *val, int32_t *idx,
-                              ulonglong2 *rowinfo, uint4 *prop, hipStream_t s)
+                              ulonglong2 *rowinfo, int32_t *hubs, int *nhub, uint4 *prop, hipStream_t s)
 {
     int64_t blocks = (nv + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > 65536) blocks = 65536;
@@ -1719,6 +1835,16 @@ hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(alias_merge_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, label, nv,
                        vrec, rmax, val, idx, rowinfo, prop);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the long rows: listed, then one thread per entry
+    if ((e = hipMemsetAsync(nhub, 0, sizeof(int), s)) != hipSuccess) return e;
+    int64_t lb = (nv + 255) / 256;
+    if (lb > 4096) lb = 4096;
+    if (lb < 1) lb = 1;
+    hipLaunchKernelGGL(alias_hub_list_kernel, dim3((unsigned)lb), dim3(256), 0, s, row_ptr, nv, hubs, nhub);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(alias_hub_kernel, dim3(64, 1024), dim3(256), 0, s, row_ptr, col, h, label, vrec, rmax, val, idx,
+                       rowinfo, hubs, nhub, prop);
     return hipGetLastError();
 }
 
