@@ -1213,6 +1213,8 @@ using u128 = unsigned __int128;
 constexpr int64_t kAlias64Max = (int64_t)1 << 15;
 // Rows longer than this are merged by alias_hub_kernel, many waves per row.
 constexpr int64_t kAliasHubRow = 8192;
+// Rows of at most this many entries are built by alias_small_kernel, one lane per row.
+constexpr int64_t kAliasSmallRow = 16;
 
 template <typename T>
 __device__ __forceinline__ T shfl_t(T x, int src)
@@ -1324,7 +1326,7 @@ __global__ void __launch_bounds__(kBlock) alias_scan_kernel(const int64_t *row_p
     for (int64_t v = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; v < nv; v += nw) {
         const int64_t b = row_ptr[v];
         const int64_t n = row_ptr[v + 1] - b;
-        if (n == 0) continue;
+        if (n <= kAliasSmallRow) continue;  // alias_small_kernel
         const float hmax = rmax ? rmax[v] : __uint_as_float(vrec[v].z);
         if (n <= kAlias64Max) alias_scan_row<uint64_t>(h, b, n, hmax, val, idx, rowinfo + v);
         else alias_scan_row<u128>(h, b, n, hmax, val, idx, rowinfo + v);
@@ -1439,7 +1441,7 @@ __global__ void __launch_bounds__(kBlock) alias_merge_kernel(const int64_t *row_
     for (int64_t v = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; v < nv; v += nw) {
         const int64_t b = row_ptr[v];
         const int64_t n = row_ptr[v + 1] - b;
-        if (n == 0) continue;
+        if (n <= kAliasSmallRow) continue;  // alias_small_kernel
         const ulonglong2 ri = rowinfo[v];
         const uint64_t Q = (uint64_t)ri.x;
         const int64_t nl = (int64_t)ri.y;
@@ -1452,6 +1454,52 @@ __global__ void __launch_bounds__(kBlock) alias_merge_kernel(const int64_t *row_
         const float hmax = rmax ? rmax[v] : __uint_as_float(vrec[v].z);
         if (n <= kAlias64Max) alias_merge_row<uint64_t>(col, h, label, vrec, val, idx, b, n, Q, nl, hmax, prop);
         else alias_merge_row<u128>(col, h, label, vrec, val, idx, b, n, Q, nl, hmax, prop);
+    }
+}
+
+// Rows of 1 .. kAliasSmallRow entries, one lane per row: the sweep itself, in entry order.
+// A(k) = q_k * n.  With the current heavy entry j holding residual r: each light entry i
+// (A < Q) first closes the heavy entries whose residual has fallen below Q (bucket j keeps
+// r, aliased to the next heavy entry, which then holds A(j') - (Q - r)), then keeps A(i)
+// with j as its alias, and r loses Q - A(i); the heavy entries left at the end are closed
+// the same way, a full bucket being its own alias.  This is the table the two passes
+// above build for longer rows (sums here stay below 16 * 16 * 2^32).
+__global__ void __launch_bounds__(256) alias_small_kernel(const int64_t *row_ptr, const int32_t *col, const float *h,
+                                                          const uint8_t *label, int64_t nv, const uint4 *vrec,
+                                                          const float *rmax, uint4 *prop)
+{
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nv; v += (int64_t)gridDim.x * 256) {
+        const int64_t b = row_ptr[v];
+        const int32_t n = (int32_t)(row_ptr[v + 1] - b);
+        if (n == 0 || n > kAliasSmallRow) continue;
+        const float hmax = rmax ? rmax[v] : __uint_as_float(vrec[v].z);
+        uint64_t Q = 0;
+        for (int32_t k = 0; k < n; ++k) Q += alias_q(h, b + k, hmax);
+        auto A = [&](int32_t k) { return alias_q(h, b + k, hmax) * (uint64_t)n; };
+        int32_t j = 0;
+        while (A(j) < Q) ++j;  // the first heavy entry (the A sum to n * Q)
+        uint64_t r = A(j);
+        for (int32_t i = 0; i < n; ++i) {
+            const uint64_t ai = A(i);
+            if (ai >= Q) continue;
+            while (r < Q) {  // a later heavy entry exists while a light entry is left
+                int32_t jn = j + 1;
+                while (jn < n - 1 && A(jn) < Q) ++jn;
+                write_record(col, h, label, vrec, b, j, jn, alias_thr((u128)r, Q), prop);
+                r = A(jn) - (Q - r);
+                j = jn;
+            }
+            write_record(col, h, label, vrec, b, i, j, alias_thr((u128)ai, Q), prop);
+            r -= Q - ai;
+        }
+        for (;;) {
+            int32_t jn = j + 1;
+            while (jn < n && A(jn) < Q) ++jn;
+            write_record(col, h, label, vrec, b, j, (r < Q && jn < n) ? jn : j, alias_thr((u128)r, Q), prop);
+            if (jn >= n) break;
+            r = A(jn) - (Q - r);
+            j = jn;
+        }
     }
 }
 
@@ -1835,6 +1883,13 @@ hipError_t launch_build_alias(const int64_t *row_ptr, const int32_t *col, const 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(alias_merge_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, row_ptr, col, h, label, nv,
                        vrec, rmax, val, idx, rowinfo, prop);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // the short rows, one lane each
+    int64_t sb = (nv + 255) / 256;
+    if (sb > 65536) sb = 65536;
+    if (sb < 1) sb = 1;
+    hipLaunchKernelGGL(alias_small_kernel, dim3((unsigned)sb), dim3(256), 0, s, row_ptr, col, h, label, nv, vrec, rmax,
+                       prop);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // the long rows: listed, then one thread per entry
     if ((e = hipMemsetAsync(nhub, 0, sizeof(int), s)) != hipSuccess) return e;
