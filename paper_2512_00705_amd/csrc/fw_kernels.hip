@@ -27,11 +27,11 @@ namespace fw {
 
 enum Mode : int { kIdle = 0, kSetup = 1, kRjs = 2, kRvs = 3, kAdv = 4 };
 
-// Dynamic LDS of a walk block: each wave's two slots of 64 vertex records filled by LDS DMA
+// Dynamic LDS of a walk block: each wave's four slots of 64 vertex records filled by LDS DMA
 // from proposal records, then each wave's N(prev) staging area (lds_cap int32).
 static size_t walk_lds_bytes(int lds_cap)
 {
-    return (size_t)kWavesPerBlock * (size_t)lds_cap * sizeof(int32_t) + (size_t)kWavesPerBlock * 2 * kWave * 16;
+    return (size_t)kWavesPerBlock * (size_t)lds_cap * sizeof(int32_t) + (size_t)kWavesPerBlock * 4 * kWave * 16;
 }
 
 // An LDS address for the LDS-DMA load builtin (the pointer must lie in this block's LDS).
@@ -474,12 +474,12 @@ __global__ void __launch_bounds__(kBlock, (STATS || HV > 1) ? kMinWavesCounted :
 walk_kernel(WalkArgs a)
 {
     extern __shared__ int32_t lds_all[];
-    // this wave's two slots of 64 vertex records (candidate kept, alias taken), then its
-    // N(prev) staging area
+    // this wave's four slots of 64 vertex records (the first and second proposal's
+    // candidate kept and alias taken), then its N(prev) staging area
     // (its offset is uniform over the wave; readfirstlane keeps it in a scalar register)
     uint4 *nvstage = reinterpret_cast<uint4 *>(lds_all) +
-                     __builtin_amdgcn_readfirstlane((uint32_t)(threadIdx.x / kWave) * 2 * kWave);
-    int32_t *lds = lds_all + kWavesPerBlock * 2 * kWave * 4 + (threadIdx.x / kWave) * a.lds_cap;
+                     __builtin_amdgcn_readfirstlane((uint32_t)(threadIdx.x / kWave) * 4 * kWave);
+    int32_t *lds = lds_all + kWavesPerBlock * 4 * kWave * 4 + (threadIdx.x / kWave) * a.lds_cap;
     const int lane = lane_id();
     const uint64_t below = lanes_below(lane);
 
@@ -779,7 +779,7 @@ walk_kernel(WalkArgs a)
                                           ? -1.0f
                                           : (j == 0 ? 1.0f : fminf(sw.ret, (MB && mb) ? sw.oth : sw.lo));
             bool sure = false;
-            // the batch's first proposal (the one most often accepted) also copies its
+            // the batch's first two proposals (those most often accepted) also copy their
             // two candidates' vertex records into this wave's LDS slots, in the same
             // request as the rest of the record (LDS DMA: no registers): an accepted
             // candidate's record is then read from LDS.  A line read again after its
@@ -812,10 +812,10 @@ walk_kernel(WalkArgs a)
                 } else if (hprop) {
                     const uint32_t f = scaled_fraction_hi(x.x0, x.x1, pn);
                     const uint4 *rec = precs + kPropU4 * k;
-                    if (r == 0) {
-                        __builtin_amdgcn_global_load_lds(rec + 2, lds_ptr(nvstage), 16, 0, 0);
-                        __builtin_amdgcn_global_load_lds(rec + 3, lds_ptr(nvstage + kWave), 16, 0, 0);
-                        nv0_ok = true;
+                    if (r < 2) {
+                        __builtin_amdgcn_global_load_lds(rec + 2, lds_ptr(nvstage + 2 * r * kWave), 16, 0, 0);
+                        __builtin_amdgcn_global_load_lds(rec + 3, lds_ptr(nvstage + (2 * r + 1) * kWave), 16, 0, 0);
+                        if (r == 0) nv0_ok = true;
                     }
                     const uint4 r0 = rec[0], r1 = rec[1];
                     const bool keep = f < r1.x;
@@ -908,8 +908,8 @@ walk_kernel(WalkArgs a)
                     hnext = hsel;
                     if (hprop && !ol[0] && !mr[0]) {
                         // the record's line holds the accepted candidate's vertex record
-                        nvrec = (r == 0 && nv0_ok)
-                                    ? nvstage[(rsel[0] & 1u) * kWave + lane]
+                        nvrec = (r < 2 && nv0_ok)
+                                    ? nvstage[(2 * r + (rsel[0] & 1u)) * kWave + lane]
                                     : precs[kPropU4 * (pb + (int64_t)(rsel[0] >> 1)) + 2 + (rsel[0] & 1u)];
                         have_nv = true;
                     }
