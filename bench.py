@@ -25,12 +25,15 @@ KERNEL_SOURCES = ("paper_2512_00705_amd/csrc/fw_kernels.hip", "paper_2512_00705_
 TRAFFIC_FILE = "profiles/traffic_walk_kernel_node2vec_rmat22.txt"
 
 
+PLAN_FIELDS = ("rho", "d_lo", "lds_cap", "bound", "proposal", "rjs_cap", "grid", "hub_deg", "hub_lanes", "rvs_share")
+
+
 def parse_plan(text: str):
-    """A plan from ``rho,d_lo,lds_cap[,bound[,proposal[,rjs_cap[,grid[,hub_deg,hub_lanes]]]]]``;
+    """A plan from ``rho,d_lo,lds_cap[,bound[,proposal[,rjs_cap[,grid[,hub_deg,hub_lanes[,rvs_share]]]]]]]``;
     omitted fields take fw_plan_default's values."""
     import paper_2512_00705_amd as fw
     f = text.split(",")
-    names = ("rho", "d_lo", "lds_cap", "bound", "proposal", "rjs_cap", "grid", "hub_deg", "hub_lanes")
+    names = PLAN_FIELDS
     if not 3 <= len(f) <= len(names):
         raise SystemExit(f"--plan: expected 3..{len(names)} comma-separated fields, got {len(f)}")
     kw = {n: (float(v) if n == "rho" else int(v)) for n, v in zip(names, f)}
@@ -40,12 +43,12 @@ def parse_plan(text: str):
 def plan_arg(plan) -> str:
     """The --plan text that reproduces ``plan`` (float rho in full precision)."""
     return ",".join([repr(float(plan.rho))] + [str(int(getattr(plan, n))) for n in
-                     ("d_lo", "lds_cap", "bound", "proposal", "rjs_cap", "grid", "hub_deg", "hub_lanes")])
+                     PLAN_FIELDS[1:]])
 
 
 def plan_dict(plan) -> dict:
     return {n: (float(getattr(plan, n)) if n == "rho" else int(getattr(plan, n))) for n in
-            ("rho", "d_lo", "lds_cap", "bound", "proposal", "rjs_cap", "grid", "hub_deg", "hub_lanes")}
+            PLAN_FIELDS}
 
 
 def one_off_share(prep_ms, profile_ms, index_ms, alias_ms, tune_ms, job_ms) -> dict:
@@ -148,7 +151,7 @@ def main():
     ap.add_argument("--skew-scale", type=int, default=20, help="skew: R-MAT scale of the topology")
     ap.add_argument("--skew-L", type=int, default=20, help="skew: walk length")
     ap.add_argument("--plan", default="",
-                    help="rho,d_lo,lds_cap[,bound[,proposal[,rjs_cap[,grid[,hub_deg,hub_lanes]]]]]: use this plan "
+                    help="rho,d_lo,lds_cap[,bound[,proposal[,rjs_cap[,grid[,hub_deg,hub_lanes[,rvs_share]]]]]]]: use this plan "
                          "instead of autotuning (the plan_arg of a bench line)")
     ap.add_argument("--per-query", type=int, default=1, help="batched: also time one launch per query")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -342,7 +345,8 @@ def main():
               else oracle.Logic(kind=oracle.METAPATH, weighted=True, schema=(0, 1, 2, 3, 4))
               if args.logic == "metapath"
               else oracle.Logic(kind=oracle.NODE2VEC, weighted=True, p=args.p, q=args.q))
-        pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap, bound=plan.bound, proposal=plan.proposal)
+        pl = oracle.Plan(rho=plan.rho, d_lo=plan.d_lo, rjs_cap=plan.rjs_cap, bound=plan.bound, proposal=plan.proposal,
+                         hub_deg=plan.hub_deg, hub_lanes=plan.hub_lanes, rvs_share=bool(plan.rvs_share))
         cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
         smode = {"auto": 0, "rvs": 1, "rjs": 2}[args.strategy]
         k = args.cpu_sample or 2048

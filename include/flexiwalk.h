@@ -107,6 +107,15 @@ typedef struct fw_logic {
  *            items share a skip threshold and so the random stream, never the distribution;
  *            fw_walk only: fw_batch_create, fw_batch_run_noalloc and fw_server_create
  *            return FW_E_INVALID for hub_deg > 0 with hub_lanes != 64
+ *   rvs_share 0 or 1 (changes the stream, never the distribution).  0: each eRVS lane
+ *            keeps its own threshold after the shared round-0 maximum (Section 3.2,
+ *            parallel description).  1 (an extension): after every scan round in which
+ *            some lane drew a key, each lane below the largest threshold thr_g takes it
+ *            and rescales its remaining skip, T' = ((T - S) * thr) / thr_g in float32
+ *            (the remaining skip is exponential with rate -thr; scaled, it is the skip
+ *            of thr_g), S' = 0; a lane with no threshold yet (-inf) keeps T = 0, and
+ *            thr_g >= 0 makes T' = +inf.  Keys below thr_g cannot win, so only fewer
+ *            keys are drawn.  A round is P items (hub_lanes on hub rows).
  *   lds_cap  int32 entries of N(prev) staged in LDS per wavefront, 0..8192 (0: never stage)
  *   grid     persistent blocks (0 = fill the device)
  *   bound    eRJS bound (changes the stream, never the distribution):
@@ -157,6 +166,7 @@ typedef struct fw_plan {
     int32_t proposal;
     int32_t hub_deg;
     int32_t hub_lanes;
+    int32_t rvs_share;
 } fw_plan;
 
 /* Counters accumulated by fw_walk into a device array of FW_NSTATS uint64 values:
@@ -275,7 +285,8 @@ int fw_plan_profile(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stre
  * proposal: h-proportional too for a weighted logic once fw_graph_build_alias ran, and
  * label-conditioned for MetaPath once fw_graph_build_label_alias ran), then for the
  * degree gate d_lo in {0, 8, 32, 128}, the LDS budget for N(prev), the eRJS trial cap
- * rjs_cap in {16, 64, 256, 1024, 4096}, the eRVS lanes on long rows (hub_lanes 128 or
+ * rjs_cap in {16, 64, 256, 1024, 4096}, the lanes' shared eRVS threshold (rvs_share,
+ * taken only when 2 % faster), the eRVS lanes on long rows (hub_lanes 128 or
  * 256 from hub_deg 1024 or 8192; fw_plan_autotune only, never for a mix) and the
  * persistent grid (the occupancy limit, half of it, twice it); the fastest plan is
  * returned.  Every candidate

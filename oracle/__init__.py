@@ -59,7 +59,7 @@ class _Plan(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_float), ("d_lo", ctypes.c_int32), ("rjs_cap", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("jump", ctypes.c_int32), ("bound_scale", ctypes.c_float),
                 ("bound", ctypes.c_int32), ("proposal", ctypes.c_int32), ("hub_deg", ctypes.c_int32),
-                ("hub_lanes", ctypes.c_int32)]
+                ("hub_lanes", ctypes.c_int32), ("rvs_share", ctypes.c_int32)]
 
 
 @dataclass
@@ -97,6 +97,7 @@ class Plan:
     # 2: as 1, and MetaPath proposes within the wanted label's group (label_alias)
     hub_deg: int = 0  # eRVS rows of at least this degree use hub_lanes lanes (0: never)
     hub_lanes: int = 64
+    rvs_share: bool = False  # eRVS lanes take the largest threshold after each round with a jump event
 
     def _c(self):
         s = _Plan()
@@ -104,6 +105,7 @@ class Plan:
         s.jump, s.bound_scale, s.bound = int(self.jump), self.bound_scale, self.bound
         s.proposal = self.proposal
         s.hub_deg, s.hub_lanes = self.hub_deg, self.hub_lanes
+        s.rvs_share = int(self.rvs_share)
         return s
 
 

@@ -17,7 +17,10 @@
  *     otherwise; the first step has no v' and uses weight 1;
  *   - eRVS: exponential keys k_i = u_i^(1/w~_i), argmax wins, ">=" so later items win
  *     ties (Section 3.2, Algorithm 1), plus the jump of Eq. (jump) run per lane with a
- *     shared initial maximum (Section 3.2, parallel description);
+ *     shared initial maximum (Section 3.2, parallel description); optionally (plan
+ *     rvs_share) the lanes also take the largest threshold among them after each round
+ *     in which one drew a key, their remaining skips rescaled to it (an extension: the
+ *     remaining skip is exponential, so the rescaled skip is that of the new threshold);
  *   - eRJS: uniform proposal, accept when U * c' < w~ for any bound c' >= max w~
  *     (Section 3.3 and its proof);
  *   - bound max(w) * max(h) and sum estimate mean(w) * sum(h) (Section 3.3, Section 4.2
@@ -72,7 +75,9 @@
  * its h(v, x) / h_MAX test, 10 averages the Node2Vec return values over 2 instead of their 3
  * branches in the sum estimate, 11 inverts the cost model's choice, 12 charges 8 bytes
  * instead of 16 for the row pointer pair of a step, 13 builds a label group's alias table
- * from the whole row's h maximum and ignores the group's weights (uniform within the group).
+ * from the whole row's h maximum and ignores the group's weights (uniform within the group),
+ * 14 inverts the ratio that rescales a lane's skip to a shared eRVS threshold, 15 shares the
+ * threshold without rescaling the skip.
  */
 #ifndef OG_MUTANT
 #define OG_MUTANT 0
@@ -179,6 +184,8 @@ typedef struct {
                             and MetaPath proposes within the wanted label's group (og_build_label_alias) */
     int32_t hub_deg;     /* rows of at least this degree run eRVS with hub_lanes lanes (0: never) */
     int32_t hub_lanes;   /* P for those rows */
+    int32_t rvs_share;   /* 1: after each eRVS round with a jump event the lanes take the largest
+                            threshold among them, their skips rescaled (rvs_sample) */
 } og_plan;
 
 /* OG_RANDOM_SELECT and OG_DEGREE_SELECT are the two selection policies the paper compares
@@ -453,6 +460,40 @@ static double bytes_per_item(const og_ctx *cx)
     return b;
 }
 
+/* One eRVS lane: its best key lk (a logarithm) at item li, its threshold thr (the key
+ * to beat), and the skip of Eq. (jump): the item whose running weight S passes T draws. */
+typedef struct {
+    float lk, thr, T, S;
+    int64_t li;
+} og_lane;
+
+/* Item i of a lane's scan (Section 3.2, Eq. (jump)): add its weight to S; where S passes
+ * T the item gets a key conditioned to beat thr, u' ~ U(exp(thr)^w~, 1), i.e.
+ * ln u' = log1p(expm1(w~ * thr) * V), which becomes the lane's key and threshold, and a
+ * new skip T = ln(r) / thr starts.  Returns 1 when a key was drawn. */
+static int rvs_item(const og_ctx *cx, uint32_t w, int j, int32_t prev, int64_t base, int64_t deg, int64_t dvp,
+                    int64_t i, og_lane *ln, og_info *info)
+{
+    uint32_t x[4];
+    float wt = transition_weight(cx, base + i, j, prev, deg, dvp);
+    ln->S = ln->S + wt;
+    if (ln->T > 0.0f && ln->T < INFINITY) note_margin(info, ln->S, ln->T);
+    if (!(ln->S > ln->T)) return 0;
+    draw(cx->seed, w, (uint32_t)j, (uint32_t)i, 1, x);
+    float a = wt * ln->thr;
+    float m1 = expm1_f(a);
+    float z = m1 * og_uniform(x[0]);
+    float L = log1p_f(z);
+    if (OG_MUTANT == 2) L = ln_f(og_uniform(x[0]));
+    ln->lk = L / wt;
+    ln->li = i;
+    ln->thr = ln->lk;
+    if (OG_MUTANT != 3) ln->S = 0.0f;
+    ln->T = ln->thr >= 0.0f ? INFINITY : ln_f(og_uniform(x[1])) / ln->thr;
+    info->triggers++;
+    return 1;
+}
+
 /* eRVS over the row of `cur`, Section 3.2.  Returns the CSR offset within the row or -1. */
 static int64_t rvs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int64_t base, int64_t deg,
                           int64_t dvp, og_info *info)
@@ -483,48 +524,63 @@ static int64_t rvs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
 
     /* Round 0: lane l keys its first item l; the maximum is shared by all lanes. */
     const int64_t n0 = deg < P ? deg : P;
-    float *key0 = (float *)malloc(sizeof(float) * (size_t)n0);
-    float *thr_u = (float *)malloc(sizeof(float) * (size_t)n0);
+    og_lane *ln = (og_lane *)malloc(sizeof(og_lane) * (size_t)n0);
     float lkg = -INFINITY;
     for (int64_t l = 0; l < n0; ++l) {
         float wt = transition_weight(cx, base + l, j, prev, deg, dvp);
         draw(cx->seed, w, (uint32_t)j, (uint32_t)l, 1, x);
-        key0[l] = wt > 0.0f ? ln_f(og_uniform(x[0])) / wt : -INFINITY;
-        thr_u[l] = og_uniform(x[1]);
-        if (key0[l] > lkg) lkg = key0[l];
+        ln[l].lk = wt > 0.0f ? ln_f(og_uniform(x[0])) / wt : -INFINITY;
+        ln[l].li = l;
+        ln[l].T = og_uniform(x[1]); /* the threshold draw, until lkg is known */
+        if (ln[l].lk > lkg) lkg = ln[l].lk;
+    }
+    for (int64_t l = 0; l < n0; ++l) {
+        ln[l].thr = lkg;
+        ln[l].T = lkg == -INFINITY ? 0.0f : (lkg >= 0.0f ? INFINITY : ln_f(ln[l].T) / lkg);
+        ln[l].S = 0.0f;
     }
 
-    /* Each lane scans items l+P, l+2P, ... with the jump of Eq. (jump). */
+    if (!cx->pl->rvs_share) {
+        /* Each lane scans items l+P, l+2P, ... on its own thresholds (Eq. (jump)). */
+        for (int64_t l = 0; l < n0; ++l)
+            for (int64_t i = l + P; i < deg; i += P)
+                rvs_item(cx, w, j, prev, base, deg, dvp, i, &ln[l], info);
+    } else {
+        /* Round r holds items rP .. rP+P-1, lane l item rP+l.  After a round in which some
+           lane drew a key, every lane whose threshold lies below the largest one, thr_g,
+           takes thr_g: its remaining skip T - S is exponential with rate -thr (memoryless:
+           no item since its last draw has passed it), and scaled by thr / thr_g it is
+           exponential with rate -thr_g, the skip towards the first item whose key beats
+           thr_g.  Keys below thr_g cannot win the final argmax, so no item loses its
+           chance; only fewer keys are drawn.  A lane without a threshold (thr = -inf,
+           every item so far of weight 0) keeps T = 0. */
+        for (int64_t r0 = P; r0 < deg; r0 += P) {
+            int drew = 0;
+            for (int64_t l = 0; l < n0 && r0 + l < deg; ++l)
+                drew |= rvs_item(cx, w, j, prev, base, deg, dvp, r0 + l, &ln[l], info);
+            if (!drew) continue;
+            float g = -INFINITY;
+            for (int64_t l = 0; l < n0; ++l)
+                if (ln[l].thr > g) g = ln[l].thr;
+            for (int64_t l = 0; l < n0; ++l) {
+                if (!(ln[l].thr > -INFINITY) || !(ln[l].thr < g)) continue;
+                if (OG_MUTANT != 15) {
+                    ln[l].T = g >= 0.0f ? INFINITY
+                                        : (OG_MUTANT == 14 ? ((ln[l].T - ln[l].S) * g) / ln[l].thr
+                                                           : ((ln[l].T - ln[l].S) * ln[l].thr) / g);
+                    ln[l].S = 0.0f;
+                }
+                ln[l].thr = g;
+            }
+        }
+    }
+
+    /* lexicographic maximum over (key, index): larger index wins ties */
     float best = -INFINITY, second = -INFINITY;
     int64_t best_i = -1;
     for (int64_t l = 0; l < n0; ++l) {
-        float lk = key0[l];
-        int64_t li = l;
-        float thr = lkg;
-        float T = thr == -INFINITY ? 0.0f : (thr >= 0.0f ? INFINITY : ln_f(thr_u[l]) / thr);
-        float S = 0.0f;
-        for (int64_t i = l + P; i < deg; i += P) {
-            float wt = transition_weight(cx, base + i, j, prev, deg, dvp);
-            S = S + wt;
-            if (T > 0.0f && T < INFINITY) note_margin(info, S, T);
-            if (S > T) {
-                /* the item that ends the skip gets a key conditioned to beat thr:
-                   u' ~ U(thr_lin^wt, 1), i.e. log u' = log1p(expm1(wt*thr) * V) */
-                draw(cx->seed, w, (uint32_t)j, (uint32_t)i, 1, x);
-                float a = wt * thr;
-                float m1 = expm1_f(a);
-                float z = m1 * og_uniform(x[0]);
-                float L = log1p_f(z);
-                if (OG_MUTANT == 2) L = ln_f(og_uniform(x[0]));
-                lk = L / wt;
-                li = i;
-                thr = lk;
-                if (OG_MUTANT != 3) S = 0.0f;
-                T = thr >= 0.0f ? INFINITY : ln_f(og_uniform(x[1])) / thr;
-                info->triggers++;
-            }
-        }
-        /* lexicographic maximum over (key, index): larger index wins ties */
+        const float lk = ln[l].lk;
+        const int64_t li = ln[l].li;
         if (lk > best || (lk == best && li > best_i)) {
             second = best;
             best = lk;
@@ -534,8 +590,7 @@ static int64_t rvs_sample(const og_ctx *cx, uint32_t w, int j, int32_t prev, int
         }
     }
     if (best > -INFINITY && second > -INFINITY) note_margin(info, best, second);
-    free(key0);
-    free(thr_u);
+    free(ln);
     return best > -INFINITY ? best_i : -1;
 }
 

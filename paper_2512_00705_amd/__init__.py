@@ -58,7 +58,7 @@ class fw_plan(ctypes.Structure):
     _fields_ = [("rho", ctypes.c_float), ("d_lo", ctypes.c_int32), ("rjs_cap", ctypes.c_int32),
                 ("lanes", ctypes.c_int32), ("lds_cap", ctypes.c_int32), ("grid", ctypes.c_int32),
                 ("bound", ctypes.c_int32), ("proposal", ctypes.c_int32), ("hub_deg", ctypes.c_int32),
-                ("hub_lanes", ctypes.c_int32)]
+                ("hub_lanes", ctypes.c_int32), ("rvs_share", ctypes.c_int32)]
 
 
 class fw_query(ctypes.Structure):

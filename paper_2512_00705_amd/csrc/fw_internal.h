@@ -135,6 +135,7 @@ struct WalkArgs {
     int32_t nlab;               // labels 0 .. nlab - 1 have groups
     int32_t hub_deg;            // eRVS rows of at least this degree use hub_v * 64 lanes (0: never)
     int32_t hub_v;              // virtual lanes per lane there: 1, 2 or 4
+    int32_t rvs_share;          // 1: eRVS lanes take the largest threshold after a round with a jump event
     uint64_t mtab_mask;         // buckets - 1
 
     QueryDev q0;                // the query of a single-query launch

@@ -208,6 +208,20 @@ __device__ __forceinline__ float weight_of_member(uint2 e, int j, int32_t prev, 
     return member ? sw.mem * hv : sw.oth * hv;
 }
 
+// Shared eRVS threshold (plan rvs_share): after a scan round in which some lane drew a
+// key, a lane whose threshold lies below the largest one, g, takes g.  Its remaining skip
+// T - S is exponential with rate -thr (no item since its last draw has passed it), so
+// scaled by thr / g it is the skip towards the first item whose key beats g; keys below g
+// cannot win the argmax.  A lane with no threshold yet (-inf) keeps T = 0.
+__device__ __forceinline__ void take_shared_threshold(float &thr, float &T, float &S, float g)
+{
+    if (thr > -INFINITY && thr < g) {
+        T = g >= 0.0f ? INFINITY : ((T - S) * thr) / g;
+        S = 0.0f;
+        thr = g;
+    }
+}
+
 // eRVS for one step, all 64 lanes cooperating.  Returns the next vertex or -1 when no
 // neighbour has positive weight, with the h of the chosen edge in `hsel`.  `trig`
 // receives the number of jump events.  `merge`: find u in N(prev) by merging the rows
@@ -246,6 +260,7 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q
         const int64_t i = i0 + lane;
         const uint2 ei = i < deg ? edge_rec(a, base + i) : make_uint2(0u, 0u);
         const bool memi = merge && merge_member(mem, (int32_t)ei.x, i < deg, mlo);
+        bool drew = false;
         if (i < deg) {
             const int64_t k = base + i;
             const float wt = merge ? weight_of_member<KIND, W>(ei, j, prev, memi, sw)
@@ -264,8 +279,10 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q
                 S = 0.0f;
                 T = thr >= 0.0f ? INFINITY : ln_f(unit_uniform(x.x1)) / thr;
                 ++nt;
+                drew = true;
             }
         }
+        if (a.rvs_share && __ballot(drew) != 0) take_shared_threshold(thr, T, S, wave_max(thr));
     }
     wave_argmax(key, bi);
     trig = (uint32_t)wave_sum_u64(nt);
@@ -328,6 +345,7 @@ __device__ __forceinline__ int32_t rvs_step_hub(const WalkArgs &a, const QueryDe
     // scan: a key is drawn only where a virtual lane's running weight passes its skip
     // threshold T = log(r) / log(k_thr)
     for (int64_t i0 = P; i0 < deg; i0 += P) {
+        bool drew = false;
         uint2 ei[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
@@ -355,8 +373,17 @@ __device__ __forceinline__ int32_t rvs_step_hub(const WalkArgs &a, const QueryDe
                     S[v] = 0.0f;
                     T[v] = thr[v] >= 0.0f ? INFINITY : ln_f(unit_uniform(x.x1)) / thr[v];
                     ++nt;
+                    drew = true;
                 }
             }
+        }
+        if (a.rvs_share && __ballot(drew) != 0) {
+            float tm = thr[0];
+#pragma unroll
+            for (int v = 1; v < V; ++v) tm = fmaxf(tm, thr[v]);
+            const float g = wave_max(tm);
+#pragma unroll
+            for (int v = 0; v < V; ++v) take_shared_threshold(thr[v], T[v], S[v], g);
         }
     }
     float key0 = key[0];

@@ -60,7 +60,7 @@ def fw_logic(lg: oracle.Logic):
 def fw_plan(pl: oracle.Plan, **speed):
     assert pl.lanes == 64 and pl.jump and pl.bound_scale == 1.0
     return fw.fw_plan_default(rho=pl.rho, d_lo=pl.d_lo, rjs_cap=pl.rjs_cap, bound=pl.bound, proposal=pl.proposal,
-                              hub_deg=pl.hub_deg, hub_lanes=pl.hub_lanes, **speed)
+                              hub_deg=pl.hub_deg, hub_lanes=pl.hub_lanes, rvs_share=int(pl.rvs_share), **speed)
 
 
 def gpu_walk(gg: GpuGraph, lg: oracle.Logic, pl: oracle.Plan, strategy: int, starts: np.ndarray, L: int,

@@ -67,7 +67,7 @@ def test_host_only_argument_checks():
     assert (lg.kind, lg.weighted, lg.p, lg.q) == (fw.FW_NODE2VEC, 1, 2.0, 0.5)
     pl = fw.fw_plan_default()
     assert (pl.rho, pl.d_lo, pl.rjs_cap, pl.lanes, pl.bound, pl.proposal) == (8.0, 0, 1024, 64, 0, 0)
-    assert (pl.hub_deg, pl.hub_lanes) == (0, 64)
+    assert (pl.hub_deg, pl.hub_lanes, pl.rvs_share) == (0, 64, 0)
     with pytest.raises(fw.FlexiWalkError):
         fw.fw_graph_create(-1, 0, None, None)
 

@@ -85,11 +85,11 @@ def test_one_off_share():
 def test_plan_argument_round_trip():
     """--plan text: a bench line's plan_arg reproduces its plan field for field; short
     forms take the library defaults; a wrong field count is refused."""
-    p = bench.parse_plan("0.43,0,1024,2,1,64,0,1024,256")
+    p = bench.parse_plan("0.43,0,1024,2,1,64,0,1024,256,1")
     assert bench.plan_dict(p) == {"rho": float(p.rho), "d_lo": 0, "lds_cap": 1024, "bound": 2, "proposal": 1,
-                                  "rjs_cap": 64, "grid": 0, "hub_deg": 1024, "hub_lanes": 256}
+                                  "rjs_cap": 64, "grid": 0, "hub_deg": 1024, "hub_lanes": 256, "rvs_share": 1}
     assert bench.plan_dict(bench.parse_plan(bench.plan_arg(p))) == bench.plan_dict(p)
     q = bench.parse_plan("0.5,8,512")
-    assert (q.bound, q.proposal, q.rjs_cap, q.hub_deg, q.hub_lanes) == (0, 0, 1024, 0, 64)
+    assert (q.bound, q.proposal, q.rjs_cap, q.hub_deg, q.hub_lanes, q.rvs_share) == (0, 0, 1024, 0, 64, 0)
     with pytest.raises(SystemExit):
         bench.parse_plan("0.5,8")

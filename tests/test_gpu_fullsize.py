@@ -83,7 +83,7 @@ def test_node2vec_scale22(g22, gg22, og22, tuned22, strategy, k, bound, proposal
     pl = oracle.Plan(rho=tuned.rho if rho is None else rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap,
                      bound=tuned.bound if bound is None else bound,
                      proposal=tuned.proposal if proposal is None else proposal, hub_deg=tuned.hub_deg,
-                     hub_lanes=tuned.hub_lanes)
+                     hub_lanes=tuned.hub_lanes, rvs_share=bool(tuned.rvs_share))
     starts = synth.all_vertices(g22["nv"])
     p, ln, st = gpu_walk(gg22, N2V, pl, strategy, starts, 80, 42)
     # the launch the benchmark times (no counter array, the counter-free kernel variant)
@@ -106,13 +106,14 @@ def test_node2vec_scale22(g22, gg22, og22, tuned22, strategy, k, bound, proposal
         assert (ora.kinds == 0).any() and (ora.kinds == 1).any()
 
 
-@pytest.mark.parametrize("hub_deg,hub_lanes", [(1024, 256), (4096, 128)])
-def test_node2vec_scale22_hub_lanes(g22, gg22, og22, tuned22, hub_deg, hub_lanes):
+@pytest.mark.parametrize("hub_deg,hub_lanes,share", [(1024, 256, False), (4096, 128, False), (0, 64, True),
+                                                     (1024, 256, True)])
+def test_node2vec_scale22_hub_lanes(g22, gg22, og22, tuned22, hub_deg, hub_lanes, share):
     """eRVS-only at scale 22 with P = hub_lanes on rows of degree >= hub_deg (a third of the
-    steps, most of the scanned entries): 16,384 sampled walkers against the oracle with
-    the same degree bucket."""
+    steps, most of the scanned entries), and with the lanes' shared threshold: 16,384
+    sampled walkers against the oracle with the same degree bucket and sharing."""
     pl = oracle.Plan(rho=tuned22.rho, d_lo=tuned22.d_lo, rjs_cap=tuned22.rjs_cap, bound=tuned22.bound,
-                     proposal=tuned22.proposal, hub_deg=hub_deg, hub_lanes=hub_lanes)
+                     proposal=tuned22.proposal, hub_deg=hub_deg, hub_lanes=hub_lanes, rvs_share=share)
     starts = synth.all_vertices(g22["nv"])
     p, ln, st = gpu_walk(gg22, N2V, pl, oracle.RVS_ONLY, starts, 80, 42, counters=False)
     ok, pad_ok, _ = edge_check_torch(g22, p, ln)
@@ -120,7 +121,7 @@ def test_node2vec_scale22_hub_lanes(g22, gg22, og22, tuned22, hub_deg, hub_lanes
     sub = _sample(g22["nv"], 16384, 1234)
     ora = oracle.walk(og22, N2V, pl, oracle.RVS_ONLY, starts[sub], 80, 42, walker_ids=sub)
     rep = parity(p[sub], ln[sub], ora)
-    print("scale22 hub lanes", hub_deg, hub_lanes, {k2: (v if not isinstance(v, list) else len(v))
+    print("scale22 hub lanes", hub_deg, hub_lanes, share, {k2: (v if not isinstance(v, list) else len(v))
                                                     for k2, v in rep.items()})
     assert_parity(rep)
     assert rep["steps"] >= 16384 * 40
@@ -135,7 +136,7 @@ def test_second_pr_scale22(g22, gg22, og22, bound):
     tuned = fw.fw_plan_autotune(gg22.handle, fw.fw_logic_second_pr(0.2, True))
     pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap,
                      bound=tuned.bound if bound is None else bound, proposal=tuned.proposal,
-                     hub_deg=tuned.hub_deg, hub_lanes=tuned.hub_lanes)
+                     hub_deg=tuned.hub_deg, hub_lanes=tuned.hub_lanes, rvs_share=bool(tuned.rvs_share))
     starts = synth.all_vertices(g22["nv"])
     p, ln, st = gpu_walk(gg22, lg, pl, oracle.AUTO, starts, 80, 42)
     p2, ln2, _ = gpu_walk(gg22, lg, pl, oracle.AUTO, starts, 80, 42, counters=False)
@@ -164,7 +165,8 @@ def test_node2vec_scale22_h8(g22):
         starts = synth.all_vertices(g22["nv"])
         for strategy, k in ((oracle.AUTO, 65536), (oracle.RVS_ONLY, 16384)):
             pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap, bound=tuned.bound,
-                             proposal=tuned.proposal, hub_deg=tuned.hub_deg, hub_lanes=tuned.hub_lanes)
+                             proposal=tuned.proposal, hub_deg=tuned.hub_deg, hub_lanes=tuned.hub_lanes,
+                             rvs_share=bool(tuned.rvs_share))
             p, ln, st = gpu_walk(gg, N2V, pl, strategy, starts, 80, 42)
             ok, pad_ok, _ = edge_check_torch(g22, p, ln)
             assert ok and pad_ok
@@ -184,7 +186,8 @@ def test_metapath_scale22(g22, gg22, og22, proposal):
     proposals forced; every walker replayed by the oracle."""
     tuned = fw.fw_plan_autotune(gg22.handle, fw.fw_logic_metapath([0, 1, 2, 3, 4], True))
     pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap, hub_deg=tuned.hub_deg,
-                     hub_lanes=tuned.hub_lanes, proposal=tuned.proposal if proposal is None else proposal)
+                     hub_lanes=tuned.hub_lanes, proposal=tuned.proposal if proposal is None else proposal,
+                     rvs_share=bool(tuned.rvs_share))
     starts = synth.uniform_starts(g22["nv"], 1 << 20, 42)
     p, ln, st = gpu_walk(gg22, MP, pl, oracle.AUTO, starts, 40, 42)
     ok, pad_ok, (pos, taken) = edge_check_torch(g22, p, ln)
@@ -218,7 +221,7 @@ def test_batched_scale24():
         stats = torch.zeros(fw.FW_NSTATS, dtype=torch.int64, device=dev)
         tuned = fw.fw_plan_autotune(gg.handle, fw.fw_logic_node2vec(1.0, 1.0, True))
         pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap, bound=tuned.bound,
-                         proposal=tuned.proposal)
+                         proposal=tuned.proposal, rvs_share=bool(tuned.rvs_share))
         qs = []
         for i in range(4096):
             q = fw.fw_query()
@@ -283,7 +286,7 @@ def test_served_scale25():
         mix.append(fw.fw_logic_metapath([0, 1, 2, 3, 4], True))
         tuned = fw.fw_plan_autotune_mix(gg.handle, mix)
         pl = oracle.Plan(rho=tuned.rho, d_lo=tuned.d_lo, rjs_cap=tuned.rjs_cap, bound=tuned.bound,
-                         proposal=tuned.proposal)
+                         proposal=tuned.proposal, rvs_share=bool(tuned.rvs_share))
         print("plan", tuned.rho, tuned.d_lo, tuned.lds_cap, tuned.bound, tuned.proposal, tuned.rjs_cap, flush=True)
         rng = np.random.default_rng(25)
         reqs = []

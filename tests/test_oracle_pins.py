@@ -124,6 +124,7 @@ STRATS = [
     ("rvs_P1", oracle.RVS_ONLY, oracle.Plan(lanes=1)),
     ("rvs_P2", oracle.RVS_ONLY, oracle.Plan(lanes=2)),
     ("rvs_P64", oracle.RVS_ONLY, oracle.Plan(lanes=64)),
+    ("rvs_P2_share", oracle.RVS_ONLY, oracle.Plan(lanes=2, rvs_share=True)),
     ("rvs_nojump", oracle.RVS_ONLY, oracle.Plan(jump=False)),
     ("rjs", oracle.RJS_ONLY, oracle.Plan()),
     ("rjs_x4", oracle.RJS_ONLY, oracle.Plan(bound_scale=4.0)),
@@ -186,6 +187,10 @@ def _hub_case(plan, strategy, n=40000, seed=5):
     ("rvs_jump_P256", oracle.RVS_ONLY, oracle.Plan(lanes=256)),
     ("rvs_jump_P1024", oracle.RVS_ONLY, oracle.Plan(lanes=1024)),
     ("rvs_hub_bucket_P256", oracle.RVS_ONLY, oracle.Plan(hub_deg=600, hub_lanes=256)),
+    ("rvs_share_P7", oracle.RVS_ONLY, oracle.Plan(lanes=7, rvs_share=True)),
+    ("rvs_share_P64", oracle.RVS_ONLY, oracle.Plan(lanes=64, rvs_share=True)),
+    ("rvs_share_P256", oracle.RVS_ONLY, oracle.Plan(lanes=256, rvs_share=True)),
+    ("rvs_share_hub_bucket_P128", oracle.RVS_ONLY, oracle.Plan(hub_deg=600, hub_lanes=128, rvs_share=True)),
     ("rvs_nojump", oracle.RVS_ONLY, oracle.Plan(jump=False)),
     ("rjs", oracle.RJS_ONLY, oracle.Plan()),
 ])
@@ -213,6 +218,38 @@ def test_hub_lane_bucket_dispatch():
     assert np.array_equal(walk(oracle.Plan(hub_deg=600, hub_lanes=256)), p256)
     assert np.array_equal(walk(oracle.Plan(hub_deg=601, hub_lanes=256)), p64)
     assert np.array_equal(walk(oracle.Plan(hub_deg=0, hub_lanes=256)), p64)
+
+
+def test_rvs_share_draws_fewer_keys():
+    """Sharing the largest threshold after each round with a jump event leaves fewer lanes
+    able to pass it: at the 600-neighbour hub with 64 lanes the key draws per step fall by
+    more than half (the sampler stays exact: test_hub_distribution)."""
+    _, paper = _hub_case(oracle.Plan(lanes=64), oracle.RVS_ONLY)
+    _, share = _hub_case(oracle.Plan(lanes=64, rvs_share=True), oracle.RVS_ONLY)
+    assert share.counters["steps"] == paper.counters["steps"]
+    assert share.counters["rvs_triggers"] < 0.5 * paper.counters["rvs_triggers"]
+
+
+def test_rvs_share_cases_that_equal_the_paper_form():
+    """Where no lane can hold a threshold below another's the shared form is the paper's
+    bit for bit: one lane (P = 1), and rows of at most P entries (round 0 decides them)."""
+    og = oracle.Graph(hub_ring_graph())
+    lg = oracle.Logic(**N2V)
+    starts = np.arange(0, 601, dtype=np.int32)
+    walk = lambda pl: oracle.walk(og, lg, pl, oracle.RVS_ONLY, starts, 5, 23, diagnostics=False)
+    a, b = walk(oracle.Plan(lanes=1)), walk(oracle.Plan(lanes=1, rvs_share=True))
+    np.testing.assert_array_equal(a.paths, b.paths)
+    assert a.counters == b.counters
+    a, b = walk(oracle.Plan(lanes=1024)), walk(oracle.Plan(lanes=1024, rvs_share=True))
+    np.testing.assert_array_equal(a.paths, b.paths)
+    # with P = 64 the hub's scan differs
+    a, b = walk(oracle.Plan(lanes=64)), walk(oracle.Plan(lanes=64, rvs_share=True))
+    assert a.counters["rvs_triggers"] != b.counters["rvs_triggers"]
+
+
+def _pin_rvs_share():
+    for lanes in (7, 64):
+        test_hub_distribution(f"share{lanes}", oracle.RVS_ONLY, oracle.Plan(lanes=lanes, rvs_share=True))
 
 
 def test_rjs_mean_trials_and_known_bound():
@@ -915,9 +952,14 @@ MUTANTS = {
     11: "cost model's choice inverted",
     12: "row pointer pair charged 8 bytes instead of 16",
     13: "label groups proposed uniformly, ignoring h",
+    14: "shared eRVS threshold rescales the skip by the inverted ratio",
+    15: "shared eRVS threshold taken without rescaling the skip",
 }
-# planted mistakes caught by deterministic pins (hand-computed states), not by chi-square
-DETERMINISTIC_PINS = {10: "_pin_selector", 11: "_pin_selector", 12: "_pin_bytes", 13: "_pin_label_groups"}
+# planted mistakes caught by a pin of their own: hand-computed states (10-13), or the
+# hub-row chi-square of the shared eRVS threshold (14, 15), where the triangle graph's
+# rows are too short for the scan to pass a shared threshold often
+OWN_PINS = {10: "_pin_selector", 11: "_pin_selector", 12: "_pin_bytes", 13: "_pin_label_groups",
+            14: "_pin_rvs_share", 15: "_pin_rvs_share"}
 
 
 def _pin_label_groups():
@@ -932,10 +974,10 @@ def mutant_libs(tmp_path_factory):
 
 @pytest.mark.parametrize("mut", sorted(MUTANTS), ids=[MUTANTS[k] for k in sorted(MUTANTS)])
 def test_planted_mistake_is_caught(mut, mutant_libs):
-    if mut in DETERMINISTIC_PINS:
+    if mut in OWN_PINS:
         with oracle.use_library(mutant_libs[mut]):
             with pytest.raises(AssertionError):
-                globals()[DETERMINISTIC_PINS[mut]]()
+                globals()[OWN_PINS[mut]]()
         return
     g = triangle_graph(labels=True)
     caught = []
