@@ -483,7 +483,8 @@ int fw_walk(fw_graph *g, const fw_logic *lg, const fw_plan *pl, int32_t strategy
     a.q0.key0 = (uint32_t)seed;
     a.q0.key1 = (uint32_t)(seed >> 32);
     a.nq = 1;
-    const int grid = pl->grid > 0 ? pl->grid : fw::walk_grid(lg->kind, weighted, false, a.lds_cap, n);
+    const int grid =
+        pl->grid > 0 ? pl->grid : fw::walk_grid(lg->kind, weighted, false, a.lds_cap, n, strategy == FW_RVS_ONLY);
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(fw::launch_zero(g->scratch, 1, s));
     HIP_TRY(fw::launch_walk(a, lg->kind, weighted, false, grid, s));

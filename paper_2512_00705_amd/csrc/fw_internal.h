@@ -68,6 +68,8 @@ constexpr int kMergeRatio = FW_MERGE_RATIO;  // eRVS merges N(v) with N(prev) wh
 constexpr int kMinWaves = FW_MIN_WAVES;
 constexpr int kMinWavesBatch = FW_MIN_WAVES_BATCH;
 constexpr int kMinWavesCounted = 4;
+// the eRVS-only variant (no eRJS code) fits 6 waves in its registers without spills
+constexpr int kMinWavesRvsOnly = 6;
 
 // Per-query constants of a walk job.  Float constants are prepared on the host in float32
 // exactly as the definition states, so every float32 evaluation agrees bit for bit.
@@ -197,6 +199,9 @@ hipError_t launch_profile(const WalkArgs &a, int kind, bool weighted, bool rjs_s
                           int nsample, int per_node, float *sink, hipStream_t s);
 // {vertex k * stride, its degree} for k < n (stride * (n - 1) < nv).
 hipError_t launch_profile_pick(const int64_t *row_ptr, int64_t stride, int n, int2 *out, hipStream_t s);
-int walk_grid(int kind, bool weighted, bool batch, int lds_cap, int64_t n);
+// Persistent grid filling the device: resident blocks per CU (of the counter-free kernel
+// variant the launch takes: batched, eRVS-only (strategy FW_RVS_ONLY, single query) or the
+// general one) times the CUs, at most one block per 256 walkers.
+int walk_grid(int kind, bool weighted, bool batch, int lds_cap, int64_t n, bool rvs_only = false);
 
 }  // namespace fw

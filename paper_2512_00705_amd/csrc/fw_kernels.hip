@@ -197,6 +197,48 @@ __device__ __forceinline__ bool merge_member(const Mem &m, int32_t u, bool valid
     return found;
 }
 
+// merge_member with the block of N(prev) at the cursor loaded before the items are first
+// used (it does not depend on them), so that its load overlaps the load of the round's
+// edges instead of following it.  Same results.  Used by the eRVS-only kernel variant: in
+// the others the register budget is held by the eRJS path, where the longer-lived block
+// spills.
+__device__ __forceinline__ bool merge_member_early(const Mem &m, int32_t u, bool valid, int64_t &lo)
+{
+    const int lane = lane_id();
+    int32_t v = lo + lane < m.len ? m.p[lo + lane] : INT32_MAX;
+    const uint64_t vm = __ballot(valid);
+    if (vm == 0) return false;
+    const int32_t umax = __builtin_amdgcn_readlane(u, 63 - __builtin_clzll((unsigned long long)vm));
+    if (umax < __builtin_amdgcn_readfirstlane(v)) return false;
+    bool found = false, done = !valid;
+    int32_t c = 0;
+    for (;;) {
+        c = 0;
+#pragma unroll
+        for (int s = kWave / 2; s > 0; s >>= 1) {
+            const int32_t pv = __shfl(v, c + s - 1, kWave);
+            if (pv < u) c += s;
+        }
+        const int32_t vc = __shfl(v, c & (kWave - 1), kWave);
+        const int32_t vlast = __shfl(v, kWave - 1, kWave);
+        if (!done) {
+            found = c < kWave && vc == u;
+            done = u <= vlast;
+        }
+        if (__ballot(!done) == 0) break;
+        lo += kWave;
+        v = lo + lane < m.len ? m.p[lo + lane] : INT32_MAX;
+    }
+    lo += __shfl(c, kWave - 1, kWave);
+    return found;
+}
+
+template <bool EARLY>
+__device__ __forceinline__ bool merge_member_t(const Mem &m, int32_t u, bool valid, int64_t &lo)
+{
+    return EARLY ? merge_member_early(m, u, valid, lo) : merge_member(m, u, valid, lo);
+}
+
 // Transition weight from the membership of u in N(prev) (the same expression as
 // edge_weight, for Node2Vec and second-order PageRank).
 template <int KIND, bool W>
@@ -226,7 +268,7 @@ __device__ __forceinline__ void take_shared_threshold(float &thr, float &T, floa
 // neighbour has positive weight, with the h of the chosen edge in `hsel`.  `trig`
 // receives the number of jump events.  `merge`: find u in N(prev) by merging the rows
 // (merge_member) instead of searching `mem` per item.
-template <int KIND, bool W>
+template <int KIND, bool W, bool EARLY>
 __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q, const Mem &mem, uint32_t wid,
                                             int j, int32_t prev, int64_t base, int64_t deg, uint8_t want,
                                             const StepW &sw, uint32_t &trig, float &hsel, bool merge)
@@ -239,7 +281,7 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q
     int64_t mlo = 0;  // merge cursor in N(prev)
     // round 0: lane l keys neighbour l, k = u^(1/w~) kept as log(u) / w~
     const uint2 e0 = lane < deg ? edge_rec(a, base + lane) : make_uint2(0u, 0u);
-    const bool mem0 = merge && merge_member(mem, (int32_t)e0.x, lane < deg, mlo);
+    const bool mem0 = merge && merge_member_t<EARLY>(mem, (int32_t)e0.x, lane < deg, mlo);
     if (lane < deg) {
         const int64_t k = base + lane;
         const float wt = merge ? weight_of_member<KIND, W>(e0, j, prev, mem0, sw)
@@ -259,7 +301,7 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q
     for (int64_t i0 = kWave; i0 < deg; i0 += kWave) {
         const int64_t i = i0 + lane;
         const uint2 ei = i < deg ? edge_rec(a, base + i) : make_uint2(0u, 0u);
-        const bool memi = merge && merge_member(mem, (int32_t)ei.x, i < deg, mlo);
+        const bool memi = merge && merge_member_t<EARLY>(mem, (int32_t)ei.x, i < deg, mlo);
         bool drew = false;
         if (i < deg) {
             const int64_t k = base + i;
@@ -298,7 +340,7 @@ __device__ __forceinline__ int32_t rvs_step(const WalkArgs &a, const QueryDev &Q
 // so a long row is scanned with V times the reads in flight.  Results, `trig` and `hsel`
 // as for rvs_step; the lane's best virtual lane (larger index wins ties) then enters the
 // wave's argmax.
-template <int KIND, bool W, int V>
+template <int KIND, bool W, int V, bool EARLY>
 __device__ __forceinline__ int32_t rvs_step_hub(const WalkArgs &a, const QueryDev &Q, const Mem &mem, uint32_t wid,
                                             int j, int32_t prev, int64_t base, int64_t deg, uint8_t want,
                                             const StepW &sw, uint32_t &trig, float &hsel, bool merge)
@@ -320,7 +362,7 @@ __device__ __forceinline__ int32_t rvs_step_hub(const WalkArgs &a, const QueryDe
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const int64_t l = lane + kWave * v;
-        const bool memv = merge && merge_member(mem, (int32_t)e0[v].x, l < deg, mlo);
+        const bool memv = merge && merge_member_t<EARLY>(mem, (int32_t)e0[v].x, l < deg, mlo);
         key[v] = -INFINITY;
         bi[v] = -1;
         T[v] = 0.5f;  // holds the threshold draw until lkg is known
@@ -355,7 +397,7 @@ __device__ __forceinline__ int32_t rvs_step_hub(const WalkArgs &a, const QueryDe
 #pragma unroll
         for (int v = 0; v < V; ++v) {
             const int64_t i = i0 + lane + kWave * v;
-            const bool memi = merge && merge_member(mem, (int32_t)ei[v].x, i < deg, mlo);
+            const bool memi = merge && merge_member_t<EARLY>(mem, (int32_t)ei[v].x, i < deg, mlo);
             if (i < deg) {
                 const float wt = merge ? weight_of_member<KIND, W>(ei[v], j, prev, memi, sw)
                                        : edge_weight<KIND, W>(a, Q, base + i, ei[v], j, prev, mem, want, sw);
@@ -496,8 +538,11 @@ __device__ __forceinline__ void flush_stats(const WalkArgs &a, uint32_t (&cnt)[k
 // per-lane counts are dead code and their registers go to the walk.
 // HV: virtual lanes per lane of eRVS on rows of degree >= hub_deg (P = 64 * HV there); a
 // variant of its own so that the extra lane state costs the other plans no registers.
-template <int KIND, bool W, bool BATCH, bool MB, bool STATS, int HV = 1>
-__global__ void __launch_bounds__(kBlock, (STATS || HV > 1) ? kMinWavesCounted : (BATCH ? kMinWavesBatch : kMinWaves))
+// RO: the launch samples every step by eRVS (FW_RVS_ONLY): the eRJS code is left out, and
+// the eRVS merge loads each block of N(prev) ahead of the round's items (merge_member_early)
+template <int KIND, bool W, bool BATCH, bool MB, bool STATS, int HV = 1, bool RO = false>
+__global__ void __launch_bounds__(kBlock, (STATS || HV > 1) ? kMinWavesCounted
+                                                          : (BATCH ? kMinWavesBatch : (RO ? kMinWavesRvsOnly : kMinWaves)))
 walk_kernel(WalkArgs a)
 {
     extern __shared__ int32_t lds_all[];
@@ -660,7 +705,9 @@ walk_kernel(WalkArgs a)
                         pbase = g0;  // MetaPath has no N(prev): these hold the group
                         pdeg = (int32_t)(g1 - g0);
                         bool rjs;
-                        if (a.strategy == kRjsOnly) {
+                        if (RO) {
+                            rjs = false;
+                        } else if (a.strategy == kRjsOnly) {
                             rjs = true;
                         } else if (a.strategy == kRandomSelect) {
                             const U4 x = philox((uint32_t)wid, (uint32_t)j, 0u, 4u, Q.key0, Q.key1);
@@ -685,7 +732,7 @@ walk_kernel(WalkArgs a)
                 } else {
                     bool rjs = false;
                     fell_back = false;
-                    if (a.strategy != kRvsOnly) {
+                    if (!RO && a.strategy != kRvsOnly) {
                         float wmax = (j == 0) ? Q.wmax0 : Q.wmax1;
                         float wavg = (j == 0) ? Q.wavg0 : Q.wavg1;
                         if (KIND == kSecondPR && j > 0) {
@@ -768,7 +815,7 @@ walk_kernel(WalkArgs a)
         // 3. eRJS trials inside the lane (Section 3.3): propose uniformly, accept if
         //    U * B < w~; the membership search runs only when the bounds of w~ leave
         //    the test open
-        if (mode == kRjs) {
+        if (!RO && mode == kRjs) {
             const QueryDev &Q = query<BATCH>(a, q);
             const uint8_t want = (KIND == kMetaPath) ? Q.schema[j % Q.schema_len] : (uint8_t)0;
             // issue the loads of the next kRjsBatch proposals together, then decide them
@@ -1033,10 +1080,10 @@ walk_kernel(WalkArgs a)
                 const StepW sw = step_weights<KIND>(Q, s_deg, s_pdeg);
                 // P = 64 lanes, or 64 * HV on a row of degree >= hub_deg
                 if (HV > 1 && a.hub_deg > 0 && s_deg >= a.hub_deg)
-                    res = rvs_step_hub<KIND, W, HV>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, sw, trig, hres,
+                    res = rvs_step_hub<KIND, W, HV, RO>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, sw, trig, hres,
                                                     merge);
                 else
-                    res = rvs_step<KIND, W>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, sw, trig, hres, merge);
+                    res = rvs_step<KIND, W, RO>(a, Q, m, s_wid, s_j, s_prev, s_base, s_deg, want, sw, trig, hres, merge);
                 if (lane == src) served(res, hres, trig);
             }
         }
@@ -1746,7 +1793,10 @@ hipError_t launch_random_reads(const uint2 *a, uint64_t mask, int blocks, int ro
 template <int KIND, bool W, bool BATCH, bool STATS, int HV>
 static void launch_walk_h(const WalkArgs &a, int grid, size_t lds, hipStream_t s)
 {
-    if (uses_membership(KIND) && a.bound == 2)
+    if (!BATCH && a.strategy == kRvsOnly)
+        hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, false, STATS, HV, !BATCH>), dim3(grid), dim3(kBlock), lds, s,
+                           a);
+    else if (uses_membership(KIND) && a.bound == 2)
         hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, uses_membership(KIND), STATS, HV>), dim3(grid), dim3(kBlock),
                            lds, s, a);
     else
@@ -1788,35 +1838,37 @@ hipError_t launch_walk(const WalkArgs &a, int kind, bool weighted, bool batch, i
     return batch ? launch_walk_b<true>(a, kind, weighted, grid, s) : launch_walk_b<false>(a, kind, weighted, grid, s);
 }
 
-template <int KIND, bool W, bool BATCH>
+template <int KIND, bool W, bool BATCH, bool RO>
 static int occupancy_blocks(int lds_cap)
 {
     int nb = 0;
     const size_t lds = walk_lds_bytes(lds_cap);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<KIND, W, BATCH, false, false>, kBlock, lds) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<KIND, W, BATCH, false, false, 1, RO>, kBlock,
+                                                     lds) != hipSuccess)
         nb = 1;
     return nb > 0 ? nb : 1;
 }
 
-template <bool BATCH>
+template <bool BATCH, bool RO>
 static int occupancy_b(int kind, bool weighted, int lds_cap)
 {
-    if (kind == kNode2Vec) return weighted ? occupancy_blocks<kNode2Vec, true, BATCH>(lds_cap)
-                                           : occupancy_blocks<kNode2Vec, false, BATCH>(lds_cap);
-    if (kind == kSecondPR) return weighted ? occupancy_blocks<kSecondPR, true, BATCH>(lds_cap)
-                                           : occupancy_blocks<kSecondPR, false, BATCH>(lds_cap);
-    return weighted ? occupancy_blocks<kMetaPath, true, BATCH>(lds_cap)
-                    : occupancy_blocks<kMetaPath, false, BATCH>(lds_cap);
+    if (kind == kNode2Vec) return weighted ? occupancy_blocks<kNode2Vec, true, BATCH, RO>(lds_cap)
+                                           : occupancy_blocks<kNode2Vec, false, BATCH, RO>(lds_cap);
+    if (kind == kSecondPR) return weighted ? occupancy_blocks<kSecondPR, true, BATCH, RO>(lds_cap)
+                                           : occupancy_blocks<kSecondPR, false, BATCH, RO>(lds_cap);
+    return weighted ? occupancy_blocks<kMetaPath, true, BATCH, RO>(lds_cap)
+                    : occupancy_blocks<kMetaPath, false, BATCH, RO>(lds_cap);
 }
 
-int walk_grid(int kind, bool weighted, bool batch, int lds_cap, int64_t n)
+int walk_grid(int kind, bool weighted, bool batch, int lds_cap, int64_t n, bool rvs_only)
 {
     int dev = 0, cus = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (cus <= 0) cus = 1;
-    const int nb = batch ? occupancy_b<true>(kind, weighted, lds_cap) : occupancy_b<false>(kind, weighted, lds_cap);
+    const int nb = batch ? occupancy_b<true, false>(kind, weighted, lds_cap)
+                         : (rvs_only ? occupancy_b<false, true>(kind, weighted, lds_cap)
+                                     : occupancy_b<false, false>(kind, weighted, lds_cap));
     int64_t grid = (int64_t)nb * cus;
     const int64_t need = (n + kBlock - 1) / kBlock;
     if (grid > need) grid = need;
