@@ -69,7 +69,7 @@ constexpr int kMinWaves = FW_MIN_WAVES;
 constexpr int kMinWavesBatch = FW_MIN_WAVES_BATCH;
 constexpr int kMinWavesCounted = 4;
 // the eRVS-only variant (no eRJS code) fits 6 waves in its registers without spills
-constexpr int kMinWavesRvsOnly = 6;
+constexpr int kMinWavesRvsOnly = 7;
 
 // Per-query constants of a walk job.  Float constants are prepared on the host in float32
 // exactly as the definition states, so every float32 evaluation agrees bit for bit.

@@ -29,9 +29,12 @@ enum Mode : int { kIdle = 0, kSetup = 1, kRjs = 2, kRvs = 3, kAdv = 4 };
 
 // Dynamic LDS of a walk block: each wave's four slots of 64 vertex records filled by LDS DMA
 // from proposal records, then each wave's N(prev) staging area (lds_cap int32).
-static size_t walk_lds_bytes(int lds_cap)
+// Dynamic LDS of a walk block: per wave, four slots of 64 vertex records (eRJS proposals'
+// candidates; not in the eRVS-only variant, rvs_only) and lds_cap entries of N(prev).
+static size_t walk_lds_bytes(int lds_cap, bool rvs_only = false)
 {
-    return (size_t)kWavesPerBlock * (size_t)lds_cap * sizeof(int32_t) + (size_t)kWavesPerBlock * 4 * kWave * 16;
+    return (size_t)kWavesPerBlock * (size_t)lds_cap * sizeof(int32_t) +
+           (rvs_only ? 0 : (size_t)kWavesPerBlock * 4 * kWave * 16);
 }
 
 // An LDS address for the LDS-DMA load builtin (the pointer must lie in this block's LDS).
@@ -197,40 +200,54 @@ __device__ __forceinline__ bool merge_member(const Mem &m, int32_t u, bool valid
     return found;
 }
 
-// merge_member with the block of N(prev) at the cursor loaded before the items are first
-// used (it does not depend on them), so that its load overlaps the load of the round's
-// edges instead of following it.  Same results.  Used by the eRVS-only kernel variant: in
-// the others the register budget is held by the eRJS path, where the longer-lived block
-// spills.
+// merge_member for the eRVS-only kernel variant, same results.  The block of N(prev) at
+// the cursor is loaded before the items are first used (it does not depend on them), so
+// that its load overlaps the load of the round's edges instead of following it.  Of the
+// block, only entries within [smallest item, largest item] can equal an item; when there
+// are few (a hub row scanned against a shorter N(prev): a handful per round), each is
+// broadcast from its lane and compared with every item at once, with no LDS round trip;
+// otherwise each lane bisects the block as merge_member does.  The cursor then moves past
+// every entry up to the largest item (later rounds hold only larger items).  In the other
+// kernel variants the register budget is held by the eRJS path, where the longer-lived
+// block spilled.
+constexpr int kMergeBcast = 16;  // most in-range entries compared by broadcast
 __device__ __forceinline__ bool merge_member_early(const Mem &m, int32_t u, bool valid, int64_t &lo)
 {
     const int lane = lane_id();
     int32_t v = lo + lane < m.len ? m.p[lo + lane] : INT32_MAX;
     const uint64_t vm = __ballot(valid);
     if (vm == 0) return false;
+    // items are consecutive entries of a sorted row held by a prefix of the lanes
+    const int32_t umin = __builtin_amdgcn_readlane(u, __builtin_ctzll((unsigned long long)vm));
     const int32_t umax = __builtin_amdgcn_readlane(u, 63 - __builtin_clzll((unsigned long long)vm));
     if (umax < __builtin_amdgcn_readfirstlane(v)) return false;
-    bool found = false, done = !valid;
-    int32_t c = 0;
+    bool found = false;
     for (;;) {
-        c = 0;
+        const uint64_t inr = __ballot(v >= umin && v <= umax);
+        if (__popcll(inr) <= kMergeBcast) {
+            for (uint64_t mm = inr; mm != 0; mm &= mm - 1) {
+                const int32_t e = __builtin_amdgcn_readlane(v, __builtin_ctzll((unsigned long long)mm));
+                found = found || u == e;
+            }
+        } else {
+            int32_t c = 0;
 #pragma unroll
-        for (int s = kWave / 2; s > 0; s >>= 1) {
-            const int32_t pv = __shfl(v, c + s - 1, kWave);
-            if (pv < u) c += s;
+            for (int s = kWave / 2; s > 0; s >>= 1) {
+                const int32_t pv = __shfl(v, c + s - 1, kWave);
+                if (pv < u) c += s;
+            }
+            const int32_t vc = __shfl(v, c & (kWave - 1), kWave);
+            found = found || (c < kWave && vc == u);
         }
-        const int32_t vc = __shfl(v, c & (kWave - 1), kWave);
-        const int32_t vlast = __shfl(v, kWave - 1, kWave);
-        if (!done) {
-            found = c < kWave && vc == u;
-            done = u <= vlast;
+        const uint64_t le = __ballot(v <= umax);  // a prefix of the block: entries up to the largest item
+        if (~le != 0ull) {
+            lo += __popcll(le);
+            break;
         }
-        if (__ballot(!done) == 0) break;
         lo += kWave;
         v = lo + lane < m.len ? m.p[lo + lane] : INT32_MAX;
     }
-    lo += __shfl(c, kWave - 1, kWave);
-    return found;
+    return found && valid;
 }
 
 template <bool EARLY>
@@ -551,7 +568,7 @@ walk_kernel(WalkArgs a)
     // (its offset is uniform over the wave; readfirstlane keeps it in a scalar register)
     uint4 *nvstage = reinterpret_cast<uint4 *>(lds_all) +
                      __builtin_amdgcn_readfirstlane((uint32_t)(threadIdx.x / kWave) * 4 * kWave);
-    int32_t *lds = lds_all + kWavesPerBlock * 4 * kWave * 4 + (threadIdx.x / kWave) * a.lds_cap;
+    int32_t *lds = lds_all + (RO ? 0 : kWavesPerBlock * 4 * kWave * 4) + (threadIdx.x / kWave) * a.lds_cap;
     const int lane = lane_id();
     const uint64_t below = lanes_below(lane);
 
@@ -1794,8 +1811,8 @@ template <int KIND, bool W, bool BATCH, bool STATS, int HV>
 static void launch_walk_h(const WalkArgs &a, int grid, size_t lds, hipStream_t s)
 {
     if (!BATCH && a.strategy == kRvsOnly)
-        hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, false, STATS, HV, !BATCH>), dim3(grid), dim3(kBlock), lds, s,
-                           a);
+        hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, false, STATS, HV, !BATCH>), dim3(grid), dim3(kBlock),
+                           walk_lds_bytes(a.lds_cap, true), s, a);
     else if (uses_membership(KIND) && a.bound == 2)
         hipLaunchKernelGGL((walk_kernel<KIND, W, BATCH, uses_membership(KIND), STATS, HV>), dim3(grid), dim3(kBlock),
                            lds, s, a);
@@ -1842,7 +1859,7 @@ template <int KIND, bool W, bool BATCH, bool RO>
 static int occupancy_blocks(int lds_cap)
 {
     int nb = 0;
-    const size_t lds = walk_lds_bytes(lds_cap);
+    const size_t lds = walk_lds_bytes(lds_cap, RO);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, walk_kernel<KIND, W, BATCH, false, false, 1, RO>, kBlock,
                                                      lds) != hipSuccess)
         nb = 1;
