@@ -210,7 +210,7 @@ __device__ __forceinline__ bool merge_member(const Mem &m, int32_t u, bool valid
 // every entry up to the largest item (later rounds hold only larger items).  In the other
 // kernel variants the register budget is held by the eRJS path, where the longer-lived
 // block spilled.
-constexpr int kMergeBcast = 16;  // most in-range entries compared by broadcast
+constexpr int kMergeBcast = 8;  // most in-range entries compared by broadcast (8: 2.98 s, 16: 3.01 s, 32: 3.20 s on eRVS-only scale 22)
 __device__ __forceinline__ bool merge_member_early(const Mem &m, int32_t u, bool valid, int64_t &lo)
 {
     const int lane = lane_id();

@@ -6,7 +6,7 @@ also sorted, by walking a cursor through N(prev) in blocks of 64 (Section 3.2's 
 the Node2Vec weight of Eq. (node2vec), whose middle case is that membership).  Two forms
 run on the device: the bisection of each lane's item in the block, and, in the eRVS-only
 kernel variant, the broadcast of the few block entries that lie between the round's
-smallest and largest item (a bisection when there are more than 16), the cursor moving
+smallest and largest item (a bisection when there are more than 8), the cursor moving
 past every entry up to the largest item.  This replica restates both loops in plain Python
 and checks them against set membership over whole scans: dense and sparse N(prev), empty
 N(prev), N(prev) entirely below or above the row, entries equal to a round's first or
@@ -56,7 +56,7 @@ def merge_bisect(nprev, items, valid, lo):
     return found, lo + cs[W - 1]
 
 
-def merge_broadcast(nprev, items, valid, lo, bcast=16):
+def merge_broadcast(nprev, items, valid, lo, bcast=8):
     """The eRVS-only variant's form: (found per lane, new cursor)."""
     vm = [l for l in range(W) if valid[l]]
     if not vm:
@@ -117,7 +117,7 @@ CASES = [  # (row length, N(prev) length, universe)
 ]
 
 
-@pytest.mark.parametrize("bcast", [16, 0, 64])
+@pytest.mark.parametrize("bcast", [8, 0, 64])
 @pytest.mark.parametrize("case", CASES, ids=[f"{a}x{b}" for a, b, _ in CASES])
 def test_merge_forms_equal_membership(case, bcast):
     n_row, n_prev, universe = case
