@@ -469,7 +469,7 @@ def bench_skew(args):
                  "auto_uniform_proposals": (fw.FW_AUTO, uni),
                  "random": (fw.FW_RANDOM_SELECT, plan),
                  "degree": (fw.FW_DEGREE_SELECT, fw.fw_plan_default(d_lo=1000, bound=plan.bound,
-                                                                   proposal=plan.proposal)),
+                                                                   proposal=plan.proposal, lds_cap=plan.lds_cap)),
                  "rjs_only": (fw.FW_RJS_ONLY, plan),
                  "rvs_only": (fw.FW_RVS_ONLY, plan)}
         row = {"weights": name, "h_max": float(h.max()), "h_median": float(np.median(h)), "plan_rho": plan.rho,

@@ -32,7 +32,8 @@ enum Stat : int {
 
 constexpr int kBlock = 256;          // 4 wavefronts per block, each independent
 constexpr int kWavesPerBlock = kBlock / 64;
-constexpr int kDefaultLdsCap = 1024; // int32 entries of N(prev) per wavefront (5 blocks of 16 KB per CU)
+constexpr int kDefaultLdsCap = 512;  // int32 entries of N(prev) per wavefront: with the four 1 KB vertex-record
+                                     // slots a block takes 24 KB, six blocks per CU (1024: 32 KB blocks, slower)
 // eRJS proposals whose loads a lane issues together.  Only depth 3 is built: a build with
 // depth 4 whose counted launches were compiled for 5 waves per SIMD (heavy spills) left the
 // oracle's path after eRJS cap fall-backs, and that failure has no identified cause, so no
