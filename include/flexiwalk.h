@@ -284,7 +284,8 @@ int fw_plan_profile(fw_graph *g, const fw_logic *logic, fw_plan *out, void *stre
  * graph, the member board for second-order PageRank; and each
  * proposal: h-proportional too for a weighted logic once fw_graph_build_alias ran, and
  * label-conditioned for MetaPath once fw_graph_build_label_alias ran), then for the
- * degree gate d_lo in {0, 8, 32, 128}, the LDS budget for N(prev), the eRJS trial cap
+ * degree gate d_lo in {0, 8, 32, 128}, the LDS budget for N(prev) (lds_cap in
+ * {256, 512, 1024, 2048, 4096}), the eRJS trial cap
  * rjs_cap in {16, 64, 256, 1024, 4096}, the lanes' shared eRVS threshold (rvs_share,
  * taken only when 2 % faster), the eRVS lanes on long rows (hub_lanes 128 or
  * 256 from hub_deg 1024 or 8192; fw_plan_autotune only, never for a mix) and the

@@ -871,7 +871,7 @@ int fw_plan_autotune_mix(fw_graph *g, const fw_logic *logics, int32_t n_logics, 
         if ((rc = time_plan(p, &t)) != FW_OK) return rc;
         if (t < bestt) bestt = t, bestp = p;
     }
-    for (int32_t cap : {512, 2048, 4096}) {
+    for (int32_t cap : {256, 1024, 2048, 4096}) {  // around the default of 512
         fw_plan p = bestp;
         p.lds_cap = cap;
         float t;
